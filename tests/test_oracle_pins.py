@@ -1,0 +1,519 @@
+"""Pins of the FP64 oracle against closed forms, brute force, finite differences and LAPACK.
+
+Each test fixes one part of the oracle with something other than the oracle itself, so
+that a dropped term, a wrong sign or index, or a transposed operand fails at least one:
+  * projection: the isotropic on-axis closed form, a hand-placed point, and the EWA
+    covariance rebuilt from scipy's rotation and a finite-difference perspective Jacobian;
+  * keys, rects and lists: float32 depth bits from numpy, the q <= 9 containment
+    invariant checked pixel by pixel, lists rebuilt with numpy's lexsort;
+  * compositing: brute force equals the tiled renderer exactly; single and stacked
+    Gaussians in closed form; Eq. 1-2 sums;
+  * Jacobian rows: FP64 central finite differences through the frozen compositor;
+  * blocks: rows summed outer-product by outer-product in numpy; dense level 1 equals
+    the level-2 block expansion;
+  * log-det: numpy slogdet; the block-diagonal identity on a dense matrix;
+  * information gain: eigenvalue closed form when the training set sees nothing, the
+    full sum rebuilt from blocks with numpy, object-centric zeros, IG >= 0, zero for a
+    camera that looks away;
+  * Eq. 10-11 and argmax: training views score a mean of exactly one; brute-force argmax.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import scenegen
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RP = oracle.RasterParams()
+IG = oracle.IGParams()
+
+
+def axis_camera(W=64, H=48, f=50.0):
+    """Camera at the world origin looking down +z (R = I, t = 0)."""
+    return scenegen.Camera(R=np.eye(3, dtype=np.float32), t=np.zeros(3, np.float32), fx=f, fy=f,
+                           cx=W / 2.0, cy=H / 2.0, width=W, height=H)
+
+
+def f64(x):
+    return float(np.float32(x))
+
+
+def small_scene(k=4, seed=3, n=6, spread=0.04, z=0.5):
+    """A few overlapping Gaussians near the optical axis, FP64 arrays (for finite differences)."""
+    rng = np.random.default_rng(seed)
+    means = np.column_stack([rng.normal(0, spread, n), rng.normal(0, spread, n), z + rng.normal(0, 0.05, n)])
+    ls = np.log(rng.uniform(0.01, 0.03, (n, 3)))
+    q = rng.normal(size=(n, 4))
+    ol = rng.normal(0.0, 0.7, n)
+    rgb = rng.uniform(0, 1, (n, 3))
+    o = rng.normal(0, 1.0, (n, k))
+    sc = scenegen.tiny_scene(means, ls, q, ol, rgb, o)
+    # keep FP64 copies (finite differences perturb below float32 resolution)
+    sc.mean = np.ascontiguousarray(means.T); sc.log_scale = np.ascontiguousarray(ls.T)
+    sc.rot = np.ascontiguousarray(q.T); sc.opacity_logit = np.ascontiguousarray(ol)
+    sc.rgb = np.ascontiguousarray(rgb.T); sc.obj_logit = np.ascontiguousarray(o.T)
+    return sc
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    return cfg, scene, cands, train
+
+
+# ------------------------------------------------------------------------------------------
+# Paper constants and generator
+# ------------------------------------------------------------------------------------------
+
+def test_defaults_match_paper_constants():
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+    d = oracle.IGParams()
+    assert d.alpha_obj == gold["alpha_obj"] and d.alpha_opa == gold["alpha_opa"]
+    assert d.beta_d == gold["beta_d"] and d.beta_o == gold["beta_o"]
+    assert scenegen.CONFIGS["mid"].n_train == gold["n_initial_views"]
+
+
+def test_generator_structure(tiny):
+    cfg, scene, cands, train = tiny
+    n, k = scene.n, scene.k
+    counts = np.bincount(scene.cluster, minlength=cfg.clusters)
+    assert counts.max() - counts.min() <= 1
+    qn = np.linalg.norm(scene.rot.astype(np.float64), axis=0)
+    assert np.allclose(qn, 1.0, atol=1e-6)
+    ls = scene.log_scale.astype(np.float64)
+    assert ls.min() >= math.log(0.002) - 1e-6 and ls.max() <= math.log(0.02) + 1e-6
+    from scipy.stats import kstest
+    u = (ls.reshape(-1) - math.log(0.002)) / (math.log(0.02) - math.log(0.002))
+    assert kstest(u, "uniform").pvalue > 1e-3
+    assert kstest(scene.opacity_logit.astype(np.float64), "norm").pvalue > 1e-3
+    # softmax of the tempered one-hot logits: kappa = q + (1 - q) / K, argmax = cluster
+    gt = oracle.gaussian_terms(scene)
+    q = scene.confidence.astype(np.float64)
+    assert np.allclose(gt["kappa"], q + (1 - q) / k, atol=2e-6)
+    assert np.array_equal(gt["argmax"], scene.cluster)
+    assert np.allclose(gt["p"].sum(axis=1), 1.0, atol=1e-12)
+    # cameras: look at the origin, right-handed OpenCV frame, requested radius
+    for c in cands + train:
+        R = c.R.astype(np.float64)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-6) and np.linalg.det(R) > 0
+        eye = -R.T @ c.t
+        assert abs(np.linalg.norm(eye) - 0.6) < 1e-5
+        assert np.allclose(R @ np.zeros(3) + c.t, [0, 0, np.linalg.norm(eye)], atol=1e-5)
+
+
+def test_confidence_eq7_eq12_properties():
+    k = 5
+    big = 30.0
+    # kappa -> 1 and sigma -> 1 gives c = 1 (Eq. 7)
+    o = np.full((3, k), -big); o[:, 1] = big
+    sc = scenegen.tiny_scene(np.zeros((3, 3)), np.zeros((3, 3)), np.tile([1, 0, 0, 0], (3, 1)),
+                             [big, 0.0, -2.0], np.zeros((3, 3)), o)
+    gt = oracle.gaussian_terms(sc)
+    assert abs(gt["conf"][0] - 1.0) < 1e-6
+    assert np.all(gt["conf"] >= 1.0 - 1e-12)
+    assert gt["conf"][2] > gt["conf"][1] > gt["conf"][0]           # decreasing in sigma
+    # alpha_obj = 1, alpha_opa = 0 reduces Eq. 7 to 1 / kappa
+    rng = np.random.default_rng(0)
+    o2 = rng.normal(size=(8, k))
+    sc2 = scenegen.tiny_scene(np.zeros((8, 3)), np.zeros((8, 3)), np.tile([1, 0, 0, 0], (8, 1)),
+                              rng.normal(size=8), np.zeros((8, 3)), o2)
+    gt2 = oracle.gaussian_terms(sc2, oracle.IGParams(alpha_obj=1.0, alpha_opa=0.0))
+    p = np.exp(o2.astype(np.float32).astype(np.float64))
+    p /= p.sum(1, keepdims=True)
+    assert np.allclose(gt2["conf"], 1.0 / p.max(1), rtol=1e-12)
+    # Eq. 12: zero off the target, target probability on it
+    gt3 = oracle.gaussian_terms(sc2, oracle.IGParams(alpha_obj=1.0, alpha_opa=0.0, target_id=2))
+    on = p.argmax(1) == 2
+    assert np.all(gt3["conf"][~on] == 0.0)
+    assert np.allclose(gt3["conf"][on], 1.0 / p[on, 2], rtol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Projection, keys, rects, lists
+# ------------------------------------------------------------------------------------------
+
+def test_projection_isotropic_on_axis_closed_form():
+    s, z, f = 0.01, 0.5, 50.0
+    rng = np.random.default_rng(1)
+    quats = np.vstack([[1, 0, 0, 0], rng.normal(size=(4, 4))])
+    n = len(quats)
+    sc = scenegen.tiny_scene(np.tile([0, 0, z], (n, 1)), np.full((n, 3), math.log(s)), quats,
+                             np.zeros(n), np.zeros((n, 3)), np.zeros((n, 2)))
+    cam = axis_camera(f=f)
+    pr = oracle.project(sc, cam)
+    s32 = math.exp(f64(math.log(s)))
+    v = f64(f) ** 2 * s32 ** 2 / f64(z) ** 2 + f64(0.3)
+    assert np.allclose(pr["cov"][0], v, rtol=1e-12) and np.allclose(pr["cov"][2], v, rtol=1e-12)
+    assert np.allclose(pr["cov"][1], 0.0, atol=1e-12 * v)
+    assert np.allclose(pr["conic"][0], 1 / v, rtol=1e-12) and np.allclose(pr["conic"][2], 1 / v, rtol=1e-12)
+    assert np.all(pr["radius"] == math.ceil(3 * math.sqrt(v)))
+    assert np.allclose(pr["m"][0], cam.cx) and np.allclose(pr["m"][1], cam.cy)
+    assert np.all(pr["z"] == f64(z))
+
+
+def test_projection_point_and_ewa_covariance():
+    # hand-placed point: camera coordinates (0.1, -0.05, 0.5), f = 100 -> (cx + 20, cy - 10)
+    cam = scenegen.look_at(np.array([0.3, -0.4, 0.5]), 128, 96, 100.0)
+    R = cam.R.astype(np.float64); t = cam.t.astype(np.float64)
+    Xc = np.array([0.1, -0.05, 0.5])
+    mu = np.linalg.solve(R, Xc - t)      # R is float32-orthonormal only; solve exactly
+    sc = scenegen.tiny_scene([mu], [[-4, -4, -4]], [[1, 0, 0, 0]], [0], [[0, 0, 0]], [[0, 0]])
+    sc.mean = np.ascontiguousarray(mu.reshape(3, 1))
+    pr = oracle.project(sc, cam)
+    assert abs(pr["m"][0, 0] - (64 + 20)) < 1e-9 and abs(pr["m"][1, 0] - (48 - 10)) < 1e-9
+    # anisotropic Gaussians: Sigma2 = J R Sigma3 R^T J^T + eps I, with J from finite differences
+    # of the pinhole map and Sigma3 from scipy's quaternion rotation
+    rng = np.random.default_rng(2)
+    n = 20
+    means = rng.normal(0, 0.1, (n, 3))
+    ls = np.log(rng.uniform(0.003, 0.03, (n, 3)))
+    q = rng.normal(size=(n, 4))
+    sc = scenegen.tiny_scene(means, ls, q, np.zeros(n), np.zeros((n, 3)), np.zeros((n, 2)))
+    pr = oracle.project(sc, cam)
+    fx, fy, cx, cy = f64(cam.fx), f64(cam.fy), f64(cam.cx), f64(cam.cy)
+    pin = lambda X: np.array([fx * X[0] / X[2] + cx, fy * X[1] / X[2] + cy])
+    for g in range(n):
+        m = sc.mean[:, g].astype(np.float64)
+        X = R @ m + t
+        J = np.zeros((2, 3))
+        for j in range(3):
+            h = 1e-6
+            e = np.zeros(3); e[j] = h
+            J[:, j] = (pin(X + e) - pin(X - e)) / (2 * h)
+        qq = sc.rot[:, g].astype(np.float64)
+        Rg = Rotation.from_quat([qq[1], qq[2], qq[3], qq[0]]).as_matrix()
+        S3 = Rg @ np.diag(np.exp(2 * sc.log_scale[:, g].astype(np.float64))) @ Rg.T
+        S2 = J @ R @ S3 @ R.T @ J.T + f64(0.3) * np.eye(2)
+        got = np.array([[pr["cov"][0, g], pr["cov"][1, g]], [pr["cov"][1, g], pr["cov"][2, g]]])
+        assert np.allclose(got, S2, rtol=1e-6, atol=1e-9 * np.abs(S2).max())
+        Qg = np.array([[pr["conic"][0, g], pr["conic"][1, g]], [pr["conic"][1, g], pr["conic"][2, g]]])
+        assert np.allclose(Qg @ got, np.eye(2), atol=1e-12)
+        assert np.allclose(pr["m"][:, g], pin(X), rtol=1e-12)
+        assert pr["zkey"][g] == np.float32(X[2]).view(np.uint32) or not pr["valid"][g]
+
+
+def test_keys_rect_containment_and_lists(tiny):
+    cfg, scene, cands, train = tiny
+    cam = cands[1]
+    pr = oracle.project(scene, cam)
+    W, H, B = cam.width, cam.height, RP.tile
+    TW, TH = -(-W // B), -(-H // B)
+    valid = pr["valid"].astype(bool)
+    # depth keys: bits of float32(Z), re-derived with numpy
+    assert np.array_equal(pr["zkey"][valid], pr["z"][valid].astype(np.float32).view(np.uint32))
+    # containment: every pixel centre with q <= 9 lies in a tile of the Gaussian's rect
+    xs, ys = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    inside = 0
+    for g in np.nonzero(pr["z"] > f64(0.05))[0][:400]:
+        dx, dy = xs - pr["m"][0, g], ys - pr["m"][1, g]
+        qv = pr["conic"][0, g] * dx * dx + 2 * pr["conic"][1, g] * dx * dy + pr["conic"][2, g] * dy * dy
+        hit = qv <= 9.0
+        if not hit.any():
+            continue
+        inside += 1
+        assert valid[g]
+        ty, tx = np.nonzero(hit)
+        tx, ty = tx // B, ty // B
+        x0, y0, x1, y1 = pr["rect"][:, g]
+        assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
+    assert inside > 100
+    # lists: emit every (tile, gid) of the rects and sort with numpy's lexsort
+    tl = oracle.tile_lists(scene, cam)
+    tiles, gids = [], []
+    for g in np.nonzero(valid)[0]:
+        x0, y0, x1, y1 = pr["rect"][:, g]
+        for ty in range(y0, y1 + 1):
+            for tx in range(x0, x1 + 1):
+                tiles.append(ty * TW + tx); gids.append(g)
+    tiles = np.array(tiles, np.uint64); gids = np.array(gids, np.uint32)
+    zk = pr["zkey"][gids].astype(np.uint64)
+    order = np.lexsort((gids, zk, tiles))
+    assert tl["m"] == len(order)
+    assert np.array_equal(tl["gids"], gids[order])
+    assert np.array_equal(tl["keys"], (tiles[order] << np.uint64(32)) | zk[order])
+    counts = np.bincount(tiles.astype(np.int64), minlength=TW * TH)
+    assert np.array_equal(tl["ranges"][1] - tl["ranges"][0], counts)
+    assert np.array_equal(tl["ranges"][0], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+
+
+# ------------------------------------------------------------------------------------------
+# Compositing
+# ------------------------------------------------------------------------------------------
+
+def test_brute_force_equals_tiled(tiny):
+    cfg, scene, cands, train = tiny
+    for cam in cands[:3]:
+        a = oracle.render(scene, cam)
+        b = oracle.render(scene, cam, brute=True)
+        for key in ("rgb", "depth", "obj", "objp", "t_final", "id", "kbar", "ncontrib"):
+            assert np.array_equal(a[key], b[key]), key
+
+
+def test_single_and_stacked_gaussians_closed_form():
+    s, z, f = 0.01, 0.5, 50.0
+    cam = axis_camera(f=f)
+    sig_l = 2.0
+    rgb = [0.2, 0.5, 0.9]
+    for n in (1, 3, 12):
+        o = np.tile([0.3, -0.2, 1.0], (n, 1))
+        sc = scenegen.tiny_scene(np.tile([0, 0, z], (n, 1)), np.full((n, 3), math.log(s)),
+                                 np.tile([1, 0, 0, 0], (n, 1)), np.full(n, sig_l), np.tile(rgb, (n, 1)), o)
+        img = oracle.render(sc, cam)
+        v = f64(f) ** 2 * math.exp(2 * f64(math.log(s))) / f64(z) ** 2 + f64(0.3)
+        sigma = 1 / (1 + math.exp(-f64(sig_l)))
+        for (px, py) in [(32, 24), (33, 22), (30, 25)]:
+            r2 = (px + 0.5 - 32) ** 2 + (py + 0.5 - 24) ** 2
+            assert r2 / v < 9.0
+            alpha = min(f64(0.99), sigma * math.exp(-0.5 * r2 / v))
+            assert alpha > 1 / 255
+            nc = 0
+            while nc < n and (1 - alpha) ** (nc + 1) >= f64(1e-4):
+                nc += 1
+            tf = (1 - alpha) ** nc
+            assert img["ncontrib"][py, px] == nc
+            assert abs(img["t_final"][py, px] - tf) < 1e-12
+            assert np.allclose(img["rgb"][:, py, px], np.array([f64(c) for c in rgb]) * (1 - tf), atol=1e-12)
+            assert abs(img["depth"][py, px] - f64(z) * (1 - tf)) < 1e-12
+            p = np.exp(np.array([f64(x) for x in o[0]])); p /= p.sum()
+            assert np.allclose(img["objp"][:, py, px], p * (1 - tf), atol=1e-12)
+            exp_o = p * (1 - tf); exp_o[0] += tf
+            assert np.allclose(img["obj"][:, py, px], exp_o, atol=1e-12)
+            assert abs(img["kbar"][py, px] - p.max()) < 1e-12
+    # far outside the footprint nothing is composited
+    assert img["ncontrib"][0, 0] == 0 and img["t_final"][0, 0] == 1.0
+
+
+def test_stop_rule_ends_the_walk():
+    """Once T (1 - alpha) would drop below t_min the pixel stops: a faint Gaussian further
+    back, which on its own would pass every test, is not composited."""
+    n = 12
+    cam = axis_camera(f=50.0)
+    means = np.vstack([np.tile([0, 0, 0.5], (n, 1)), [[0, 0, 0.6]]])
+    ls = np.full((n + 1, 3), math.log(0.01))
+    sc = scenegen.tiny_scene(means, ls, np.tile([1, 0, 0, 0], (n + 1, 1)), np.r_[np.full(n, 2.0), -3.0],
+                             np.tile([0.2, 0.5, 0.9], (n + 1, 1)), np.zeros((n + 1, 3)))
+    img = oracle.render(sc, cam)
+    v = f64(50.0) ** 2 * math.exp(2 * f64(math.log(0.01))) / f64(0.5) ** 2 + f64(0.3)
+    alpha = (1 / (1 + math.exp(-2.0))) * math.exp(-0.5 * 0.5 / v)
+    nc = max(j for j in range(n + 1) if (1 - alpha) ** j >= f64(1e-4))
+    assert nc < n
+    tf = (1 - alpha) ** nc
+    faint = (1 / (1 + math.exp(3.0))) * math.exp(-0.5 * 0.5 / (f64(50.0) ** 2 * math.exp(2 * f64(math.log(0.01))) / f64(0.6) ** 2 + f64(0.3)))
+    assert faint > 1 / 255 and tf * (1 - faint) >= 1e-4     # the faint one would pass on its own
+    assert img["ncontrib"][24, 32] == nc
+    assert abs(img["t_final"][24, 32] - tf) < 1e-15
+
+
+def test_eq1_eq2_sums(tiny):
+    cfg, scene, cands, train = tiny
+    img = oracle.render(scene, cands[2])
+    sp = img["objp"].sum(0)
+    assert np.allclose(sp, 1 - img["t_final"], atol=1e-12)
+    assert np.all(sp <= 1 + 1e-12)
+    assert np.allclose(img["obj"].sum(0), 1.0, atol=1e-12)
+    assert np.all(img["obj"][0] >= img["t_final"] - 1e-12)
+    assert np.array_equal(img["id"], np.argmax(img["obj"], axis=0))
+    assert img["ncontrib"].sum() > 0
+
+
+# ------------------------------------------------------------------------------------------
+# Jacobian rows, blocks
+# ------------------------------------------------------------------------------------------
+
+def _perturbed(sc, name, idx, g, h):
+    import copy
+    s2 = copy.copy(sc)
+    arr = getattr(sc, name).copy()
+    if arr.ndim == 1:
+        arr[g] += h
+    else:
+        arr[idx, g] += h
+    setattr(s2, name, arr)
+    return s2
+
+
+@pytest.mark.parametrize("eq2", [1, 0])
+def test_jacobian_rows_match_finite_differences(eq2):
+    k = 4
+    sc = small_scene(k=k)
+    cam = axis_camera(W=32, H=32, f=40.0)
+    ig = oracle.IGParams(obj_eq2=eq2)
+    rp = oracle.RasterParams()
+    img = oracle.render(sc, cam, ig=ig)
+    checked = 0
+    for (px, py) in [(16, 16), (14, 18), (19, 13)]:
+        rows = oracle.pixel_rows(sc, cam, px, py, ig=ig)
+        seq = rows["gids"]
+        assert len(seq) == img["ncontrib"][py, px] and len(seq) >= 2
+        params = [("mean", i) for i in range(3)] + [("log_scale", i) for i in range(3)] + \
+                 [("rot", i) for i in range(4)] + [("opacity_logit", None)]
+        for ci, g in enumerate(seq):
+            for j, (name, idx) in enumerate(params):
+                base = getattr(sc, name)
+                val = base[g] if base.ndim == 1 else base[idx, g]
+                h = 1e-6 * max(1.0, abs(val))
+                fp = oracle.pixel_eval_frozen(_perturbed(sc, name, idx, g, h), cam, px, py, seq, rp, ig)
+                fm = oracle.pixel_eval_frozen(_perturbed(sc, name, idx, g, -h), cam, px, py, seq, rp, ig)
+                fd = (fp - fm) / (2 * h)
+                an = np.concatenate([rows["rgb"][ci][:, j], [rows["d"][ci][j]], rows["o"][ci][:, j]])
+                assert np.allclose(fd, an, rtol=1e-5, atol=1e-6 * max(1.0, np.abs(an).max())), (name, idx, ci)
+                checked += 1
+            for c in range(3):
+                h = 1e-6
+                fp = oracle.pixel_eval_frozen(_perturbed(sc, "rgb", c, g, h), cam, px, py, seq, rp, ig)
+                fm = oracle.pixel_eval_frozen(_perturbed(sc, "rgb", c, g, -h), cam, px, py, seq, rp, ig)
+                fd = (fp - fm) / (2 * h)
+                assert np.allclose(fd[:3], rows["rgb"][ci][:, 11 + c], atol=1e-8)
+            for m in range(k):
+                h = 1e-6
+                fp = oracle.pixel_eval_frozen(_perturbed(sc, "obj_logit", m, g, h), cam, px, py, seq, rp, ig)
+                fm = oracle.pixel_eval_frozen(_perturbed(sc, "obj_logit", m, g, -h), cam, px, py, seq, rp, ig)
+                fd = (fp - fm) / (2 * h)
+                assert np.allclose(fd[4:], rows["o"][ci][:, 11 + m], atol=1e-8)
+    assert checked > 50
+
+
+def test_blocks_are_sums_of_row_outer_products():
+    k = 4
+    sc = small_scene(k=k, n=5)
+    cam = axis_camera(W=32, H=32, f=40.0)
+    ref = {}
+    for py in range(32):
+        for px in range(32):
+            rows = oracle.pixel_rows(sc, cam, px, py)
+            for ci, g in enumerate(rows["gids"]):
+                A = ref.setdefault(int(g), [np.zeros((14, 14)), np.zeros((11, 11)), np.zeros((11 + k, 11 + k))])
+                A[0] += rows["rgb"][ci].T @ rows["rgb"][ci]
+                A[1] += np.outer(rows["d"][ci], rows["d"][ci])
+                A[2] += rows["o"][ci].T @ rows["o"][ci]
+    for level in (1, 2):
+        vb = oracle.view_blocks(sc, cam, ig=oracle.IGParams(level=level))
+        assert sorted(ref) == list(vb.gids)
+        for i, g in enumerate(vb.gids):
+            for f, blk in enumerate((vb.rgb[i], vb.d[i], vb.o[i])):
+                assert np.allclose(blk, ref[int(g)][f], rtol=1e-12, atol=1e-12 * np.abs(ref[int(g)][f]).max())
+
+
+def test_level1_equals_level2(tiny):
+    cfg, scene, cands, train = tiny
+    b1 = oracle.view_blocks(scene, cands[3], ig=oracle.IGParams(level=1))
+    b2 = oracle.view_blocks(scene, cands[3], ig=oracle.IGParams(level=2))
+    assert np.array_equal(b1.gids, b2.gids)
+    for x, y in ((b1.rgb, b2.rgb), (b1.d, b2.d), (b1.o, b2.o)):
+        scale = np.abs(x).reshape(len(x), -1).max(1)[:, None, None]
+        assert np.all(np.abs(x - y) <= 1e-12 * scale)
+    # blocks are symmetric positive semi-definite
+    ev = np.linalg.eigvalsh(b2.o)
+    assert np.all(ev >= -1e-9 * np.abs(ev).max(axis=1, keepdims=True))
+
+
+# ------------------------------------------------------------------------------------------
+# Log-det and information gain
+# ------------------------------------------------------------------------------------------
+
+def test_logdet_matches_lapack_and_block_identity():
+    rng = np.random.default_rng(4)
+    blocks = []
+    for l in (14, 11, 43, 75):
+        X = rng.normal(size=(l, 2 * l)) * np.exp(rng.uniform(-4, 4, size=(l, 1)))
+        A = X @ X.T + 0.1 * np.eye(l)
+        s, ld = np.linalg.slogdet(A)
+        assert s > 0 and abs(oracle.logdet(A) - ld) < 1e-9 * max(1, abs(ld))
+        blocks.append(A)
+    dense = np.zeros((sum(b.shape[0] for b in blocks),) * 2)
+    o = 0
+    for b in blocks:
+        dense[o:o + len(b), o:o + len(b)] = b
+        o += len(b)
+    assert abs(np.linalg.slogdet(dense)[1] - sum(oracle.logdet(b) for b in blocks)) < 1e-8
+    assert math.isnan(oracle.logdet(-np.eye(3)))
+
+
+def _numpy_ig(scene, train, cam, ig):
+    """IG_f rebuilt with numpy slogdet from the oracle's (separately pinned) view blocks."""
+    gt = oracle.gaussian_terms(scene, ig)
+    vb = oracle.view_blocks(scene, cam, ig=ig)
+    H = oracle.train_blocks(scene, train, vb.gids, ig=ig)
+    out = np.zeros(3)
+    for i, g in enumerate(vb.gids):
+        c = gt["conf"][g]
+        for f, (A, Hf) in enumerate(((vb.rgb[i], H["rgb"][i]), (vb.d[i], H["d"][i]), (vb.o[i], H["o"][i]))):
+            out[f] += np.linalg.slogdet(Hf + c * A)[1] - np.linalg.slogdet(Hf)[1]
+    return out, vb, gt
+
+
+def test_train_blocks_prior_and_weights(tiny):
+    cfg, scene, cands, train = tiny
+    ig = oracle.IGParams()
+    gt = oracle.gaussian_terms(scene, ig)
+    vbs = [oracle.view_blocks(scene, t) for t in train]
+    q = np.array(sorted(set(vbs[0].gids[:20]) | set(vbs[1].gids[-20:]) | {0, 1, 2}), np.int32)
+    H = oracle.train_blocks(scene, train, q, ig=ig)
+    for i, g in enumerate(q):
+        for f, lo in enumerate((14, 11, 11 + scene.k)):
+            ref = ig.lambda_prior * np.eye(lo)
+            ref = float(np.float32(ig.lambda_prior)) * np.eye(lo)
+            for vb in vbs:
+                j = np.nonzero(vb.gids == g)[0]
+                if len(j):
+                    ref = ref + gt["conf"][g] * (vb.rgb, vb.d, vb.o)[f][j[0]]
+            got = (H["rgb"], H["d"], H["o"])[f][i]
+            assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_info_gain_rebuilt_with_numpy(tiny):
+    cfg, scene, cands, train = tiny
+    for target in (-1, 3):
+        ig = oracle.IGParams(target_id=target)
+        r = oracle.score(scene, train, cands[:2], ig=ig)
+        for c in range(2):
+            ref, vb, gt = _numpy_ig(scene, train, cands[c], ig)
+            assert np.allclose(r.ig_cand[c], ref, rtol=1e-9), (target, c)
+            assert np.all(r.ig_cand[c] >= 0)
+        if target >= 0:
+            # object-centric: only target Gaussians contribute
+            ref_w, _, _ = _numpy_ig(scene, train, cands[0], oracle.IGParams())
+            assert np.all(r.ig_cand[0] < ref_w)
+            assert np.all(gt["conf"][gt["argmax"] != target] == 0)
+
+
+def test_info_gain_eigenvalue_closed_form_when_training_sees_nothing(tiny):
+    cfg, scene, cands, train = tiny
+    away = [scenegen.look_at(np.array([5.0, 0.0, 0.5]), 128, 96, 100.0, target=(10.0, 0.0, 0.5))]
+    assert np.all(np.isfinite(away[0].R))
+    img = oracle.render(scene, away[0])
+    assert np.all(img["t_final"] == 1.0) and np.all(img["rgb"] == 0.0)
+    ig = oracle.IGParams()
+    r = oracle.score(scene, away, cands[:1], ig=ig)
+    assert r.status == -5                      # normalisers are zero: degenerate
+    assert np.all(r.ig_train == 0.0)
+    vb = oracle.view_blocks(scene, cands[0])
+    gt = oracle.gaussian_terms(scene, ig)
+    lam = float(np.float32(ig.lambda_prior))
+    ref = np.zeros(3)
+    for i, g in enumerate(vb.gids):
+        for f, A in enumerate((vb.rgb[i], vb.d[i], vb.o[i])):
+            mu = np.linalg.eigvalsh(A)
+            ref[f] += np.sum(np.log1p(gt["conf"][g] * np.clip(mu, 0, None) / lam))
+    assert np.allclose(r.ig_cand[0], ref, rtol=1e-9)
+    # and a candidate that sees nothing gains nothing
+    r2 = oracle.score(scene, train, away, ig=ig)
+    assert np.all(r2.ig_cand == 0.0)
+
+
+def test_normalisation_eq10_and_argmax(tiny):
+    cfg, scene, cands, train = tiny
+    r = oracle.score(scene, train, train + cands[:4])
+    assert r.status == 0
+    t = len(train)
+    assert np.allclose(r.scores[:t, :3].mean(0), 1.0, atol=1e-12)
+    assert np.allclose(r.ig_cand[:t], r.ig_train, rtol=0, atol=0)
+    assert np.allclose(r.scores[:, :3], r.ig_cand / r.norm, rtol=1e-14)
+    tot = r.scores[:, 0] + 10.0 * r.scores[:, 1] + r.scores[:, 2]
+    assert np.allclose(r.scores[:, 3], tot, rtol=1e-14)
+    assert r.best == int(np.argmax(r.scores[:, 3]))
