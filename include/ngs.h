@@ -1,0 +1,262 @@
+/* ngs.h -- C ABI of the MI355X (gfx950) next-best-view scorer for object-aware
+ * 3D Gaussian Splatting (arXiv 2602.08266).
+ *
+ * The library renders colour, depth and the object vector of a Gaussian map for
+ * candidate camera poses (tile-based splatting, Sec. III-A, Eq. 1-2) and scores each
+ * pose by the confidence-weighted, block-diagonal log-det information gain
+ * (Sec. III-B, Eq. 5-11), normalised per output by the training views.
+ *
+ * Conventions
+ *  - Every function returns ngs_status; no C++ exception crosses the ABI. On error the
+ *    outputs are unspecified and the context stays usable.
+ *  - Array arguments are caller-owned, contiguous DEVICE pointers unless marked
+ *    "host". The library never frees, retains or reallocates caller memory.
+ *  - All work is enqueued on the caller's stream (hipStream_t passed as void*; NULL is
+ *    the default stream). Outputs are valid after the stream is synchronised.
+ *    Functions that must read a device count back (marked "syncs") synchronise the
+ *    stream before returning.
+ *  - Float arrays are FP32 structure-of-arrays: "[3][n]" means three planes of n.
+ *    Per-output information-gain sums are FP64.
+ *  - One context per host thread; a context is bound to one device.
+ */
+#ifndef NGS_H
+#define NGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ngs_status;
+#define NGS_OK 0
+#define NGS_INVALID_ARG (-1)      /* NULL where a pointer is required, negative size ... */
+#define NGS_CAPACITY (-2)         /* an output buffer is too small; the needed size is reported */
+#define NGS_WORKSPACE_TOO_SMALL (-3)
+#define NGS_HIP_ERROR (-4)        /* a HIP runtime call failed; see ngs_last_hip_error */
+#define NGS_DEGENERATE (-5)       /* an enabled Eq. 10 normaliser is not positive */
+#define NGS_UNSUPPORTED (-6)      /* e.g. k > 64, tile != 16, more than 4096 tiles */
+
+#define NGS_MAX_K 64
+#define NGS_MAX_TILES 4096
+
+/* Output bits of ngs_ig_params.outputs (Sec. III-B.3). */
+#define NGS_OUT_RGB 1u
+#define NGS_OUT_DEPTH 2u
+#define NGS_OUT_OBJ 4u
+
+/* ngs_ig_params.mode */
+#define NGS_MODE_SCORE 0          /* IG_f(T, c) of one candidate view (Eq. 5) */
+#define NGS_MODE_ACCUMULATE 1     /* add c_g * A_t,g of a training view into H_T (Eq. 9) */
+
+typedef struct ngs_ctx ngs_ctx;
+
+/* Gaussian map (Sec. III-A.1): mean mu, log-scale, raw quaternion (w, x, y, z), opacity
+ * logit, SH degree-0 colour and object logits o of length k = n_objects + 1 (channel 0 is
+ * the background). The derived arrays are caller-allocated and written by
+ * ngs_prepare_scene: prob = softmax(o) row-major [n][k]; opacity = sigmoid(logit);
+ * kappa = max_k prob; conf = c_g of Eq. 7 (or Eq. 12 for a target); label = argmax_k
+ * prob (lowest k on ties). */
+typedef struct {
+  int32_t n, k;
+  const float* mean;           /* [3][n] */
+  const float* log_scale;      /* [3][n] */
+  const float* rot;            /* [4][n] */
+  const float* opacity_logit;  /* [n] */
+  const float* rgb;            /* [3][n] */
+  const float* obj_logit;      /* [k][n] */
+  float* prob;                 /* [n][k] derived */
+  float* opacity;              /* [n] derived */
+  float* kappa;                /* [n] derived */
+  float* conf;                 /* [n] derived */
+  int32_t* label;              /* [n] derived */
+} ngs_scene;
+
+/* Pinhole camera: world -> camera rotation R (row-major) and translation t; OpenCV axes
+ * (x right, y down, z forward); focal lengths and principal point in pixels. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} ngs_camera;
+
+/* Rasterizer constants of the 3DGS pipeline the paper follows (Sec. IV-A.2):
+ * tile = 16, z_near = 0.05, eps2d = 0.3, cutoff_q = 9, alpha_min = 1/255,
+ * alpha_max = 0.99, t_min = 1e-4. */
+typedef struct {
+  int32_t tile;
+  float z_near, eps2d, cutoff_q, alpha_min, alpha_max, t_min;
+} ngs_raster_params;
+
+/* Information-gain constants: Eq. 7 exponents (0.3, 0.3) and Eq. 11 weights (10, 1)
+ * from Sec. IV-A.2; lambda_prior adds lambda*I to every block of H (a reading: the
+ * paper is silent on regularisation); target_id < 0 scores the whole scene (Eq. 7),
+ * otherwise Eq. 12 for that object; conf_on_train = 1 weights training views by c_g
+ * too (Eq. 9 read for every view); obj_eq2 = 1 differentiates O of Eq. 2 (else O'). */
+typedef struct {
+  float lambda_prior, alpha_obj, alpha_opa, beta_d, beta_o;
+  int32_t target_id;
+  uint32_t outputs;
+  int32_t conf_on_train;
+  int32_t obj_eq2;
+  int32_t mode;
+} ngs_ig_params;
+
+/* Per-view projection (one entry per Gaussian). rect is inclusive tile bounds
+ * (x0, y0, x1, y1); count = number of tiles (0: culled). zkey = bits of float32(Z). */
+typedef struct {
+  float* mean2d;    /* [2][n] */
+  float* conic;     /* [3][n] Q = Sigma2^-1: xx, xy, yy */
+  float* depth;     /* [n] camera-space Z */
+  uint32_t* zkey;   /* [n] */
+  int16_t* rect;    /* [4][n] */
+  uint32_t* count;  /* [n] */
+} ngs_projected;
+
+/* Per-view tile lists: (tile, depth, gid)-sorted Gaussian ids and per-tile ranges.
+ * keys (optional) = (tile << 32) | zkey. n_pairs is a device scalar. An empty tile has
+ * start = end = the number of pairs in lower tiles. */
+typedef struct {
+  uint64_t* keys;     /* [capacity] or NULL */
+  uint32_t* gids;     /* [capacity] */
+  int64_t capacity;
+  int64_t* n_pairs;   /* [1] */
+  uint32_t* ranges;   /* [2][tiles]: start, end */
+} ngs_tile_lists;
+
+/* Rendered images, planes of H x W. Optional outputs may be NULL. */
+typedef struct {
+  float* rgb;          /* [3][H][W] */
+  float* depth;        /* [H][W] sum of Z alpha T (unnormalised, background 0) */
+  float* obj;          /* [k][H][W] O of Eq. 2, or NULL */
+  float* t_final;      /* [H][W] */
+  float* mean_conf;    /* [H][W] sum kappa alpha T / (1 - T_final), or NULL */
+  int32_t* argmax_id;  /* [H][W] argmax_k O_k (lowest k on ties) */
+  int32_t* n_contrib;  /* [H][W] or NULL */
+} ngs_image;
+
+/* Training information H_T (Eq. 9 with prior lambda*I), stored only for Gaussians
+ * that a training view touched; every other Gaussian has H_T = lambda*I.
+ * Blocks are packed upper triangles, row-major, FP64, entry-major across slots:
+ * h_rgb[e * capacity + slot] for e < 105 (l = 14), h_d (66, l = 11), h_o
+ * ((11+k)(12+k)/2, l = 11 + k). logdet[f * capacity + slot], f = rgb, depth, obj.
+ * slot_of[n] must be filled with -1 and n_slots with 0 before the first training view
+ * (ngs_hessian_reset). */
+typedef struct {
+  int32_t k;
+  int32_t capacity;
+  int32_t* slot_of;    /* [n] */
+  int32_t* n_slots;    /* [1] */
+  int32_t* gid_of;     /* [capacity] */
+  double* h_rgb;
+  double* h_d;
+  double* h_o;
+  double* logdet;      /* [3][capacity] */
+} ngs_hessian;
+
+/* Per-view statistics the kernels add into (device, int64 [6], caller-zeroed):
+ * [0] views, [1] pairs M, [2] touched Gaussians with a nonzero weight U,
+ * [3] contributing (pixel, Gaussian) pairs P, [4] walked (tile, entry) pairs,
+ * [5] views whose slot workspace overflowed. */
+#define NGS_STATS_LEN 6
+
+/* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch.
+ * dims: n, k, width, height, pair capacity, slot capacity (all host). */
+typedef struct {
+  int64_t n, k, width, height, max_pairs, max_slots;
+} ngs_dims;
+
+/* ---------------------------------------------------------------------------------
+ * Context and helpers
+ * --------------------------------------------------------------------------------- */
+ngs_status ngs_create(int device, ngs_ctx** out);
+ngs_status ngs_destroy(ngs_ctx* ctx);
+const char* ngs_status_string(ngs_status s);
+int32_t ngs_version(void);
+/* Last hipError_t seen by this context (0 if none). */
+int32_t ngs_last_hip_error(const ngs_ctx* ctx);
+ngs_status ngs_workspace_size(int32_t op, const ngs_dims* dims, size_t* bytes);
+
+/* Per-scene precompute: p = softmax(o) (Sec. III-A.1), sigma, kappa, the confidence
+ * c_g of Eq. 7 (target_id < 0) or Eq. 12 (target_id >= 0), and labels. */
+ngs_status ngs_prepare_scene(ngs_ctx* ctx, ngs_scene* scene, const ngs_ig_params* ig, void* stream);
+
+/* Projection of every Gaussian for one camera (host struct), following the 3DGS pipeline
+ * (Sec. IV-A.2): X = R mu + t, cull Z <= z_near, 2D mean, EWA covariance
+ * J R Sigma3 R^T J^T + eps2d I, conic, radius ceil(3 sqrt(lambda_max)), tile rect. The
+ * depth key, 2D mean, covariance, radius and rect are evaluated in FP64 in a fixed order
+ * without contraction, so keys and rects are reproducible bit for bit. */
+ngs_status ngs_project(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cam,
+                       const ngs_raster_params* rp, ngs_projected* out, void* stream);
+
+/* Tile binning and sorting: every (tile, Gaussian) pair of the rects sorted by
+ * (tile, float32 depth bits, gid), and per-tile [start, end) ranges. Radix sort:
+ * depth digits over the visible Gaussians, then a stable pass on tile digits over the
+ * emitted pairs. Syncs (reads M). If M > capacity returns NGS_CAPACITY with M in
+ * *n_pairs. ws: ngs_workspace_size(0, ...) bytes. */
+ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                        const ngs_camera* cam, const ngs_raster_params* rp, ngs_tile_lists* out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Front-to-back compositing per 16x16 tile (Eq. 1-2): colour, depth, object vector O,
+ * final transmittance, argmax id, mean confidence, contributor count. */
+ngs_status ngs_render(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                      const ngs_tile_lists* lists, const ngs_camera* cam,
+                      const ngs_raster_params* rp, ngs_image* out, void* stream);
+
+/* Information of one view (Eq. 6, block diagonal per Gaussian, Sec. III-B.1) with the
+ * per-output parameter subsets of Sec. III-B.3 (rgb: 14, depth: 11, object: 11 + k).
+ * SCORE mode: ig_out[3] (device, FP64) = IG_f(T, c) = sum_g logdet(H_T,g + c_g A_g) -
+ * logdet(H_T,g) (Eq. 5, 6, 9); h may be NULL (H_T = lambda I). ACCUMULATE mode: adds
+ * w_g A_g into h (w_g = c_g, or 1 when conf_on_train = 0); call ngs_hessian_finalize
+ * after the last training view. stats (device int64 [NGS_STATS_LEN]) may be NULL.
+ * ws: ngs_workspace_size(1, ...) bytes. */
+ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                         const ngs_tile_lists* lists, const ngs_camera* cam,
+                         const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,
+                         double* ig_out, int64_t* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Clears a training store (slot_of = -1, n_slots = 0). */
+ngs_status ngs_hessian_reset(ngs_ctx* ctx, ngs_hessian* h, int32_t n, void* stream);
+/* Computes logdet of every stored block after the last ACCUMULATE view. Syncs; fails
+ * with NGS_CAPACITY (needed slots in *n_slots) if a training view overflowed. */
+ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream);
+
+/* Scores n_views candidates (host camera array): per view projection, binning,
+ * information gain (SCORE mode), then Eq. 10 normalisation with normalisers[3] (host,
+ * the mean training-view gains), Eq. 11 combination and argmax (Eq. 5, lowest index on
+ * ties). scores [n_views][4] device FP32: normalised rgb, depth, object, combined.
+ * best: device int32. ig_raw [n_views][3] device FP64 receives the raw gains IG_f.
+ * stats (device int64 [NGS_STATS_LEN], may be NULL) accumulates; on return stats[0] =
+ * views and stats[1] = total pairs. Returns NGS_DEGENERATE if an enabled normaliser is
+ * not positive, NGS_CAPACITY if a view overflows the workspace. ws:
+ * ngs_workspace_size(2, ...) sized for the largest view; syncs once per view. */
+ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
+                           const double* normalisers, const ngs_camera* cams, int32_t n_views,
+                           const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores,
+                           int32_t* best, double* ig_raw, int64_t* stats, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Optional kernel timing: while enabled, every kernel the library launches is bracketed
+ * by two hipEvents recorded on its launch stream. ngs_profile_read synchronises the
+ * recorded events and returns the total milliseconds and launch count of kernel class id
+ * (0 <= id < ngs_profile_kernels()); ngs_profile_kernel_name names the class. Enabling
+ * (or disabling) clears the totals. The profile is process-wide. */
+ngs_status ngs_profile_enable(ngs_ctx* ctx, int32_t on);
+int32_t ngs_profile_kernels(void);
+const char* ngs_profile_kernel_name(int32_t id);
+ngs_status ngs_profile_read(ngs_ctx* ctx, int32_t id, double* total_ms, int64_t* launches);
+
+/* Backward rasterizer (scene refinement, Sec. III-A.2). Not provided in this version:
+ * returns NGS_UNSUPPORTED. */
+ngs_status ngs_render_backward(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                               const ngs_tile_lists* lists, const ngs_camera* cam,
+                               const ngs_raster_params* rp, const ngs_image* fwd,
+                               const void* grad_image, void* grad_scene, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NGS_H */

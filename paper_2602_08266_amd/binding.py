@@ -1,0 +1,440 @@
+"""ctypes binding of libngs (include/ngs.h): argument marshalling only.
+
+Every step of the scoring path runs in the HIP kernels of libngs.so; this module only
+allocates device buffers with torch, fills the C structs and calls the entry points with
+the same names. It raises when the library has not been built: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libngs.so")
+
+NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
+NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
+MODE_SCORE, MODE_ACCUMULATE = 0, 1
+OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
+STATS_LEN = 6
+EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
+           "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_bin_sort", "ngs_render",
+           "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
+           "ngs_render_backward", "ngs_profile_enable", "ngs_profile_kernels", "ngs_profile_kernel_name",
+           "ngs_profile_read"]
+
+
+class NgsError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed: {msg} ({status})")
+        self.status = status
+
+
+P = C.c_void_p
+
+
+class ngs_scene(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("mean", P), ("log_scale", P), ("rot", P),
+                ("opacity_logit", P), ("rgb", P), ("obj_logit", P), ("prob", P), ("opacity", P),
+                ("kappa", P), ("conf", P), ("label", P)]
+
+
+class ngs_camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class ngs_raster_params(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("z_near", C.c_float), ("eps2d", C.c_float), ("cutoff_q", C.c_float),
+                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float)]
+
+
+class ngs_ig_params(C.Structure):
+    _fields_ = [("lambda_prior", C.c_float), ("alpha_obj", C.c_float), ("alpha_opa", C.c_float),
+                ("beta_d", C.c_float), ("beta_o", C.c_float), ("target_id", C.c_int32), ("outputs", C.c_uint32),
+                ("conf_on_train", C.c_int32), ("obj_eq2", C.c_int32), ("mode", C.c_int32)]
+
+
+class ngs_projected(C.Structure):
+    _fields_ = [("mean2d", P), ("conic", P), ("depth", P), ("zkey", P), ("rect", P), ("count", P)]
+
+
+class ngs_tile_lists(C.Structure):
+    _fields_ = [("keys", P), ("gids", P), ("capacity", C.c_int64), ("n_pairs", P), ("ranges", P)]
+
+
+class ngs_image(C.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("obj", P), ("t_final", P), ("mean_conf", P), ("argmax_id", P),
+                ("n_contrib", P)]
+
+
+class ngs_hessian(C.Structure):
+    _fields_ = [("k", C.c_int32), ("capacity", C.c_int32), ("slot_of", P), ("n_slots", P), ("gid_of", P),
+                ("h_rgb", P), ("h_d", P), ("h_o", P), ("logdet", P)]
+
+
+class ngs_dims(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("width", C.c_int64), ("height", C.c_int64),
+                ("max_pairs", C.c_int64), ("max_slots", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libngs.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        i32 = C.c_int32
+        L.ngs_create.argtypes = [C.c_int, C.POINTER(P)]
+        L.ngs_destroy.argtypes = [P]
+        L.ngs_status_string.argtypes = [i32]
+        L.ngs_status_string.restype = C.c_char_p
+        L.ngs_version.restype = i32
+        L.ngs_last_hip_error.argtypes = [P]
+        L.ngs_last_hip_error.restype = i32
+        L.ngs_workspace_size.argtypes = [i32, P, C.POINTER(C.c_size_t)]
+        L.ngs_prepare_scene.argtypes = [P, P, P, P]
+        L.ngs_project.argtypes = [P, P, P, P, P, P]
+        L.ngs_bin_sort.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_render.argtypes = [P, P, P, P, P, P, P, P]
+        L.ngs_info_gain.argtypes = [P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_hessian_reset.argtypes = [P, P, i32, P]
+        L.ngs_hessian_finalize.argtypes = [P, P, P]
+        L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_render_backward.argtypes = [P] * 10
+        L.ngs_profile_enable.argtypes = [P, i32]
+        L.ngs_profile_kernels.restype = i32
+        L.ngs_profile_kernel_name.argtypes = [i32]
+        L.ngs_profile_kernel_name.restype = C.c_char_p
+        L.ngs_profile_read.argtypes = [P, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for name in EXPORTS:
+            if name not in ("ngs_status_string", "ngs_version", "ngs_last_hip_error", "ngs_profile_kernels",
+                            "ngs_profile_kernel_name"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int, ctx=None):
+    if status != NGS_OK:
+        msg = lib().ngs_status_string(status).decode()
+        if ctx is not None and status == NGS_HIP_ERROR:
+            msg += f" (hipError {lib().ngs_last_hip_error(ctx.handle)})"
+        raise NgsError(fn, status, msg)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ref(x):
+    return C.byref(x)
+
+
+# ------------------------------------------------------------------------------------------
+# Parameter structs
+# ------------------------------------------------------------------------------------------
+
+def raster_params(tile=16, z_near=0.05, eps2d=0.3, cutoff_q=9.0, alpha_min=1.0 / 255.0, alpha_max=0.99,
+                  t_min=1e-4) -> ngs_raster_params:
+    return ngs_raster_params(tile, z_near, eps2d, cutoff_q, alpha_min, alpha_max, t_min)
+
+
+def ig_params(lambda_prior=0.1, alpha_obj=0.3, alpha_opa=0.3, beta_d=10.0, beta_o=1.0, target_id=-1,
+              outputs=7, conf_on_train=1, obj_eq2=1, mode=MODE_SCORE) -> ngs_ig_params:
+    return ngs_ig_params(lambda_prior, alpha_obj, alpha_opa, beta_d, beta_o, target_id, outputs, conf_on_train,
+                         obj_eq2, mode)
+
+
+def camera(cam) -> ngs_camera:
+    """ngs_camera from an object with R (3x3), t (3), fx, fy, cx, cy, width, height."""
+    import numpy as np
+    R = np.asarray(cam.R, dtype=np.float32).reshape(-1)
+    t = np.asarray(cam.t, dtype=np.float32).reshape(-1)
+    return ngs_camera((C.c_float * 9)(*R.tolist()), (C.c_float * 3)(*t.tolist()), cam.fx, cam.fy, cam.cx, cam.cy,
+                      int(cam.width), int(cam.height))
+
+
+# ------------------------------------------------------------------------------------------
+# Context and device-resident objects
+# ------------------------------------------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check("ngs_create", lib().ngs_create(device, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().ngs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceScene:
+    """Scene arrays resident on the GPU (float32 SoA) plus the derived arrays."""
+
+    def __init__(self, scene, device: str = "cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        self.n, self.k = int(scene.n), int(scene.k)
+        self.mean, self.log_scale, self.rot = f(scene.mean), f(scene.log_scale), f(scene.rot)
+        self.opacity_logit, self.rgb, self.obj_logit = f(scene.opacity_logit), f(scene.rgb), f(scene.obj_logit)
+        n, k = self.n, self.k
+        self.prob = torch.empty((max(n, 1), k), dtype=torch.float32, device=device)
+        self.opacity = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+        self.kappa = torch.empty_like(self.opacity)
+        self.conf = torch.empty_like(self.opacity)
+        self.label = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.device = device
+
+    def c(self) -> ngs_scene:
+        return ngs_scene(self.n, self.k, _p(self.mean), _p(self.log_scale), _p(self.rot), _p(self.opacity_logit),
+                         _p(self.rgb), _p(self.obj_logit), _p(self.prob), _p(self.opacity), _p(self.kappa),
+                         _p(self.conf), _p(self.label))
+
+
+@dataclass
+class Projected:
+    mean2d: torch.Tensor
+    conic: torch.Tensor
+    depth: torch.Tensor
+    zkey: torch.Tensor
+    rect: torch.Tensor
+    count: torch.Tensor
+
+    def c(self) -> ngs_projected:
+        return ngs_projected(_p(self.mean2d), _p(self.conic), _p(self.depth), _p(self.zkey), _p(self.rect),
+                             _p(self.count))
+
+
+@dataclass
+class TileLists:
+    keys: Optional[torch.Tensor]
+    gids: torch.Tensor
+    n_pairs: torch.Tensor
+    ranges: torch.Tensor
+    capacity: int
+
+    def c(self) -> ngs_tile_lists:
+        return ngs_tile_lists(_p(self.keys), _p(self.gids), self.capacity, _p(self.n_pairs), _p(self.ranges))
+
+
+class Hessian:
+    """Training information store H_T (packed FP64 blocks of the touched Gaussians)."""
+
+    def __init__(self, n: int, k: int, capacity: int, device: str = "cuda"):
+        lo = 11 + k
+        cap = max(int(capacity), 1)
+        self.k, self.capacity = k, int(capacity)
+        self.slot_of = torch.full((max(n, 1),), -1, dtype=torch.int32, device=device)
+        self.n_slots = torch.zeros(1, dtype=torch.int32, device=device)
+        self.gid_of = torch.full((cap,), -1, dtype=torch.int32, device=device)
+        self.h_rgb = torch.zeros((105, cap), dtype=torch.float64, device=device)
+        self.h_d = torch.zeros((66, cap), dtype=torch.float64, device=device)
+        self.h_o = torch.zeros((lo * (lo + 1) // 2, cap), dtype=torch.float64, device=device)
+        self.logdet = torch.zeros((3, cap), dtype=torch.float64, device=device)
+
+    def c(self) -> ngs_hessian:
+        return ngs_hessian(self.k, self.capacity, _p(self.slot_of), _p(self.n_slots), _p(self.gid_of),
+                           _p(self.h_rgb), _p(self.h_d), _p(self.h_o), _p(self.logdet))
+
+
+def workspace_size(op: int, n: int, k: int, width: int = 0, height: int = 0, max_pairs: int = 0,
+                   max_slots: int = 0) -> int:
+    d = ngs_dims(n, k, width, height, max_pairs, max_slots)
+    b = C.c_size_t()
+    _check("ngs_workspace_size", lib().ngs_workspace_size(op, _ref(d), C.byref(b)))
+    return int(b.value)
+
+
+def _bytes(nbytes: int, device: str = "cuda") -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ------------------------------------------------------------------------------------------
+
+def ngs_prepare_scene(ctx: Context, scene: DeviceScene, ig: ngs_ig_params):
+    sc = scene.c()
+    _check("ngs_prepare_scene", lib().ngs_prepare_scene(ctx.handle, _ref(sc), _ref(ig), _stream()), ctx)
+
+
+def ngs_project(ctx: Context, scene: DeviceScene, cam: ngs_camera, rp: ngs_raster_params) -> Projected:
+    n, dev = max(scene.n, 1), scene.device
+    out = Projected(torch.empty((2, n), dtype=torch.float32, device=dev),
+                    torch.empty((3, n), dtype=torch.float32, device=dev),
+                    torch.empty(n, dtype=torch.float32, device=dev),
+                    torch.empty(n, dtype=torch.int32, device=dev),
+                    torch.empty((4, n), dtype=torch.int16, device=dev),
+                    torch.empty(n, dtype=torch.int32, device=dev))
+    sc, pc = scene.c(), out.c()
+    _check("ngs_project", lib().ngs_project(ctx.handle, _ref(sc), _ref(cam), _ref(rp), _ref(pc), _stream()), ctx)
+    return out
+
+
+def ngs_bin_sort(ctx: Context, scene: DeviceScene, proj: Projected, cam: ngs_camera, rp: ngs_raster_params,
+                 capacity: int = 1 << 20, want_keys: bool = False) -> TileLists:
+    """Sorted tile lists; grows the capacity and retries when the library reports CAPACITY."""
+    dev = scene.device
+    tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    while True:
+        cap = max(int(capacity), 1)
+        lists = TileLists(torch.empty(cap, dtype=torch.int64, device=dev) if want_keys else None,
+                          torch.empty(cap, dtype=torch.int32, device=dev),
+                          torch.zeros(1, dtype=torch.int64, device=dev),
+                          torch.empty((2, max(tiles, 1)), dtype=torch.int32, device=dev), cap)
+        ws = _bytes(workspace_size(0, scene.n, scene.k, max_pairs=cap), dev)
+        sc, pc, lc = scene.c(), proj.c(), lists.c()
+        st = lib().ngs_bin_sort(ctx.handle, _ref(sc), _ref(pc), _ref(cam), _ref(rp), _ref(lc), _p(ws),
+                                ws.numel(), _stream())
+        if st == NGS_CAPACITY:
+            capacity = int(lists.n_pairs.item())
+            continue
+        _check("ngs_bin_sort", st, ctx)
+        return lists
+
+
+def ngs_render(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLists, cam: ngs_camera,
+               rp: ngs_raster_params, want_obj: bool = True) -> Dict[str, torch.Tensor]:
+    H, W, dev = cam.height, cam.width, scene.device
+    f = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+    out = dict(rgb=f(3, H, W), depth=f(H, W), obj=f(scene.k, H, W) if want_obj else None, t_final=f(H, W),
+               mean_conf=f(H, W), argmax_id=torch.empty((H, W), dtype=torch.int32, device=dev),
+               n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev))
+    img = ngs_image(*[_p(out[x]) for x in ("rgb", "depth", "obj", "t_final", "mean_conf", "argmax_id",
+                                           "n_contrib")])
+    sc, pc, lc = scene.c(), proj.c(), lists.c()
+    _check("ngs_render", lib().ngs_render(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam), _ref(rp), _ref(img),
+                                          _stream()), ctx)
+    return out
+
+
+class IgWorkspace:
+    def __init__(self, scene: DeviceScene, max_slots: int = 1 << 16):
+        self.buf = _bytes(workspace_size(1, scene.n, scene.k, max_slots=max_slots), scene.device)
+
+
+def ngs_info_gain(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLists, cam: ngs_camera,
+                  rp: ngs_raster_params, ig: ngs_ig_params, h: Optional[Hessian], ws: IgWorkspace,
+                  stats: Optional[torch.Tensor] = None) -> torch.Tensor:
+    out = torch.zeros(3, dtype=torch.float64, device=scene.device)
+    sc, pc, lc = scene.c(), proj.c(), lists.c()
+    hc = h.c() if h is not None else None
+    _check("ngs_info_gain", lib().ngs_info_gain(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam), _ref(rp),
+                                                _ref(ig), _ref(hc) if hc is not None else None, _p(out),
+                                                _p(stats), _p(ws.buf), ws.buf.numel(), _stream()), ctx)
+    return out
+
+
+def ngs_hessian_reset(ctx: Context, h: Hessian, n: int):
+    hc = h.c()
+    _check("ngs_hessian_reset", lib().ngs_hessian_reset(ctx.handle, _ref(hc), n, _stream()), ctx)
+
+
+def ngs_hessian_finalize(ctx: Context, h: Hessian):
+    hc = h.c()
+    _check("ngs_hessian_finalize", lib().ngs_hessian_finalize(ctx.handle, _ref(hc), _stream()), ctx)
+
+
+def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], normalisers: Sequence[float],
+                    cams: Sequence[ngs_camera], rp: ngs_raster_params, ig: ngs_ig_params, ws: torch.Tensor,
+                    stats: Optional[torch.Tensor] = None):
+    nv = len(cams)
+    dev = scene.device
+    scores = torch.empty((max(nv, 1), 4), dtype=torch.float32, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    ig_raw = torch.empty((max(nv, 1), 3), dtype=torch.float64, device=dev)
+    arr = (ngs_camera * max(nv, 1))(*cams)
+    norm = (C.c_double * 3)(*[float(x) for x in normalisers])
+    sc = scene.c()
+    hc = h.c() if h is not None else None
+    _check("ngs_score_batch", lib().ngs_score_batch(ctx.handle, _ref(sc), _ref(hc) if hc is not None else None,
+                                                    norm, arr, nv, _ref(rp), _ref(ig), _p(scores), _p(best),
+                                                    _p(ig_raw), _p(stats), _p(ws), ws.numel(), _stream()), ctx)
+    return scores[:nv], best, ig_raw[:nv]
+
+
+def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16) -> torch.Tensor:
+    return _bytes(workspace_size(2, scene.n, scene.k, max_pairs=max_pairs, max_slots=max_slots), scene.device)
+
+
+def ngs_profile_enable(ctx: Context, on: bool):
+    _check("ngs_profile_enable", lib().ngs_profile_enable(ctx.handle, 1 if on else 0), ctx)
+
+
+def ngs_profile_read(ctx: Context) -> Dict[str, tuple]:
+    """{kernel class: (total ms, launches)} of the event profile."""
+    L = lib()
+    out = {}
+    for i in range(L.ngs_profile_kernels()):
+        ms, cnt = C.c_double(), C.c_int64()
+        _check("ngs_profile_read", L.ngs_profile_read(ctx.handle, i, C.byref(ms), C.byref(cnt)), ctx)
+        out[L.ngs_profile_kernel_name(i).decode()] = (ms.value, cnt.value)
+    return out
+
+
+# ------------------------------------------------------------------------------------------
+# The next-best-view scoring pipeline
+# ------------------------------------------------------------------------------------------
+
+class NbvScorer:
+    """Training setup (H_T and Eq. 10 normalisers) and candidate scoring on one GPU."""
+
+    def __init__(self, ctx: Context, scene: DeviceScene, rp: ngs_raster_params, ig: ngs_ig_params,
+                 max_pairs: int = 1 << 24, max_slots: int = 1 << 16, store_capacity: int = 1 << 17):
+        self.ctx, self.scene, self.rp, self.ig = ctx, scene, rp, ig
+        self.max_pairs, self.max_slots = max_pairs, max_slots
+        ngs_prepare_scene(ctx, scene, ig)
+        self.h = Hessian(scene.n, scene.k, store_capacity, scene.device)
+        self.igws = IgWorkspace(scene, max_slots)
+        self.norm = None
+        self.ig_train = None
+        self.ws = None
+
+    def _view(self, cam: ngs_camera):
+        proj = ngs_project(self.ctx, self.scene, cam, self.rp)
+        lists = ngs_bin_sort(self.ctx, self.scene, proj, cam, self.rp, capacity=self.max_pairs)
+        return proj, lists
+
+    def setup(self, train_cams: Sequence[ngs_camera]):
+        ngs_hessian_reset(self.ctx, self.h, self.scene.n)
+        acc = ngs_ig_params(*[getattr(self.ig, f[0]) for f in ngs_ig_params._fields_])
+        acc.mode = MODE_ACCUMULATE
+        for cam in train_cams:
+            proj, lists = self._view(cam)
+            ngs_info_gain(self.ctx, self.scene, proj, lists, cam, self.rp, acc, self.h, self.igws)
+        ngs_hessian_finalize(self.ctx, self.h)
+        sc = ngs_ig_params(*[getattr(self.ig, f[0]) for f in ngs_ig_params._fields_])
+        sc.mode = MODE_SCORE
+        gains = []
+        for cam in train_cams:
+            proj, lists = self._view(cam)
+            gains.append(ngs_info_gain(self.ctx, self.scene, proj, lists, cam, self.rp, sc, self.h, self.igws))
+        self.ig_train = torch.stack(gains).cpu().numpy()
+        self.norm = self.ig_train.mean(axis=0)
+        return self.norm
+
+    def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None):
+        if self.ws is None:
+            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots)
+        return ngs_score_batch(self.ctx, self.scene, self.h, self.norm, cams, self.rp, self.ig, self.ws, stats)

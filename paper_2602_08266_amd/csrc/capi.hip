@@ -1,0 +1,431 @@
+// capi.hip -- the extern "C" boundary of libngs (declared in include/ngs.h): argument
+// validation, workspace carving, stream ordering and status codes. No C++ exception and
+// no HIP error code crosses the boundary; every failure maps to an ngs_status.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+struct ngs_ctx {
+  int device = 0;
+  int32_t last_hip = 0;
+  // IG workspace known to be in its resting state (accumulators zero, no slot assigned)
+  const void* ig_ready_ptr = nullptr;
+  size_t ig_ready_bytes = 0;
+  int64_t ig_ready_n = -1, ig_ready_k = -1;
+  int64_t* pinned = nullptr;  // host-pinned scratch for reading device counters
+};
+
+namespace {
+
+using namespace ngs;
+
+constexpr size_t kAlign = 256;
+inline size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+#define NGS_TRY_HIP(ctx, expr)                         \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) {                            \
+      if (ctx) (ctx)->last_hip = (int32_t)e_;          \
+      return NGS_HIP_ERROR;                            \
+    }                                                  \
+  } while (0)
+
+ngs_status check_scene(const ngs_scene* s, bool need_derived) {
+  if (!s || s->n < 0 || s->k <= 0) return NGS_INVALID_ARG;
+  if (s->k > NGS_MAX_K) return NGS_UNSUPPORTED;
+  if (s->n == 0) return NGS_OK;
+  if (!s->mean || !s->log_scale || !s->rot || !s->opacity_logit || !s->rgb || !s->obj_logit) return NGS_INVALID_ARG;
+  if (need_derived && (!s->prob || !s->opacity || !s->kappa || !s->conf || !s->label)) return NGS_INVALID_ARG;
+  return NGS_OK;
+}
+
+ngs_status check_cam(const ngs_camera* c, const ngs_raster_params* rp) {
+  if (!c || !rp) return NGS_INVALID_ARG;
+  if (rp->tile != kTile) return NGS_UNSUPPORTED;
+  if (c->width <= 0 || c->height <= 0) return NGS_INVALID_ARG;
+  if (!(c->fx > 0.f) || !(c->fy > 0.f) || !std::isfinite(c->cx) || !std::isfinite(c->cy)) return NGS_INVALID_ARG;
+  for (int i = 0; i < 9; ++i) if (!std::isfinite(c->R[i])) return NGS_INVALID_ARG;
+  for (int i = 0; i < 3; ++i) if (!std::isfinite(c->t[i])) return NGS_INVALID_ARG;
+  const int64_t tiles = (int64_t)((c->width + kTile - 1) / kTile) * ((c->height + kTile - 1) / kTile);
+  if (tiles > NGS_MAX_TILES) return NGS_UNSUPPORTED;
+  if (!(rp->alpha_max > 0.f && rp->alpha_max < 1.f) || !(rp->t_min > 0.f) || !(rp->eps2d >= 0.f)) return NGS_INVALID_ARG;
+  return NGS_OK;
+}
+
+ngs_status check_proj(const ngs_projected* p) {
+  if (!p || !p->mean2d || !p->conic || !p->depth || !p->zkey || !p->rect || !p->count) return NGS_INVALID_ARG;
+  return NGS_OK;
+}
+
+ngs_status check_lists(const ngs_tile_lists* l) {
+  if (!l || !l->gids || !l->ranges || !l->n_pairs || l->capacity < 0) return NGS_INVALID_ARG;
+  return NGS_OK;
+}
+
+ngs_status check_ig(const ngs_ig_params* ig) {
+  if (!ig) return NGS_INVALID_ARG;
+  if (!(ig->lambda_prior > 0.f) || ig->outputs == 0u || (ig->outputs & ~7u)) return NGS_INVALID_ARG;
+  if (ig->mode != NGS_MODE_SCORE && ig->mode != NGS_MODE_ACCUMULATE) return NGS_INVALID_ARG;
+  return NGS_OK;
+}
+
+// IG workspace: [256 B header: sticky overflow flag][IgWs regions]
+constexpr size_t kIgHeader = 256;
+
+int64_t ig_slots_for(size_t ws_bytes, int64_t n, int64_t k) {
+  if (ws_bytes < kIgHeader) return 0;
+  const size_t per = (size_t)stat_len((int)k) * 4 + 4;
+  const size_t fixed = al((size_t)std::max<int64_t>(n, 1) * 4) + 4 * kAlign;
+  if (ws_bytes < kIgHeader + fixed) return 0;
+  int64_t s = (int64_t)((ws_bytes - kIgHeader - fixed) / per);
+  while (s > 0 && kIgHeader + ig_ws_bytes(n, k, s) > ws_bytes) --s;
+  return s;
+}
+
+ngs_status ig_prepare(ngs_ctx* ctx, void* ws, size_t ws_bytes, int64_t n, int64_t k, hipStream_t st, IgWs* w,
+                      int32_t** sticky) {
+  const int64_t slots = ig_slots_for(ws_bytes, n, k);
+  if (slots < 1) return NGS_WORKSPACE_TOO_SMALL;
+  *sticky = static_cast<int32_t*>(ws);
+  *w = ig_ws_carve(static_cast<char*>(ws) + kIgHeader, n, k, slots);
+  if (ctx->ig_ready_ptr != ws || ctx->ig_ready_bytes != ws_bytes || ctx->ig_ready_n != n || ctx->ig_ready_k != k) {
+    NGS_TRY_HIP(ctx, ig_reset(*w, (int)n, (int)k, st));
+    NGS_TRY_HIP(ctx, hipMemsetAsync(*sticky, 0, kIgHeader, st));
+    ctx->ig_ready_ptr = ws;
+    ctx->ig_ready_bytes = ws_bytes;
+    ctx->ig_ready_n = n;
+    ctx->ig_ready_k = k;
+  }
+  return NGS_OK;
+}
+
+ngs_status read_i64(ngs_ctx* ctx, const void* dev, size_t bytes, hipStream_t st, int64_t* out) {
+  *ctx->pinned = 0;
+  NGS_TRY_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, st));
+  NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
+  if (bytes == 4) {
+    int32_t v;
+    std::memcpy(&v, ctx->pinned, 4);
+    *out = v;
+  } else {
+    *out = *ctx->pinned;
+  }
+  return NGS_OK;
+}
+
+// Score-batch workspace: projected arrays, lists, binning workspace, IG workspace.
+struct BatchWs {
+  ngs_projected proj;
+  ngs_tile_lists lists;
+  void* bin;
+  size_t bin_bytes;
+  void* ig;
+  size_t ig_bytes;
+};
+
+size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
+  const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
+  return al(nn * 8) + al(nn * 12) + al(nn * 4) + al(nn * 4) + al(nn * 8) + al(nn * 4) + al(mp * 4) +
+         al(2 * NGS_MAX_TILES * 4) + al(8) + al(bin_ws_bytes(n, max_pairs));
+}
+
+BatchWs batch_carve(void* ws, size_t ws_bytes, int64_t n, int64_t max_pairs) {
+  const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t b) { char* r = p; p += al(b); return r; };
+  BatchWs b;
+  b.proj.mean2d = (float*)take(nn * 8);
+  b.proj.conic = (float*)take(nn * 12);
+  b.proj.depth = (float*)take(nn * 4);
+  b.proj.zkey = (uint32_t*)take(nn * 4);
+  b.proj.rect = (int16_t*)take(nn * 8);
+  b.proj.count = (uint32_t*)take(nn * 4);
+  b.lists.gids = (uint32_t*)take(mp * 4);
+  b.lists.ranges = (uint32_t*)take(2 * NGS_MAX_TILES * 4);
+  b.lists.n_pairs = (int64_t*)take(8);
+  b.lists.keys = nullptr;
+  b.lists.capacity = max_pairs;
+  b.bin_bytes = al(bin_ws_bytes(n, max_pairs));
+  b.bin = take(b.bin_bytes);
+  b.ig = p;
+  const size_t used = (size_t)(p - static_cast<char*>(ws));
+  b.ig_bytes = ws_bytes > used ? ws_bytes - used : 0;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+ngs_status ngs_create(int device, ngs_ctx** out) {
+  if (!out) return NGS_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return NGS_INVALID_ARG;
+  ngs_ctx* c = new (std::nothrow) ngs_ctx();
+  if (!c) return NGS_HIP_ERROR;
+  c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return NGS_HIP_ERROR;
+  }
+  *out = c;
+  return NGS_OK;
+}
+
+ngs_status ngs_destroy(ngs_ctx* ctx) {
+  if (!ctx) return NGS_INVALID_ARG;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return NGS_OK;
+}
+
+const char* ngs_status_string(ngs_status s) {
+  switch (s) {
+    case NGS_OK: return "ok";
+    case NGS_INVALID_ARG: return "invalid argument";
+    case NGS_CAPACITY: return "output capacity too small";
+    case NGS_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case NGS_HIP_ERROR: return "HIP runtime error";
+    case NGS_DEGENERATE: return "degenerate normaliser";
+    case NGS_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int32_t ngs_version(void) { return 1; }
+
+int32_t ngs_last_hip_error(const ngs_ctx* ctx) { return ctx ? ctx->last_hip : 0; }
+
+ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
+  if (!d || !bytes || d->n < 0 || d->k <= 0 || d->max_pairs < 0 || d->max_slots < 0) return NGS_INVALID_ARG;
+  if (d->k > NGS_MAX_K) return NGS_UNSUPPORTED;
+  const size_t igb = kIgHeader + ig_ws_bytes(d->n, d->k, std::max<int64_t>(d->max_slots, 1));
+  switch (op) {
+    case 0: *bytes = bin_ws_bytes(d->n, d->max_pairs); return NGS_OK;
+    case 1: *bytes = igb; return NGS_OK;
+    case 2: *bytes = batch_fixed_bytes(d->n, d->max_pairs) + igb; return NGS_OK;
+    default: return NGS_INVALID_ARG;
+  }
+}
+
+ngs_status ngs_prepare_scene(ngs_ctx* ctx, ngs_scene* scene, const ngs_ig_params* ig, void* stream) {
+  if (!ctx) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s != NGS_OK) return s;
+  if (!ig) return NGS_INVALID_ARG;
+  if (ig->target_id >= scene->k) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, launch_prepare_scene(*scene, *ig, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_project(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cam, const ngs_raster_params* rp,
+                       ngs_projected* out, void* stream) {
+  if (!ctx) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, false);
+  if (s == NGS_OK) s = check_cam(cam, rp);
+  if (s == NGS_OK) s = check_proj(out);
+  if (s != NGS_OK) return s;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, launch_project(*scene, make_devcam(*cam, kTile), *rp, *out, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj, const ngs_camera* cam,
+                        const ngs_raster_params* rp, ngs_tile_lists* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, false);
+  if (s == NGS_OK) s = check_cam(cam, rp);
+  if (s == NGS_OK) s = check_proj(proj);
+  if (s == NGS_OK) s = check_lists(out);
+  if (s != NGS_OK) return s;
+  if (!ws || ws_bytes < bin_ws_bytes(scene->n, out->capacity)) return NGS_WORKSPACE_TOO_SMALL;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const DevCam dc = make_devcam(*cam, kTile);
+  const BinWs w = bin_ws_carve(ws, scene->n, out->capacity);
+  NGS_TRY_HIP(ctx, bin_count_pairs(*proj, scene->n, w, st));
+  int64_t m = 0;
+  s = read_i64(ctx, w.offsets + scene->n, 8, st, &m);
+  if (s != NGS_OK) return s;
+  if (m > out->capacity || m >= (int64_t)UINT32_MAX) {
+    NGS_TRY_HIP(ctx, hipMemcpyAsync(out->n_pairs, w.offsets + scene->n, 8, hipMemcpyDeviceToDevice, st));
+    NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
+    return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
+  }
+  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, m, w, *out, st));
+  return NGS_OK;
+}
+
+ngs_status ngs_render(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj, const ngs_tile_lists* lists,
+                      const ngs_camera* cam, const ngs_raster_params* rp, ngs_image* out, void* stream) {
+  if (!ctx) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s == NGS_OK) s = check_cam(cam, rp);
+  if (s == NGS_OK) s = check_proj(proj);
+  if (s == NGS_OK) s = check_lists(lists);
+  if (s != NGS_OK) return s;
+  if (!out || !out->rgb || !out->depth || !out->t_final || !out->argmax_id) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, launch_render(*scene, *proj, *lists, make_devcam(*cam, kTile), make_raster(*rp), *out,
+                                 (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_hessian_reset(ngs_ctx* ctx, ngs_hessian* h, int32_t n, void* stream) {
+  if (!ctx || !h || n < 0 || !h->slot_of || !h->n_slots) return NGS_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, launch_fill_i32(h->slot_of, -1, (size_t)n, st));
+  NGS_TRY_HIP(ctx, hipMemsetAsync(h->n_slots, 0, 4, st));
+  return NGS_OK;
+}
+
+ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream) {
+  if (!ctx || !h || !h->n_slots || !h->logdet || !h->h_rgb || !h->h_d || !h->h_o || h->capacity < 0) return NGS_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  int64_t used = 0;
+  ngs_status s = read_i64(ctx, h->n_slots, 4, st, &used);
+  if (s != NGS_OK) return s;
+  if (used > h->capacity) return NGS_CAPACITY;
+  NGS_TRY_HIP(ctx, launch_hessian_logdet(h, (int32_t)used, 0.f, st));
+  return NGS_OK;
+}
+
+ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj, const ngs_tile_lists* lists,
+                         const ngs_camera* cam, const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,
+                         double* ig_out, int64_t* stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s == NGS_OK) s = check_cam(cam, rp);
+  if (s == NGS_OK) s = check_proj(proj);
+  if (s == NGS_OK) s = check_lists(lists);
+  if (s == NGS_OK) s = check_ig(ig);
+  if (s != NGS_OK) return s;
+  if (ig->mode == NGS_MODE_ACCUMULATE && (!h || !h->slot_of || !h->n_slots || !h->gid_of || !h->h_rgb || !h->h_d || !h->h_o))
+    return NGS_INVALID_ARG;
+  if (ig->mode == NGS_MODE_SCORE && !ig_out) return NGS_INVALID_ARG;
+  if (h && (h->k != scene->k || (h->capacity > 0 && !h->logdet))) return NGS_INVALID_ARG;
+  if (!ws) return NGS_WORKSPACE_TOO_SMALL;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  IgWs w;
+  int32_t* sticky = nullptr;
+  s = ig_prepare(ctx, ws, ws_bytes, scene->n, scene->k, st, &w, &sticky);
+  if (s != NGS_OK) return s;
+  if (ig_out) NGS_TRY_HIP(ctx, hipMemsetAsync(ig_out, 0, 3 * sizeof(double), st));
+  const DevCam dc = make_devcam(*cam, kTile);
+  NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, dc, make_raster(*rp), *ig, w, stats, st));
+  NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_out ? ig_out : nullptr, stats, sticky, st));
+  int64_t of = 0;
+  s = read_i64(ctx, sticky, 4, st, &of);
+  if (s != NGS_OK) return s;
+  if (of) {
+    NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, 4, st));
+    return NGS_CAPACITY;
+  }
+  return NGS_OK;
+}
+
+ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                           const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
+                           const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw, int64_t* stats,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !normalisers || !cams || n_views < 0 || !scores || !best || !ig_raw) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s == NGS_OK) s = check_ig(ig);
+  if (s != NGS_OK) return s;
+  if (ig->mode != NGS_MODE_SCORE) return NGS_INVALID_ARG;
+  if (h && h->k != scene->k) return NGS_INVALID_ARG;
+  for (int v = 0; v < n_views; ++v) {
+    s = check_cam(&cams[v], rp);
+    if (s != NGS_OK) return s;
+  }
+  for (int f = 0; f < 3; ++f)
+    if (((ig->outputs >> f) & 1u) && !(normalisers[f] > 0.0)) return NGS_DEGENERATE;
+  if (!ws) return NGS_WORKSPACE_TOO_SMALL;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  // the largest pair capacity that leaves room for at least one IG slot
+  int64_t max_pairs = 0;
+  {
+    int64_t lo = 0, hi = (int64_t)(ws_bytes / 20) + 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      const size_t fixed = batch_fixed_bytes(scene->n, mid);
+      if (fixed < ws_bytes && ig_slots_for(ws_bytes - fixed, scene->n, scene->k) >= 1024) lo = mid; else hi = mid - 1;
+    }
+    max_pairs = lo;
+  }
+  if (max_pairs < 1) return NGS_WORKSPACE_TOO_SMALL;
+  BatchWs b = batch_carve(ws, ws_bytes, scene->n, max_pairs);
+  IgWs w;
+  int32_t* sticky = nullptr;
+  s = ig_prepare(ctx, b.ig, b.ig_bytes, scene->n, scene->k, st, &w, &sticky);
+  if (s != NGS_OK) return s;
+  NGS_TRY_HIP(ctx, hipMemsetAsync(ig_raw, 0, (size_t)3 * sizeof(double) * std::max(n_views, 1), st));
+  const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
+  int64_t total_pairs = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const DevCam dc = make_devcam(cams[v], kTile);
+    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
+    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
+    int64_t m = 0;
+    s = read_i64(ctx, bw.offsets + scene->n, 8, st, &m);
+    if (s != NGS_OK) return s;
+    if (m > max_pairs) return NGS_CAPACITY;
+    total_pairs += m;
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, m, bw, b.lists, st));
+    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, w, stats, st));
+    NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_raw + 3 * (size_t)v, stats, sticky, st));
+  }
+  NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, normalisers[0], normalisers[1], normalisers[2], ig->beta_d,
+                                        ig->beta_o, ig->outputs, scores, best, st));
+  int64_t of = 0;
+  s = read_i64(ctx, sticky, 4, st, &of);
+  if (s != NGS_OK) return s;
+  if (stats) {
+    ctx->pinned[0] = n_views;
+    ctx->pinned[1] = total_pairs;
+    NGS_TRY_HIP(ctx, hipMemcpyAsync(stats, ctx->pinned, 16, hipMemcpyHostToDevice, st));
+    NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
+  }
+  if (of) {
+    NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, 4, st));
+    return NGS_CAPACITY;
+  }
+  return NGS_OK;
+}
+
+ngs_status ngs_profile_enable(ngs_ctx* ctx, int32_t on) {
+  if (!ctx) return NGS_INVALID_ARG;
+  prof_enable(on != 0);
+  return NGS_OK;
+}
+
+int32_t ngs_profile_kernels(void) { return kProfKernels; }
+
+const char* ngs_profile_kernel_name(int32_t id) { return prof_name(id); }
+
+ngs_status ngs_profile_read(ngs_ctx* ctx, int32_t id, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches || id < 0 || id >= kProfKernels) return NGS_INVALID_ARG;
+  prof_read(id, total_ms, launches);
+  return NGS_OK;
+}
+
+ngs_status ngs_render_backward(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                               const ngs_tile_lists* lists, const ngs_camera* cam, const ngs_raster_params* rp,
+                               const ngs_image* fwd, const void* grad_image, void* grad_scene, void* stream) {
+  (void)ctx; (void)scene; (void)proj; (void)lists; (void)cam; (void)rp; (void)fwd; (void)grad_image;
+  (void)grad_scene; (void)stream;
+  return NGS_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// common.hpp -- internal declarations shared by the HIP translation units of libngs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ngs.h"
+
+namespace ngs {
+
+constexpr int kTile = 16;
+constexpr int kTilePix = kTile * kTile;  // one workgroup of 256 lanes per tile
+constexpr int kWave = 64;
+constexpr int kNGeo = 11;                // mu 3, log-scale 3, quaternion 4, opacity logit 1
+constexpr int kNScreen = 6;              // m_x, m_y, Q_xx, Q_xy, Q_yy, opacity logit
+
+// Screen-space statistics of one touched Gaussian (per view), FP32, accumulated over its
+// contributing pixels:
+//   Y_rgb  sym 6x6  sum |w_rgb|^2 y y^T
+//   X_rgb  6x3      sum a y w_rgb^T
+//   Y_d    sym 7x7  sum e e^T, e = (w_d y, a)         (e_6 e_6 = sum a^2)
+//   Y_o    sym 6x6  sum |w_o|^2 y y^T
+//   m1     6        sum a T y
+//   Z_o    6 x k    sum (a / (1 - alpha)) y S~^T      (S~: object suffix incl. Eq. 2 residual)
+// y = d alpha / d(m_x, m_y, Q_xx, Q_xy, Q_yy, l), a = alpha T, w = d out / d alpha.
+constexpr int kStatYrgb = 0;
+constexpr int kStatXrgb = 21;
+constexpr int kStatYd = 39;
+constexpr int kStatYo = 67;
+constexpr int kStatM1 = 88;
+constexpr int kStatScalar = 94;          // first index of Z_o
+inline __host__ __device__ int stat_len(int k) { return kStatScalar + 6 * k; }
+
+inline __host__ __device__ int tri_len(int l) { return l * (l + 1) / 2; }
+// packed upper triangle, row-major: (i, j) with i <= j
+inline __host__ __device__ int tri_idx(int i, int j, int l) { return i * l - (i * (i - 1)) / 2 + (j - i); }
+
+// Quadratic form q = d^T Q d of the conic and the unclamped opacity sigma exp(-q / 2),
+// evaluated without FMA contraction so that every kernel that re-walks a tile takes the
+// same cut-off and alpha decisions bit for bit.
+__device__ __forceinline__ float conic_q(float qa, float qb, float qc, float dx, float dy) {
+#pragma clang fp contract(off)
+  return qa * dx * dx + 2.f * qb * dx * dy + qc * dy * dy;
+}
+__device__ __forceinline__ float gauss_alpha(float op, float q) {
+#pragma clang fp contract(off)
+  return op * __expf(-0.5f * q);
+}
+__device__ __forceinline__ float transmit(float T, float alpha) {
+#pragma clang fp contract(off)
+  return T * (1.f - alpha);
+}
+
+struct DevCam {
+  float R[9], t[3], fx, fy, cx, cy;
+  int width, height, tiles_x, tiles_y;
+};
+
+inline DevCam make_devcam(const ngs_camera& c, int tile) {
+  DevCam d;
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  d.width = c.width; d.height = c.height;
+  d.tiles_x = (c.width + tile - 1) / tile;
+  d.tiles_y = (c.height + tile - 1) / tile;
+  return d;
+}
+
+struct RasterConst {
+  float z_near, eps2d, cutoff_q, alpha_min, alpha_max, t_min;
+};
+
+inline RasterConst make_raster(const ngs_raster_params& r) {
+  return RasterConst{r.z_near, r.eps2d, r.cutoff_q, r.alpha_min, r.alpha_max, r.t_min};
+}
+
+// Kernel classes of the optional event profiler (prof.hip). ProfScope brackets one launch.
+enum ProfId {
+  kProfPrepare = 0, kProfProject, kProfDepthHist, kProfDepthScan, kProfDepthScatter, kProfCountScan,
+  kProfEmit, kProfRanges, kProfKeys64, kProfRender, kProfIgTiles, kProfIgFinalize, kProfHessianLogdet,
+  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfKernels
+};
+class ProfScope {
+ public:
+  ProfScope(int id, hipStream_t st);
+  ~ProfScope();
+ private:
+  int id_;
+  hipStream_t st_;
+  void* a_;
+};
+void prof_enable(bool on);
+void prof_read(int id, double* ms, int64_t* count);
+const char* prof_name(int id);
+
+// Launchers implemented in the .hip files (stream-ordered, no synchronisation).
+hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st);
+hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+                          const ngs_projected& out, hipStream_t st);
+
+// Radix-sort building blocks (sort.hip).
+struct SortWs {
+  uint32_t* hist;       // [256][max blocks]
+  uint32_t* rowtot;     // [256]
+  size_t max_blocks;
+};
+size_t sort_blocks_for(size_t n);
+hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_a,
+                            uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
+                            int begin_bit, int end_bit, const SortWs& ws, hipStream_t st,
+                            uint32_t** keys_out, uint32_t** vals_out, int prof_base);
+hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st);
+
+// Binning (bin.hip).
+struct BinWs {
+  uint32_t* dkeys[2];   // depth keys ping-pong [n]
+  uint32_t* dvals[2];   // gids ping-pong [n]
+  uint64_t* offsets;    // [n + 1] exclusive scan of tile counts in depth order
+  uint64_t* blocksum;   // scan partials
+  uint32_t* tkeys[2];   // tile ids ping-pong [max_pairs]
+  uint32_t* tvals;      // gid ping-pong partner [max_pairs]
+  SortWs sort;
+};
+size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
+BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);
+hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st);
+hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, int64_t m,
+                             const BinWs& w, const ngs_tile_lists& out, hipStream_t st);
+
+// Rendering (render.hip).
+hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
+                         const DevCam& cam, const RasterConst& rc, const ngs_image& img,
+                         hipStream_t st);
+
+// Information gain (info_gain.hip, finalize.hip).
+struct IgWs {
+  float* acc;           // [stat_len(k)][max_slots] per-view screen statistics
+  int32_t* slot_of;     // [n] per-view slot, -1 when untouched
+  int32_t* gid_of;      // [max_slots]
+  int32_t* n_slots;     // [1]
+  int32_t* overflow;    // [1]
+  int64_t max_slots;
+};
+size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
+IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
+hipError_t ig_reset(const IgWs& w, int n, int k, hipStream_t st);
+hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
+                           const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
+                           const IgWs& w, int64_t* stats, hipStream_t st);
+hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+                              const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
+                              double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);
+hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st);
+hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
+                                float beta_d, float beta_o, uint32_t outputs, float* scores,
+                                int32_t* best, hipStream_t st);
+
+}  // namespace ngs

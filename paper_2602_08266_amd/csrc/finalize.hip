@@ -1,0 +1,431 @@
+// finalize.hip -- per touched Gaussian: screen-space statistics -> parameter-space blocks
+// (FP64 chain rule), confidence weighting, log-det information gain; training-store updates
+// and log-dets; Eq. 10-11 combination and argmax.
+//
+// Parameter order within a block (Sec. III-B.3 subsets): geometry (mean 3, log-scale 3,
+// raw quaternion 4, opacity logit 1), then colour (3) for RGB or object logits (k) for the
+// object vector; depth uses geometry only. With u = (m_x, m_y, Q_xx, Q_xy, Q_yy, l) and
+// P = du / d theta (6 x 11), the blocks are
+//   A_rgb = [[P^T Y_rgb P, P^T X_rgb], [X_rgb^T P, (sum a^2) I_3]]
+//   A_d   = P7^T Y_d P7,  P7 = [P; dZ/d theta]
+//   A_o   = [[P^T Y_o P, P^T X_o S], [S X_o^T P, (sum a^2) S S]],
+//   X_o = m1 p^T - Z_o,  S = diag(p) - p p^T (softmax Jacobian).
+// Information gain of the view (Eq. 5, 6, 9): sum_g logdet(H_T,g + c_g A_g) - logdet(H_T,g).
+#include "common.hpp"
+
+namespace ngs {
+namespace {
+
+constexpr int kFinThreads = 64;
+constexpr int kMaxL = kNGeo + NGS_MAX_K;  // 75
+
+struct FinShared {
+  double A[kMaxL * kMaxL];
+  double st[kStatScalar + 6 * NGS_MAX_K];
+  double P[7][kNGeo];      // rows 0..5: du/dtheta, row 6: dZ/dtheta
+  double Y[7][7];          // current symmetric screen matrix
+  double YP[7][kNGeo];
+  double XS[6][NGS_MAX_K]; // X_o S, or X_rgb in its first 3 columns
+  double p[NGS_MAX_K];
+  double red;
+  int hs;                  // training-store slot
+  int hs_new;
+};
+
+// dQ = -Q dSigma Q for the conic Q = (q00, q01, q11) and dSigma = [[da, db], [db, dc]].
+__device__ inline void dconic(double q00, double q01, double q11, double da, double db, double dc, double* out) {
+  out[0] = -(q00 * q00 * da + 2.0 * q00 * q01 * db + q01 * q01 * dc);
+  out[1] = -(q00 * q01 * da + (q00 * q11 + q01 * q01) * db + q01 * q11 * dc);
+  out[2] = -(q01 * q01 * da + 2.0 * q01 * q11 * db + q11 * q11 * dc);
+}
+
+// Hand chain rule of the projection (3DGS EWA splatting) in FP64: rows of P for
+// (m_x, m_y, Q_xx, Q_xy, Q_yy, l) and the depth row, w.r.t. the 11 geometric parameters.
+__device__ void chain_rule(const float* mean, const float* log_scale, const float* rot, int n, int g,
+                           const DevCam& cam, double eps2d, double P[7][kNGeo]) {
+  double W[9];
+  for (int i = 0; i < 9; ++i) W[i] = cam.R[i];
+  const double mu[3] = {mean[g], mean[n + g], mean[2 * n + g]};
+  double X[3];
+  for (int i = 0; i < 3; ++i) X[i] = W[3 * i] * mu[0] + W[3 * i + 1] * mu[1] + W[3 * i + 2] * mu[2] + cam.t[i];
+  const double Z = X[2], fx = cam.fx, fy = cam.fy;
+  const double iz = 1.0 / Z, iz2 = iz * iz, iz3 = iz2 * iz;
+  const double Jp[6] = {fx * iz, 0.0, -fx * X[0] * iz2, 0.0, fy * iz, -fy * X[1] * iz2};
+  double T[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = Jp[3 * i] * W[j] + Jp[3 * i + 1] * W[3 + j] + Jp[3 * i + 2] * W[6 + j];
+  double s2[3];
+  for (int i = 0; i < 3; ++i) { const double s = exp((double)log_scale[(size_t)i * n + g]); s2[i] = s * s; }
+  const double q4[4] = {rot[g], rot[n + g], rot[2 * n + g], rot[3 * n + g]};
+  const double qn = sqrt(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+  const double w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+  const double Rg[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  double S3[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S3[3 * i + j] = Rg[3 * i] * s2[0] * Rg[3 * j] + Rg[3 * i + 1] * s2[1] * Rg[3 * j + 1] +
+                                                Rg[3 * i + 2] * s2[2] * Rg[3 * j + 2];
+  // V = Sigma3 T^T (3 x 2), Sigma2 = T V + eps I
+  double V[6];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j) V[2 * i + j] = S3[3 * i] * T[3 * j] + S3[3 * i + 1] * T[3 * j + 1] + S3[3 * i + 2] * T[3 * j + 2];
+  const double a = T[0] * V[0] + T[1] * V[2] + T[2] * V[4] + eps2d;
+  const double b = T[0] * V[1] + T[1] * V[3] + T[2] * V[5];
+  const double c = T[3] * V[1] + T[4] * V[3] + T[5] * V[5] + eps2d;
+  const double det = a * c - b * b;
+  const double q00 = c / det, q01 = -b / det, q11 = a / det;
+  for (int r = 0; r < 7; ++r)
+    for (int j = 0; j < kNGeo; ++j) P[r][j] = 0.0;
+  // mean: m through T, Q through the perspective Jacobian's dependence on X = W mu + t
+  double dS[3][3];  // dSigma2 / dX_m as (da, db, dc)
+  for (int m = 0; m < 3; ++m) {
+    double dJ[6] = {0, 0, 0, 0, 0, 0};
+    if (m == 0) dJ[2] = -fx * iz2;
+    if (m == 1) dJ[5] = -fy * iz2;
+    if (m == 2) { dJ[0] = -fx * iz2; dJ[2] = 2.0 * fx * X[0] * iz3; dJ[4] = -fy * iz2; dJ[5] = 2.0 * fy * X[1] * iz3; }
+    double dT[6];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j) dT[3 * i + j] = dJ[3 * i] * W[j] + dJ[3 * i + 1] * W[3 + j] + dJ[3 * i + 2] * W[6 + j];
+    double B[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) B[2 * i + j] = dT[3 * i] * V[j] + dT[3 * i + 1] * V[2 + j] + dT[3 * i + 2] * V[4 + j];
+    dS[m][0] = 2.0 * B[0];
+    dS[m][1] = B[1] + B[2];
+    dS[m][2] = 2.0 * B[3];
+  }
+  for (int j = 0; j < 3; ++j) {
+    P[0][j] = T[j];
+    P[1][j] = T[3 + j];
+    double da = 0, db = 0, dc = 0;
+    for (int m = 0; m < 3; ++m) { da += W[3 * m + j] * dS[m][0]; db += W[3 * m + j] * dS[m][1]; dc += W[3 * m + j] * dS[m][2]; }
+    double o[3];
+    dconic(q00, q01, q11, da, db, dc, o);
+    P[2][j] = o[0]; P[3][j] = o[1]; P[4][j] = o[2];
+    P[6][j] = W[6 + j];
+  }
+  // log-scales: dSigma3 = 2 s_i^2 r_i r_i^T
+  for (int i = 0; i < 3; ++i) {
+    const double u0 = T[0] * Rg[i] + T[1] * Rg[3 + i] + T[2] * Rg[6 + i];
+    const double u1 = T[3] * Rg[i] + T[4] * Rg[3 + i] + T[5] * Rg[6 + i];
+    double o[3];
+    dconic(q00, q01, q11, 2.0 * s2[i] * u0 * u0, 2.0 * s2[i] * u0 * u1, 2.0 * s2[i] * u1 * u1, o);
+    P[2][3 + i] = o[0]; P[3][3 + i] = o[1]; P[4][3 + i] = o[2];
+  }
+  // quaternion: Rg(q / |q|)
+  double U[6];  // T Rg
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) U[3 * i + j] = T[3 * i] * Rg[j] + T[3 * i + 1] * Rg[3 + j] + T[3 * i + 2] * Rg[6 + j];
+  const double dR[4][9] = {
+      {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0},
+      {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x},
+      {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y},
+      {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0}};
+  const double qh[4] = {w, x, y, z};
+  for (int j = 0; j < 4; ++j) {
+    double dRg[9];
+    for (int e = 0; e < 9; ++e) {
+      double v = 0.0;
+      for (int l = 0; l < 4; ++l) v += dR[l][e] * (((l == j) ? 1.0 : 0.0) - qh[l] * qh[j]) / qn;
+      dRg[e] = v;
+    }
+    double dU[6];
+    for (int i = 0; i < 2; ++i)
+      for (int e = 0; e < 3; ++e) dU[3 * i + e] = T[3 * i] * dRg[e] + T[3 * i + 1] * dRg[3 + e] + T[3 * i + 2] * dRg[6 + e];
+    double B[4];
+    for (int i = 0; i < 2; ++i)
+      for (int k2 = 0; k2 < 2; ++k2)
+        B[2 * i + k2] = dU[3 * i] * s2[0] * U[3 * k2] + dU[3 * i + 1] * s2[1] * U[3 * k2 + 1] + dU[3 * i + 2] * s2[2] * U[3 * k2 + 2];
+    double o[3];
+    dconic(q00, q01, q11, 2.0 * B[0], B[1] + B[2], 2.0 * B[3], o);
+    P[2][6 + j] = o[0]; P[3][6 + j] = o[1]; P[4][6 + j] = o[2];
+  }
+  P[5][10] = 1.0;
+}
+
+// In-place Cholesky of the l x l matrix A (full storage, lower triangle used) by one
+// 64-lane workgroup; returns log det A, or NaN if A is not positive definite.
+__device__ double chol_logdet(double* A, int l) {
+  double ld = 0.0;
+  for (int j = 0; j < l; ++j) {
+    __syncthreads();
+    const double d = A[j * l + j];
+    if (!(d > 0.0)) return __builtin_nan("");
+    const double r = sqrt(d);
+    ld += 2.0 * log(r);
+    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) A[i * l + j] /= r;
+    __syncthreads();
+    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) {
+      const double lij = A[i * l + j];
+      for (int c = j + 1; c <= i; ++c) A[i * l + c] -= lij * A[c * l + j];
+    }
+  }
+  __syncthreads();
+  return ld;
+}
+
+// A[0..10][0..10] = Pr^T Y Pr over the first `rows` rows of P (Y symmetric rows x rows).
+__device__ void geo_block(FinShared& S, int rows, int l) {
+  for (int e = threadIdx.x; e < rows * kNGeo; e += kFinThreads) {
+    const int a = e / kNGeo, j = e % kNGeo;
+    double v = 0.0;
+    for (int b = 0; b < rows; ++b) v += S.Y[a][b] * S.P[b][j];
+    S.YP[a][j] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+    const int i = e / kNGeo, j = e % kNGeo;
+    double v = 0.0;
+    for (int a = 0; a < rows; ++a) v += S.P[a][i] * S.YP[a][j];
+    S.A[i * l + j] = v;
+  }
+}
+
+__device__ void load_sym6(FinShared& S, int base) {
+  if (threadIdx.x == 0) {
+    int s = base;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j) { S.Y[i][j] = S.st[s]; S.Y[j][i] = S.st[s]; ++s; }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(
+    int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
+    const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
+    uint32_t outputs, int mode, int conf_on_train, float* __restrict__ acc, int stride,
+    int32_t* __restrict__ slot_of, int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots,
+    const int32_t* __restrict__ overflow, ngs_hessian h, int has_h, double* __restrict__ ig_out,
+    int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
+  __shared__ FinShared S;
+  const int used = min(*n_slots, stride);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (stats) atomicAdd((unsigned long long*)&stats[2], (unsigned long long)used);
+    if (*overflow) {
+      if (stats) atomicAdd((unsigned long long*)&stats[5], 1ull);
+      if (sticky) atomicOr(sticky, 1);
+    }
+  }
+  const int nst = stat_len(k);
+  const int lo = kNGeo + k;
+  for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
+    __syncthreads();
+    const int g = gid_of[slot];
+    for (int s = threadIdx.x; s < nst; s += kFinThreads) {
+      float* ap = &acc[(size_t)s * stride + slot];
+      S.st[s] = (double)*ap;
+      *ap = 0.f;
+    }
+    __syncthreads();
+    if (g < 0) continue;
+    if (threadIdx.x == 0) {
+      slot_of[g] = -1;
+      gid_of[slot] = -1;
+      chain_rule(mean, log_scale, rot, n, g, cam, eps2d, S.P);
+      S.hs = has_h ? h.slot_of[g] : -1;
+      S.hs_new = 0;
+    }
+    for (int c = threadIdx.x; c < k; c += kFinThreads) S.p[c] = (double)prob[(size_t)g * k + c];
+    __syncthreads();
+    const double cg = (double)conf[g];
+    const double wacc = conf_on_train ? cg : 1.0;
+    const double a2 = S.st[kStatYd + tri_idx(6, 6, 7)];
+    if (mode == NGS_MODE_ACCUMULATE) {
+      if (cg == 0.0) continue;  // never enters a gain: c_g = 0 makes the log-det difference 0
+      if (threadIdx.x == 0 && S.hs < 0) {
+        const int ns = atomicAdd(h.n_slots, 1);
+        if (ns < h.capacity) { h.slot_of[g] = ns; h.gid_of[ns] = g; S.hs = ns; S.hs_new = 1; }
+      }
+      __syncthreads();
+      if (S.hs < 0) continue;  // store full: ngs_hessian_finalize reports it
+    }
+    for (int f = 0; f < 3; ++f) {
+      if (!((outputs >> f) & 1u)) continue;
+      const int l = f == 0 ? 14 : (f == 1 ? kNGeo : lo);
+      // ---- build A (unweighted) ----
+      for (int e = threadIdx.x; e < l * l; e += kFinThreads) S.A[e] = 0.0;
+      __syncthreads();
+      if (f == 0) {
+        load_sym6(S, kStatYrgb);
+        geo_block(S, 6, l);
+        for (int e = threadIdx.x; e < kNGeo * 3; e += kFinThreads) {
+          const int i = e / 3, ch = e % 3;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.st[kStatXrgb + a * 3 + ch];
+          S.A[i * l + kNGeo + ch] = v;
+          S.A[(kNGeo + ch) * l + i] = v;
+        }
+        if (threadIdx.x < 3) S.A[(kNGeo + threadIdx.x) * l + kNGeo + threadIdx.x] = a2;
+      } else if (f == 1) {
+        if (threadIdx.x == 0) {
+          int s = kStatYd;
+          for (int i = 0; i < 7; ++i)
+            for (int j = i; j < 7; ++j) { S.Y[i][j] = S.st[s]; S.Y[j][i] = S.st[s]; ++s; }
+        }
+        __syncthreads();
+        geo_block(S, 7, l);
+      } else {
+        load_sym6(S, kStatYo);
+        geo_block(S, 6, l);
+        // X_o S with X_o = m1 p^T - Z_o
+        for (int a = threadIdx.x; a < 6; a += kFinThreads) {
+          double xp = 0.0;
+          for (int c = 0; c < k; ++c) xp += (S.st[kStatM1 + a] * S.p[c] - S.st[kStatScalar + a * k + c]) * S.p[c];
+          for (int m = 0; m < k; ++m) {
+            const double x = S.st[kStatM1 + a] * S.p[m] - S.st[kStatScalar + a * k + m];
+            S.XS[a][m] = S.p[m] * (x - xp);
+          }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) {
+          const int i = e / k, m = e % k;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.XS[a][m];
+          S.A[i * l + kNGeo + m] = v;
+          S.A[(kNGeo + m) * l + i] = v;
+        }
+        double s2 = 0.0;
+        for (int c = 0; c < k; ++c) s2 += S.p[c] * S.p[c];
+        for (int e = threadIdx.x; e < k * k; e += kFinThreads) {
+          const int m = e / k, j = e % k;
+          const double pm = S.p[m], pj = S.p[j];
+          const double ss = (m == j ? pm * pm : 0.0) - pm * pm * pj - pm * pj * pj + pm * pj * s2;
+          S.A[(kNGeo + m) * l + kNGeo + j] = a2 * ss;
+        }
+      }
+      __syncthreads();
+      double* hblk = f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o);
+      const int hs = S.hs;
+      if (mode == NGS_MODE_ACCUMULATE) {
+        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
+          // unpack (i, j), i <= j, from the packed row-major upper index
+          int i = 0, rem = e;
+          while (rem >= l - i) { rem -= l - i; ++i; }
+          const int j = i + rem;
+          double* hp = &hblk[(size_t)e * h.capacity + hs];
+          const double base = S.hs_new ? (i == j ? lambda : 0.0) : *hp;
+          *hp = base + wacc * S.A[i * l + j];
+        }
+        continue;
+      }
+      // ---- SCORE: M = H_T + c A, gain = logdet M - logdet H_T ----
+      double ld_h;
+      if (hs >= 0) {
+        ld_h = h.logdet[(size_t)f * h.capacity + hs];
+        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
+          int i = 0, rem = e;
+          while (rem >= l - i) { rem -= l - i; ++i; }
+          const int j = i + rem;
+          const double hv = hblk[(size_t)e * h.capacity + hs];
+          const double v = hv + cg * S.A[i * l + j];
+          S.A[i * l + j] = v;
+          S.A[j * l + i] = v;
+        }
+      } else {
+        ld_h = (double)l * log(lambda);
+        for (int e = threadIdx.x; e < l * l; e += kFinThreads) {
+          const int i = e / l, j = e % l;
+          S.A[e] = cg * S.A[e] + (i == j ? lambda : 0.0);
+        }
+      }
+      __syncthreads();
+      const double ld_m = chol_logdet(S.A, l);
+      if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], ld_m - ld_h);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, int used, double lambda) {
+  __shared__ FinShared S;
+  const int lo = kNGeo + h.k;
+  for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
+    for (int f = 0; f < 3; ++f) {
+      const int l = f == 0 ? 14 : (f == 1 ? kNGeo : lo);
+      const double* hblk = f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o);
+      __syncthreads();
+      for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
+        int i = 0, rem = e;
+        while (rem >= l - i) { rem -= l - i; ++i; }
+        const int j = i + rem;
+        const double v = hblk[(size_t)e * h.capacity + slot];
+        S.A[i * l + j] = v;
+        S.A[j * l + i] = v;
+      }
+      __syncthreads();
+      const double ld = chol_logdet(S.A, l);
+      if (threadIdx.x == 0) h.logdet[(size_t)f * h.capacity + slot] = ld;
+    }
+  }
+  (void)lambda;
+}
+
+// Eq. 10 normalisation, Eq. 11 combination and the argmax of Eq. 5 (lowest index on ties).
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ ig_raw, int nv, double n0, double n1,
+                                                 double n2, double bd, double bo, uint32_t outputs,
+                                                 float* __restrict__ scores, int32_t* __restrict__ best) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  double bv = -INFINITY;
+  int bi = -1;
+  const double nf[3] = {n0, n1, n2}, beta[3] = {1.0, bd, bo};
+  for (int v = threadIdx.x; v < nv; v += 256) {
+    double tot = 0.0;
+    for (int f = 0; f < 3; ++f) {
+      const double s = ((outputs >> f) & 1u) ? ig_raw[3 * v + f] / nf[f] : 0.0;
+      scores[4 * v + f] = (float)s;
+      tot += beta[f] * s;
+    }
+    scores[4 * v + 3] = (float)tot;
+    if (tot > bv) { bv = tot; bi = v; }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const double ov = sv[threadIdx.x + off];
+      const int oi = si[threadIdx.x + off];
+      if (oi >= 0 && (si[threadIdx.x] < 0 || ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *best = si[0];
+}
+
+}  // namespace
+
+hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp, const ngs_ig_params& ig,
+                              const IgWs& w, ngs_hessian* h, double* ig_out, int64_t* stats, int32_t* sticky,
+                              hipStream_t st) {
+  ngs_hessian hh{};
+  if (h) hh = *h;
+  const int blocks = (int)std::min<int64_t>(w.max_slots, 4096);
+  ProfScope ps(kProfIgFinalize, st);
+  hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
+                     s.prob, cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
+                     w.acc, (int)w.max_slots, w.slot_of, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out,
+                     stats, sticky);
+  return hipGetLastError();
+}
+
+hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st) {
+  const int used = std::min(n_slots, h->capacity);
+  if (used <= 0) return hipSuccess;
+  const int blocks = std::min(used, 4096);
+  ProfScope ps(kProfHessianLogdet, st);
+  hipLaunchKernelGGL(k_hessian_logdet, dim3(blocks), dim3(kFinThreads), 0, st, *h, used, (double)lambda_prior);
+  return hipGetLastError();
+}
+
+hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2, float beta_d,
+                                float beta_o, uint32_t outputs, float* scores, int32_t* best, hipStream_t st) {
+  ProfScope ps(kProfCombine, st);
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st, ig_raw, n_views, n0, n1, n2, (double)beta_d,
+                     (double)beta_o, outputs, scores, best);
+  return hipGetLastError();
+}
+
+}  // namespace ngs

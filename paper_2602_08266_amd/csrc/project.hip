@@ -1,0 +1,161 @@
+// project.hip -- per-scene precompute (softmax, confidence) and per-view projection.
+//
+// Compiled with -ffp-contract=off: the FP64 key path below (depth, 2D mean, EWA covariance,
+// radius, tile rect) is evaluated operation by operation in a fixed order, so that the
+// depth keys and tile rects it produces are reproducible bit for bit by any IEEE-754 FP64
+// evaluation of the same sequence.
+#include "common.hpp"
+
+namespace ngs {
+namespace {
+
+// p = softmax(o) (Sec. III-A.1), sigma = sigmoid(opacity logit), kappa = max_k p,
+// label = argmax_k o (identical to argmax_k p, lowest k on ties), and the confidence
+// c_g of Eq. 7 -- or Eq. 12 when a target object is given.
+__global__ __launch_bounds__(256) void k_prepare(int n, int k, const float* __restrict__ logit,
+                                                 const float* __restrict__ op_logit, float alpha_obj,
+                                                 float alpha_opa, int target, float* __restrict__ prob,
+                                                 float* __restrict__ opacity, float* __restrict__ kappa,
+                                                 float* __restrict__ conf, int32_t* __restrict__ label) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float mx = logit[g];
+  int am = 0;
+  for (int c = 1; c < k; ++c) {
+    const float v = logit[(size_t)c * n + g];
+    if (v > mx) { mx = v; am = c; }
+  }
+  float z = 0.f;
+  for (int c = 0; c < k; ++c) z += expf(logit[(size_t)c * n + g] - mx);
+  const float inv = 1.f / z;
+  for (int c = 0; c < k; ++c) prob[(size_t)g * k + c] = expf(logit[(size_t)c * n + g] - mx) * inv;
+  const float sig = 1.f / (1.f + expf(-op_logit[g]));
+  const float kap = inv;  // exp(0) / z at the argmax
+  opacity[g] = sig;
+  kappa[g] = kap;
+  label[g] = am;
+  float c;
+  if (target < 0) {
+    c = powf(kap, -alpha_obj) * powf(sig, -alpha_opa);
+  } else {
+    c = (am == target) ? powf(expf(logit[(size_t)target * n + g] - mx) * inv, -alpha_obj) * powf(sig, -alpha_opa)
+                       : 0.f;
+  }
+  conf[g] = c;
+}
+
+__device__ inline int tile_floor(double v, int tile, int lim) {
+  double f = floor(v / (double)tile);
+  if (f < -1.0) f = -1.0;
+  if (f > (double)lim) f = (double)lim;
+  return (int)f;
+}
+
+// One thread per Gaussian. FP64 key path in the order: X = R mu + t (row by row,
+// left to right), Z; m = (f X / Z) + c; Sigma3 = Rg diag(s^2) Rg^T; T = Jp R; M = T Sigma3;
+// Sigma2 = M T^T; +eps on the diagonal; conic; lambda_max; radius; rect.
+__global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ mean,
+                                                 const float* __restrict__ log_scale,
+                                                 const float* __restrict__ rot, DevCam cam, double z_near,
+                                                 double eps2d, int tile, float* __restrict__ mean2d,
+                                                 float* __restrict__ conic, float* __restrict__ depth,
+                                                 uint32_t* __restrict__ zkey, int16_t* __restrict__ rect,
+                                                 uint32_t* __restrict__ count) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double R[9];
+  for (int i = 0; i < 9; ++i) R[i] = (double)cam.R[i];
+  const double mu0 = mean[g], mu1 = mean[n + g], mu2 = mean[2 * n + g];
+  double X[3];
+  for (int i = 0; i < 3; ++i) X[i] = ((R[3 * i] * mu0 + R[3 * i + 1] * mu1) + R[3 * i + 2] * mu2) + (double)cam.t[i];
+  const double Z = X[2];
+  bool valid = Z > z_near;
+  float mxf = 0.f, myf = 0.f, qa = 0.f, qb = 0.f, qc = 0.f;
+  int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+  if (valid) {
+    const double fx = cam.fx, fy = cam.fy;
+    const double mx = (fx * X[0]) / Z + (double)cam.cx;
+    const double my = (fy * X[1]) / Z + (double)cam.cy;
+    const double s0 = exp((double)log_scale[g]), s1 = exp((double)log_scale[n + g]),
+                 s2 = exp((double)log_scale[2 * n + g]);
+    const double sc2[3] = {s0 * s0, s1 * s1, s2 * s2};
+    const double qw = rot[g], qx = rot[n + g], qy = rot[2 * n + g], qz = rot[3 * n + g];
+    const double qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    double Rg[9];
+    Rg[0] = 1.0 - 2.0 * (y * y + z * z); Rg[1] = 2.0 * (x * y - w * z);       Rg[2] = 2.0 * (x * z + w * y);
+    Rg[3] = 2.0 * (x * y + w * z);       Rg[4] = 1.0 - 2.0 * (x * x + z * z); Rg[5] = 2.0 * (y * z - w * x);
+    Rg[6] = 2.0 * (x * z - w * y);       Rg[7] = 2.0 * (y * z + w * x);       Rg[8] = 1.0 - 2.0 * (x * x + y * y);
+    double S3[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc = acc + (Rg[3 * i + k] * sc2[k]) * Rg[3 * j + k];
+        S3[3 * i + j] = acc;
+      }
+    const double Jp[6] = {fx / Z, 0.0, -(fx * X[0]) / (Z * Z), 0.0, fy / Z, -(fy * X[1]) / (Z * Z)};
+    double T[6], M[6];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j)
+        T[3 * i + j] = ((Jp[3 * i] * R[j] + Jp[3 * i + 1] * R[3 + j]) + Jp[3 * i + 2] * R[6 + j]);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j)
+        M[3 * i + j] = ((T[3 * i] * S3[j] + T[3 * i + 1] * S3[3 + j]) + T[3 * i + 2] * S3[6 + j]);
+    const double S00 = ((M[0] * T[0] + M[1] * T[1]) + M[2] * T[2]);
+    const double S01 = ((M[0] * T[3] + M[1] * T[4]) + M[2] * T[5]);
+    const double S11 = ((M[3] * T[3] + M[4] * T[4]) + M[5] * T[5]);
+    const double a = S00 + eps2d, b = S01, c = S11 + eps2d;
+    const double det = a * c - b * b;
+    const double half = (a - c) * 0.5;
+    const double lmax = (a + c) * 0.5 + sqrt(half * half + b * b);
+    const double r = ceil(3.0 * sqrt(lmax));
+    x0 = max(0, tile_floor(mx - r, tile, cam.tiles_x));
+    x1 = min(cam.tiles_x - 1, tile_floor(mx + r, tile, cam.tiles_x));
+    y0 = max(0, tile_floor(my - r, tile, cam.tiles_y));
+    y1 = min(cam.tiles_y - 1, tile_floor(my + r, tile, cam.tiles_y));
+    valid = (x0 <= x1) && (y0 <= y1);
+    mxf = (float)mx;
+    myf = (float)my;
+    qa = (float)(c / det);
+    qb = (float)(-b / det);
+    qc = (float)(a / det);
+  }
+  mean2d[g] = mxf;
+  mean2d[n + g] = myf;
+  conic[g] = qa;
+  conic[n + g] = qb;
+  conic[2 * n + g] = qc;
+  const float zf = (float)Z;
+  depth[g] = zf;
+  zkey[g] = valid ? __float_as_uint(zf) : 0xFFFFFFFFu;
+  if (!valid) { x0 = 0; y0 = 0; x1 = -1; y1 = -1; }
+  rect[g] = (int16_t)x0;
+  rect[n + g] = (int16_t)y0;
+  rect[2 * n + g] = (int16_t)x1;
+  rect[3 * n + g] = (int16_t)y1;
+  count[g] = valid ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+}
+
+}  // namespace
+
+hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  const int blocks = (s.n + 255) / 256;
+  ProfScope ps(kProfPrepare, st);
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, s.n, s.k, s.obj_logit, s.opacity_logit,
+                     ig.alpha_obj, ig.alpha_opa, ig.target_id, s.prob, s.opacity, s.kappa, s.conf, s.label);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+                          const ngs_projected& out, hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  const int blocks = (s.n + 255) / 256;
+  ProfScope ps(kProfProject, st);
+  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, cam,
+                     (double)rp.z_near, (double)rp.eps2d, rp.tile, out.mean2d, out.conic, out.depth, out.zkey,
+                     out.rect, out.count);
+  return hipGetLastError();
+}
+
+}  // namespace ngs

@@ -1,0 +1,201 @@
+// sort.hip -- stable LSD radix sort of (u32 key, u32 value) pairs, 8-bit digits.
+//
+// One pass = histogram (per block digit counts), per-digit scan across blocks, scatter.
+// The scatter ranks keys inside each wavefront with ballot match masks (8 ballots give the
+// set of lanes sharing a digit), so equal digits keep their input order across lanes,
+// waves, rounds and blocks: the pass is stable, and successive passes from the least
+// significant digit sort by the whole key with ties kept in input order.
+#include "common.hpp"
+
+namespace ngs {
+namespace {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTileElems = kSortThreads * kSortItems;  // 4096 keys per block
+constexpr int kWavesPerBlock = kSortThreads / kWave;
+
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
+                                                       uint32_t* __restrict__ hist, size_t nblocks) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * kSortTileElems;
+#pragma unroll 4
+  for (int j = 0; j < kSortItems; ++j) {
+    const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns the total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sm, uint32_t* total) {
+  const int t = threadIdx.x;
+  sm[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kSortThreads; off <<= 1) {
+    const uint32_t add = (t >= off) ? sm[t - off] : 0u;
+    __syncthreads();
+    sm[t] += add;
+    __syncthreads();
+  }
+  const uint32_t incl = sm[t];
+  *total = sm[kSortThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// One block per digit: exclusive scan of that digit's counts across blocks, in place;
+// rowtot[d] = total count of digit d.
+__global__ __launch_bounds__(kSortThreads) void k_scan_rows(uint32_t* __restrict__ hist, size_t nblocks,
+                                                            uint32_t* __restrict__ rowtot) {
+  __shared__ uint32_t sm[kSortThreads];
+  uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (size_t b0 = 0; b0 < nblocks; b0 += kSortThreads) {
+    const size_t i = b0 + threadIdx.x;
+    const uint32_t v = (i < nblocks) ? row[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, sm, &tot);
+    if (i < nblocks) row[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin, size_t n, int shift,
+                                                          const uint32_t* __restrict__ hist, size_t nblocks,
+                                                          const uint32_t* __restrict__ rowtot,
+                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t sm[kSortThreads];
+  __shared__ uint32_t base[kRadix];            // global start of each digit for this block
+  __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+  const int t = threadIdx.x;
+  const int wave = t / kWave;
+  const int lane = t % kWave;
+  {
+    uint32_t tot;
+    const uint32_t digit_start = block_exclusive_scan(rowtot[t], sm, &tot);
+    base[t] = digit_start + hist[(size_t)t * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const size_t blk = (size_t)blockIdx.x * kSortTileElems;
+  for (int j = 0; j < kSortItems; ++j) {
+    const size_t i = blk + (size_t)j * kSortThreads + t;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = __popcll(peers & lt_mask);
+    const bool leader = valid && (peers & lt_mask) == 0ull;
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][t] = 0u;
+    __syncthreads();
+    if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      uint32_t run = base[t];
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        const uint32_t c = wcnt[w][t];
+        wcnt[w][t] = run;
+        run += c;
+      }
+      base[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[wave][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_iota(uint32_t* v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (uint32_t)i;
+}
+__global__ void k_fill_u32(uint32_t* v, uint32_t x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+__global__ void k_fill_i32(int32_t* v, int32_t x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+
+}  // namespace
+
+size_t sort_blocks_for(size_t n) { return (n + kSortTileElems - 1) / kSortTileElems; }
+
+hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  ProfScope ps(kProfFill, st);
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  ProfScope ps(kProfFill, st);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  ProfScope ps(kProfFill, st);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
+
+// Sorts bits [begin_bit, end_bit) of the keys; the result is in (*keys_out, *vals_out),
+// which is one of the two ping-pong buffers (a, b). The inputs are only read.
+hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_a,
+                            uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n, int begin_bit,
+                            int end_bit, const SortWs& ws, hipStream_t st, uint32_t** keys_out,
+                            uint32_t** vals_out, int prof_base) {
+  const size_t nb = sort_blocks_for(n);
+  if (nb > ws.max_blocks) return hipErrorInvalidValue;
+  const uint32_t* kin = keys_in;
+  const uint32_t* vin = vals_in;
+  uint32_t* kdst = keys_a;
+  uint32_t* vdst = vals_a;
+  *keys_out = const_cast<uint32_t*>(keys_in);
+  *vals_out = const_cast<uint32_t*>(vals_in);
+  if (n == 0) return hipSuccess;
+  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
+    {
+      ProfScope ps(prof_base, st);
+      hipLaunchKernelGGL(k_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n, shift, ws.hist, nb);
+    }
+    {
+      ProfScope ps(prof_base + 1, st);
+      hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kSortThreads), 0, st, ws.hist, nb, ws.rowtot);
+    }
+    {
+      ProfScope ps(prof_base + 2, st);
+      hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, n, shift, ws.hist, nb,
+                         ws.rowtot, kdst, vdst);
+    }
+    *keys_out = kdst;
+    *vals_out = vdst;
+    kin = kdst;
+    vin = vdst;
+    if (kdst == keys_a) { kdst = keys_b; vdst = vals_b; } else { kdst = keys_a; vdst = vals_a; }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ngs

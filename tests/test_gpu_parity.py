@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded
+inputs (small configurations; the oracle runs live)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from parity_util import check_gain, check_image
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_08266_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0)
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def device_scene(B, ctx, scene, target=-1):
+    ds = B.DeviceScene(scene, "cuda")
+    B.ngs_prepare_scene(ctx, ds, B.ig_params(target_id=target))
+    return ds
+
+
+def small_scene(k=4, n=40, seed=5, spread=0.06):
+    rng = np.random.default_rng(seed)
+    means = np.column_stack([rng.normal(0, spread, n), rng.normal(0, spread, n), rng.normal(0, 0.05, n)])
+    ls = np.log(rng.uniform(0.004, 0.03, (n, 3)))
+    return scenegen.tiny_scene(means, ls, rng.normal(size=(n, 4)), rng.normal(0, 1, n), rng.uniform(0, 1, (n, 3)),
+                               rng.normal(0, 1.5, (n, k)))
+
+
+def test_prepare_scene(B, ctx):
+    log("test_prepare_scene")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    for target in (-1, 3):
+        ds = device_scene(B, ctx, scene, target)
+        gt = oracle.gaussian_terms(scene, oracle.IGParams(target_id=target))
+        assert np.allclose(ds.prob.cpu().numpy(), gt["p"], rtol=1e-5, atol=1e-7)
+        assert np.allclose(ds.opacity.cpu().numpy(), gt["sigma"], rtol=1e-5)
+        assert np.allclose(ds.kappa.cpu().numpy(), gt["kappa"], rtol=1e-5)
+        assert np.allclose(ds.conf.cpu().numpy(), gt["conf"], rtol=1e-5)
+        assert np.array_equal(ds.label.cpu().numpy(), gt["argmax"])
+
+
+@pytest.mark.parametrize("wl,view", [("tiny", 0), ("tiny", 5)])
+def test_project_bitexact_keys_and_rects(B, ctx, wl, view):
+    log(f"test_project {wl} view {view}")
+    cfg, scene, cands, train = scenegen.make_workload(wl, 0)
+    cam = cands[view]
+    ds = device_scene(B, ctx, scene)
+    pr = B.ngs_project(ctx, ds, B.camera(cam), B.raster_params())
+    ref = oracle.project(scene, cam)
+    valid = ref["valid"].astype(bool)
+    cnt = pr.count.cpu().numpy()
+    assert np.array_equal(cnt > 0, valid)
+    zk = pr.zkey.cpu().numpy().view(np.uint32)
+    assert np.array_equal(zk[valid], ref["zkey"][valid])
+    rect = pr.rect.cpu().numpy().astype(np.int32)
+    assert np.array_equal(rect[:, valid], ref["rect"][:, valid])
+    area = (ref["rect"][2] - ref["rect"][0] + 1) * (ref["rect"][3] - ref["rect"][1] + 1)
+    assert np.array_equal(cnt[valid], area[valid])
+    m2 = pr.mean2d.cpu().numpy().astype(np.float64)
+    assert np.allclose(m2[:, valid], ref["m"][:, valid], rtol=1e-6, atol=1e-4)
+    con = pr.conic.cpu().numpy().astype(np.float64)
+    assert np.allclose(con[:, valid], ref["conic"][:, valid], rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("wl,view", [("tiny", 0), ("tiny", 3)])
+def test_bin_sort_bitexact(B, ctx, wl, view):
+    log(f"test_bin_sort {wl} view {view}")
+    cfg, scene, cands, train = scenegen.make_workload(wl, 0)
+    cam = cands[view]
+    ds = device_scene(B, ctx, scene)
+    rp = B.raster_params()
+    c = B.camera(cam)
+    pr = B.ngs_project(ctx, ds, c, rp)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=16, want_keys=True)   # grows through CAPACITY
+    ref = oracle.tile_lists(scene, cam)
+    m = int(lists.n_pairs.item())
+    assert m == ref["m"]
+    assert np.array_equal(lists.gids[:m].cpu().numpy().view(np.uint32), ref["gids"])
+    assert np.array_equal(lists.keys[:m].cpu().numpy().view(np.uint64), ref["keys"])
+    assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+
+
+def render_gpu(B, ctx, ds, cam, want_obj=True):
+    rp = B.raster_params()
+    c = B.camera(cam)
+    pr = B.ngs_project(ctx, ds, c, rp)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=1 << 20)
+    img = B.ngs_render(ctx, ds, pr, lists, c, rp, want_obj=want_obj)
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in img.items()}, pr, lists
+
+
+@pytest.mark.parametrize("view", [0, 2, 7])
+def test_render_parity_tiny(B, ctx, view):
+    log(f"test_render tiny view {view}")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = device_scene(B, ctx, scene)
+    img, _, _ = render_gpu(B, ctx, ds, cands[view])
+    ref = oracle.render(scene, cands[view])
+    stats = check_image(img, ref, scene.k, depth_max=1.0)
+    log(f"  {stats}")
+
+
+def test_render_ragged_and_edge_cases(B, ctx):
+    log("test_render ragged")
+    sc = small_scene(k=4, n=60)
+    # image size not a multiple of the tile; camera close enough for large footprints
+    cam = scenegen.look_at(np.array([0.25, -0.2, 0.2]), 100, 70, 60.0)
+    ds = device_scene(B, ctx, sc)
+    img, _, lists = render_gpu(B, ctx, ds, cam)
+    ref = oracle.render(sc, cam)
+    check_image(img, ref, sc.k, depth_max=1.0)
+    assert ref["ncontrib"].sum() > 0
+    # a camera that looks away: nothing binned, empty image
+    away = scenegen.look_at(np.array([3.0, 0.0, 0.2]), 100, 70, 60.0, target=(6.0, 0.0, 0.2))
+    img, _, lists = render_gpu(B, ctx, ds, away)
+    assert int(lists.n_pairs.item()) == 0
+    assert np.all(img["t_final"] == 1.0) and np.all(img["rgb"] == 0.0) and np.all(img["argmax_id"] == 0)
+
+
+def gpu_gain(B, ctx, ds, cam, ig, h=None, stats=None):
+    rp = B.raster_params()
+    c = B.camera(cam)
+    pr = B.ngs_project(ctx, ds, c, rp)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=1 << 20)
+    ws = B.IgWorkspace(ds, 1 << 14)
+    return B.ngs_info_gain(ctx, ds, pr, lists, c, rp, ig, h, ws, stats).cpu().numpy()
+
+
+@pytest.mark.parametrize("target", [-1, 2])
+def test_info_gain_prior_only_tiny(B, ctx, target):
+    """H_T = lambda I (no training information): gain of each candidate view."""
+    log(f"test_info_gain prior-only target {target}")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = device_scene(B, ctx, scene, target)
+    away = [scenegen.look_at(np.array([5.0, 0.0, 0.5]), 128, 96, 100.0, target=(10.0, 0.0, 0.5))]
+    ref = oracle.score(scene, away, cands[:3], ig=oracle.IGParams(target_id=target))
+    for v in range(3):
+        g = gpu_gain(B, ctx, ds, cands[v], B.ig_params(target_id=target))
+        r = check_gain(g, ref.ig_cand[v], f"view {v}")
+        log(f"  view {v}: gpu {g} ref {ref.ig_cand[v]} rel {r:.2e}")
+
+
+def test_info_gain_small_scene_all_outputs(B, ctx):
+    log("test_info_gain small scene")
+    sc = small_scene(k=4, n=30, seed=11)
+    cam = scenegen.look_at(np.array([0.3, 0.1, 0.25]), 64, 48, 60.0)
+    ds = device_scene(B, ctx, sc)
+    away = [scenegen.look_at(np.array([5.0, 0.0, 0.5]), 64, 48, 60.0, target=(10.0, 0.0, 0.5))]
+    for outputs in (1, 2, 4, 7):
+        for eq2 in (1, 0):
+            ref = oracle.score(sc, away, [cam], ig=oracle.IGParams(outputs=outputs, obj_eq2=eq2))
+            g = gpu_gain(B, ctx, ds, cam, B.ig_params(outputs=outputs, obj_eq2=eq2))
+            check_gain(g, ref.ig_cand[0], f"outputs {outputs} eq2 {eq2}")
+
+
+@pytest.mark.parametrize("target", [-1, 3])
+def test_score_pipeline_tiny(B, ctx, target):
+    """Training setup (H_T, Eq. 10 normalisers) and batched scoring against the oracle."""
+    log(f"test_score_pipeline tiny target {target}")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = B.DeviceScene(scene, "cuda")
+    ig = B.ig_params(target_id=target)
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=1 << 18, max_slots=1 << 14,
+                         store_capacity=1 << 14)
+    norm = scorer.setup([B.camera(c) for c in train])
+    ref = oracle.score(scene, train, cands, ig=oracle.IGParams(target_id=target))
+    assert ref.status == 0
+    check_gain(norm, ref.norm, "normalisers")
+    for t in range(len(train)):
+        check_gain(scorer.ig_train[t], ref.ig_train[t], f"train {t}")
+    import torch
+    stats = torch.zeros(6, dtype=torch.int64, device="cuda")
+    scores, best, raw = scorer.score([B.camera(c) for c in cands], stats)
+    raw = raw.cpu().numpy()
+    for v in range(len(cands)):
+        check_gain(raw[v], ref.ig_cand[v], f"candidate {v}")
+    sc = scores.cpu().numpy().astype(np.float64)
+    assert np.allclose(sc, ref.scores, rtol=2e-3)
+    top = np.sort(ref.scores[:, 3])
+    if (top[-1] - top[-2]) / abs(top[-1]) > 1e-3:
+        assert int(best.item()) == ref.best
+    st = stats.cpu().numpy()
+    assert st[0] == len(cands) and st[5] == 0
+    log(f"  best gpu {int(best.item())} oracle {ref.best}; stats {st}")
+
+
+def test_abi_errors(B, ctx):
+    log("test_abi_errors")
+    import ctypes as C
+    L = B.lib()
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = device_scene(B, ctx, scene)
+    cam = B.camera(cands[0])
+    rp = B.raster_params()
+    pr = B.ngs_project(ctx, ds, cam, rp)
+    sc, pc = ds.c(), pr.c()
+    bad_rp = B.raster_params(tile=8)
+    assert L.ngs_project(ctx.handle, C.byref(sc), C.byref(cam), C.byref(bad_rp), C.byref(pc), None) == B.NGS_UNSUPPORTED
+    assert L.ngs_project(ctx.handle, None, C.byref(cam), C.byref(rp), C.byref(pc), None) == B.NGS_INVALID_ARG
+    big = B.ngs_camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy, 4096, 4096)
+    assert L.ngs_project(ctx.handle, C.byref(sc), C.byref(big), C.byref(rp), C.byref(pc), None) == B.NGS_UNSUPPORTED
+    sc_bad = ds.c()
+    sc_bad.k = 65
+    assert L.ngs_project(ctx.handle, C.byref(sc_bad), C.byref(cam), C.byref(rp), C.byref(pc), None) == B.NGS_UNSUPPORTED
+    # degenerate normalisers
+    import torch
+    ws = B.score_workspace(ds, 1 << 16, 1 << 12)
+    with pytest.raises(B.NgsError) as e:
+        B.ngs_score_batch(ctx, ds, None, [1.0, 0.0, 1.0], [cam], rp, B.ig_params(), ws)
+    assert e.value.status == B.NGS_DEGENERATE
+    # too small a workspace for the IG slots
+    tiny_ws = B.IgWorkspace.__new__(B.IgWorkspace)
+    tiny_ws.buf = torch.empty(64, dtype=torch.uint8, device="cuda")
+    lists = B.ngs_bin_sort(ctx, ds, pr, cam, rp, capacity=1 << 16)
+    with pytest.raises(B.NgsError) as e:
+        B.ngs_info_gain(ctx, ds, pr, lists, cam, rp, B.ig_params(), None, tiny_ws)
+    assert e.value.status == B.NGS_WORKSPACE_TOO_SMALL
+    assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, None, None, None, None) == B.NGS_UNSUPPORTED
