@@ -1,0 +1,213 @@
+"""Throughput of exact next-best-view scoring on one MI355X.
+
+Workload: 1M Gaussians in 64 object clusters (object vector k = 64), object-centric scoring
+of a seeded target (Eq. 12), candidate views at 640x480 (fx = fy = 525) on a sphere of
+radius U[0.4, 0.9] m -- the 640x480 share of the mixed-resolution batch. One step scores
+every candidate view: projection, binning and sorting, the fused compositing +
+information-gain walk, the FP64 finalize, Eq. 10-11 and the argmax. The training set
+(4 views: H_T and the Eq. 10 normalisers) is built once before timing and reported apart.
+
+Prints one JSON line. With --gpus N > 1 it exits: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "candidate views scored/sec at 1M Gaussians 640x480 (exact vs surrogate); % HBM peak"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2602_08266_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# Algorithmic HBM bytes per kernel class, from per-step counts: n Gaussians, k, views V,
+# pairs M (summed over views), walked (tile, list entry) pairs W.
+def algorithmic_bytes(name, n, k, V, M, W):
+    if name == "project":
+        return V * n * (40 + 40)                 # mean, log-scale, quaternion in; 2D mean, conic, depth, key, rect, count out
+    if name == "depth_sort_scatter":
+        return V * 4 * n * 16                    # 4 passes, key + value in and out
+    if name == "depth_sort_hist":
+        return V * 4 * n * 4
+    if name == "count_scan":
+        return V * n * 16
+    if name == "emit_pairs":
+        return 8 * M + V * n * 24
+    if name == "tile_sort_scatter":
+        return 2 * 16 * M                        # two 8-bit tile-digit passes (<= 4096 tiles)
+    if name == "tile_sort_hist":
+        return 2 * 4 * M
+    if name == "tile_ranges":
+        return 4 * M
+    if name == "ig_tiles":
+        return W * (4 + 24)                      # list entry + projected geometry per walked entry
+    return None
+
+
+KERNEL_FILES = {
+    "project": ["project.hip", "common.hpp"], "depth_sort_scatter": ["sort.hip", "common.hpp"],
+    "depth_sort_hist": ["sort.hip", "common.hpp"], "count_scan": ["bin.hip", "common.hpp"],
+    "emit_pairs": ["bin.hip", "common.hpp"], "tile_sort_scatter": ["sort.hip", "common.hpp"],
+    "tile_sort_hist": ["sort.hip", "common.hpp"], "tile_ranges": ["bin.hip", "common.hpp"],
+    "ig_tiles": ["info_gain.hip", "common.hpp"], "ig_finalize": ["finalize.hip", "common.hpp"],
+}
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it still matches
+    the kernel's source; else None."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash(KERNEL_FILES.get(kernel, [])):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload_name, seed, threads=None):
+    """The FP64 oracle timed on the host on a bounded sample: one candidate view of the
+    workload scored against H_T = lambda I (training blocks would triple the time)."""
+    import oracle
+    import scenegen
+    cfg, scene, cands, train = scenegen.make_workload(workload_name, seed)
+    ig = oracle.IGParams(target_id=scene.target)
+    th = threads or oracle.default_threads()
+    t0 = time.perf_counter()
+    r = oracle.score(scene, [], cands[:1], ig=ig, threads=th)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "views/s", "cores": th, "kind": "oracle",
+            "sample": f"1 candidate view ({cands[0].width}x{cands[0].height}, {scene.n} Gaussians, k={scene.k}, "
+                      f"object-centric), H_T = lambda I, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched640")
+    ap.add_argument("--views", type=int, default=None, help="limit candidate views per step")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (for scaling rocprofv3 FETCH/WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the scorer is not sharded across GPUs in this build "
+              "(views would be split across GPUs with one all-gather of the scores).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2602_08266_amd import binding as B
+
+    torch.cuda.set_device(0)
+    cfg, scene, cands, train = scenegen.make_workload(args.workload, args.seed, n_views=args.views)
+    V = len(cands)
+    ctx = B.Context(0)
+    ds = B.DeviceScene(scene, "cuda:0")
+    rp = B.raster_params()
+    ig = B.ig_params(target_id=scene.target)
+    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=48 << 20, max_slots=1 << 16, store_capacity=1 << 17)
+    cam_c = [B.camera(c) for c in cands]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norm = scorer.setup([B.camera(c) for c in train])
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    stats = torch.zeros(6, dtype=torch.int64, device="cuda:0")
+    for _ in range(args.warmup):
+        scorer.score(cam_c, stats)
+    torch.cuda.synchronize()
+    stats.zero_()
+    if not args.no_profile:
+        B.ngs_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        scores, best, raw = scorer.score(cam_c, stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = B.ngs_profile_read(ctx) if not args.no_profile else {}
+    B.ngs_profile_enable(ctx, False)
+    st = stats.cpu().numpy()
+    K = args.steps
+    ms_per_step = dt * 1e3 / K
+    value = V * K / dt
+    # per step counts (the score call overwrites stats[0..1] with its own views and pairs)
+    M_step = int(st[1])
+    W_step = int(st[4]) / K
+    roofline = None
+    if prof:
+        timed = {k: v for k, v in prof.items() if v[1] > 0}
+        dom = max(timed, key=lambda k: timed[k][0])
+        ms_tot, launches = timed[dom]
+        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step)
+        if alg is not None:
+            per_launch = alg / (launches / K)
+            avg_s = ms_tot / launches / 1e3
+            achieved = per_launch / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, args.workload),
+                        "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+                        "algorithmic_bytes_per_launch": int(per_launch)}
+        else:
+            roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                        "traffic": None, "kernel": dom, "avg_launch_us": round(ms_tot / launches * 1e3, 2)}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "views/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {scene.n} Gaussians, {cfg.clusters} clusters, k={scene.k}, "
+                               f"{V} candidate views at {cands[0].width}x{cands[0].height}, object-centric target "
+                               f"{scene.target}, radius U{list(cfg.radius)} m, 4 training views",
+                   "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact"},
+        "roofline": roofline,
+        "setup_ms": round(setup_ms, 1),
+        "pairs_per_view": M_step / V, "walked_entries_per_view": W_step / V,
+        "contrib_pairs_per_view": int(st[3]) / K / V, "touched_weighted_per_view": int(st[2]) / K / V,
+        "best_view": int(best.item()), "normalisers": [float(x) for x in norm],
+        "kernels_ms_per_step": {k: round(v[0] / K, 3) for k, v in sorted(prof.items(), key=lambda x: -x[1][0])
+                                if v[1] > 0},
+        "surrogate": None,
+    }
+    if not args.no_cpu_baseline:
+        sys.stderr.write("timing the CPU oracle on one view...\n")
+        sys.stderr.flush()
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

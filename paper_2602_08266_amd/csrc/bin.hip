@@ -81,24 +81,47 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
   }
 }
 
-// Emission in depth order: entry r of the depth-sorted Gaussians writes its rect's tiles
-// row by row at offsets[r].
-__global__ __launch_bounds__(256) void k_emit(int n, const uint32_t* __restrict__ order,
-                                              const uint64_t* __restrict__ offsets,
-                                              const uint32_t* __restrict__ count, const int16_t* __restrict__ rect,
-                                              int tiles_x, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t g = order[r];
-  if (count[g] == 0) return;
-  const int x0 = rect[g], y0 = rect[n + g], x1 = rect[2 * n + g], y1 = rect[3 * n + g];
-  uint64_t o = offsets[r];
-  for (int ty = y0; ty <= y1; ++ty)
-    for (int tx = x0; tx <= x1; ++tx) {
-      tkey[o] = (uint32_t)(ty * tiles_x + tx);
-      tval[o] = g;
-      ++o;
+// Emission in depth order. A block owns 256 consecutive depth ranks and the contiguous
+// output range [offsets[r0], offsets[r0 + 256]); its lanes stride over that range, so the
+// writes are coalesced and a Gaussian with a huge rect is expanded by the whole block. Each
+// output finds its Gaussian by binary search over the block's offsets in LDS; a Gaussian's
+// tiles go row by row.
+constexpr int kEmitRanks = 256;
+
+__global__ __launch_bounds__(kEmitRanks) void k_emit(int n, const uint32_t* __restrict__ order,
+                                                     const uint64_t* __restrict__ offsets,
+                                                     const int16_t* __restrict__ rect, int tiles_x,
+                                                     uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval) {
+  __shared__ uint64_t s_off[kEmitRanks + 1];
+  __shared__ uint32_t s_gid[kEmitRanks];
+  __shared__ int32_t s_x0[kEmitRanks], s_y0[kEmitRanks], s_w[kEmitRanks];
+  const int r0 = blockIdx.x * kEmitRanks;
+  const int cnt = min(kEmitRanks, n - r0);
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const uint32_t g = order[r0 + t];
+    s_gid[t] = g;
+    s_x0[t] = rect[g];
+    s_y0[t] = rect[n + g];
+    s_w[t] = rect[2 * n + g] - rect[g] + 1;
+    s_off[t] = offsets[r0 + t];
+  }
+  if (t == 0) s_off[cnt] = offsets[r0 + cnt];
+  __syncthreads();
+  const uint64_t beg = s_off[0], end = s_off[cnt];
+  for (uint64_t p = beg + t; p < end; p += kEmitRanks) {
+    // largest i with s_off[i] <= p (entries with zero tiles are skipped by the search)
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= p) lo = mid; else hi = mid;
     }
+    const uint32_t j = (uint32_t)(p - s_off[lo]);
+    const uint32_t w = (uint32_t)s_w[lo];
+    const uint32_t ty = (uint32_t)s_y0[lo] + j / w, tx = (uint32_t)s_x0[lo] + j % w;
+    tkey[p] = ty * (uint32_t)tiles_x + tx;
+    tval[p] = s_gid[lo];
+  }
 }
 
 // Per-tile [start, end) over the tile-sorted pairs. An empty tile gets start = end = the
@@ -215,7 +238,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, i
   if (m == 0) return hipSuccess;
   {
     ProfScope ps(kProfEmit, st);
-    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, n, order, w.offsets, p.count, p.rect,
+    hipLaunchKernelGGL(k_emit, dim3((n + kEmitRanks - 1) / kEmitRanks), dim3(kEmitRanks), 0, st, n, order, w.offsets, p.rect,
                        cam.tiles_x, ek, ev);
   }
   uint32_t *ko, *vo;

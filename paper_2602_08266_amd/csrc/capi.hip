@@ -10,10 +10,6 @@
 struct ngs_ctx {
   int device = 0;
   int32_t last_hip = 0;
-  // IG workspace known to be in its resting state (accumulators zero, no slot assigned)
-  const void* ig_ready_ptr = nullptr;
-  size_t ig_ready_bytes = 0;
-  int64_t ig_ready_n = -1, ig_ready_k = -1;
   int64_t* pinned = nullptr;  // host-pinned scratch for reading device counters
 };
 
@@ -91,14 +87,7 @@ ngs_status ig_prepare(ngs_ctx* ctx, void* ws, size_t ws_bytes, int64_t n, int64_
   if (slots < 1) return NGS_WORKSPACE_TOO_SMALL;
   *sticky = static_cast<int32_t*>(ws);
   *w = ig_ws_carve(static_cast<char*>(ws) + kIgHeader, n, k, slots);
-  if (ctx->ig_ready_ptr != ws || ctx->ig_ready_bytes != ws_bytes || ctx->ig_ready_n != n || ctx->ig_ready_k != k) {
-    NGS_TRY_HIP(ctx, ig_reset(*w, (int)n, (int)k, st));
-    NGS_TRY_HIP(ctx, hipMemsetAsync(*sticky, 0, kIgHeader, st));
-    ctx->ig_ready_ptr = ws;
-    ctx->ig_ready_bytes = ws_bytes;
-    ctx->ig_ready_n = n;
-    ctx->ig_ready_k = k;
-  }
+  NGS_TRY_HIP(ctx, hipMemsetAsync(*sticky, 0, kIgHeader, st));
   return NGS_OK;
 }
 

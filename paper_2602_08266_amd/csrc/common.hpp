@@ -149,7 +149,7 @@ struct IgWs {
 };
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
-hipError_t ig_reset(const IgWs& w, int n, int k, hipStream_t st);
+hipError_t ig_reset(const IgWs& w, int n, hipStream_t st);
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
                            const IgWs& w, int64_t* stats, hipStream_t st);

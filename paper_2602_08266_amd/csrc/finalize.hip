@@ -211,16 +211,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
     __syncthreads();
     const int g = gid_of[slot];
-    for (int s = threadIdx.x; s < nst; s += kFinThreads) {
-      float* ap = &acc[(size_t)s * stride + slot];
-      S.st[s] = (double)*ap;
-      *ap = 0.f;
-    }
-    __syncthreads();
-    if (g < 0) continue;
+    if (g < 0) continue;  // a slot left unused by a lost publication race
+    for (int s = threadIdx.x; s < nst; s += kFinThreads) S.st[s] = (double)acc[(size_t)s * stride + slot];
     if (threadIdx.x == 0) {
-      slot_of[g] = -1;
-      gid_of[slot] = -1;
       chain_rule(mean, log_scale, rot, n, g, cam, eps2d, S.P);
       S.hs = has_h ? h.slot_of[g] : -1;
       S.hs_new = 0;

@@ -41,6 +41,7 @@ struct IgShared {
   static constexpr int kRow = (kRecScalar + kCh) | 1;  // odd stride: conflict-free column reads
   float rec[kTilePix / kWave][kWave][kRow];
   int red_i[kTilePix / kWave];
+  int red_new[kTilePix / kWave];
   int flag;
 };
 
@@ -197,25 +198,38 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
         rec[13] = a * Tg; rec[14] = 1.f; rec[15] = wd * wd;
         rec[16] = ao * y0; rec[17] = ao * y1; rec[18] = ao * y2; rec[19] = ao * y3; rec[20] = ao * y4;
         rec[21] = ao * y5;
-        // slot of this Gaussian in the per-view accumulator
+        // Slot of this Gaussian in the per-view accumulator. A new slot is taken from the
+        // counter, zeroed by the whole wavefront, and only then published in slot_of with a
+        // compare-and-swap (a wavefront that loses the race leaves its zeroed slot unused,
+        // marked by gid_of = -1); every later update of a published slot is an atomic add.
+        const uint32_t gq = S.gid[j];
         if (lane == 0) {
-          const uint32_t g = S.gid[j];
-          int s = __atomic_load_n(&slot_of[g], __ATOMIC_RELAXED);
+          int s = __atomic_load_n(&slot_of[gq], __ATOMIC_RELAXED);
+          int fresh = -1;
           if (s < 0) {
             const int ns = atomicAdd(n_slots, 1);
-            if (ns >= max_slots) {
-              atomicOr(overflow, 1);
-              s = -1;
-            } else {
-              const int old = atomicCAS(&slot_of[g], -1, ns);
-              if (old == -1) { gid_of[ns] = (int)g; s = ns; } else { s = old; }
-            }
+            if (ns >= max_slots) atomicOr(overflow, 1); else fresh = ns;
           }
           S.red_i[wave] = s;
+          S.red_new[wave] = fresh;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int fresh = S.red_new[wave];
+        if (fresh >= 0) {
+          for (int s = lane; s < stat_len(k); s += kWave) acc[(size_t)s * stride + fresh] = 0.f;
+          __threadfence();
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) {
+            const int old = atomicCAS(&slot_of[gq], -1, fresh);
+            gid_of[fresh] = (old == -1) ? (int)gq : -1;
+            S.red_i[wave] = (old == -1) ? fresh : old;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         const int slot = S.red_i[wave];
         if (slot >= 0) {
           const float* rows = &S.rec[wave][0][0];
@@ -341,21 +355,17 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   return w;
 }
 
-// Brings a workspace to its resting state: accumulators zero, no slot assigned. The
-// finalize kernel restores this state after every view, so this is needed only once per
-// workspace.
-hipError_t ig_reset(const IgWs& w, int n, int k, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(w.acc, 0, (size_t)stat_len(k) * (size_t)w.max_slots * 4, st);
-  if (e != hipSuccess) return e;
-  e = launch_fill_i32(w.slot_of, -1, (size_t)std::max(n, 1), st);
-  if (e != hipSuccess) return e;
-  return launch_fill_i32(w.gid_of, -1, (size_t)w.max_slots, st);
+// Per-view reset: no Gaussian holds a slot. Accumulator slots are zeroed when taken.
+hipError_t ig_reset(const IgWs& w, int n, hipStream_t st) {
+  return launch_fill_i32(w.slot_of, -1, (size_t)std::max(n, 1), st);
 }
 
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats,
                            hipStream_t st) {
   hipError_t e = upload_stat_table();
+  if (e != hipSuccess) return e;
+  e = ig_reset(w, s.n, st);
   if (e != hipSuccess) return e;
   {
     ProfScope ps(kProfFill, st);

@@ -72,26 +72,44 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
                                                           const uint32_t* __restrict__ hist, size_t nblocks,
                                                           const uint32_t* __restrict__ rowtot,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  // The block's 4096 pairs are first ranked into digit order in LDS (stable), then streamed
+  // out: consecutive lanes write consecutive positions of each digit's run.
   __shared__ uint32_t sm[kSortThreads];
-  __shared__ uint32_t base[kRadix];            // global start of each digit for this block
+  __shared__ uint32_t gbase[kRadix];           // global position of this block's first key of digit d
+  __shared__ uint32_t lstart[kRadix];          // local position of the first key of digit d
+  __shared__ uint32_t lrun[kRadix];            // local running position of digit d
   __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+  __shared__ uint32_t sk[kSortTileElems], sv[kSortTileElems];
   const int t = threadIdx.x;
   const int wave = t / kWave;
   const int lane = t % kWave;
+  const size_t blk = (size_t)blockIdx.x * kSortTileElems;
+  const int cnt = (int)min((size_t)kSortTileElems, n - blk);
+  uint32_t keys[kSortItems], vals[kSortItems];
+  wcnt[0][t] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int li = j * kSortThreads + t;
+    keys[j] = li < cnt ? kin[blk + li] : 0u;
+    vals[j] = li < cnt ? vin[blk + li] : 0u;
+    if (li < cnt) atomicAdd(&wcnt[0][(keys[j] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
   {
     uint32_t tot;
+    const uint32_t local = block_exclusive_scan(wcnt[0][t], sm, &tot);
+    lstart[t] = local;
+    lrun[t] = local;
     const uint32_t digit_start = block_exclusive_scan(rowtot[t], sm, &tot);
-    base[t] = digit_start + hist[(size_t)t * nblocks + blockIdx.x];
+    gbase[t] = digit_start + hist[(size_t)t * nblocks + blockIdx.x];
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const size_t blk = (size_t)blockIdx.x * kSortTileElems;
+#pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const size_t i = blk + (size_t)j * kSortThreads + t;
-    const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const bool valid = j * kSortThreads + t < cnt;
+    const uint32_t d = (keys[j] >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -106,21 +124,28 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
     if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     {
-      uint32_t run = base[t];
+      uint32_t run = lrun[t];
       for (int w = 0; w < kWavesPerBlock; ++w) {
         const uint32_t c = wcnt[w][t];
         wcnt[w][t] = run;
         run += c;
       }
-      base[t] = run;
+      lrun[t] = run;
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = wcnt[wave][d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      const uint32_t lp = wcnt[wave][d] + rank;
+      sk[lp] = keys[j];
+      sv[lp] = vals[j];
     }
     __syncthreads();
+  }
+  for (int i = t; i < cnt; i += kSortThreads) {
+    const uint32_t key = sk[i];
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t pos = gbase[d] + ((uint32_t)i - lstart[d]);
+    kout[pos] = key;
+    vout[pos] = sv[i];
   }
 }
 

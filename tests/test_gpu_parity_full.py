@@ -1,0 +1,98 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
+
+Keys, lists and images are compared with the oracle run live (projection, sort and
+rendering are fast in the oracle); information gains are compared with FP64 oracle values
+stored by tests/golden/make_golden.py (the oracle needs 10-30 s per view at these sizes).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from parity_util import check_gain, check_image
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_08266_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0)
+
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        _cache[name] = scenegen.make_workload(name, 0)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name,view", [("mid", 0), ("batched640", 17)])
+def test_lists_and_render_full_size(B, ctx, name, view):
+    log(f"full-size lists + render: {name} view {view}")
+    cfg, scene, cands, train = workload(name)
+    cam = cands[view]
+    ds = B.DeviceScene(scene, "cuda")
+    B.ngs_prepare_scene(ctx, ds, B.ig_params(target_id=scene.target))
+    rp = B.raster_params()
+    c = B.camera(cam)
+    pr = B.ngs_project(ctx, ds, c, rp)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=48 << 20)
+    m = int(lists.n_pairs.item())
+    ref = oracle.tile_lists(scene, cam)
+    log(f"  pairs {m}")
+    assert m == ref["m"]
+    assert np.array_equal(lists.gids[:m].cpu().numpy().view(np.uint32), ref["gids"])
+    assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+    del ref
+    img = B.ngs_render(ctx, ds, pr, lists, c, rp, want_obj=False)
+    img = {k: (v.cpu().numpy() if v is not None else None) for k, v in img.items()}
+    rimg = oracle.render(scene, cam)
+    st = check_image(img, rimg, scene.k, depth_max=1.5)
+    log(f"  {st}")
+
+
+@pytest.mark.parametrize("name", ["mid", "batched640"])
+def test_information_gain_full_size(B, ctx, name):
+    gold = json.load(open(os.path.join(HERE, "golden", f"ig_{name}_seed0.json")))
+    log(f"full-size IG: {name} views {gold['views']}")
+    cfg, scene, cands, train = workload(name)
+    assert scene.target == gold["target_id"]
+    ds = B.DeviceScene(scene, "cuda")
+    ig = B.ig_params(target_id=scene.target)
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=48 << 20, max_slots=1 << 16,
+                         store_capacity=1 << 17)
+    norm = scorer.setup([B.camera(c) for c in train])
+    check_gain(norm, gold["norm"], "normalisers")
+    for t in range(len(train)):
+        check_gain(scorer.ig_train[t], gold["ig_train"][t], f"train {t}")
+    scores, best, raw = scorer.score([B.camera(cands[v]) for v in gold["views"]])
+    raw = raw.cpu().numpy()
+    for i, v in enumerate(gold["views"]):
+        r = check_gain(raw[i], gold["ig_cand"][i], f"view {v}")
+        log(f"  view {v}: gpu {raw[i]} oracle {gold['ig_cand'][i]} rel {r:.2e}")
+    assert np.allclose(scores.cpu().numpy(), gold["scores"], rtol=2e-3)
+    top = np.sort(np.array(gold["scores"])[:, 3])
+    if (top[-1] - top[-2]) / abs(top[-1]) > 1e-3:
+        assert int(best.item()) == gold["best_of_views"]
