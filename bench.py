@@ -45,14 +45,10 @@ def algorithmic_bytes(name, n, k, V, M, W):
         return V * 4 * n * 4
     if name == "count_scan":
         return V * n * 16
-    if name == "emit_pairs":
-        return 8 * M + V * n * 24
-    if name == "tile_sort_scatter":
-        return 2 * 16 * M                        # two 8-bit tile-digit passes (<= 4096 tiles)
-    if name == "tile_sort_hist":
-        return 2 * 4 * M
-    if name == "tile_ranges":
-        return 4 * M
+    if name == "tile_part_hist":
+        return V * n * 24                        # rank order, offsets, rects of every Gaussian
+    if name == "tile_part_scatter":
+        return 4 * M + V * n * 24                # final gid per pair + the same per-Gaussian reads
     if name == "ig_tiles":
         return W * (4 + 24)                      # list entry + projected geometry per walked entry
     return None
@@ -61,8 +57,7 @@ def algorithmic_bytes(name, n, k, V, M, W):
 KERNEL_FILES = {
     "project": ["project.hip", "common.hpp"], "depth_sort_scatter": ["sort.hip", "common.hpp"],
     "depth_sort_hist": ["sort.hip", "common.hpp"], "count_scan": ["bin.hip", "common.hpp"],
-    "emit_pairs": ["bin.hip", "common.hpp"], "tile_sort_scatter": ["sort.hip", "common.hpp"],
-    "tile_sort_hist": ["sort.hip", "common.hpp"], "tile_ranges": ["bin.hip", "common.hpp"],
+    "tile_part_hist": ["bin.hip", "common.hpp"], "tile_part_scatter": ["bin.hip", "common.hpp"],
     "ig_tiles": ["info_gain.hip", "common.hpp"], "ig_finalize": ["finalize.hip", "common.hpp"],
 }
 
@@ -165,8 +160,8 @@ def main():
     K = args.steps
     ms_per_step = dt * 1e3 / K
     value = V * K / dt
-    # per step counts (the score call overwrites stats[0..1] with its own views and pairs)
-    M_step = int(st[1])
+    # per step counts (stats accumulate over the timed calls)
+    M_step = int(st[1]) / K
     W_step = int(st[4]) / K
     roofline = None
     if prof:

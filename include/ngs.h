@@ -229,15 +229,15 @@ ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream);
  * the mean training-view gains), Eq. 11 combination and argmax (Eq. 5, lowest index on
  * ties). scores [n_views][4] device FP32: normalised rgb, depth, object, combined.
  * best: device int32. ig_raw [n_views][3] device FP64 receives the raw gains IG_f.
- * stats (device int64 [NGS_STATS_LEN], may be NULL) accumulates; on return stats[0] =
- * views and stats[1] = total pairs. Returns NGS_DEGENERATE if an enabled normaliser is
- * not positive, NGS_CAPACITY if a view overflows the workspace. ws:
- * ngs_workspace_size(2, ...) sized for the largest view; syncs once per view. */
+ * stats (device int64 [NGS_STATS_LEN], may be NULL) accumulates (stats[1]: pairs of all
+ * views); on return stats[0] = n_views. Returns NGS_DEGENERATE if an enabled normaliser is
+ * not positive, NGS_CAPACITY if a view overflows dims->max_pairs or dims->max_slots. ws:
+ * ngs_workspace_size(2, dims) bytes, carved by the same dims (host); syncs once per batch. */
 ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
                            const double* normalisers, const ngs_camera* cams, int32_t n_views,
                            const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores,
-                           int32_t* best, double* ig_raw, int64_t* stats, void* ws,
-                           size_t ws_bytes, void* stream);
+                           int32_t* best, double* ig_raw, int64_t* stats, const ngs_dims* dims,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* Optional kernel timing: while enabled, every kernel the library launches is bracketed
  * by two hipEvents recorded on its launch stream. ngs_profile_read synchronises the

@@ -108,7 +108,7 @@ def lib():
         L.ngs_info_gain.argtypes = [P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_hessian_reset.argtypes = [P, P, i32, P]
         L.ngs_hessian_finalize.argtypes = [P, P, P]
-        L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_render_backward.argtypes = [P] * 10
         L.ngs_profile_enable.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
@@ -356,8 +356,17 @@ def ngs_hessian_finalize(ctx: Context, h: Hessian):
     _check("ngs_hessian_finalize", lib().ngs_hessian_finalize(ctx.handle, _ref(hc), _stream()), ctx)
 
 
+class ScoreWorkspace:
+    """Scratch of ngs_score_batch and the dims it was sized (and is carved) with."""
+
+    def __init__(self, scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16):
+        self.dims = ngs_dims(scene.n, scene.k, 0, 0, max_pairs, max_slots)
+        self.buf = _bytes(workspace_size(2, scene.n, scene.k, max_pairs=max_pairs, max_slots=max_slots),
+                          scene.device)
+
+
 def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], normalisers: Sequence[float],
-                    cams: Sequence[ngs_camera], rp: ngs_raster_params, ig: ngs_ig_params, ws: torch.Tensor,
+                    cams: Sequence[ngs_camera], rp: ngs_raster_params, ig: ngs_ig_params, ws: ScoreWorkspace,
                     stats: Optional[torch.Tensor] = None):
     nv = len(cams)
     dev = scene.device
@@ -370,12 +379,13 @@ def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], norm
     hc = h.c() if h is not None else None
     _check("ngs_score_batch", lib().ngs_score_batch(ctx.handle, _ref(sc), _ref(hc) if hc is not None else None,
                                                     norm, arr, nv, _ref(rp), _ref(ig), _p(scores), _p(best),
-                                                    _p(ig_raw), _p(stats), _p(ws), ws.numel(), _stream()), ctx)
+                                                    _p(ig_raw), _p(stats), _ref(ws.dims), _p(ws.buf), ws.buf.numel(),
+                                                    _stream()), ctx)
     return scores[:nv], best, ig_raw[:nv]
 
 
-def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16) -> torch.Tensor:
-    return _bytes(workspace_size(2, scene.n, scene.k, max_pairs=max_pairs, max_slots=max_slots), scene.device)
+def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16) -> ScoreWorkspace:
+    return ScoreWorkspace(scene, max_pairs, max_slots)
 
 
 def ngs_profile_enable(ctx: Context, on: bool):

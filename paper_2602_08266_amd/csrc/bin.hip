@@ -4,9 +4,13 @@
 // two stages, because all pairs of one Gaussian share its depth bits:
 //   1. depth digits: the n Gaussians are sorted by their 32-bit depth key (4 passes over n
 //      entries instead of over the M >> n pairs); gid order breaks ties (stable LSD);
-//   2. the pairs are emitted in that depth order and a stable pass on the tile digits
-//      (ceil(log2 tiles) bits) groups them by tile without disturbing the depth order.
-// The result equals a sort of (tile << 32 | depth bits) with ties broken by gid.
+//   2. one stable counting pass on the tile digit (<= 12 bits) over the pairs, fused with
+//      their generation: each single-wavefront block expands the rects of 256 consecutive
+//      depth ranks, counts its pairs per tile (pass a), and after a scan over blocks and
+//      tiles (pass b) writes each pair's gid at its final position (pass c), ranking lanes
+//      that share a tile with ballot match masks so the depth order survives.
+// The result equals a sort of (tile << 32 | depth bits) with ties broken by gid; the
+// per-tile ranges fall out of the scan, and no pair array other than the output is written.
 #include "common.hpp"
 
 namespace ngs {
@@ -81,100 +85,204 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
   }
 }
 
-// Emission in depth order. A block owns 256 consecutive depth ranks and the contiguous
-// output range [offsets[r0], offsets[r0 + 256]); its lanes stride over that range, so the
-// writes are coalesced and a Gaussian with a huge rect is expanded by the whole block. Each
-// output finds its Gaussian by binary search over the block's offsets in LDS; a Gaussian's
-// tiles go row by row.
-constexpr int kEmitRanks = 256;
+constexpr int kPartRanks = 256;  // depth ranks per partition block (one wavefront)
+constexpr int kTileBits = 12;    // NGS_MAX_TILES = 4096
 
-__global__ __launch_bounds__(kEmitRanks) void k_emit(int n, const uint32_t* __restrict__ order,
-                                                     const uint64_t* __restrict__ offsets,
-                                                     const int16_t* __restrict__ rect, int tiles_x,
-                                                     uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval) {
-  __shared__ uint64_t s_off[kEmitRanks + 1];
-  __shared__ uint32_t s_gid[kEmitRanks];
-  __shared__ int32_t s_x0[kEmitRanks], s_y0[kEmitRanks], s_w[kEmitRanks];
-  const int r0 = blockIdx.x * kEmitRanks;
-  const int cnt = min(kEmitRanks, n - r0);
-  const int t = threadIdx.x;
-  if (t < cnt) {
+// The block's ranks, their pair offsets and rect geometry in LDS; returns the pair count.
+struct PartShared {
+  uint64_t off[kPartRanks + 1];
+  uint32_t gid[kPartRanks];
+  int32_t x0[kPartRanks], y0[kPartRanks], w[kPartRanks];
+  uint32_t cnt[NGS_MAX_TILES];
+};
+
+__device__ __forceinline__ int part_load(PartShared& S, int n, const uint32_t* __restrict__ order,
+                                         const uint64_t* __restrict__ offsets, const int16_t* __restrict__ rect) {
+  const int r0 = blockIdx.x * kPartRanks;
+  const int cnt = min(kPartRanks, n - r0);
+  for (int t = threadIdx.x; t < cnt; t += kWave) {
     const uint32_t g = order[r0 + t];
-    s_gid[t] = g;
-    s_x0[t] = rect[g];
-    s_y0[t] = rect[n + g];
-    s_w[t] = rect[2 * n + g] - rect[g] + 1;
-    s_off[t] = offsets[r0 + t];
+    S.gid[t] = g;
+    S.x0[t] = rect[g];
+    S.y0[t] = rect[n + g];
+    S.w[t] = rect[2 * n + g] - rect[g] + 1;
+    S.off[t] = offsets[r0 + t];
   }
-  if (t == 0) s_off[cnt] = offsets[r0 + cnt];
+  if (threadIdx.x == 0) S.off[cnt] = offsets[r0 + cnt];
+  return cnt;
+}
+
+// Pair p of the block -> its Gaussian (largest i with off[i] <= p) and tile; rects are
+// expanded row by row.
+__device__ __forceinline__ uint32_t part_pair(const PartShared& S, int cnt, uint64_t p, int tiles_x, uint32_t* gid) {
+  int lo = 0, hi = cnt;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S.off[mid] <= p) lo = mid; else hi = mid;
+  }
+  const uint32_t j = (uint32_t)(p - S.off[lo]);
+  const uint32_t w = (uint32_t)S.w[lo];
+  *gid = S.gid[lo];
+  return ((uint32_t)S.y0[lo] + j / w) * (uint32_t)tiles_x + (uint32_t)S.x0[lo] + j % w;
+}
+
+// Pass a: pairs per (tile, block), written tile-major: hist[t * nblk + block].
+__global__ __launch_bounds__(kWave) void k_part_hist(int n, const uint32_t* __restrict__ order,
+                                                     const uint64_t* __restrict__ offsets,
+                                                     const int16_t* __restrict__ rect, int tiles_x, int ntiles,
+                                                     uint32_t* __restrict__ hist, int nblk) {
+  __shared__ PartShared S;
+  for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = 0u;
+  const int cnt = part_load(S, n, order, offsets, rect);
   __syncthreads();
-  const uint64_t beg = s_off[0], end = s_off[cnt];
-  for (uint64_t p = beg + t; p < end; p += kEmitRanks) {
-    // largest i with s_off[i] <= p (entries with zero tiles are skipped by the search)
-    int lo = 0, hi = cnt;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= p) lo = mid; else hi = mid;
+  const uint64_t beg = S.off[0], end = S.off[cnt];
+  for (uint64_t p = beg + threadIdx.x; p < end; p += kWave) {
+    uint32_t g;
+    atomicAdd(&S.cnt[part_pair(S, cnt, p, tiles_x, &g)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += kWave) hist[(size_t)t * nblk + blockIdx.x] = S.cnt[t];
+}
+
+// Pass b1: per tile, exclusive scan of its counts across blocks (in place); totals.
+__global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ hist, int nblk,
+                                                        uint32_t* __restrict__ tot) {
+  __shared__ uint32_t sm[256];
+  uint32_t* row = hist + (size_t)blockIdx.x * nblk;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    const int i = b0 + threadIdx.x;
+    const uint32_t v = (i < nblk) ? row[i] : 0u;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t add = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sm[threadIdx.x] += add;
+      __syncthreads();
     }
-    const uint32_t j = (uint32_t)(p - s_off[lo]);
-    const uint32_t w = (uint32_t)s_w[lo];
-    const uint32_t ty = (uint32_t)s_y0[lo] + j / w, tx = (uint32_t)s_x0[lo] + j % w;
-    tkey[p] = ty * (uint32_t)tiles_x + tx;
-    tval[p] = s_gid[lo];
+    if (i < nblk) row[i] = carry + sm[threadIdx.x] - v;
+    carry += sm[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Pass b2: tile starts (exclusive scan of the totals) -> ranges; an empty tile gets
+// start = end = the number of pairs in lower tiles. If the pairs exceed the list capacity,
+// every range is left empty and *overflow is raised (the scatter then writes nothing).
+__global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict__ tot, int ntiles,
+                                                     uint32_t* __restrict__ ranges, int64_t capacity,
+                                                     int32_t* __restrict__ overflow, int64_t* __restrict__ stats) {
+  __shared__ uint32_t sm[256];
+  constexpr int kPer = NGS_MAX_TILES / 256;
+  const int t0 = threadIdx.x * kPer;
+  uint32_t v[kPer];
+  uint32_t run = 0;
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = run;
+    run += (t0 + j < ntiles) ? tot[t0 + j] : 0u;
+  }
+  sm[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sm[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint32_t total = sm[255];
+  const bool over = (int64_t)total > capacity;
+  const uint32_t excl = sm[threadIdx.x] - run;
+  for (int j = 0; j < kPer; ++j)
+    if (t0 + j < ntiles) {
+      ranges[t0 + j] = over ? 0u : excl + v[j];
+      ranges[ntiles + t0 + j] = over ? 0u : excl + v[j] + tot[t0 + j];
+    }
+  if (threadIdx.x == 0) {
+    if (over && overflow) atomicOr(overflow, 1);
+    if (stats) atomicAdd((unsigned long long*)&stats[1], (unsigned long long)total);
   }
 }
 
-// Per-tile [start, end) over the tile-sorted pairs. An empty tile gets start = end = the
-// number of pairs in lower tiles; each gap between two present tiles is filled by the
-// thread that sees the second one.
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, int64_t m,
-                                                uint32_t* __restrict__ ranges, int ntiles) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint32_t t = tkey[i];
-  if (i == 0 || tkey[i - 1] != t) {
-    ranges[t] = (uint32_t)i;
-    const uint32_t prev = (i == 0) ? 0u : tkey[i - 1] + 1u;
-    for (uint32_t u = prev; u < t; ++u) { ranges[u] = (uint32_t)i; ranges[ntiles + u] = (uint32_t)i; }
-  }
-  if (i == m - 1 || tkey[i + 1] != t) {
-    ranges[ntiles + t] = (uint32_t)(i + 1);
-    if (i == m - 1)
-      for (int u = (int)t + 1; u < ntiles; ++u) { ranges[u] = (uint32_t)m; ranges[ntiles + u] = (uint32_t)m; }
+// Pass c: every pair goes to ranges[tile] + (pairs of lower blocks for the tile) + (earlier
+// pairs of this block for the tile). Pairs are generated in depth-rank order, 64 per round;
+// lanes of a round that share a tile are ranked by a 12-ballot match mask and the lowest of
+// them advances the tile's running position, so equal tiles keep the depth order.
+__global__ __launch_bounds__(kWave) void k_part_scatter(int n, const uint32_t* __restrict__ order,
+                                                        const uint64_t* __restrict__ offsets,
+                                                        const int16_t* __restrict__ rect, int tiles_x, int ntiles,
+                                                        const uint32_t* __restrict__ hist, int nblk,
+                                                        const uint32_t* __restrict__ ranges, int64_t capacity,
+                                                        uint32_t* __restrict__ gids_out) {
+  __shared__ PartShared S;
+  const int cnt = part_load(S, n, order, offsets, rect);
+  for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = ranges[t] + hist[(size_t)t * nblk + blockIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t beg = S.off[0], end = S.off[cnt];
+  for (uint64_t p0 = beg; p0 < end; p0 += kWave) {
+    const uint64_t p = p0 + lane;
+    const bool valid = p < end;
+    uint32_t g = 0, t = 0;
+    if (valid) t = part_pair(S, cnt, p, tiles_x, &g);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kTileBits; ++b) {
+      const bool bit = (t >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t base = valid ? S.cnt[t] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lt_mask) == 0ull) S.cnt[t] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (valid && (int64_t)(base + rank) < capacity) gids_out[base + rank] = g;
   }
 }
 
-__global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ gids,
-                                                const uint32_t* __restrict__ zkey, int64_t m,
+// keys (tile << 32 | depth bits) of the sorted pairs: one block per tile.
+__global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ ranges, int ntiles,
+                                                const uint32_t* __restrict__ gids, const uint32_t* __restrict__ zkey,
                                                 uint64_t* __restrict__ keys) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  keys[i] = ((uint64_t)tkey[i] << 32) | (uint64_t)zkey[gids[i]];
+  const uint32_t t = blockIdx.x;
+  for (uint32_t i = ranges[t] + threadIdx.x; i < ranges[ntiles + t]; i += blockDim.x)
+    keys[i] = ((uint64_t)t << 32) | (uint64_t)zkey[gids[i]];
 }
 
 }  // namespace
 
 // Workspace layout (all 256-byte aligned):
-//   dkeys[2], dvals[2]: u32 [n]        depth-sort ping-pong
-//   offsets: u64 [n + 1], blocksum: u64 [ceil(n / 1024)]
-//   tkeys[2]: u32 [max_pairs], tvals: u32 [max_pairs]
-//   hist: u32 [256][blocks(max(n, max_pairs))], rowtot: u32 [256]
+//   dkeys[2], dvals[2]: u32 [n]          depth-sort ping-pong
+//   offsets: u64 [n + 1], blocksum: u64 [ceil(n / 1024) + 1]
+//   phist: u32 [4096][ceil(n / 256)]     pairs per (tile, partition block)
+//   ptot: u32 [4096]
+//   hist: u32 [256][blocks(n)], rowtot: u32 [256]   radix-sort scratch
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
-  const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
-  const size_t nb = sort_blocks_for(std::max(nn, mp));
+  (void)max_pairs;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  const size_t nb = sort_blocks_for(nn);
+  const size_t nblk = (nn + kPartRanks - 1) / kPartRanks;
   size_t b = 0;
   b += 4 * align_up(nn * 4, 256);
   b += align_up((nn + 1) * 8, 256);
   b += align_up(((nn + kScanTile - 1) / kScanTile + 1) * 8, 256);
-  b += 3 * align_up(mp * 4, 256);
+  b += align_up((size_t)NGS_MAX_TILES * nblk * 4, 256);
+  b += align_up((size_t)NGS_MAX_TILES * 4, 256);
   b += align_up(256 * nb * 4, 256);
   b += align_up(256 * 4, 256);
   return b;
 }
 
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
-  const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
-  const size_t nb = sort_blocks_for(std::max(nn, mp));
+  (void)max_pairs;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  const size_t nb = sort_blocks_for(nn);
+  const size_t nblk = (nn + kPartRanks - 1) / kPartRanks;
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += align_up(bytes, 256); return r; };
   BinWs w;
@@ -182,8 +290,8 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nn * 4);
   w.offsets = (uint64_t*)take((nn + 1) * 8);
   w.blocksum = (uint64_t*)take(((nn + kScanTile - 1) / kScanTile + 1) * 8);
-  for (int i = 0; i < 2; ++i) w.tkeys[i] = (uint32_t*)take(mp * 4);
-  w.tvals = (uint32_t*)take(mp * 4);
+  w.phist = (uint32_t*)take((size_t)NGS_MAX_TILES * nblk * 4);
+  w.ptot = (uint32_t*)take((size_t)NGS_MAX_TILES * 4);
   w.sort.hist = (uint32_t*)take(256 * nb * 4);
   w.sort.rowtot = (uint32_t*)take(256 * 4);
   w.sort.max_blocks = nb;
@@ -213,46 +321,33 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
   return e != hipSuccess ? e : hipGetLastError();
 }
 
-hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, int64_t m, const BinWs& w,
-                             const ngs_tile_lists& out, hipStream_t st) {
+hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
+                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
-  int bits = 1;
-  while ((1 << bits) < ntiles) ++bits;
-  const int passes = (bits + 7) / 8;
   const uint32_t* order = w.dvals[1];
-  // Choose where emission writes so that the last pass lands in out.gids.
-  uint32_t *ek, *ev, *ak, *av, *bk, *bv;
-  if (passes % 2 == 1) {
-    ek = w.tkeys[1]; ev = w.tvals;
-    ak = w.tkeys[0]; av = out.gids;
-    bk = w.tkeys[1]; bv = w.tvals;
-  } else {
-    ek = w.tkeys[1]; ev = out.gids;
-    ak = w.tkeys[0]; av = w.tvals;
-    bk = w.tkeys[1]; bv = out.gids;
-  }
-  hipError_t e = hipMemsetAsync(out.ranges, 0, sizeof(uint32_t) * 2 * (size_t)ntiles, st);
+  hipError_t e = hipMemcpyAsync(out.n_pairs, w.offsets + n, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(out.n_pairs, w.offsets + n, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return e;
-  if (m == 0) return hipSuccess;
+  if (n == 0) return hipMemsetAsync(out.ranges, 0, sizeof(uint32_t) * 2 * (size_t)ntiles, st);
+  const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
-    ProfScope ps(kProfEmit, st);
-    hipLaunchKernelGGL(k_emit, dim3((n + kEmitRanks - 1) / kEmitRanks), dim3(kEmitRanks), 0, st, n, order, w.offsets, p.rect,
-                       cam.tiles_x, ek, ev);
+    ProfScope ps(kProfTileHist, st);
+    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, w.offsets, p.rect, cam.tiles_x, ntiles,
+                       w.phist, nblk);
   }
-  uint32_t *ko, *vo;
-  e = radix_sort_pairs(ek, ev, ak, av, bk, bv, (size_t)m, 0, bits, w.sort, st, &ko, &vo, kProfTileHist);
-  if (e != hipSuccess) return e;
-  if (vo != out.gids) return hipErrorInvalidValue;
-  const unsigned gb = (unsigned)((m + 255) / 256);
   {
-    ProfScope ps(kProfRanges, st);
-    hipLaunchKernelGGL(k_ranges, dim3(gb), dim3(256), 0, st, ko, m, out.ranges, ntiles);
+    ProfScope ps(kProfTileScan, st);
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(ntiles), dim3(256), 0, st, w.phist, nblk, w.ptot);
+    hipLaunchKernelGGL(k_part_ranges, dim3(1), dim3(256), 0, st, w.ptot, ntiles, out.ranges, out.capacity, overflow,
+                       stats);
+  }
+  {
+    ProfScope ps(kProfTileScatter, st);
+    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, w.offsets, p.rect, cam.tiles_x, ntiles,
+                       w.phist, nblk, out.ranges, out.capacity, out.gids);
   }
   if (out.keys) {
     ProfScope ps(kProfKeys64, st);
-    hipLaunchKernelGGL(k_keys64, dim3(gb), dim3(256), 0, st, ko, out.gids, p.zkey, m, out.keys);
+    hipLaunchKernelGGL(k_keys64, dim3(ntiles), dim3(256), 0, st, out.ranges, ntiles, out.gids, p.zkey, out.keys);
   }
   return hipGetLastError();
 }

@@ -248,7 +248,7 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
     NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
     return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
   }
-  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, m, w, *out, st));
+  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, w, *out, nullptr, nullptr, st));
   return NGS_OK;
 }
 
@@ -326,8 +326,9 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
 ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
                            const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
                            const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw, int64_t* stats,
-                           void* ws, size_t ws_bytes, void* stream) {
-  if (!ctx || !normalisers || !cams || n_views < 0 || !scores || !best || !ig_raw) return NGS_INVALID_ARG;
+                           const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !normalisers || !cams || n_views < 0 || !scores || !best || !ig_raw || !dims) return NGS_INVALID_ARG;
+  if (dims->n != scene->n || dims->k != scene->k || dims->max_pairs < 1 || dims->max_slots < 1) return NGS_INVALID_ARG;
   ngs_status s = check_scene(scene, true);
   if (s == NGS_OK) s = check_ig(ig);
   if (s != NGS_OK) return s;
@@ -342,36 +343,25 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
   if (!ws) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  // the largest pair capacity that leaves room for at least one IG slot
-  int64_t max_pairs = 0;
-  {
-    int64_t lo = 0, hi = (int64_t)(ws_bytes / 20) + 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) / 2;
-      const size_t fixed = batch_fixed_bytes(scene->n, mid);
-      if (fixed < ws_bytes && ig_slots_for(ws_bytes - fixed, scene->n, scene->k) >= 1024) lo = mid; else hi = mid - 1;
-    }
-    max_pairs = lo;
-  }
-  if (max_pairs < 1) return NGS_WORKSPACE_TOO_SMALL;
-  BatchWs b = batch_carve(ws, ws_bytes, scene->n, max_pairs);
+  size_t need = 0;
+  s = ngs_workspace_size(2, dims, &need);
+  if (s != NGS_OK) return s;
+  if (ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
+  const int64_t max_pairs = dims->max_pairs;
+  BatchWs b = batch_carve(ws, need, scene->n, max_pairs);
   IgWs w;
   int32_t* sticky = nullptr;
   s = ig_prepare(ctx, b.ig, b.ig_bytes, scene->n, scene->k, st, &w, &sticky);
   if (s != NGS_OK) return s;
   NGS_TRY_HIP(ctx, hipMemsetAsync(ig_raw, 0, (size_t)3 * sizeof(double) * std::max(n_views, 1), st));
   const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
-  int64_t total_pairs = 0;
+  // No host synchronisation inside the loop: list overflow is caught on the device (empty
+  // ranges, sticky flag) and reported once the batch has run.
   for (int v = 0; v < n_views; ++v) {
     const DevCam dc = make_devcam(cams[v], kTile);
     NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
-    int64_t m = 0;
-    s = read_i64(ctx, bw.offsets + scene->n, 8, st, &m);
-    if (s != NGS_OK) return s;
-    if (m > max_pairs) return NGS_CAPACITY;
-    total_pairs += m;
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, m, bw, b.lists, st));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, st));
     NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, w, stats, st));
     NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_raw + 3 * (size_t)v, stats, sticky, st));
   }
@@ -382,8 +372,7 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
   if (s != NGS_OK) return s;
   if (stats) {
     ctx->pinned[0] = n_views;
-    ctx->pinned[1] = total_pairs;
-    NGS_TRY_HIP(ctx, hipMemcpyAsync(stats, ctx->pinned, 16, hipMemcpyHostToDevice, st));
+    NGS_TRY_HIP(ctx, hipMemcpyAsync(stats, ctx->pinned, 8, hipMemcpyHostToDevice, st));
     NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
   }
   if (of) {

@@ -54,6 +54,21 @@ __device__ __forceinline__ float transmit(float T, float alpha) {
   return T * (1.f - alpha);
 }
 
+// Half-extents of the conic's ellipse q <= cut along x and y (x within m_x +- sqrt(cut *
+// Sigma_xx), Sigma = Q^-1), widened by 1% + 0.05 px so that FP32 rounding never culls a
+// pixel with q <= cut. Used to skip, per wavefront, entries that cannot reach any of its
+// pixels; a degenerate conic is never culled.
+__device__ __forceinline__ void conic_extent(float qa, float qb, float qc, float cut, float* hx, float* hy) {
+  const float det = qa * qc - qb * qb;
+  if (!(det > 0.f) || !(qa > 0.f) || !(qc > 0.f)) {
+    *hx = __builtin_inff();
+    *hy = __builtin_inff();
+    return;
+  }
+  *hx = sqrtf(cut * qc / det) * 1.01f + 0.05f;
+  *hy = sqrtf(cut * qa / det) * 1.01f + 0.05f;
+}
+
 struct DevCam {
   float R[9], t[3], fx, fy, cx, cy;
   int width, height, tiles_x, tiles_y;
@@ -123,15 +138,17 @@ struct BinWs {
   uint32_t* dvals[2];   // gids ping-pong [n]
   uint64_t* offsets;    // [n + 1] exclusive scan of tile counts in depth order
   uint64_t* blocksum;   // scan partials
-  uint32_t* tkeys[2];   // tile ids ping-pong [max_pairs]
-  uint32_t* tvals;      // gid ping-pong partner [max_pairs]
+  uint32_t* phist;      // pairs per (tile, partition block) [4096][ceil(n / 256)]
+  uint32_t* ptot;       // pairs per tile [4096]
   SortWs sort;
 };
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);
 hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st);
-hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, int64_t m,
-                             const BinWs& w, const ngs_tile_lists& out, hipStream_t st);
+// Pairs beyond out.capacity are not written: the ranges are left empty and *overflow (may
+// be NULL) is raised; stats[1] (may be NULL) accumulates the pair count.
+hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
+                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st);
 
 // Rendering (render.hip).
 hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,

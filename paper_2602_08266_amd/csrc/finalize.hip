@@ -20,14 +20,14 @@ constexpr int kFinThreads = 64;
 constexpr int kMaxL = kNGeo + NGS_MAX_K;  // 75
 
 struct FinShared {
-  double A[kMaxL * kMaxL];
+  double A[kMaxL * (kMaxL + 1) / 2];  // packed lower triangle
   double st[kStatScalar + 6 * NGS_MAX_K];
   double P[7][kNGeo];      // rows 0..5: du/dtheta, row 6: dZ/dtheta
   double Y[7][7];          // current symmetric screen matrix
   double YP[7][kNGeo];
   double XS[6][NGS_MAX_K]; // X_o S, or X_rgb in its first 3 columns
   double p[NGS_MAX_K];
-  double red;
+  double col[kMaxL];
   int hs;                  // training-store slot
   int hs_new;
 };
@@ -143,29 +143,51 @@ __device__ void chain_rule(const float* mean, const float* log_scale, const floa
   P[5][10] = 1.0;
 }
 
-// In-place Cholesky of the l x l matrix A (full storage, lower triangle used) by one
-// 64-lane workgroup; returns log det A, or NaN if A is not positive definite.
-__device__ double chol_logdet(double* A, int l) {
-  double ld = 0.0;
+// Packed lower triangle: entry (i, c), c <= i, at i (i + 1) / 2 + c.
+__device__ __forceinline__ int lo_idx(int i, int c) { return i * (i + 1) / 2 + c; }
+
+// Row-major packed upper index e -> (i, j), i <= j.
+__device__ __forceinline__ void upper_rc(int e, int l, int* i, int* j) {
+  int r = 0, rem = e;
+  while (rem >= l - r) { rem -= l - r; ++r; }
+  *i = r;
+  *j = r + rem;
+}
+
+// log det of the symmetric l x l matrix held as a packed lower triangle, by an in-place
+// LDL^T factorisation on one 64-lane workgroup (no square roots); the pivots' mantissas and
+// exponents are accumulated separately so that a single log is taken at the end. Returns
+// NaN if a pivot is not positive (matrix not positive definite).
+__device__ double ldl_logdet(double* A, int l, double* col) {
+  double mant = 1.0;
+  int expo = 0;
   for (int j = 0; j < l; ++j) {
     __syncthreads();
-    const double d = A[j * l + j];
+    const double d = A[lo_idx(j, j)];
     if (!(d > 0.0)) return __builtin_nan("");
-    const double r = sqrt(d);
-    ld += 2.0 * log(r);
-    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) A[i * l + j] /= r;
+    int e1, e2;
+    const double md = frexp(d, &e1);
+    mant = frexp(mant * md, &e2);
+    expo += e1 + e2;
+    const double inv = 1.0 / d;
+    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) col[i] = A[lo_idx(i, j)];
     __syncthreads();
-    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) {
-      const double lij = A[i * l + j];
-      for (int c = j + 1; c <= i; ++c) A[i * l + c] -= lij * A[c * l + j];
+    const int m = l - j - 1;
+    const int ntri = m * (m + 1) / 2;
+    for (int e = threadIdx.x; e < ntri; e += kFinThreads) {
+      int ii = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      while (ii * (ii + 1) / 2 > e) --ii;
+      const int i = j + 1 + ii, c = j + 1 + (e - ii * (ii + 1) / 2);
+      A[lo_idx(i, c)] -= col[i] * col[c] * inv;
     }
   }
   __syncthreads();
-  return ld;
+  return log(mant) + (double)expo * 0.69314718055994530942;
 }
 
-// A[0..10][0..10] = Pr^T Y Pr over the first `rows` rows of P (Y symmetric rows x rows).
-__device__ void geo_block(FinShared& S, int rows, int l) {
+// Lower part of A[0..10][0..10] = Pr^T Y Pr over the first `rows` rows of P.
+__device__ void geo_block(FinShared& S, int rows) {
   for (int e = threadIdx.x; e < rows * kNGeo; e += kFinThreads) {
     const int a = e / kNGeo, j = e % kNGeo;
     double v = 0.0;
@@ -173,19 +195,20 @@ __device__ void geo_block(FinShared& S, int rows, int l) {
     S.YP[a][j] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
-    const int i = e / kNGeo, j = e % kNGeo;
+  for (int e = threadIdx.x; e < kNGeo * (kNGeo + 1) / 2; e += kFinThreads) {
+    int i = 0, c = e;
+    while (c > i) { c -= i + 1; ++i; }
     double v = 0.0;
-    for (int a = 0; a < rows; ++a) v += S.P[a][i] * S.YP[a][j];
-    S.A[i * l + j] = v;
+    for (int a = 0; a < rows; ++a) v += S.P[a][i] * S.YP[a][c];
+    S.A[lo_idx(i, c)] = v;
   }
 }
 
-__device__ void load_sym6(FinShared& S, int base) {
+__device__ void load_sym(FinShared& S, int base, int dim) {
   if (threadIdx.x == 0) {
     int s = base;
-    for (int i = 0; i < 6; ++i)
-      for (int j = i; j < 6; ++j) { S.Y[i][j] = S.st[s]; S.Y[j][i] = S.st[s]; ++s; }
+    for (int i = 0; i < dim; ++i)
+      for (int j = i; j < dim; ++j) { S.Y[i][j] = S.st[s]; S.Y[j][i] = S.st[s]; ++s; }
   }
   __syncthreads();
 }
@@ -193,10 +216,9 @@ __device__ void load_sym6(FinShared& S, int base) {
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
     const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
-    uint32_t outputs, int mode, int conf_on_train, float* __restrict__ acc, int stride,
-    int32_t* __restrict__ slot_of, int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots,
-    const int32_t* __restrict__ overflow, ngs_hessian h, int has_h, double* __restrict__ ig_out,
-    int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
+    uint32_t outputs, int mode, int conf_on_train, const float* __restrict__ acc, int stride,
+    const int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots, const int32_t* __restrict__ overflow,
+    ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
   __shared__ FinShared S;
   const int used = min(*n_slots, stride);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -235,31 +257,25 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     for (int f = 0; f < 3; ++f) {
       if (!((outputs >> f) & 1u)) continue;
       const int l = f == 0 ? 14 : (f == 1 ? kNGeo : lo);
-      // ---- build A (unweighted) ----
-      for (int e = threadIdx.x; e < l * l; e += kFinThreads) S.A[e] = 0.0;
+      // ---- build the lower triangle of A (unweighted) ----
+      for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) S.A[e] = 0.0;
       __syncthreads();
       if (f == 0) {
-        load_sym6(S, kStatYrgb);
-        geo_block(S, 6, l);
+        load_sym(S, kStatYrgb, 6);
+        geo_block(S, 6);
         for (int e = threadIdx.x; e < kNGeo * 3; e += kFinThreads) {
           const int i = e / 3, ch = e % 3;
           double v = 0.0;
           for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.st[kStatXrgb + a * 3 + ch];
-          S.A[i * l + kNGeo + ch] = v;
-          S.A[(kNGeo + ch) * l + i] = v;
+          S.A[lo_idx(kNGeo + ch, i)] = v;
         }
-        if (threadIdx.x < 3) S.A[(kNGeo + threadIdx.x) * l + kNGeo + threadIdx.x] = a2;
+        if (threadIdx.x < 3) S.A[lo_idx(kNGeo + threadIdx.x, kNGeo + threadIdx.x)] = a2;
       } else if (f == 1) {
-        if (threadIdx.x == 0) {
-          int s = kStatYd;
-          for (int i = 0; i < 7; ++i)
-            for (int j = i; j < 7; ++j) { S.Y[i][j] = S.st[s]; S.Y[j][i] = S.st[s]; ++s; }
-        }
-        __syncthreads();
-        geo_block(S, 7, l);
+        load_sym(S, kStatYd, 7);
+        geo_block(S, 7);
       } else {
-        load_sym6(S, kStatYo);
-        geo_block(S, 6, l);
+        load_sym(S, kStatYo, 6);
+        geo_block(S, 6);
         // X_o S with X_o = m1 p^T - Z_o
         for (int a = threadIdx.x; a < 6; a += kFinThreads) {
           double xp = 0.0;
@@ -274,16 +290,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
           const int i = e / k, m = e % k;
           double v = 0.0;
           for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.XS[a][m];
-          S.A[i * l + kNGeo + m] = v;
-          S.A[(kNGeo + m) * l + i] = v;
+          S.A[lo_idx(kNGeo + m, i)] = v;
         }
         double s2 = 0.0;
         for (int c = 0; c < k; ++c) s2 += S.p[c] * S.p[c];
-        for (int e = threadIdx.x; e < k * k; e += kFinThreads) {
-          const int m = e / k, j = e % k;
+        for (int e = threadIdx.x; e < k * (k + 1) / 2; e += kFinThreads) {
+          int m = 0, j = e;
+          while (j > m) { j -= m + 1; ++m; }
           const double pm = S.p[m], pj = S.p[j];
           const double ss = (m == j ? pm * pm : 0.0) - pm * pm * pj - pm * pj * pj + pm * pj * s2;
-          S.A[(kNGeo + m) * l + kNGeo + j] = a2 * ss;
+          S.A[lo_idx(kNGeo + m, kNGeo + j)] = a2 * ss;
         }
       }
       __syncthreads();
@@ -291,13 +307,11 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       const int hs = S.hs;
       if (mode == NGS_MODE_ACCUMULATE) {
         for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-          // unpack (i, j), i <= j, from the packed row-major upper index
-          int i = 0, rem = e;
-          while (rem >= l - i) { rem -= l - i; ++i; }
-          const int j = i + rem;
+          int i, j;
+          upper_rc(e, l, &i, &j);
           double* hp = &hblk[(size_t)e * h.capacity + hs];
           const double base = S.hs_new ? (i == j ? lambda : 0.0) : *hp;
-          *hp = base + wacc * S.A[i * l + j];
+          *hp = base + wacc * S.A[lo_idx(j, i)];
         }
         continue;
       }
@@ -306,29 +320,27 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       if (hs >= 0) {
         ld_h = h.logdet[(size_t)f * h.capacity + hs];
         for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-          int i = 0, rem = e;
-          while (rem >= l - i) { rem -= l - i; ++i; }
-          const int j = i + rem;
-          const double hv = hblk[(size_t)e * h.capacity + hs];
-          const double v = hv + cg * S.A[i * l + j];
-          S.A[i * l + j] = v;
-          S.A[j * l + i] = v;
+          int i, j;
+          upper_rc(e, l, &i, &j);
+          const int x = lo_idx(j, i);
+          S.A[x] = hblk[(size_t)e * h.capacity + hs] + cg * S.A[x];
         }
       } else {
         ld_h = (double)l * log(lambda);
-        for (int e = threadIdx.x; e < l * l; e += kFinThreads) {
-          const int i = e / l, j = e % l;
-          S.A[e] = cg * S.A[e] + (i == j ? lambda : 0.0);
+        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
+          int i = 0, c = e;
+          while (c > i) { c -= i + 1; ++i; }
+          S.A[e] = cg * S.A[e] + (i == c ? lambda : 0.0);
         }
       }
       __syncthreads();
-      const double ld_m = chol_logdet(S.A, l);
+      const double ld_m = ldl_logdet(S.A, l, S.col);
       if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], ld_m - ld_h);
     }
   }
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, int used, double lambda) {
+__global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, int used) {
   __shared__ FinShared S;
   const int lo = kNGeo + h.k;
   for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
@@ -337,19 +349,15 @@ __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, i
       const double* hblk = f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o);
       __syncthreads();
       for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-        int i = 0, rem = e;
-        while (rem >= l - i) { rem -= l - i; ++i; }
-        const int j = i + rem;
-        const double v = hblk[(size_t)e * h.capacity + slot];
-        S.A[i * l + j] = v;
-        S.A[j * l + i] = v;
+        int i, j;
+        upper_rc(e, l, &i, &j);
+        S.A[lo_idx(j, i)] = hblk[(size_t)e * h.capacity + slot];
       }
       __syncthreads();
-      const double ld = chol_logdet(S.A, l);
+      const double ld = ldl_logdet(S.A, l, S.col);
       if (threadIdx.x == 0) h.logdet[(size_t)f * h.capacity + slot] = ld;
     }
   }
-  (void)lambda;
 }
 
 // Eq. 10 normalisation, Eq. 11 combination and the argmax of Eq. 5 (lowest index on ties).
@@ -399,8 +407,7 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
   ProfScope ps(kProfIgFinalize, st);
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
                      s.prob, cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
-                     w.acc, (int)w.max_slots, w.slot_of, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out,
-                     stats, sticky);
+                     w.acc, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats, sticky);
   return hipGetLastError();
 }
 
@@ -409,7 +416,8 @@ hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_p
   if (used <= 0) return hipSuccess;
   const int blocks = std::min(used, 4096);
   ProfScope ps(kProfHessianLogdet, st);
-  hipLaunchKernelGGL(k_hessian_logdet, dim3(blocks), dim3(kFinThreads), 0, st, *h, used, (double)lambda_prior);
+  hipLaunchKernelGGL(k_hessian_logdet, dim3(blocks), dim3(kFinThreads), 0, st, *h, used);
+  (void)lambda_prior;
   return hipGetLastError();
 }
 

@@ -15,35 +15,78 @@
 // transmittance and last contributor. Pass 2 walks back to front from the tile's last
 // contributor, recovering T before each Gaussian as T_after / (1 - alpha) and keeping the
 // suffixes S in registers. For each Gaussian with a nonzero confidence weight, every
-// wavefront writes one record per lane to LDS and reduces the statistics transposed: lane
-// s sums statistic s over the 64 pixels (and lane k sums the k-th column of the 6 x k
-// object term), then adds its result to the Gaussian's accumulator with one atomic.
+// wavefront forms its pixels' statistic contributions in registers and sums them over its
+// 64 lanes with a recursive-halving reduce-scatter (64 statistics per round, 63 lane
+// exchanges), after which lane s holds statistic s and adds it to the Gaussian's
+// accumulator with one atomic. In both passes a wavefront only visits the batch entries whose
+// conservative 3-sigma bounding box reaches its 16 x 4 pixel strip (a ballot mask); the
+// skipped entries would fail the cut-off test at every one of its pixels.
 #include "common.hpp"
 
 namespace ngs {
 namespace {
 
 constexpr int kBatch = 32;
-constexpr int kRecScalar = 22;  // y[6] a w_rgb[3] w_d |w_rgb|^2 |w_o|^2 aT 1 w_d^2 z[6]
-constexpr int kChunk = 16;      // object-suffix channels transposed per round
 
-// statistic s = rec[i0] * rec[i1] * rec[i2]
+// Statistic s of a pixel is rv[i0] * rv[i1] * rv[i2] over the per-pixel record
+// rv = (y[6], a, w_rgb[3], w_d, |w_rgb|^2, |w_o|^2, a T, 1, w_d^2), in the order of
+// common.hpp: Y_rgb (upper 6x6), X_rgb (6x3), Y_d (upper 7x7 of e = (w_d y, a)), Y_o, m1.
 struct StatDesc { unsigned char i0, i1, i2; };
-__constant__ StatDesc c_stats[kStatScalar];
+struct StatTable { StatDesc d[kStatScalar]; };
+
+constexpr StatTable make_stat_table() {
+  StatTable t{};
+  int s = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) t.d[s++] = {11, (unsigned char)i, (unsigned char)j};
+  for (int i = 0; i < 6; ++i)
+    for (int ch = 0; ch < 3; ++ch) t.d[s++] = {6, (unsigned char)i, (unsigned char)(7 + ch)};
+  for (int i = 0; i < 7; ++i)
+    for (int j = i; j < 7; ++j) {
+      if (j < 6) t.d[s++] = {15, (unsigned char)i, (unsigned char)j};
+      else if (i < 6) t.d[s++] = {10, (unsigned char)i, 6};
+      else t.d[s++] = {6, 6, 14};
+    }
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) t.d[s++] = {12, (unsigned char)i, (unsigned char)j};
+  for (int i = 0; i < 6; ++i) t.d[s++] = {13, (unsigned char)i, 14};
+  return t;
+}
+constexpr StatTable kStatTable = make_stat_table();
+static_assert(kStatTable.d[kStatScalar - 1].i0 == 13 && kStatTable.d[kStatYd + 27].i2 == 14, "statistic table layout");
+
+// Sums v over the 64 lanes of the wavefront and leaves entry l's total in lane l
+// (recursive halving: at each step a lane keeps the half of its window selected by one bit
+// of its lane id and adds the partner lane's copy of that half).
+__device__ __forceinline__ float wave_reduce_scatter64(float (&v)[kWave], int lane) {
+#pragma unroll
+  for (int s = kWave / 2; s >= 1; s >>= 1) {
+    const bool up = (lane & s) != 0;
+#pragma unroll
+    for (int i = 0; i < s; ++i) {
+      const float send = up ? v[i] : v[i + s];
+      const float keep = up ? v[i + s] : v[i];
+      v[i] = keep + __shfl_xor(send, s);
+    }
+  }
+  return v[0];
+}
 
 template <int KP>
 struct IgShared {
   float mx[kBatch], my[kBatch], qa[kBatch], qb[kBatch], qc[kBatch], op[kBatch];
-  float z[kBatch], r[kBatch], g[kBatch], b[kBatch], conf[kBatch];
+  float z[kBatch], r[kBatch], g[kBatch], b[kBatch], conf[kBatch], hx[kBatch], hy[kBatch];
   uint32_t gid[kBatch];
   float p[kBatch][KP];
-  static constexpr int kCh = KP < kChunk ? KP : kChunk;
-  static constexpr int kRow = (kRecScalar + kCh) | 1;  // odd stride: conflict-free column reads
-  float rec[kTilePix / kWave][kWave][kRow];
-  int red_i[kTilePix / kWave];
-  int red_new[kTilePix / kWave];
   int flag;
 };
+
+// Whether batch entry l's ellipse can reach the wavefront's strip (entries past cnt: no).
+template <class Sh>
+__device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, float sx1, float sy0, float sy1) {
+  return l < cnt && S.mx[l] + S.hx[l] >= sx0 && S.mx[l] - S.hx[l] <= sx1 && S.my[l] + S.hy[l] >= sy0 &&
+         S.my[l] - S.hy[l] <= sy1;
+}
 
 template <int KP>
 __global__ __launch_bounds__(kTilePix) void k_ig_tile(
@@ -65,6 +108,9 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
   const int stride = max_slots;
+  // pixel-centre bounds of this wavefront's 16 x 4 strip
+  const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
+  const float sy0 = (float)(ty * kTile + wave * (kWave / kTile)) + 0.5f, sy1 = sy0 + (float)(kWave / kTile - 1);
 
   // ---- pass 1: front to back, final transmittance and last contributor -----------------
   float T = 1.f;
@@ -79,10 +125,14 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
       S.mx[j] = mean2d[g]; S.my[j] = mean2d[n + g];
       S.qa[j] = conic[g]; S.qb[j] = conic[n + g]; S.qc[j] = conic[2 * n + g];
       S.op[j] = opacity[g];
+      conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
     }
     __syncthreads();
+    uint64_t live = __ballot(reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
     if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+      while (live) {
+        const int j = __ffsll((unsigned long long)live) - 1;
+        live &= live - 1;
         const float dx = fxp - S.mx[j], dy = fyp - S.my[j];
         const float q = conic_q(S.qa[j], S.qb[j], S.qc[j], dx, dy);
         if (q > rc.cutoff_q) continue;
@@ -127,7 +177,6 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
 #pragma unroll
   for (int c = 0; c < KP; ++c) So[c] = 0.f;
   if (obj_eq2) So[0] = t_final;  // S~ = S_o + T_final e_0
-  float* rec = &S.rec[wave][lane][0];
   for (int hi = tile_last + 1; hi > (int)start; hi -= kBatch) {
     const int lo = max((int)start, hi - kBatch);
     const int cnt = hi - lo;
@@ -141,13 +190,17 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
       S.op[j] = opacity[g]; S.z[j] = depth[g];
       S.r[j] = rgb[g]; S.g[j] = rgb[n + g]; S.b[j] = rgb[2 * n + g];
       S.conf[j] = conf[g];
+      conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
     }
     for (int idx = threadIdx.x; idx < cnt * KP; idx += kTilePix) {
       const int j = idx / KP, c = idx % KP;
       S.p[j][c] = (c < k) ? prob[(size_t)gids[lo + j] * k + c] : 0.f;
     }
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    uint64_t live = __ballot(reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
+    while (live) {
+      const int j = 63 - __clzll((long long)live);
+      live &= ~(1ull << j);
       const int li = lo + j;
       bool contrib = false;
       float alpha = 0.f, dx = 0.f, dy = 0.f, raw = 0.f;
@@ -192,31 +245,24 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
             no += w * w;
           }
         }
+        float rv[16] = {y0, y1, y2, y3, y4, y5, a, wr, wg, wb, wd, nrgb, no, a * Tg, 1.f, wd * wd};
         const float ao = a * om;
-        rec[0] = y0; rec[1] = y1; rec[2] = y2; rec[3] = y3; rec[4] = y4; rec[5] = y5;
-        rec[6] = a; rec[7] = wr; rec[8] = wg; rec[9] = wb; rec[10] = wd; rec[11] = nrgb; rec[12] = no;
-        rec[13] = a * Tg; rec[14] = 1.f; rec[15] = wd * wd;
-        rec[16] = ao * y0; rec[17] = ao * y1; rec[18] = ao * y2; rec[19] = ao * y3; rec[20] = ao * y4;
-        rec[21] = ao * y5;
+        const float zv[6] = {ao * y0, ao * y1, ao * y2, ao * y3, ao * y4, ao * y5};
         // Slot of this Gaussian in the per-view accumulator. A new slot is taken from the
         // counter, zeroed by the whole wavefront, and only then published in slot_of with a
         // compare-and-swap (a wavefront that loses the race leaves its zeroed slot unused,
         // marked by gid_of = -1); every later update of a published slot is an atomic add.
         const uint32_t gq = S.gid[j];
+        int slot = -1, fresh = -1;
         if (lane == 0) {
-          int s = __atomic_load_n(&slot_of[gq], __ATOMIC_RELAXED);
-          int fresh = -1;
-          if (s < 0) {
+          slot = __atomic_load_n(&slot_of[gq], __ATOMIC_RELAXED);
+          if (slot < 0) {
             const int ns = atomicAdd(n_slots, 1);
             if (ns >= max_slots) atomicOr(overflow, 1); else fresh = ns;
           }
-          S.red_i[wave] = s;
-          S.red_new[wave] = fresh;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int fresh = S.red_new[wave];
+        slot = __shfl(slot, 0);
+        fresh = __shfl(fresh, 0);
         if (fresh >= 0) {
           for (int s = lane; s < stat_len(k); s += kWave) acc[(size_t)s * stride + fresh] = 0.f;
           __threadfence();
@@ -224,62 +270,43 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
           if (lane == 0) {
             const int old = atomicCAS(&slot_of[gq], -1, fresh);
             gid_of[fresh] = (old == -1) ? (int)gq : -1;
-            S.red_i[wave] = (old == -1) ? fresh : old;
+            slot = (old == -1) ? fresh : old;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          slot = __shfl(slot, 0);
         }
-        const int slot = S.red_i[wave];
         if (slot >= 0) {
-          const float* rows = &S.rec[wave][0][0];
-          constexpr int R = IgShared<KP>::kRow;
-          constexpr int CH = IgShared<KP>::kCh;
-          // scalar statistics: lane s handles s and s + 64
-          for (int s = lane; s < kStatScalar; s += kWave) {
-            const StatDesc d = c_stats[s];
-            float v = 0.f;
-            for (int p = 0; p < kWave; ++p) {
-              const float* rp = rows + p * R;
-              v += rp[d.i0] * rp[d.i1] * rp[d.i2];
+          // Sum this lane's contributions over the wavefront, 64 statistics at a time: the
+          // padded statistic vector is [94 scalar statistics | Z_o as 6 x KP]; after the
+          // reduce-scatter lane l holds entry 64 q + l of chunk q.
+          constexpr int kLen = kStatScalar + 6 * KP;
+#pragma unroll
+          for (int q = 0; q < (kLen + kWave - 1) / kWave; ++q) {
+            float v[kWave];
+#pragma unroll
+            for (int e = 0; e < kWave; ++e) {
+              const int idx = q * kWave + e;
+              if (idx < kStatScalar) {
+                const StatDesc d = kStatTable.d[idx < kStatScalar ? idx : 0];
+                v[e] = rv[d.i0] * rv[d.i1] * rv[d.i2];
+              } else if (idx < kLen) {
+                const int f = idx - kStatScalar;
+                v[e] = zv[f / KP] * So[f % KP];
+              } else {
+                v[e] = 0.f;
+              }
             }
-            if (v != 0.f) atomicAdd(&acc[(size_t)s * stride + slot], v);
-          }
-          // object term Z_o[i][c] = sum_p z_i S~_c, CH channels per round; lanes form
-          // groups of CH channels that split the 64 pixels, then combine by shuffles.
-          constexpr int G = kWave / CH;
-          const int cl = lane % CH, grp = lane / CH;
-#pragma unroll
-          for (int c0 = 0; c0 < KP; c0 += CH) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int c = 0; c < CH; ++c) rec[kRecScalar + c] = contrib ? So[c0 + c] : 0.f;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float zz[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int p = grp; p < kWave; p += G) {
-              const float* rp = rows + p * R;
-              const float sv = rp[kRecScalar + cl];
-#pragma unroll
-              for (int i = 0; i < 6; ++i) zz[i] += rp[16 + i] * sv;
+            const float tot = wave_reduce_scatter64(v, lane);
+            const int idx = q * kWave + lane;
+            int dst = -1;
+            if (idx < kStatScalar) {
+              dst = idx;
+            } else if (idx < kLen) {
+              const int f = idx - kStatScalar, c = f % KP;
+              if (c < k) dst = kStatScalar + (f / KP) * k + c;
             }
-#pragma unroll
-            for (int off = CH; off < kWave; off <<= 1)
-#pragma unroll
-              for (int i = 0; i < 6; ++i) zz[i] += __shfl_xor(zz[i], off);
-            const int c = c0 + cl;
-            if (grp == 0 && c < k)
-#pragma unroll
-              for (int i = 0; i < 6; ++i)
-                if (zz[i] != 0.f) atomicAdd(&acc[(size_t)(kStatScalar + i * k + c) * stride + slot], zz[i]);
+            if (dst >= 0 && tot != 0.f) atomicAdd(&acc[(size_t)dst * stride + slot], tot);
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
       if (contrib) {
         Sr += S.r[j] * a; Sg += S.g[j] * a; Sb += S.b[j] * a;
@@ -307,31 +334,6 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, s.conf, ig.obj_eq2, w.acc, w.slot_of,
                      w.gid_of, w.n_slots, w.overflow, (int)w.max_slots, stats);
   return hipGetLastError();
-}
-
-bool g_stats_uploaded = false;
-
-hipError_t upload_stat_table() {
-  if (g_stats_uploaded) return hipSuccess;
-  StatDesc t[kStatScalar];
-  int s = 0;
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) t[s++] = {11, (unsigned char)i, (unsigned char)j};          // Y_rgb
-  for (int i = 0; i < 6; ++i)
-    for (int ch = 0; ch < 3; ++ch) t[s++] = {6, (unsigned char)i, (unsigned char)(7 + ch)};  // X_rgb
-  for (int i = 0; i < 7; ++i)
-    for (int j = i; j < 7; ++j) {                                                            // Y_d
-      if (j < 6) t[s++] = {15, (unsigned char)i, (unsigned char)j};
-      else if (i < 6) t[s++] = {10, (unsigned char)i, 6};
-      else t[s++] = {6, 6, 14};
-    }
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) t[s++] = {12, (unsigned char)i, (unsigned char)j};          // Y_o
-  for (int i = 0; i < 6; ++i) t[s++] = {13, (unsigned char)i, 14};                          // m1
-  if (s != kStatScalar) return hipErrorInvalidValue;
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_stats), t, sizeof(t));
-  if (e == hipSuccess) g_stats_uploaded = true;
-  return e;
 }
 
 }  // namespace
@@ -363,9 +365,7 @@ hipError_t ig_reset(const IgWs& w, int n, hipStream_t st) {
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats,
                            hipStream_t st) {
-  hipError_t e = upload_stat_table();
-  if (e != hipSuccess) return e;
-  e = ig_reset(w, s.n, st);
+  hipError_t e = ig_reset(w, s.n, st);
   if (e != hipSuccess) return e;
   {
     ProfScope ps(kProfFill, st);

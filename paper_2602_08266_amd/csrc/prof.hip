@@ -25,8 +25,8 @@ int64_t g_cnt[kProfKernels];
 
 const char* const kNames[kProfKernels] = {
     "prepare_scene", "project", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "count_scan",
-    "emit_pairs", "tile_ranges", "tile_keys64", "render", "ig_tiles", "ig_finalize", "hessian_logdet",
-    "score_combine", "fill", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter"};
+    "unused_emit", "unused_ranges", "tile_keys64", "render", "ig_tiles", "ig_finalize", "hessian_logdet",
+    "score_combine", "fill", "tile_part_hist", "tile_part_scan", "tile_part_scatter"};
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kTilePix) void k_render(int n, int k, const uint32_
                                                      float* __restrict__ out_t, float* __restrict__ out_conf,
                                                      int32_t* __restrict__ out_id, int32_t* __restrict__ out_nc) {
   __shared__ float s_mx[kBatch], s_my[kBatch], s_qa[kBatch], s_qb[kBatch], s_qc[kBatch], s_op[kBatch];
-  __shared__ float s_z[kBatch], s_r[kBatch], s_g[kBatch], s_b[kBatch], s_kap[kBatch];
+  __shared__ float s_z[kBatch], s_r[kBatch], s_g[kBatch], s_b[kBatch], s_kap[kBatch], s_hx[kBatch], s_hy[kBatch];
   __shared__ float s_p[kBatch][KP];
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
@@ -33,6 +33,10 @@ __global__ __launch_bounds__(kTilePix) void k_render(int n, int k, const uint32_
   const bool inside = px < cam.width && py < cam.height;
   const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
   const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
+  // pixel-centre bounds of this wavefront's 16 x 4 strip
+  const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
+  const float sy0 = (float)(ty * kTile + (int)(threadIdx.x / kWave) * (kWave / kTile)) + 0.5f;
+  const float sy1 = sy0 + (float)(kWave / kTile - 1);
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, kb = 0.f;
   float Op[KP];
 #pragma unroll
@@ -50,14 +54,22 @@ __global__ __launch_bounds__(kTilePix) void k_render(int n, int k, const uint32_
       s_op[j] = opacity[g]; s_z[j] = depth[g];
       s_r[j] = rgb[g]; s_g[j] = rgb[n + g]; s_b[j] = rgb[2 * n + g];
       s_kap[j] = kappa[g];
+      conic_extent(s_qa[j], s_qb[j], s_qc[j], rc.cutoff_q, &s_hx[j], &s_hy[j]);
     }
     for (int idx = threadIdx.x; idx < cnt * KP; idx += kTilePix) {
       const int j = idx / KP, c = idx % KP;
       s_p[j][c] = (c < k) ? prob[(size_t)gids[b0 + j] * k + c] : 0.f;
     }
     __syncthreads();
+    // entries whose ellipse can reach this wavefront's strip (lane l tests entry l)
+    const int l = (int)(threadIdx.x % kWave);
+    const bool reach = l < cnt && s_mx[l] + s_hx[l] >= sx0 && s_mx[l] - s_hx[l] <= sx1 &&
+                       s_my[l] + s_hy[l] >= sy0 && s_my[l] - s_hy[l] <= sy1;
+    uint64_t live = __ballot(reach);
     if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+      while (live) {
+        const int j = __ffsll((unsigned long long)live) - 1;
+        live &= live - 1;
         const float dx = fxp - s_mx[j], dy = fyp - s_my[j];
         const float q = conic_q(s_qa[j], s_qb[j], s_qc[j], dx, dy);
         if (q > rc.cutoff_q) continue;
