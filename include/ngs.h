@@ -138,12 +138,17 @@ typedef struct {
 } ngs_image;
 
 /* Training information H_T (Eq. 9 with prior lambda*I), stored only for Gaussians
- * that a training view touched; every other Gaussian has H_T = lambda*I.
- * Blocks are packed upper triangles, row-major, FP64, entry-major across slots:
- * h_rgb[e * capacity + slot] for e < 105 (l = 14), h_d (66, l = 11), h_o
- * ((11+k)(12+k)/2, l = 11 + k). logdet[f * capacity + slot], f = rgb, depth, obj.
- * slot_of[n] must be filled with -1 and n_slots with 0 before the first training view
- * (ngs_hessian_reset). */
+ * that a training view touched; every other Gaussian has H_T = lambda*I. Slot-major, FP64,
+ * each slot's block contiguous:
+ *   h_rgb[slot * 105 + e]  packed upper triangle, row-major, of the 14 x 14 RGB block;
+ *   h_d[slot * 66 + e]     the same for the 11 x 11 depth block;
+ *   h_o[slot * (68 + 12k) + e]  the (11+k) x (11+k) object block in factored form: for
+ *     softmax probabilities p and S = diag(p) - p p^T every such block (and every sum of
+ *     them plus lambda*I) is [[G, E S], [S E^T, lambda I + tau S S]]; stored are G (packed
+ *     upper 11 x 11, e < 66), tau (e = 66), lambda (e = 67), E (11 x k row-major,
+ *     e = 68 + r k + c) and p (e = 68 + 11k + c).
+ * logdet[f * capacity + slot], f = rgb, depth, obj. slot_of[n] must be filled with -1
+ * and n_slots with 0 before the first training view (ngs_hessian_reset). */
 typedef struct {
   int32_t k;
   int32_t capacity;
@@ -157,7 +162,8 @@ typedef struct {
 } ngs_hessian;
 
 /* Per-view statistics the kernels add into (device, int64 [6], caller-zeroed):
- * [0] views, [1] pairs M, [2] touched Gaussians with a nonzero weight U,
+ * [0] views, [1] pairs M, [2] Gaussians with a nonzero weight that contribute to at
+ *     least one pixel U,
  * [3] contributing (pixel, Gaussian) pairs P, [4] walked (tile, entry) pairs,
  * [5] views whose slot workspace overflowed. */
 #define NGS_STATS_LEN 6
@@ -212,7 +218,8 @@ ngs_status ngs_render(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected*
  * logdet(H_T,g) (Eq. 5, 6, 9); h may be NULL (H_T = lambda I). ACCUMULATE mode: adds
  * w_g A_g into h (w_g = c_g, or 1 when conf_on_train = 0); call ngs_hessian_finalize
  * after the last training view. stats (device int64 [NGS_STATS_LEN]) may be NULL.
- * ws: ngs_workspace_size(1, ...) bytes. */
+ * ws: ngs_workspace_size(1, ...) bytes; its slot capacity (max_slots) must cover every
+ * Gaussian with c_g > 0 whose rectangle reaches a tile of the view, else NGS_CAPACITY. */
 ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
                          const ngs_tile_lists* lists, const ngs_camera* cam,
                          const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,

@@ -14,7 +14,7 @@ from typing import Dict, List, Optional, Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "libngs.so")
+LIB_PATH = os.environ.get("NGS_LIB") or os.path.join(HERE, "_build", "libngs.so")
 
 NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
 NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
@@ -248,9 +248,9 @@ class Hessian:
         self.slot_of = torch.full((max(n, 1),), -1, dtype=torch.int32, device=device)
         self.n_slots = torch.zeros(1, dtype=torch.int32, device=device)
         self.gid_of = torch.full((cap,), -1, dtype=torch.int32, device=device)
-        self.h_rgb = torch.zeros((105, cap), dtype=torch.float64, device=device)
-        self.h_d = torch.zeros((66, cap), dtype=torch.float64, device=device)
-        self.h_o = torch.zeros((lo * (lo + 1) // 2, cap), dtype=torch.float64, device=device)
+        self.h_rgb = torch.zeros((cap, 105), dtype=torch.float64, device=device)
+        self.h_d = torch.zeros((cap, 66), dtype=torch.float64, device=device)
+        self.h_o = torch.zeros((cap, 68 + 12 * k), dtype=torch.float64, device=device)
         self.logdet = torch.zeros((3, cap), dtype=torch.float64, device=device)
 
     def c(self) -> ngs_hessian:

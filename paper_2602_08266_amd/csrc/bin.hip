@@ -5,10 +5,10 @@
 //   1. depth digits: the n Gaussians are sorted by their 32-bit depth key (4 passes over n
 //      entries instead of over the M >> n pairs); gid order breaks ties (stable LSD);
 //   2. one stable counting pass on the tile digit (<= 12 bits) over the pairs, fused with
-//      their generation: each single-wavefront block expands the rects of 256 consecutive
-//      depth ranks, counts its pairs per tile (pass a), and after a scan over blocks and
-//      tiles (pass b) writes each pair's gid at its final position (pass c), ranking lanes
-//      that share a tile with ballot match masks so the depth order survives.
+//      their generation: each single-wavefront block takes 256 consecutive depth ranks one
+//      Gaussian at a time (its lanes spread over that Gaussian's rect), counts its pairs per
+//      tile (pass a), and after a scan over blocks and tiles (pass b) writes each pair's gid
+//      at its final position (pass c); per-tile positions advance in depth order.
 // The result equals a sort of (tile << 32 | depth bits) with ties broken by gid; the
 // per-tile ranges fall out of the scan, and no pair array other than the output is written.
 #include "common.hpp"
@@ -86,18 +86,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
 }
 
 constexpr int kPartRanks = 256;  // depth ranks per partition block (one wavefront)
-constexpr int kTileBits = 12;    // NGS_MAX_TILES = 4096
 
-// The block's ranks, their pair offsets and rect geometry in LDS; returns the pair count.
+// The block's ranks and rect geometry in LDS, plus one running counter per tile.
 struct PartShared {
-  uint64_t off[kPartRanks + 1];
   uint32_t gid[kPartRanks];
-  int32_t x0[kPartRanks], y0[kPartRanks], w[kPartRanks];
+  int32_t x0[kPartRanks], y0[kPartRanks], w[kPartRanks], area[kPartRanks];
   uint32_t cnt[NGS_MAX_TILES];
 };
 
 __device__ __forceinline__ int part_load(PartShared& S, int n, const uint32_t* __restrict__ order,
-                                         const uint64_t* __restrict__ offsets, const int16_t* __restrict__ rect) {
+                                         const uint32_t* __restrict__ count, const int16_t* __restrict__ rect) {
   const int r0 = blockIdx.x * kPartRanks;
   const int cnt = min(kPartRanks, n - r0);
   for (int t = threadIdx.x; t < cnt; t += kWave) {
@@ -106,39 +104,25 @@ __device__ __forceinline__ int part_load(PartShared& S, int n, const uint32_t* _
     S.x0[t] = rect[g];
     S.y0[t] = rect[n + g];
     S.w[t] = rect[2 * n + g] - rect[g] + 1;
-    S.off[t] = offsets[r0 + t];
+    S.area[t] = (int)count[g];
   }
-  if (threadIdx.x == 0) S.off[cnt] = offsets[r0 + cnt];
   return cnt;
 }
 
-// Pair p of the block -> its Gaussian (largest i with off[i] <= p) and tile; rects are
-// expanded row by row.
-__device__ __forceinline__ uint32_t part_pair(const PartShared& S, int cnt, uint64_t p, int tiles_x, uint32_t* gid) {
-  int lo = 0, hi = cnt;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (S.off[mid] <= p) lo = mid; else hi = mid;
-  }
-  const uint32_t j = (uint32_t)(p - S.off[lo]);
-  const uint32_t w = (uint32_t)S.w[lo];
-  *gid = S.gid[lo];
-  return ((uint32_t)S.y0[lo] + j / w) * (uint32_t)tiles_x + (uint32_t)S.x0[lo] + j % w;
-}
-
-// Pass a: pairs per (tile, block), written tile-major: hist[t * nblk + block].
+// Pass a: pairs per (tile, block), tile-major: hist[t * nblk + block]. The block's Gaussians
+// are taken one at a time in depth order and the lanes spread over the tiles of the current
+// Gaussian's rect, which are distinct, so the per-tile counters need no atomics.
 __global__ __launch_bounds__(kWave) void k_part_hist(int n, const uint32_t* __restrict__ order,
-                                                     const uint64_t* __restrict__ offsets,
+                                                     const uint32_t* __restrict__ count,
                                                      const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                      uint32_t* __restrict__ hist, int nblk) {
   __shared__ PartShared S;
   for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = 0u;
-  const int cnt = part_load(S, n, order, offsets, rect);
+  const int cnt = part_load(S, n, order, count, rect);
   __syncthreads();
-  const uint64_t beg = S.off[0], end = S.off[cnt];
-  for (uint64_t p = beg + threadIdx.x; p < end; p += kWave) {
-    uint32_t g;
-    atomicAdd(&S.cnt[part_pair(S, cnt, p, tiles_x, &g)], 1u);
+  for (int r = 0; r < cnt; ++r) {
+    const int area = S.area[r], w = S.w[r], x0 = S.x0[r], y0 = S.y0[r];
+    for (int j = threadIdx.x; j < area; j += kWave) S.cnt[(y0 + j / w) * tiles_x + x0 + j % w] += 1u;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += kWave) hist[(size_t)t * nblk + blockIdx.x] = S.cnt[t];
@@ -206,42 +190,27 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
 }
 
 // Pass c: every pair goes to ranges[tile] + (pairs of lower blocks for the tile) + (earlier
-// pairs of this block for the tile). Pairs are generated in depth-rank order, 64 per round;
-// lanes of a round that share a tile are ranked by a 12-ballot match mask and the lowest of
-// them advances the tile's running position, so equal tiles keep the depth order.
+// pairs of this block for the tile). The block walks its Gaussians in depth order, so each
+// tile's running position advances in depth order: the pass is stable.
 __global__ __launch_bounds__(kWave) void k_part_scatter(int n, const uint32_t* __restrict__ order,
-                                                        const uint64_t* __restrict__ offsets,
+                                                        const uint32_t* __restrict__ count,
                                                         const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                         const uint32_t* __restrict__ hist, int nblk,
                                                         const uint32_t* __restrict__ ranges, int64_t capacity,
                                                         uint32_t* __restrict__ gids_out) {
   __shared__ PartShared S;
-  const int cnt = part_load(S, n, order, offsets, rect);
+  const int cnt = part_load(S, n, order, count, rect);
   for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = ranges[t] + hist[(size_t)t * nblk + blockIdx.x];
   __syncthreads();
-  const int lane = threadIdx.x;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t beg = S.off[0], end = S.off[cnt];
-  for (uint64_t p0 = beg; p0 < end; p0 += kWave) {
-    const uint64_t p = p0 + lane;
-    const bool valid = p < end;
-    uint32_t g = 0, t = 0;
-    if (valid) t = part_pair(S, cnt, p, tiles_x, &g);
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kTileBits; ++b) {
-      const bool bit = (t >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
+  for (int r = 0; r < cnt; ++r) {
+    const int area = S.area[r], w = S.w[r], x0 = S.x0[r], y0 = S.y0[r];
+    const uint32_t g = S.gid[r];
+    for (int j = threadIdx.x; j < area; j += kWave) {
+      const int t = (y0 + j / w) * tiles_x + x0 + j % w;
+      const uint32_t pos = S.cnt[t];
+      S.cnt[t] = pos + 1u;
+      if ((int64_t)pos < capacity) gids_out[pos] = g;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    const uint32_t base = valid ? S.cnt[t] : 0u;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && (peers & lt_mask) == 0ull) S.cnt[t] = base + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (valid && (int64_t)(base + rank) < capacity) gids_out[base + rank] = g;
   }
 }
 
@@ -331,7 +300,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, w.offsets, p.rect, cam.tiles_x, ntiles,
+    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.count, p.rect, cam.tiles_x, ntiles,
                        w.phist, nblk);
   }
   {
@@ -342,7 +311,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   }
   {
     ProfScope ps(kProfTileScatter, st);
-    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, w.offsets, p.rect, cam.tiles_x, ntiles,
+    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.count, p.rect, cam.tiles_x, ntiles,
                        w.phist, nblk, out.ranges, out.capacity, out.gids);
   }
   if (out.keys) {

@@ -97,7 +97,7 @@ inline RasterConst make_raster(const ngs_raster_params& r) {
 enum ProfId {
   kProfPrepare = 0, kProfProject, kProfDepthHist, kProfDepthScan, kProfDepthScatter, kProfCountScan,
   kProfEmit, kProfRanges, kProfKeys64, kProfRender, kProfIgTiles, kProfIgFinalize, kProfHessianLogdet,
-  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfKernels
+  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfKernels
 };
 class ProfScope {
  public:
@@ -157,16 +157,17 @@ hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_t
 
 // Information gain (info_gain.hip, finalize.hip).
 struct IgWs {
-  float* acc;           // [stat_len(k)][max_slots] per-view screen statistics
-  int32_t* slot_of;     // [n] per-view slot, -1 when untouched
+  float* acc;           // [max_slots][astride] per-view screen statistics, slot-major
+  int astride;          // stat_len(k) rounded up to 16 floats
+  int32_t* slot_of;     // [n] per-view slot, -1 for Gaussians that are not reduced
   int32_t* gid_of;      // [max_slots]
   int32_t* n_slots;     // [1]
   int32_t* overflow;    // [1]
   int64_t max_slots;
 };
+int ig_stat_stride(int64_t k);
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
-hipError_t ig_reset(const IgWs& w, int n, hipStream_t st);
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
                            const IgWs& w, int64_t* stats, hipStream_t st);

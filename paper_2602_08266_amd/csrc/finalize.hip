@@ -8,26 +8,46 @@
 // P = du / d theta (6 x 11), the blocks are
 //   A_rgb = [[P^T Y_rgb P, P^T X_rgb], [X_rgb^T P, (sum a^2) I_3]]
 //   A_d   = P7^T Y_d P7,  P7 = [P; dZ/d theta]
-//   A_o   = [[P^T Y_o P, P^T X_o S], [S X_o^T P, (sum a^2) S S]],
+//   A_o   = [[P^T Y_o P, E S], [S E^T, (sum a^2) S S]],   E = P^T X_o,
 //   X_o = m1 p^T - Z_o,  S = diag(p) - p p^T (softmax Jacobian).
 // Information gain of the view (Eq. 5, 6, 9): sum_g logdet(H_T,g + c_g A_g) - logdet(H_T,g).
+//
+// The object block is never formed. Its logit part is lambda I + tau S S for every sum of
+// such blocks (p is fixed per Gaussian) and its cross part is E S, so the (11 + k)-square
+// block is held as (G, E, tau) and its log-det is taken through the Schur complement of
+// D = lambda I + tau S S:  logdet D + logdet(G - F^T D^-1 F),  F = S E^T.  S S is diagonal
+// plus rank two (diag(p^2) + U C U^T, U = [p, p^2], C = [[p.p, -1], [-1, 0]]), so D^-1 F and
+// logdet D follow from the Woodbury identity and the determinant lemma with one 2 x 2
+// system: O(11^2 k) work instead of a dense O(k^3) factorisation.
 #include "common.hpp"
 
 namespace ngs {
 namespace {
 
-constexpr int kFinThreads = 64;
-constexpr int kMaxL = kNGeo + NGS_MAX_K;  // 75
+constexpr int kFinThreads = 128;
+constexpr int kSmallL = 16;               // register rows of the dense factorisations (l <= 14)
+// Stored object block: G (packed upper 11 x 11), tau, lambda, E (11 x k, row-major), p (k).
+constexpr int kObjTau = 66, kObjLam = 67, kObjE = 68;
 
 struct FinShared {
-  double A[kMaxL * (kMaxL + 1) / 2];  // packed lower triangle
+  double A[105];           // packed upper triangle of the RGB (14) or depth (11) block, or G'
   double st[kStatScalar + 6 * NGS_MAX_K];
   double P[7][kNGeo];      // rows 0..5: du/dtheta, row 6: dZ/dtheta
   double Y[7][7];          // current symmetric screen matrix
   double YP[7][kNGeo];
-  double XS[6][NGS_MAX_K]; // X_o S, or X_rgb in its first 3 columns
+  double G[kNGeo][kNGeo];  // object block: geometry part
+  double E[kNGeo][NGS_MAX_K];
+  double F[NGS_MAX_K][kNGeo];
+  double X[NGS_MAX_K][kNGeo];
   double p[NGS_MAX_K];
-  double col[kMaxL];
+  double dinv[NGS_MAX_K];
+  double Ep[kNGeo];
+  double V[2][kNGeo];
+  double W[2][kNGeo];
+  double red[4][kFinThreads / kWave];
+  double tau;
+  double ldD;
+  double row[2][kSmallL];  // pivot row of the factorisation (double-buffered)
   int hs;                  // training-store slot
   int hs_new;
 };
@@ -143,51 +163,55 @@ __device__ void chain_rule(const float* mean, const float* log_scale, const floa
   P[5][10] = 1.0;
 }
 
-// Packed lower triangle: entry (i, c), c <= i, at i (i + 1) / 2 + c.
-__device__ __forceinline__ int lo_idx(int i, int c) { return i * (i + 1) / 2 + c; }
+// Entry (i, j) of the symmetric l x l matrix held as a packed upper triangle.
+__device__ __forceinline__ int sym_idx(int i, int j, int l) { return i <= j ? tri_idx(i, j, l) : tri_idx(j, i, l); }
 
-// Row-major packed upper index e -> (i, j), i <= j.
-__device__ __forceinline__ void upper_rc(int e, int l, int* i, int* j) {
-  int r = 0, rem = e;
-  while (rem >= l - r) { rem -= l - r; ++r; }
-  *i = r;
-  *j = r + rem;
-}
-
-// log det of the symmetric l x l matrix held as a packed lower triangle, by an in-place
-// LDL^T factorisation on one 64-lane workgroup (no square roots); the pivots' mantissas and
-// exponents are accumulated separately so that a single log is taken at the end. Returns
-// NaN if a pivot is not positive (matrix not positive definite).
-__device__ double ldl_logdet(double* A, int l, double* col) {
+// log det of the symmetric l x l matrix A (packed upper, in LDS) by LDL^T elimination with
+// one row per thread held in registers (LM >= l; rows and columns past l act as identity).
+// At step j the pivot row j is published in LDS; every later row i subtracts
+// (A_ij / A_jj) times it, A_ij being row j's entry i by symmetry of the trailing matrix.
+// The pivots' mantissas and exponents are accumulated separately and a single log is taken
+// at the end. Returns NaN if a pivot is not positive (matrix not positive definite).
+// Called by all kFinThreads threads of the block.
+template <int LM>
+__device__ double ldl_logdet(const double* A, int l, double (*row)[kSmallL]) {
+  const int i = threadIdx.x;
+  double a[LM];
+#pragma unroll
+  for (int c = 0; c < LM; ++c) a[c] = (i < l && c < l) ? A[sym_idx(i, c, l)] : (i == c ? 1.0 : 0.0);
   double mant = 1.0;
   int expo = 0;
+  bool bad = false;
   for (int j = 0; j < l; ++j) {
+    double* rb = row[j & 1];
+    if (i == j) {
+#pragma unroll
+      for (int c = 0; c < LM; ++c) rb[c] = a[c];
+    }
     __syncthreads();
-    const double d = A[lo_idx(j, j)];
-    if (!(d > 0.0)) return __builtin_nan("");
+    const double d = rb[j];
+    if (!(d > 0.0)) { bad = true; break; }
     int e1, e2;
     const double md = frexp(d, &e1);
     mant = frexp(mant * md, &e2);
     expo += e1 + e2;
-    const double inv = 1.0 / d;
-    for (int i = j + 1 + (int)threadIdx.x; i < l; i += kFinThreads) col[i] = A[lo_idx(i, j)];
-    __syncthreads();
-    const int m = l - j - 1;
-    const int ntri = m * (m + 1) / 2;
-    for (int e = threadIdx.x; e < ntri; e += kFinThreads) {
-      int ii = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
-      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      while (ii * (ii + 1) / 2 > e) --ii;
-      const int i = j + 1 + ii, c = j + 1 + (e - ii * (ii + 1) / 2);
-      A[lo_idx(i, c)] -= col[i] * col[c] * inv;
+    if (i > j && i < l) {
+      const double m = rb[i] / d;
+#pragma unroll
+      for (int c0 = 0; c0 < LM; c0 += 8) {
+        if (c0 + 8 > j + 1) {
+#pragma unroll
+          for (int c = c0; c < c0 + 8 && c < LM; ++c) a[c] -= m * rb[c];
+        }
+      }
     }
   }
   __syncthreads();
-  return log(mant) + (double)expo * 0.69314718055994530942;
+  return bad ? __builtin_nan("") : log(mant) + (double)expo * 0.69314718055994530942;
 }
 
-// Lower part of A[0..10][0..10] = Pr^T Y Pr over the first `rows` rows of P.
-__device__ void geo_block(FinShared& S, int rows) {
+// Upper part of A[0..10][0..10] = Pr^T Y Pr over the first `rows` rows of P (block dim l).
+__device__ void geo_block(FinShared& S, int rows, int l) {
   for (int e = threadIdx.x; e < rows * kNGeo; e += kFinThreads) {
     const int a = e / kNGeo, j = e % kNGeo;
     double v = 0.0;
@@ -195,12 +219,12 @@ __device__ void geo_block(FinShared& S, int rows) {
     S.YP[a][j] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kNGeo * (kNGeo + 1) / 2; e += kFinThreads) {
-    int i = 0, c = e;
-    while (c > i) { c -= i + 1; ++i; }
+  for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+    const int i = e / kNGeo, c = e % kNGeo;
+    if (c < i) continue;
     double v = 0.0;
     for (int a = 0; a < rows; ++a) v += S.P[a][i] * S.YP[a][c];
-    S.A[lo_idx(i, c)] = v;
+    S.A[tri_idx(i, c, l)] = v;
   }
 }
 
@@ -213,29 +237,123 @@ __device__ void load_sym(FinShared& S, int base, int dim) {
   __syncthreads();
 }
 
+// Block sums of up to four values per thread; every thread receives the totals.
+__device__ void block_sum4(FinShared& S, double (&v)[4]) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double x = v[q];
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (lane == 0) S.red[q][wave] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double x = 0.0;
+    for (int w = 0; w < kFinThreads / kWave; ++w) x += S.red[q][w];
+    v[q] = x;
+  }
+  __syncthreads();
+}
+
+// log det of the object block held as (G, E, tau) with p = S.p (see the file header).
+// G (11 x 11, full) and E (11 x k) are in S; tau > 0.
+__device__ double object_logdet(FinShared& S, int k, double lambda, double tau) {
+  // F = S E^T (k x 11): F[c][r] = p_c (E[r][c] - (E p)_r)
+  for (int r = threadIdx.x; r < kNGeo; r += kFinThreads) {
+    double v = 0.0;
+    for (int c = 0; c < k; ++c) v += S.E[r][c] * S.p[c];
+    S.Ep[r] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * kNGeo; e += kFinThreads) {
+    const int c = e / kNGeo, r = e % kNGeo;
+    S.F[c][r] = S.p[c] * (S.E[r][c] - S.Ep[r]);
+  }
+  // Delta = lambda + tau p^2; Z = U^T Delta^-1 U; sum log Delta; s = p.p
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double zs[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = threadIdx.x; c < k; c += kFinThreads) {
+    const double pc = S.p[c], p2 = pc * pc;
+    const double dl = lambda + tau * p2;
+    const double di = 1.0 / dl;
+    S.dinv[c] = di;
+    acc[0] += p2 * di;            // Z00
+    acc[1] += p2 * pc * di;       // Z01
+    acc[2] += p2 * p2 * di;       // Z11
+    acc[3] += p2;                 // s
+    zs[0] += log(dl);
+  }
+  block_sum4(S, acc);
+  block_sum4(S, zs);
+  const double z00 = acc[0], z01 = acc[1], z11 = acc[2], sp = acc[3];
+  // B = I + tau C Z
+  const double b00 = 1.0 + tau * (sp * z00 - z01), b01 = tau * (sp * z01 - z11);
+  const double b10 = -tau * z00, b11 = 1.0 - tau * z01;
+  const double detb = b00 * b11 - b01 * b10;
+  const double ld_d = zs[0] + log(detb);
+  // V = U^T Delta^-1 F (2 x 11); W = B^-1 tau C V; X = Delta^-1 (F - U W)
+  for (int e = threadIdx.x; e < 2 * kNGeo; e += kFinThreads) {
+    const int q = e / kNGeo, r = e % kNGeo;
+    double v = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const double pc = S.p[c];
+      v += (q == 0 ? pc : pc * pc) * S.dinv[c] * S.F[c][r];
+    }
+    S.V[q][r] = v;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < kNGeo; r += kFinThreads) {
+    const double c0 = tau * (sp * S.V[0][r] - S.V[1][r]);  // tau C V
+    const double c1 = -tau * S.V[0][r];
+    S.W[0][r] = (b11 * c0 - b01 * c1) / detb;
+    S.W[1][r] = (-b10 * c0 + b00 * c1) / detb;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * kNGeo; e += kFinThreads) {
+    const int c = e / kNGeo, r = e % kNGeo;
+    const double pc = S.p[c];
+    S.X[c][r] = S.dinv[c] * (S.F[c][r] - pc * S.W[0][r] - pc * pc * S.W[1][r]);
+  }
+  __syncthreads();
+  // G' = G - F^T X (upper part, packed, l = 11)
+  for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+    const int r = e / kNGeo, q = e % kNGeo;
+    if (q < r) continue;
+    double v = S.G[r][q];
+    for (int c = 0; c < k; ++c) v -= S.F[c][r] * S.X[c][q];
+    S.A[tri_idx(r, q, kNGeo)] = v;
+  }
+  __syncthreads();
+  return ld_d + ldl_logdet<kSmallL>(S.A, kNGeo, S.row);
+}
+
+__device__ __forceinline__ int block_dim(int f) { return f == 0 ? 14 : kNGeo; }
+__device__ __forceinline__ int store_len(int f, int k) { return f == 0 ? 105 : (f == 1 ? 66 : kObjE + 12 * k); }
+
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
     const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
-    uint32_t outputs, int mode, int conf_on_train, const float* __restrict__ acc, int stride,
+    uint32_t outputs, int mode, int conf_on_train, const float* __restrict__ acc, int astride, int max_slots,
     const int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots, const int32_t* __restrict__ overflow,
     ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
   __shared__ FinShared S;
-  const int used = min(*n_slots, stride);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (stats) atomicAdd((unsigned long long*)&stats[2], (unsigned long long)used);
-    if (*overflow) {
-      if (stats) atomicAdd((unsigned long long*)&stats[5], 1ull);
-      if (sticky) atomicOr(sticky, 1);
-    }
+  const int used = min(*n_slots, max_slots);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && *overflow) {
+    if (stats) atomicAdd((unsigned long long*)&stats[5], 1ull);
+    if (sticky) atomicOr(sticky, 1);
   }
   const int nst = stat_len(k);
-  const int lo = kNGeo + k;
   for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
     __syncthreads();
     const int g = gid_of[slot];
-    if (g < 0) continue;  // a slot left unused by a lost publication race
-    for (int s = threadIdx.x; s < nst; s += kFinThreads) S.st[s] = (double)acc[(size_t)s * stride + slot];
+    for (int s = threadIdx.x; s < nst; s += kFinThreads) S.st[s] = (double)acc[(size_t)slot * astride + s];
+    __syncthreads();
+    // a Gaussian that reached a tile but no pixel has no statistics: its gain is zero
+    const double a2 = S.st[kStatYd + tri_idx(6, 6, 7)];
+    if (!(a2 > 0.0)) continue;
     if (threadIdx.x == 0) {
+      if (stats) atomicAdd((unsigned long long*)&stats[2], 1ull);
       chain_rule(mean, log_scale, rot, n, g, cam, eps2d, S.P);
       S.hs = has_h ? h.slot_of[g] : -1;
       S.hs_new = 0;
@@ -244,9 +362,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     __syncthreads();
     const double cg = (double)conf[g];
     const double wacc = conf_on_train ? cg : 1.0;
-    const double a2 = S.st[kStatYd + tri_idx(6, 6, 7)];
     if (mode == NGS_MODE_ACCUMULATE) {
-      if (cg == 0.0) continue;  // never enters a gain: c_g = 0 makes the log-det difference 0
       if (threadIdx.x == 0 && S.hs < 0) {
         const int ns = atomicAdd(h.n_slots, 1);
         if (ns < h.capacity) { h.slot_of[g] = ns; h.gid_of[ns] = g; S.hs = ns; S.hs_new = 1; }
@@ -254,107 +370,125 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       __syncthreads();
       if (S.hs < 0) continue;  // store full: ngs_hessian_finalize reports it
     }
+    const int hs = S.hs;
+    const bool fresh = S.hs_new != 0;
+    // weight of this view's block, and whether a stored H_T is added
+    const double wv = mode == NGS_MODE_ACCUMULATE ? wacc : cg;
+    const bool stored = mode == NGS_MODE_ACCUMULATE ? !fresh : hs >= 0;
     for (int f = 0; f < 3; ++f) {
       if (!((outputs >> f) & 1u)) continue;
-      const int l = f == 0 ? 14 : (f == 1 ? kNGeo : lo);
-      // ---- build the lower triangle of A (unweighted) ----
-      for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) S.A[e] = 0.0;
-      __syncthreads();
-      if (f == 0) {
-        load_sym(S, kStatYrgb, 6);
-        geo_block(S, 6);
-        for (int e = threadIdx.x; e < kNGeo * 3; e += kFinThreads) {
-          const int i = e / 3, ch = e % 3;
-          double v = 0.0;
-          for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.st[kStatXrgb + a * 3 + ch];
-          S.A[lo_idx(kNGeo + ch, i)] = v;
-        }
-        if (threadIdx.x < 3) S.A[lo_idx(kNGeo + threadIdx.x, kNGeo + threadIdx.x)] = a2;
-      } else if (f == 1) {
-        load_sym(S, kStatYd, 7);
-        geo_block(S, 7);
-      } else {
-        load_sym(S, kStatYo, 6);
-        geo_block(S, 6);
-        // X_o S with X_o = m1 p^T - Z_o
-        for (int a = threadIdx.x; a < 6; a += kFinThreads) {
-          double xp = 0.0;
-          for (int c = 0; c < k; ++c) xp += (S.st[kStatM1 + a] * S.p[c] - S.st[kStatScalar + a * k + c]) * S.p[c];
-          for (int m = 0; m < k; ++m) {
-            const double x = S.st[kStatM1 + a] * S.p[m] - S.st[kStatScalar + a * k + m];
-            S.XS[a][m] = S.p[m] * (x - xp);
+      const int sl = store_len(f, k);
+      double* hblk = (f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o)) + (size_t)(hs < 0 ? 0 : hs) * sl;
+      double ld_m;
+      if (f < 2) {
+        const int l = block_dim(f);
+        const int tl = tri_len(l);
+        // ---- the upper triangle of A (unweighted) ----
+        for (int e = threadIdx.x; e < tl; e += kFinThreads) S.A[e] = 0.0;
+        __syncthreads();
+        if (f == 0) {
+          load_sym(S, kStatYrgb, 6);
+          geo_block(S, 6, l);
+          for (int e = threadIdx.x; e < kNGeo * 3; e += kFinThreads) {
+            const int i = e / 3, ch = e % 3;
+            double v = 0.0;
+            for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.st[kStatXrgb + a * 3 + ch];
+            S.A[tri_idx(i, kNGeo + ch, l)] = v;
           }
+          if (threadIdx.x < 3) S.A[tri_idx(kNGeo + threadIdx.x, kNGeo + threadIdx.x, l)] = a2;
+        } else {
+          load_sym(S, kStatYd, 7);
+          geo_block(S, 7, l);
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) {
-          const int i = e / k, m = e % k;
-          double v = 0.0;
-          for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.XS[a][m];
-          S.A[lo_idx(kNGeo + m, i)] = v;
+        // M = (stored H_T or lambda I) + w A
+        for (int e = threadIdx.x; e < tl; e += kFinThreads) S.A[e] = (stored ? hblk[e] : 0.0) + wv * S.A[e];
+        __syncthreads();
+        if (!stored)
+          for (int i = threadIdx.x; i < l; i += kFinThreads) S.A[tri_idx(i, i, l)] += lambda;
+        __syncthreads();
+        if (mode == NGS_MODE_ACCUMULATE) {
+          for (int e = threadIdx.x; e < tl; e += kFinThreads) hblk[e] = S.A[e];
+          continue;
         }
-        double s2 = 0.0;
-        for (int c = 0; c < k; ++c) s2 += S.p[c] * S.p[c];
-        for (int e = threadIdx.x; e < k * (k + 1) / 2; e += kFinThreads) {
-          int m = 0, j = e;
-          while (j > m) { j -= m + 1; ++m; }
-          const double pm = S.p[m], pj = S.p[j];
-          const double ss = (m == j ? pm * pm : 0.0) - pm * pm * pj - pm * pj * pj + pm * pj * s2;
-          S.A[lo_idx(kNGeo + m, kNGeo + j)] = a2 * ss;
-        }
-      }
-      __syncthreads();
-      double* hblk = f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o);
-      const int hs = S.hs;
-      if (mode == NGS_MODE_ACCUMULATE) {
-        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-          int i, j;
-          upper_rc(e, l, &i, &j);
-          double* hp = &hblk[(size_t)e * h.capacity + hs];
-          const double base = S.hs_new ? (i == j ? lambda : 0.0) : *hp;
-          *hp = base + wacc * S.A[lo_idx(j, i)];
-        }
-        continue;
-      }
-      // ---- SCORE: M = H_T + c A, gain = logdet M - logdet H_T ----
-      double ld_h;
-      if (hs >= 0) {
-        ld_h = h.logdet[(size_t)f * h.capacity + hs];
-        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-          int i, j;
-          upper_rc(e, l, &i, &j);
-          const int x = lo_idx(j, i);
-          S.A[x] = hblk[(size_t)e * h.capacity + hs] + cg * S.A[x];
-        }
+        ld_m = ldl_logdet<kSmallL>(S.A, l, S.row);
       } else {
-        ld_h = (double)l * log(lambda);
-        for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-          int i = 0, c = e;
-          while (c > i) { c -= i + 1; ++i; }
-          S.A[e] = cg * S.A[e] + (i == c ? lambda : 0.0);
+        // ---- object block as (G, E, tau) ----
+        load_sym(S, kStatYo, 6);
+        for (int e = threadIdx.x; e < 6 * kNGeo; e += kFinThreads) {
+          const int a = e / kNGeo, j = e % kNGeo;
+          double v = 0.0;
+          for (int b = 0; b < 6; ++b) v += S.Y[a][b] * S.P[b][j];
+          S.YP[a][j] = v;
         }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+          const int i = e / kNGeo, c = e % kNGeo;
+          if (c < i) continue;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) v += S.P[a][i] * S.YP[a][c];
+          const double base = stored ? hblk[tri_idx(i, c, kNGeo)] : (i == c ? lambda : 0.0);
+          v = base + wv * v;
+          S.G[i][c] = v;
+          S.G[c][i] = v;
+        }
+        // E = P^T (m1 p^T - Z_o)
+        for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) {
+          const int r = e / k, c = e % k;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) v += S.P[a][r] * (S.st[kStatM1 + a] * S.p[c] - S.st[kStatScalar + a * k + c]);
+          S.E[r][c] = (stored ? hblk[kObjE + r * k + c] : 0.0) + wv * v;
+        }
+        if (threadIdx.x == 0) S.tau = (stored ? hblk[kObjTau] : 0.0) + wv * a2;
+        __syncthreads();
+        if (mode == NGS_MODE_ACCUMULATE) {
+          for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+            const int i = e / kNGeo, c = e % kNGeo;
+            if (c >= i) hblk[tri_idx(i, c, kNGeo)] = S.G[i][c];
+          }
+          for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) hblk[kObjE + e] = S.E[e / k][e % k];
+          if (threadIdx.x == 0) {
+            hblk[kObjTau] = S.tau;
+            hblk[kObjLam] = lambda;
+          }
+          if (fresh)
+            for (int c = threadIdx.x; c < k; c += kFinThreads) hblk[kObjE + kNGeo * k + c] = S.p[c];
+          continue;
+        }
+        ld_m = object_logdet(S, k, lambda, S.tau);
       }
-      __syncthreads();
-      const double ld_m = ldl_logdet(S.A, l, S.col);
+      // ---- SCORE: gain = logdet M - logdet H_T ----
+      const int l = f == 2 ? kNGeo + k : block_dim(f);
+      const double ld_h = hs >= 0 ? h.logdet[(size_t)f * h.capacity + hs] : (double)l * log(lambda);
       if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], ld_m - ld_h);
     }
   }
 }
 
+// logdet of every stored block (after the last training view).
 __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, int used) {
   __shared__ FinShared S;
-  const int lo = kNGeo + h.k;
+  const int k = h.k;
   for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
     for (int f = 0; f < 3; ++f) {
-      const int l = f == 0 ? 14 : (f == 1 ? kNGeo : lo);
-      const double* hblk = f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o);
+      const int sl = store_len(f, k);
+      const double* hblk = (f == 0 ? h.h_rgb : (f == 1 ? h.h_d : h.h_o)) + (size_t)slot * sl;
       __syncthreads();
-      for (int e = threadIdx.x; e < tri_len(l); e += kFinThreads) {
-        int i, j;
-        upper_rc(e, l, &i, &j);
-        S.A[lo_idx(j, i)] = hblk[(size_t)e * h.capacity + slot];
+      double ld;
+      if (f < 2) {
+        for (int e = threadIdx.x; e < tri_len(block_dim(f)); e += kFinThreads) S.A[e] = hblk[e];
+        __syncthreads();
+        ld = ldl_logdet<kSmallL>(S.A, block_dim(f), S.row);
+      } else {
+        for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+          const int i = e / kNGeo, c = e % kNGeo;
+          S.G[i][c] = hblk[tri_idx(min(i, c), max(i, c), kNGeo)];
+        }
+        for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) S.E[e / k][e % k] = hblk[kObjE + e];
+        for (int c = threadIdx.x; c < k; c += kFinThreads) S.p[c] = hblk[kObjE + kNGeo * k + c];
+        __syncthreads();
+        ld = object_logdet(S, k, hblk[kObjLam], hblk[kObjTau]);
       }
-      __syncthreads();
-      const double ld = ldl_logdet(S.A, l, S.col);
       if (threadIdx.x == 0) h.logdet[(size_t)f * h.capacity + slot] = ld;
     }
   }
@@ -407,16 +541,16 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
   ProfScope ps(kProfIgFinalize, st);
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
                      s.prob, cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
-                     w.acc, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats, sticky);
+                     w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats,
+                     sticky);
   return hipGetLastError();
 }
 
 hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st) {
   const int used = std::min(n_slots, h->capacity);
   if (used <= 0) return hipSuccess;
-  const int blocks = std::min(used, 4096);
   ProfScope ps(kProfHessianLogdet, st);
-  hipLaunchKernelGGL(k_hessian_logdet, dim3(blocks), dim3(kFinThreads), 0, st, *h, used);
+  hipLaunchKernelGGL(k_hessian_logdet, dim3(std::min(used, 4096)), dim3(kFinThreads), 0, st, *h, used);
   (void)lambda_prior;
   return hipGetLastError();
 }

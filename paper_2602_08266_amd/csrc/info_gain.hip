@@ -11,16 +11,21 @@
 // the w's: the 94 + 6k statistics listed in common.hpp. This kernel produces them; the
 // FP64 chain rule through P, the blocks and the log-dets are in finalize.hip.
 //
+// Before the tile walk a pre-pass gives an accumulator slot to every Gaussian that has a
+// nonzero confidence weight and reaches at least one tile of the view, and zeroes the
+// slots; all other Gaussians get slot -1 and are never reduced.
+//
 // One 256-lane workgroup per tile. Pass 1 walks front to back to find each pixel's final
 // transmittance and last contributor. Pass 2 walks back to front from the tile's last
 // contributor, recovering T before each Gaussian as T_after / (1 - alpha) and keeping the
-// suffixes S in registers. For each Gaussian with a nonzero confidence weight, every
-// wavefront forms its pixels' statistic contributions in registers and sums them over its
-// 64 lanes with a recursive-halving reduce-scatter (64 statistics per round, 63 lane
-// exchanges), after which lane s holds statistic s and adds it to the Gaussian's
-// accumulator with one atomic. In both passes a wavefront only visits the batch entries whose
-// conservative 3-sigma bounding box reaches its 16 x 4 pixel strip (a ballot mask); the
-// skipped entries would fail the cut-off test at every one of its pixels.
+// suffixes S in registers. For each slotted Gaussian, the wavefront's contributing lanes
+// write their per-pixel records (and object suffixes) to LDS rows, packed by rank, 16 rows
+// at a time; then every lane owns statistics (one or two scalar ones and the six Z_o
+// entries of one object channel) and sums them over the packed rows only, so the cost
+// follows the number of contributing pixels, not the 64 lanes. The sums go to the slot
+// with atomic adds on contiguous addresses. In both passes a wavefront only visits the
+// batch entries whose conservative 3-sigma bounding box reaches its 16 x 4 pixel strip (a
+// ballot mask); the skipped entries would fail the cut-off test at every one of its pixels.
 #include "common.hpp"
 
 namespace ngs {
@@ -55,29 +60,20 @@ constexpr StatTable make_stat_table() {
 constexpr StatTable kStatTable = make_stat_table();
 static_assert(kStatTable.d[kStatScalar - 1].i0 == 13 && kStatTable.d[kStatYd + 27].i2 == 14, "statistic table layout");
 
-// Sums v over the 64 lanes of the wavefront and leaves entry l's total in lane l
-// (recursive halving: at each step a lane keeps the half of its window selected by one bit
-// of its lane id and adds the partner lane's copy of that half).
-__device__ __forceinline__ float wave_reduce_scatter64(float (&v)[kWave], int lane) {
-#pragma unroll
-  for (int s = kWave / 2; s >= 1; s >>= 1) {
-    const bool up = (lane & s) != 0;
-#pragma unroll
-    for (int i = 0; i < s; ++i) {
-      const float send = up ? v[i] : v[i + s];
-      const float keep = up ? v[i + s] : v[i];
-      v[i] = keep + __shfl_xor(send, s);
-    }
-  }
-  return v[0];
-}
+__constant__ StatTable c_stats = make_stat_table();
+
+constexpr int kChunk = 16;   // packed rows per reduction round
+constexpr int kRec = 24;     // record row: rv[16], a / (1 - alpha) * y[6], 0, 0
+constexpr int kZeroCol = 22; // always-zero column of a record row
 
 template <int KP>
 struct IgShared {
   float mx[kBatch], my[kBatch], qa[kBatch], qb[kBatch], qc[kBatch], op[kBatch];
-  float z[kBatch], r[kBatch], g[kBatch], b[kBatch], conf[kBatch], hx[kBatch], hy[kBatch];
-  uint32_t gid[kBatch];
+  float z[kBatch], r[kBatch], g[kBatch], b[kBatch], hx[kBatch], hy[kBatch];
+  int32_t slot[kBatch];
   float p[kBatch][KP];
+  float rec[kTilePix / kWave][kChunk][kRec];
+  float so[kTilePix / kWave][kChunk][KP];
   int flag;
 };
 
@@ -93,10 +89,9 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
     int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
-    const float* __restrict__ conf, int obj_eq2, float* __restrict__ acc, int32_t* __restrict__ slot_of,
-    int32_t* __restrict__ gid_of, int32_t* __restrict__ n_slots, int32_t* __restrict__ overflow, int max_slots,
+    int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
     int64_t* __restrict__ stats) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   IgShared<KP>& S = *reinterpret_cast<IgShared<KP>*>(smem_raw);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
@@ -107,7 +102,15 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
   const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
-  const int stride = max_slots;
+  // statistics owned by this lane in the reduction: scalar s = lane and 64 + lane (lanes
+  // past the 94 scalars point at the zero column), Z_o channel c of pixel group grp
+  constexpr int kGroups = kWave / KP;
+  const int zc = lane % KP, grp = lane / KP;
+  const int sB = kWave + lane;
+  const int a0 = c_stats.d[lane].i0, a1 = c_stats.d[lane].i1, a2 = c_stats.d[lane].i2;
+  const int b0 = sB < kStatScalar ? c_stats.d[sB].i0 : kZeroCol;
+  const int b1 = sB < kStatScalar ? c_stats.d[sB].i1 : kZeroCol;
+  const int b2 = sB < kStatScalar ? c_stats.d[sB].i2 : kZeroCol;
   // pixel-centre bounds of this wavefront's 16 x 4 strip
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
   const float sy0 = (float)(ty * kTile + wave * (kWave / kTile)) + 0.5f, sy1 = sy0 + (float)(kWave / kTile - 1);
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
   if (threadIdx.x == 0) S.flag = 0;
   __syncthreads();
   for (int i = (int)start + threadIdx.x; i <= tile_last; i += kTilePix)
-    if (conf[gids[i]] > 0.f) S.flag = 1;
+    if (slot_of[gids[i]] >= 0) S.flag = 1;
   __syncthreads();
   if (S.flag == 0) return;
 
@@ -184,12 +187,11 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
     if ((int)threadIdx.x < cnt) {
       const int j = threadIdx.x;
       const uint32_t g = gids[lo + j];
-      S.gid[j] = g;
+      S.slot[j] = slot_of[g];
       S.mx[j] = mean2d[g]; S.my[j] = mean2d[n + g];
       S.qa[j] = conic[g]; S.qb[j] = conic[n + g]; S.qc[j] = conic[2 * n + g];
       S.op[j] = opacity[g]; S.z[j] = depth[g];
       S.r[j] = rgb[g]; S.g[j] = rgb[n + g]; S.b[j] = rgb[2 * n + g];
-      S.conf[j] = conf[g];
       conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
     }
     for (int idx = threadIdx.x; idx < cnt * KP; idx += kTilePix) {
@@ -220,92 +222,93 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
         Tg = Tc * om;
         a = alpha * Tg;
       }
-      const float cw = S.conf[j];
-      if (cw > 0.f && __any(contrib)) {
-        // record of this lane's pixel (zeros when it does not contribute)
-        float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f, y4 = 0.f, y5 = 0.f;
-        float wr = 0.f, wg = 0.f, wb = 0.f, wd = 0.f, nrgb = 0.f, no = 0.f;
-        if (contrib) {
-          if (raw < rc.alpha_max) {
-            y0 = alpha * (S.qa[j] * dx + S.qb[j] * dy);
-            y1 = alpha * (S.qb[j] * dx + S.qc[j] * dy);
-            y2 = -0.5f * alpha * dx * dx;
-            y3 = -alpha * dx * dy;
-            y4 = -0.5f * alpha * dy * dy;
-            y5 = alpha * (1.f - S.op[j]);
-          }
-          wr = S.r[j] * Tg - Sr * om;
-          wg = S.g[j] * Tg - Sg * om;
-          wb = S.b[j] * Tg - Sb * om;
-          wd = S.z[j] * Tg - Sd * om;
-          nrgb = wr * wr + wg * wg + wb * wb;
+      const int slot = S.slot[j];
+      const uint64_t cmask = __ballot(contrib);
+      if (slot >= 0 && cmask) {
+        // record of this lane's pixel
+        float rv[16], zv[6];
+        {
+          float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f, y4 = 0.f, y5 = 0.f;
+          float wr = 0.f, wg = 0.f, wb = 0.f, wd = 0.f, nrgb = 0.f, no = 0.f;
+          if (contrib) {
+            if (raw < rc.alpha_max) {
+              y0 = alpha * (S.qa[j] * dx + S.qb[j] * dy);
+              y1 = alpha * (S.qb[j] * dx + S.qc[j] * dy);
+              y2 = -0.5f * alpha * dx * dx;
+              y3 = -alpha * dx * dy;
+              y4 = -0.5f * alpha * dy * dy;
+              y5 = alpha * (1.f - S.op[j]);
+            }
+            wr = S.r[j] * Tg - Sr * om;
+            wg = S.g[j] * Tg - Sg * om;
+            wb = S.b[j] * Tg - Sb * om;
+            wd = S.z[j] * Tg - Sd * om;
+            nrgb = wr * wr + wg * wg + wb * wb;
 #pragma unroll
-          for (int c = 0; c < KP; ++c) {
-            const float w = S.p[j][c] * Tg - So[c] * om;
-            no += w * w;
+            for (int c = 0; c < KP; ++c) {
+              const float w = S.p[j][c] * Tg - So[c] * om;
+              no += w * w;
+            }
           }
+          const float ao = a * om;
+          const float r16[16] = {y0, y1, y2, y3, y4, y5, a, wr, wg, wb, wd, nrgb, no, a * Tg, 1.f, wd * wd};
+#pragma unroll
+          for (int e = 0; e < 16; ++e) rv[e] = r16[e];
+          zv[0] = ao * y0; zv[1] = ao * y1; zv[2] = ao * y2; zv[3] = ao * y3; zv[4] = ao * y4; zv[5] = ao * y5;
         }
-        float rv[16] = {y0, y1, y2, y3, y4, y5, a, wr, wg, wb, wd, nrgb, no, a * Tg, 1.f, wd * wd};
-        const float ao = a * om;
-        const float zv[6] = {ao * y0, ao * y1, ao * y2, ao * y3, ao * y4, ao * y5};
-        // Slot of this Gaussian in the per-view accumulator. A new slot is taken from the
-        // counter, zeroed by the whole wavefront, and only then published in slot_of with a
-        // compare-and-swap (a wavefront that loses the race leaves its zeroed slot unused,
-        // marked by gid_of = -1); every later update of a published slot is an atomic add.
-        const uint32_t gq = S.gid[j];
-        int slot = -1, fresh = -1;
-        if (lane == 0) {
-          slot = __atomic_load_n(&slot_of[gq], __ATOMIC_RELAXED);
-          if (slot < 0) {
-            const int ns = atomicAdd(n_slots, 1);
-            if (ns >= max_slots) atomicOr(overflow, 1); else fresh = ns;
+        const int cnt = __popcll(cmask);
+        const int rank = __popcll(cmask & ((1ull << lane) - 1ull));
+        float (*rec)[kRec] = S.rec[wave];
+        float (*sov)[KP] = S.so[wave];
+        float accA = 0.f, accB = 0.f, z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+          if (contrib && rank >= c0 && rank < c0 + kChunk) {
+            float* row = rec[rank - c0];
+#pragma unroll
+            for (int e = 0; e < 16; e += 4) *reinterpret_cast<float4*>(row + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
+            *reinterpret_cast<float4*>(row + 16) = make_float4(zv[0], zv[1], zv[2], zv[3]);
+            *reinterpret_cast<float4*>(row + 20) = make_float4(zv[4], zv[5], 0.f, 0.f);
+            float* srow = sov[rank - c0];
+#pragma unroll
+            for (int c = 0; c < KP; c += 4) *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
           }
-        }
-        slot = __shfl(slot, 0);
-        fresh = __shfl(fresh, 0);
-        if (fresh >= 0) {
-          for (int s = lane; s < stat_len(k); s += kWave) acc[(size_t)s * stride + fresh] = 0.f;
-          __threadfence();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
-          if (lane == 0) {
-            const int old = atomicCAS(&slot_of[gq], -1, fresh);
-            gid_of[fresh] = (old == -1) ? (int)gq : -1;
-            slot = (old == -1) ? fresh : old;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          const int m = min(kChunk, cnt - c0);
+#pragma unroll
+          for (int r = 0; r < kChunk; ++r) {
+            if (r < m) {
+              accA += rec[r][a0] * rec[r][a1] * rec[r][a2];
+              accB += rec[r][b0] * rec[r][b1] * rec[r][b2];
+            }
           }
-          slot = __shfl(slot, 0);
+#pragma unroll
+          for (int t = 0; t < kChunk / kGroups; ++t) {
+            const int r = t * kGroups + grp;
+            if (t * kGroups < m && r < m) {
+              const float4 u = *reinterpret_cast<const float4*>(&rec[r][16]);
+              const float2 v = *reinterpret_cast<const float2*>(&rec[r][20]);
+              const float sv = sov[r][zc];
+              z[0] += u.x * sv; z[1] += u.y * sv; z[2] += u.z * sv; z[3] += u.w * sv;
+              z[4] += v.x * sv; z[5] += v.y * sv;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        if (slot >= 0) {
-          // Sum this lane's contributions over the wavefront, 64 statistics at a time: the
-          // padded statistic vector is [94 scalar statistics | Z_o as 6 x KP]; after the
-          // reduce-scatter lane l holds entry 64 q + l of chunk q.
-          constexpr int kLen = kStatScalar + 6 * KP;
 #pragma unroll
-          for (int q = 0; q < (kLen + kWave - 1) / kWave; ++q) {
-            float v[kWave];
+        for (int off = KP; off < kWave; off <<= 1)
 #pragma unroll
-            for (int e = 0; e < kWave; ++e) {
-              const int idx = q * kWave + e;
-              if (idx < kStatScalar) {
-                const StatDesc d = kStatTable.d[idx < kStatScalar ? idx : 0];
-                v[e] = rv[d.i0] * rv[d.i1] * rv[d.i2];
-              } else if (idx < kLen) {
-                const int f = idx - kStatScalar;
-                v[e] = zv[f / KP] * So[f % KP];
-              } else {
-                v[e] = 0.f;
-              }
-            }
-            const float tot = wave_reduce_scatter64(v, lane);
-            const int idx = q * kWave + lane;
-            int dst = -1;
-            if (idx < kStatScalar) {
-              dst = idx;
-            } else if (idx < kLen) {
-              const int f = idx - kStatScalar, c = f % KP;
-              if (c < k) dst = kStatScalar + (f / KP) * k + c;
-            }
-            if (dst >= 0 && tot != 0.f) atomicAdd(&acc[(size_t)dst * stride + slot], tot);
-          }
+          for (int i = 0; i < 6; ++i) z[i] += __shfl_xor(z[i], off);
+        float* dst = acc + (size_t)slot * astride;
+        if (accA != 0.f) atomicAdd(dst + lane, accA);
+        if (sB < kStatScalar && accB != 0.f) atomicAdd(dst + sB, accB);
+        if (grp == 0 && zc < k) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i)
+            if (z[i] != 0.f) atomicAdd(dst + kStatScalar + i * k + zc, z[i]);
         }
       }
       if (contrib) {
@@ -324,6 +327,69 @@ __global__ void k_ig_clear(int32_t* n_slots, int32_t* overflow) {
   *overflow = 0;
 }
 
+// Slot of every Gaussian for this view: a fresh slot for each one that has a nonzero
+// confidence weight and reaches a tile, -1 otherwise. Each 256-thread block covers
+// kAssignPer x 256 Gaussians (coalesced), ranks its selected ones with a block scan and
+// takes its slots with a single counter update.
+constexpr int kAssignPer = 16;
+
+__global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restrict__ conf,
+                                                   const uint32_t* __restrict__ count, int32_t* __restrict__ slot_of,
+                                                   int32_t* __restrict__ gid_of, int32_t* __restrict__ n_slots,
+                                                   int32_t* __restrict__ overflow, int max_slots) {
+  __shared__ int wsum[256 / kWave];
+  __shared__ int base_sh;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int g0 = blockIdx.x * (256 * kAssignPer) + threadIdx.x;
+  uint32_t bits = 0u;
+#pragma unroll
+  for (int i = 0; i < kAssignPer; ++i) {
+    const int g = g0 + i * 256;
+    if (g < n && count[g] > 0u && conf[g] > 0.f) bits |= 1u << i;
+  }
+  const int c = __popc(bits);
+  int x = c;  // inclusive scan over the wavefront
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) wsum[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < 256 / kWave; ++w) tot += wsum[w];
+    base_sh = tot ? atomicAdd(n_slots, tot) : 0;
+  }
+  __syncthreads();
+  int slot = base_sh + x - c;
+  for (int w = 0; w < wave; ++w) slot += wsum[w];
+#pragma unroll
+  for (int i = 0; i < kAssignPer; ++i) {
+    const int g = g0 + i * 256;
+    if (g >= n) break;
+    if (!((bits >> i) & 1u)) {
+      slot_of[g] = -1;
+    } else if (slot < max_slots) {
+      slot_of[g] = slot;
+      gid_of[slot] = g;
+      ++slot;
+    } else {
+      slot_of[g] = -1;
+      atomicOr(overflow, 1);
+      ++slot;
+    }
+  }
+}
+
+// Zero the statistic rows of the assigned slots.
+__global__ __launch_bounds__(256) void k_ig_zero(float4* __restrict__ acc, const int32_t* __restrict__ n_slots,
+                                                 int max_slots, int astride) {
+  const size_t total = (size_t)min(*n_slots, max_slots) * (size_t)(astride / 4);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+    acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 template <int KP>
 hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                        const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, hipStream_t st) {
@@ -331,16 +397,18 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
   const size_t shm = sizeof(IgShared<KP>);
   ProfScope ps(kProfIgTiles, st);
   hipLaunchKernelGGL(k_ig_tile<KP>, dim3(ntiles), dim3(kTilePix), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
-                     p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, s.conf, ig.obj_eq2, w.acc, w.slot_of,
-                     w.gid_of, w.n_slots, w.overflow, (int)w.max_slots, stats);
+                     p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
+                     stats);
   return hipGetLastError();
 }
 
 }  // namespace
 
+int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
+
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  return al((size_t)stat_len((int)k) * (size_t)max_slots * 4) + al((size_t)std::max<int64_t>(n, 1) * 4) +
+  return al((size_t)ig_stat_stride(k) * (size_t)max_slots * 4) + al((size_t)std::max<int64_t>(n, 1) * 4) +
          al((size_t)max_slots * 4) + al(8);
 }
 
@@ -348,7 +416,8 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   char* p = static_cast<char*>(ws);
   IgWs w;
-  w.acc = (float*)p; p += al((size_t)stat_len((int)k) * (size_t)max_slots * 4);
+  w.astride = ig_stat_stride(k);
+  w.acc = (float*)p; p += al((size_t)w.astride * (size_t)max_slots * 4);
   w.slot_of = (int32_t*)p; p += al((size_t)std::max<int64_t>(n, 1) * 4);
   w.gid_of = (int32_t*)p; p += al((size_t)max_slots * 4);
   w.n_slots = (int32_t*)p;
@@ -357,20 +426,23 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   return w;
 }
 
-// Per-view reset: no Gaussian holds a slot. Accumulator slots are zeroed when taken.
-hipError_t ig_reset(const IgWs& w, int n, hipStream_t st) {
-  return launch_fill_i32(w.slot_of, -1, (size_t)std::max(n, 1), st);
-}
-
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats,
                            hipStream_t st) {
-  hipError_t e = ig_reset(w, s.n, st);
-  if (e != hipSuccess) return e;
   {
     ProfScope ps(kProfFill, st);
     hipLaunchKernelGGL(k_ig_clear, dim3(1), dim3(1), 0, st, w.n_slots, w.overflow);
   }
+  {
+    ProfScope ps(kProfIgAssign, st);
+    const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
+    hipLaunchKernelGGL(k_ig_assign, dim3(nb), dim3(256), 0, st, s.n, s.conf, p.count, w.slot_of, w.gid_of,
+                       w.n_slots, w.overflow, (int)w.max_slots);
+    hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
+                       (int)w.max_slots, w.astride);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (s.k <= 4) return launch_ig_k<4>(s, p, l, cam, rc, ig, w, stats, st);
   if (s.k <= 8) return launch_ig_k<8>(s, p, l, cam, rc, ig, w, stats, st);
   if (s.k <= 16) return launch_ig_k<16>(s, p, l, cam, rc, ig, w, stats, st);

@@ -81,7 +81,9 @@ def test_information_gain_full_size(B, ctx, name):
     assert scene.target == gold["target_id"]
     ds = B.DeviceScene(scene, "cuda")
     ig = B.ig_params(target_id=scene.target)
-    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=48 << 20, max_slots=1 << 16,
+    # every Gaussian with a nonzero weight that reaches a tile takes a slot: up to n when the
+    # whole scene is scored
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=48 << 20, max_slots=max(scene.n, 1 << 16),
                          store_capacity=1 << 17)
     norm = scorer.setup([B.camera(c) for c in train])
     check_gain(norm, gold["norm"], "normalisers")
