@@ -5,7 +5,7 @@
 //   1. depth digits: the n Gaussians are sorted by their 32-bit depth key (4 passes over n
 //      entries instead of over the M >> n pairs); gid order breaks ties (stable LSD);
 //   2. one stable counting pass on the tile digit (<= 12 bits) over the pairs, fused with
-//      their generation: each single-wavefront block takes 256 consecutive depth ranks one
+//      their generation: each single-wavefront block takes 512 consecutive depth ranks one
 //      Gaussian at a time (its lanes spread over that Gaussian's rect), counts its pairs per
 //      tile (pass a), and after a scan over blocks and tiles (pass b) writes each pair's gid
 //      at its final position (pass c); per-tile positions advance in depth order.
@@ -85,47 +85,72 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
   }
 }
 
-constexpr int kPartRanks = 256;  // depth ranks per partition block (one wavefront)
+constexpr int kPartRanks = 512;  // depth ranks per partition block (one wavefront)
 
-// The block's ranks and rect geometry in LDS, plus one running counter per tile.
-struct PartShared {
-  uint32_t gid[kPartRanks];
-  int32_t x0[kPartRanks], y0[kPartRanks], w[kPartRanks], area[kPartRanks];
-  uint32_t cnt[NGS_MAX_TILES];
+// One Gaussian's rect as seen by the whole wavefront: lane q's values broadcast.
+struct RectU {
+  uint32_t gid;
+  int x0, y0, w, area;
+  float inv_w;
 };
 
-__device__ __forceinline__ int part_load(PartShared& S, int n, const uint32_t* __restrict__ order,
-                                         const uint32_t* __restrict__ count, const int16_t* __restrict__ rect) {
-  const int r0 = blockIdx.x * kPartRanks;
-  const int cnt = min(kPartRanks, n - r0);
-  for (int t = threadIdx.x; t < cnt; t += kWave) {
-    const uint32_t g = order[r0 + t];
-    S.gid[t] = g;
-    S.x0[t] = rect[g];
-    S.y0[t] = rect[n + g];
-    S.w[t] = rect[2 * n + g] - rect[g] + 1;
-    S.area[t] = (int)count[g];
+__device__ __forceinline__ void part_lane_load(int n, int r, const uint32_t* __restrict__ order,
+                                               const uint32_t* __restrict__ count, const int16_t* __restrict__ rect,
+                                               uint32_t* gid, int* x0, int* y0, int* w, int* area) {
+  *gid = 0u; *x0 = 0; *y0 = 0; *w = 1; *area = 0;
+  if (r < n) {
+    const uint32_t g = order[r];
+    *gid = g;
+    *x0 = rect[g];
+    *y0 = rect[n + g];
+    *w = rect[2 * n + g] - *x0 + 1;
+    *area = (int)count[g];
   }
-  return cnt;
 }
 
-// Pass a: pairs per (tile, block), tile-major: hist[t * nblk + block]. The block's Gaussians
-// are taken one at a time in depth order and the lanes spread over the tiles of the current
-// Gaussian's rect, which are distinct, so the per-tile counters need no atomics.
+__device__ __forceinline__ RectU part_bcast(uint32_t gid, int x0, int y0, int w, int area, int q) {
+  RectU u;
+  u.gid = (uint32_t)__builtin_amdgcn_readlane((int)gid, q);
+  u.x0 = __builtin_amdgcn_readlane(x0, q);
+  u.y0 = __builtin_amdgcn_readlane(y0, q);
+  u.w = __builtin_amdgcn_readlane(w, q);
+  u.area = __builtin_amdgcn_readlane(area, q);
+  u.inv_w = 1.f / (float)u.w;
+  return u;
+}
+
+// Tile of entry j (row-major) of the rect. (j + 0.5) / w lies at least 0.5 / w from an
+// integer; with j < 4096 the FP32 product errs by less than 4096 * 2^-23 / w, far inside
+// that margin, so the truncation gives the exact row.
+__device__ __forceinline__ int part_tile(const RectU& u, int j, int tiles_x) {
+  const int row = (int)(((float)j + 0.5f) * u.inv_w);
+  return (u.y0 + row) * tiles_x + u.x0 + (j - row * u.w);
+}
+
+// Pass a: pairs per (tile, block), tile-major: hist[t * nblk + block]. Each lane loads one
+// Gaussian of the current 64 ranks; the wavefront then takes them one at a time (values
+// broadcast from that lane) and spreads its lanes over the Gaussian's tiles, which are
+// distinct, adding to the per-tile counters with LDS atomics.
 __global__ __launch_bounds__(kWave) void k_part_hist(int n, const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ count,
                                                      const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                      uint32_t* __restrict__ hist, int nblk) {
-  __shared__ PartShared S;
-  for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = 0u;
-  const int cnt = part_load(S, n, order, count, rect);
+  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < ntiles; t += kWave) cnt[t] = 0u;
   __syncthreads();
-  for (int r = 0; r < cnt; ++r) {
-    const int area = S.area[r], w = S.w[r], x0 = S.x0[r], y0 = S.y0[r];
-    for (int j = threadIdx.x; j < area; j += kWave) S.cnt[(y0 + j / w) * tiles_x + x0 + j % w] += 1u;
+  const int r0 = blockIdx.x * kPartRanks;
+  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
+    uint32_t gid;
+    int x0, y0, w, area;
+    part_lane_load(n, r0 + sub + lane, order, count, rect, &gid, &x0, &y0, &w, &area);
+    for (int q = 0; q < kWave; ++q) {
+      const RectU u = part_bcast(gid, x0, y0, w, area, q);
+      for (int j = lane; j < u.area; j += kWave) atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
+    }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < ntiles; t += kWave) hist[(size_t)t * nblk + blockIdx.x] = S.cnt[t];
+  for (int t = lane; t < ntiles; t += kWave) hist[(size_t)t * nblk + blockIdx.x] = cnt[t];
 }
 
 // Pass b1: per tile, exclusive scan of its counts across blocks (in place); totals.
@@ -190,26 +215,30 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
 }
 
 // Pass c: every pair goes to ranges[tile] + (pairs of lower blocks for the tile) + (earlier
-// pairs of this block for the tile). The block walks its Gaussians in depth order, so each
-// tile's running position advances in depth order: the pass is stable.
+// pairs of this block for the tile). The wavefront takes its Gaussians one at a time in
+// depth order and its LDS atomics execute in program order, so each tile's running
+// position advances in depth order: the pass is stable.
 __global__ __launch_bounds__(kWave) void k_part_scatter(int n, const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ count,
                                                         const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                         const uint32_t* __restrict__ hist, int nblk,
                                                         const uint32_t* __restrict__ ranges, int64_t capacity,
                                                         uint32_t* __restrict__ gids_out) {
-  __shared__ PartShared S;
-  const int cnt = part_load(S, n, order, count, rect);
-  for (int t = threadIdx.x; t < ntiles; t += kWave) S.cnt[t] = ranges[t] + hist[(size_t)t * nblk + blockIdx.x];
+  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < ntiles; t += kWave) cnt[t] = ranges[t] + hist[(size_t)t * nblk + blockIdx.x];
   __syncthreads();
-  for (int r = 0; r < cnt; ++r) {
-    const int area = S.area[r], w = S.w[r], x0 = S.x0[r], y0 = S.y0[r];
-    const uint32_t g = S.gid[r];
-    for (int j = threadIdx.x; j < area; j += kWave) {
-      const int t = (y0 + j / w) * tiles_x + x0 + j % w;
-      const uint32_t pos = S.cnt[t];
-      S.cnt[t] = pos + 1u;
-      if ((int64_t)pos < capacity) gids_out[pos] = g;
+  const int r0 = blockIdx.x * kPartRanks;
+  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
+    uint32_t gid;
+    int x0, y0, w, area;
+    part_lane_load(n, r0 + sub + lane, order, count, rect, &gid, &x0, &y0, &w, &area);
+    for (int q = 0; q < kWave; ++q) {
+      const RectU u = part_bcast(gid, x0, y0, w, area, q);
+      for (int j = lane; j < u.area; j += kWave) {
+        const uint32_t pos = atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
+        if ((int64_t)pos < capacity) gids_out[pos] = u.gid;
+      }
     }
   }
 }

@@ -33,38 +33,77 @@ namespace {
 
 constexpr int kBatch = 32;
 
-// Statistic s of a pixel is rv[i0] * rv[i1] * rv[i2] over the per-pixel record
-// rv = (y[6], a, w_rgb[3], w_d, |w_rgb|^2, |w_o|^2, a T, 1, w_d^2), in the order of
-// common.hpp: Y_rgb (upper 6x6), X_rgb (6x3), Y_d (upper 7x7 of e = (w_d y, a)), Y_o, m1.
-struct StatDesc { unsigned char i0, i1, i2; };
-struct StatTable { StatDesc d[kStatScalar]; };
+// Per-pixel record of a contributing (pixel, Gaussian) pair, laid out so that every scalar
+// statistic of common.hpp is the product of two of its entries:
+//   [0, 6) y   [6, 12) |w_rgb|^2 y   [12, 18) |w_o|^2 y   [18, 24) w_d^2 y
+//   [24, 30) a / (1 - alpha) y  (Z_o's left factor)
+//   30 a w_r, 31 a w_g, 32 a w_b, 33 a w_d, 34 a T, 35 a
+// y = d alpha / d(m_x, m_y, Q_xx, Q_xy, Q_yy, l), a = alpha T, w = d out / d alpha.
+constexpr int kRec = 36;  // 36 floats apart: the 16 rows of a chunk start on distinct 4-bank groups
+constexpr int kRecZ = 24, kRecAW = 30, kRecAT = 34, kRecA = 35;
+
+struct StatPair { unsigned char u, v; };
+struct StatTable { StatPair d[kStatScalar]; };
 
 constexpr StatTable make_stat_table() {
   StatTable t{};
   int s = 0;
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) t.d[s++] = {11, (unsigned char)i, (unsigned char)j};
-  for (int i = 0; i < 6; ++i)
-    for (int ch = 0; ch < 3; ++ch) t.d[s++] = {6, (unsigned char)i, (unsigned char)(7 + ch)};
-  for (int i = 0; i < 7; ++i)
+  for (int i = 0; i < 6; ++i)  // Y_rgb
+    for (int j = i; j < 6; ++j) t.d[s++] = {(unsigned char)(6 + i), (unsigned char)j};
+  for (int i = 0; i < 6; ++i)  // X_rgb
+    for (int ch = 0; ch < 3; ++ch) t.d[s++] = {(unsigned char)i, (unsigned char)(kRecAW + ch)};
+  for (int i = 0; i < 7; ++i)  // Y_d over e = (w_d y, a)
     for (int j = i; j < 7; ++j) {
-      if (j < 6) t.d[s++] = {15, (unsigned char)i, (unsigned char)j};
-      else if (i < 6) t.d[s++] = {10, (unsigned char)i, 6};
-      else t.d[s++] = {6, 6, 14};
+      if (j < 6) t.d[s++] = {(unsigned char)(18 + i), (unsigned char)j};
+      else if (i < 6) t.d[s++] = {(unsigned char)i, (unsigned char)(kRecAW + 3)};
+      else t.d[s++] = {(unsigned char)kRecA, (unsigned char)kRecA};
     }
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) t.d[s++] = {12, (unsigned char)i, (unsigned char)j};
-  for (int i = 0; i < 6; ++i) t.d[s++] = {13, (unsigned char)i, 14};
+  for (int i = 0; i < 6; ++i)  // Y_o
+    for (int j = i; j < 6; ++j) t.d[s++] = {(unsigned char)(12 + i), (unsigned char)j};
+  for (int i = 0; i < 6; ++i) t.d[s++] = {(unsigned char)i, (unsigned char)kRecAT};  // m1
   return t;
 }
 constexpr StatTable kStatTable = make_stat_table();
-static_assert(kStatTable.d[kStatScalar - 1].i0 == 13 && kStatTable.d[kStatYd + 27].i2 == 14, "statistic table layout");
+static_assert(kStatTable.d[kStatM1].v == kRecAT && kStatTable.d[kStatYd + 27].u == kRecA, "statistic table layout");
 
 __constant__ StatTable c_stats = make_stat_table();
 
 constexpr int kChunk = 16;   // packed rows per reduction round
-constexpr int kRec = 24;     // record row: rv[16], a / (1 - alpha) * y[6], 0, 0
-constexpr int kZeroCol = 22; // always-zero column of a record row
+
+// Adds R packed rows into this lane's statistics: the scalar statistics (u_a, v_a) and
+// (u_b, v_b), and Z_o for channel zc over the rows of its pixel group. Rows past the
+// contributing lanes hold zero records, so no row needs masking.
+template <int R, int KP>
+__device__ __forceinline__ void reduce_rows(const float (*rec)[kRec], const float (*sov)[KP + 4], int ua, int va,
+                                            int ub, int vb, int grp, int zc, float& accA, float& accB,
+                                            float (&z)[6]) {
+  constexpr int kGroups = kWave / KP;
+  constexpr int kStep = 4;  // rows per iteration: enough loads in flight, few registers
+#pragma unroll 1
+  for (int r0 = 0; r0 < R; r0 += kStep) {
+#pragma unroll
+    for (int r = r0; r < r0 + kStep; ++r) {
+      accA += rec[r][ua] * rec[r][va];
+      accB += rec[r][ub] * rec[r][vb];
+    }
+  }
+  constexpr int kRowsPerGroup = (R + kGroups - 1) / kGroups;
+  constexpr int kZStep = kRowsPerGroup < kStep ? kRowsPerGroup : kStep;
+#pragma unroll 1
+  for (int t0 = 0; t0 < kRowsPerGroup; t0 += kZStep) {
+#pragma unroll
+    for (int t = t0; t < t0 + kZStep; ++t) {
+      const int r = t * kGroups + grp;
+      if (kGroups > 1 && t * kGroups >= R) break;
+      const int rr = r < R ? r : R - 1;
+      const float4 u = *reinterpret_cast<const float4*>(&rec[rr][kRecZ]);
+      const float2 v = *reinterpret_cast<const float2*>(&rec[rr][kRecZ + 4]);
+      const float sv = r < R ? sov[rr][zc] : 0.f;
+      z[0] += u.x * sv; z[1] += u.y * sv; z[2] += u.z * sv; z[3] += u.w * sv;
+      z[4] += v.x * sv; z[5] += v.y * sv;
+    }
+  }
+}
 
 template <int KP>
 struct IgShared {
@@ -73,7 +112,7 @@ struct IgShared {
   int32_t slot[kBatch];
   float p[kBatch][KP];
   float rec[kTilePix / kWave][kChunk][kRec];
-  float so[kTilePix / kWave][kChunk][KP];
+  float so[kTilePix / kWave][kChunk][KP + 4];  // padded like the record rows
   int flag;
 };
 
@@ -85,7 +124,7 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
 }
 
 template <int KP>
-__global__ __launch_bounds__(kTilePix) void k_ig_tile(
+__global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
     int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
@@ -102,15 +141,13 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
   const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
-  // statistics owned by this lane in the reduction: scalar s = lane and 64 + lane (lanes
-  // past the 94 scalars point at the zero column), Z_o channel c of pixel group grp
+  // statistics owned by this lane in the reduction: scalar s = lane and 64 + lane (the
+  // second one is dropped past the 94 scalars), Z_o channel zc of pixel group grp
   constexpr int kGroups = kWave / KP;
   const int zc = lane % KP, grp = lane / KP;
   const int sB = kWave + lane;
-  const int a0 = c_stats.d[lane].i0, a1 = c_stats.d[lane].i1, a2 = c_stats.d[lane].i2;
-  const int b0 = sB < kStatScalar ? c_stats.d[sB].i0 : kZeroCol;
-  const int b1 = sB < kStatScalar ? c_stats.d[sB].i1 : kZeroCol;
-  const int b2 = sB < kStatScalar ? c_stats.d[sB].i2 : kZeroCol;
+  const int ua = c_stats.d[lane].u, va = c_stats.d[lane].v;
+  const int ub = sB < kStatScalar ? c_stats.d[sB].u : 0, vb = sB < kStatScalar ? c_stats.d[sB].v : 0;
   // pixel-centre bounds of this wavefront's 16 x 4 strip
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
   const float sy0 = (float)(ty * kTile + wave * (kWave / kTile)) + 0.5f, sy1 = sy0 + (float)(kWave / kTile - 1);
@@ -225,19 +262,19 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
       const int slot = S.slot[j];
       const uint64_t cmask = __ballot(contrib);
       if (slot >= 0 && cmask) {
-        // record of this lane's pixel
-        float rv[16], zv[6];
+        // record of this lane's pixel (all zero when it does not contribute)
+        float rv[kRec];
         {
-          float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f, y4 = 0.f, y5 = 0.f;
+          float y[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
           float wr = 0.f, wg = 0.f, wb = 0.f, wd = 0.f, nrgb = 0.f, no = 0.f;
           if (contrib) {
             if (raw < rc.alpha_max) {
-              y0 = alpha * (S.qa[j] * dx + S.qb[j] * dy);
-              y1 = alpha * (S.qb[j] * dx + S.qc[j] * dy);
-              y2 = -0.5f * alpha * dx * dx;
-              y3 = -alpha * dx * dy;
-              y4 = -0.5f * alpha * dy * dy;
-              y5 = alpha * (1.f - S.op[j]);
+              y[0] = alpha * (S.qa[j] * dx + S.qb[j] * dy);
+              y[1] = alpha * (S.qb[j] * dx + S.qc[j] * dy);
+              y[2] = -0.5f * alpha * dx * dx;
+              y[3] = -alpha * dx * dy;
+              y[4] = -0.5f * alpha * dy * dy;
+              y[5] = alpha * (1.f - S.op[j]);
             }
             wr = S.r[j] * Tg - Sr * om;
             wg = S.g[j] * Tg - Sg * om;
@@ -250,50 +287,46 @@ __global__ __launch_bounds__(kTilePix) void k_ig_tile(
               no += w * w;
             }
           }
-          const float ao = a * om;
-          const float r16[16] = {y0, y1, y2, y3, y4, y5, a, wr, wg, wb, wd, nrgb, no, a * Tg, 1.f, wd * wd};
+          const float ao = a * om, wd2 = wd * wd;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) rv[e] = r16[e];
-          zv[0] = ao * y0; zv[1] = ao * y1; zv[2] = ao * y2; zv[3] = ao * y3; zv[4] = ao * y4; zv[5] = ao * y5;
+          for (int i = 0; i < 6; ++i) {
+            rv[i] = y[i];
+            rv[6 + i] = nrgb * y[i];
+            rv[12 + i] = no * y[i];
+            rv[18 + i] = wd2 * y[i];
+            rv[kRecZ + i] = ao * y[i];
+          }
+          rv[kRecAW] = a * wr; rv[kRecAW + 1] = a * wg; rv[kRecAW + 2] = a * wb; rv[kRecAW + 3] = a * wd;
+          rv[kRecAT] = a * Tg; rv[kRecA] = a;
         }
         const int cnt = __popcll(cmask);
-        const int rank = __popcll(cmask & ((1ull << lane) - 1ull));
+        const uint64_t below = (1ull << lane) - 1ull;
+        const int rank = __popcll(cmask & below);       // among contributing lanes
+        const int nrank = __popcll(~cmask & below);     // among the others
         float (*rec)[kRec] = S.rec[wave];
-        float (*sov)[KP] = S.so[wave];
+        float (*sov)[KP + 4] = S.so[wave];
         float accA = 0.f, accB = 0.f, z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-          if (contrib && rank >= c0 && rank < c0 + kChunk) {
-            float* row = rec[rank - c0];
+          // rows [0, m) take the next contributing lanes; a short last chunk is padded to
+          // R rows with the (zero) records of non-contributing lanes
+          const int m = min(kChunk, cnt - c0);
+          const int R = m > kChunk / 2 ? kChunk : kChunk / 2;
+          const int row = contrib ? rank - c0 : m + nrank;
+          if (contrib ? (row >= 0 && row < m) : (row < R)) {
+            float* dst = rec[row];
 #pragma unroll
-            for (int e = 0; e < 16; e += 4) *reinterpret_cast<float4*>(row + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
-            *reinterpret_cast<float4*>(row + 16) = make_float4(zv[0], zv[1], zv[2], zv[3]);
-            *reinterpret_cast<float4*>(row + 20) = make_float4(zv[4], zv[5], 0.f, 0.f);
-            float* srow = sov[rank - c0];
+            for (int e = 0; e < kRec; e += 4) *reinterpret_cast<float4*>(dst + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
+            float* srow = sov[row];
 #pragma unroll
             for (int c = 0; c < KP; c += 4) *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          const int m = min(kChunk, cnt - c0);
-#pragma unroll
-          for (int r = 0; r < kChunk; ++r) {
-            if (r < m) {
-              accA += rec[r][a0] * rec[r][a1] * rec[r][a2];
-              accB += rec[r][b0] * rec[r][b1] * rec[r][b2];
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < kChunk / kGroups; ++t) {
-            const int r = t * kGroups + grp;
-            if (t * kGroups < m && r < m) {
-              const float4 u = *reinterpret_cast<const float4*>(&rec[r][16]);
-              const float2 v = *reinterpret_cast<const float2*>(&rec[r][20]);
-              const float sv = sov[r][zc];
-              z[0] += u.x * sv; z[1] += u.y * sv; z[2] += u.z * sv; z[3] += u.w * sv;
-              z[4] += v.x * sv; z[5] += v.y * sv;
-            }
-          }
+          if (R == kChunk)
+            reduce_rows<kChunk, KP>(rec, sov, ua, va, ub, vb, grp, zc, accA, accB, z);
+          else
+            reduce_rows<kChunk / 2, KP>(rec, sov, ua, va, ub, vb, grp, zc, accA, accB, z);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
