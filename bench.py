@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--workload", default="batched640")
     ap.add_argument("--views", type=int, default=None, help="limit candidate views per step")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--in-flight", type=int, default=8, help="candidate views scored concurrently")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -134,7 +135,8 @@ def main():
     ds = B.DeviceScene(scene, "cuda:0")
     rp = B.raster_params()
     ig = B.ig_params(target_id=scene.target)
-    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=48 << 20, max_slots=1 << 16, store_capacity=1 << 17)
+    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=48 << 20, max_slots=1 << 16, store_capacity=1 << 17,
+                         views_in_flight=args.in_flight)
     cam_c = [B.camera(c) for c in cands]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -187,7 +189,8 @@ def main():
         "config": {"workload": f"{args.workload}: {scene.n} Gaussians, {cfg.clusters} clusters, k={scene.k}, "
                                f"{V} candidate views at {cands[0].width}x{cands[0].height}, object-centric target "
                                f"{scene.target}, radius U{list(cfg.radius)} m, 4 training views",
-                   "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact"},
+                   "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
+                   "views_in_flight": args.in_flight},
         "roofline": roofline,
         "setup_ms": round(setup_ms, 1),
         "pairs_per_view": M_step / V, "walked_entries_per_view": W_step / V,

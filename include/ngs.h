@@ -169,9 +169,11 @@ typedef struct {
 #define NGS_STATS_LEN 6
 
 /* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch.
- * dims: n, k, width, height, pair capacity, slot capacity (all host). */
+ * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
+ * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
+ * at most 16). All host. */
 typedef struct {
-  int64_t n, k, width, height, max_pairs, max_slots;
+  int64_t n, k, width, height, max_pairs, max_slots, views_in_flight;
 } ngs_dims;
 
 /* ---------------------------------------------------------------------------------
@@ -239,7 +241,11 @@ ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream);
  * stats (device int64 [NGS_STATS_LEN], may be NULL) accumulates (stats[1]: pairs of all
  * views); on return stats[0] = n_views. Returns NGS_DEGENERATE if an enabled normaliser is
  * not positive, NGS_CAPACITY if a view overflows dims->max_pairs or dims->max_slots. ws:
- * ngs_workspace_size(2, dims) bytes, carved by the same dims (host); syncs once per batch. */
+ * ngs_workspace_size(2, dims) bytes, carved by the same dims (host); syncs once per batch.
+ * Up to dims->views_in_flight views run concurrently on streams of the context (created
+ * on first use, non-blocking, default priority) that wait for the work already queued on
+ * `stream` and that `stream` waits for before the combination; view v uses buffer set
+ * v mod views_in_flight. Calls on one context must not overlap. */
 ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
                            const double* normalisers, const ngs_camera* cams, int32_t n_views,
                            const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores,

@@ -79,7 +79,7 @@ class ngs_hessian(C.Structure):
 
 class ngs_dims(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("width", C.c_int64), ("height", C.c_int64),
-                ("max_pairs", C.c_int64), ("max_slots", C.c_int64)]
+                ("max_pairs", C.c_int64), ("max_slots", C.c_int64), ("views_in_flight", C.c_int64)]
 
 
 _lib = None
@@ -259,8 +259,8 @@ class Hessian:
 
 
 def workspace_size(op: int, n: int, k: int, width: int = 0, height: int = 0, max_pairs: int = 0,
-                   max_slots: int = 0) -> int:
-    d = ngs_dims(n, k, width, height, max_pairs, max_slots)
+                   max_slots: int = 0, views_in_flight: int = 0) -> int:
+    d = ngs_dims(n, k, width, height, max_pairs, max_slots, views_in_flight)
     b = C.c_size_t()
     _check("ngs_workspace_size", lib().ngs_workspace_size(op, _ref(d), C.byref(b)))
     return int(b.value)
@@ -359,10 +359,10 @@ def ngs_hessian_finalize(ctx: Context, h: Hessian):
 class ScoreWorkspace:
     """Scratch of ngs_score_batch and the dims it was sized (and is carved) with."""
 
-    def __init__(self, scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16):
-        self.dims = ngs_dims(scene.n, scene.k, 0, 0, max_pairs, max_slots)
-        self.buf = _bytes(workspace_size(2, scene.n, scene.k, max_pairs=max_pairs, max_slots=max_slots),
-                          scene.device)
+    def __init__(self, scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16, views_in_flight: int = 0):
+        self.dims = ngs_dims(scene.n, scene.k, 0, 0, max_pairs, max_slots, views_in_flight)
+        self.buf = _bytes(workspace_size(2, scene.n, scene.k, max_pairs=max_pairs, max_slots=max_slots,
+                                         views_in_flight=views_in_flight), scene.device)
 
 
 def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], normalisers: Sequence[float],
@@ -384,8 +384,9 @@ def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], norm
     return scores[:nv], best, ig_raw[:nv]
 
 
-def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16) -> ScoreWorkspace:
-    return ScoreWorkspace(scene, max_pairs, max_slots)
+def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16,
+                    views_in_flight: int = 0) -> ScoreWorkspace:
+    return ScoreWorkspace(scene, max_pairs, max_slots, views_in_flight)
 
 
 def ngs_profile_enable(ctx: Context, on: bool):
@@ -411,9 +412,10 @@ class NbvScorer:
     """Training setup (H_T and Eq. 10 normalisers) and candidate scoring on one GPU."""
 
     def __init__(self, ctx: Context, scene: DeviceScene, rp: ngs_raster_params, ig: ngs_ig_params,
-                 max_pairs: int = 1 << 24, max_slots: int = 1 << 16, store_capacity: int = 1 << 17):
+                 max_pairs: int = 1 << 24, max_slots: int = 1 << 16, store_capacity: int = 1 << 17,
+                 views_in_flight: int = 0):
         self.ctx, self.scene, self.rp, self.ig = ctx, scene, rp, ig
-        self.max_pairs, self.max_slots = max_pairs, max_slots
+        self.max_pairs, self.max_slots, self.views_in_flight = max_pairs, max_slots, views_in_flight
         ngs_prepare_scene(ctx, scene, ig)
         self.h = Hessian(scene.n, scene.k, store_capacity, scene.device)
         self.igws = IgWorkspace(scene, max_slots)
@@ -446,5 +448,5 @@ class NbvScorer:
 
     def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None):
         if self.ws is None:
-            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots)
+            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
         return ngs_score_batch(self.ctx, self.scene, self.h, self.norm, cams, self.rp, self.ig, self.ws, stats)

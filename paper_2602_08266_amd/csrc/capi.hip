@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 
@@ -11,6 +12,11 @@ struct ngs_ctx {
   int device = 0;
   int32_t last_hip = 0;
   int64_t* pinned = nullptr;  // host-pinned scratch for reading device counters
+  // Non-blocking streams (default priority) on which ngs_score_batch keeps several views in
+  // flight, and the events that fork them from and join them to the caller's stream.
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -121,6 +127,32 @@ size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
          al(2 * NGS_MAX_TILES * 4) + al(8) + al(bin_ws_bytes(n, max_pairs));
 }
 
+constexpr int kDefaultInFlight = 8;
+constexpr int kMaxInFlight = 16;
+
+int views_in_flight(const ngs_dims* d) {
+  return d->views_in_flight <= 0 ? kDefaultInFlight : (int)std::min<int64_t>(d->views_in_flight, kMaxInFlight);
+}
+
+// Creates the context's in-flight streams and events up to `want`.
+ngs_status ensure_lanes(ngs_ctx* ctx, int want) {
+  if (!ctx->fork) NGS_TRY_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  while ((int)ctx->lanes.size() < want) {
+    hipStream_t s = nullptr;
+    NGS_TRY_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      ctx->last_hip = (int32_t)err;
+      return NGS_HIP_ERROR;
+    }
+    ctx->lanes.push_back(s);
+    ctx->lane_done.push_back(e);
+  }
+  return NGS_OK;
+}
+
 BatchWs batch_carve(void* ws, size_t ws_bytes, int64_t n, int64_t max_pairs) {
   const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
   char* p = static_cast<char*>(ws);
@@ -169,6 +201,10 @@ ngs_status ngs_create(int device, ngs_ctx** out) {
 
 ngs_status ngs_destroy(ngs_ctx* ctx) {
   if (!ctx) return NGS_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  for (hipStream_t s : ctx->lanes) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : ctx->lane_done) (void)hipEventDestroy(e);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return NGS_OK;
@@ -198,7 +234,7 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
   switch (op) {
     case 0: *bytes = bin_ws_bytes(d->n, d->max_pairs); return NGS_OK;
     case 1: *bytes = igb; return NGS_OK;
-    case 2: *bytes = batch_fixed_bytes(d->n, d->max_pairs) + igb; return NGS_OK;
+    case 2: *bytes = (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + igb); return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
 }
@@ -348,22 +384,43 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
   if (s != NGS_OK) return s;
   if (ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
   const int64_t max_pairs = dims->max_pairs;
-  BatchWs b = batch_carve(ws, need, scene->n, max_pairs);
-  IgWs w;
-  int32_t* sticky = nullptr;
-  s = ig_prepare(ctx, b.ig, b.ig_bytes, scene->n, scene->k, st, &w, &sticky);
+  const int lanes = std::max(1, std::min(views_in_flight(dims), n_views));
+  s = ensure_lanes(ctx, lanes);
   if (s != NGS_OK) return s;
+  // one buffer set per in-flight view; the first set's IG header holds the sticky overflow
+  // flag that every set reports into
+  const size_t per = need / (size_t)views_in_flight(dims);
+  std::vector<BatchWs> sets(lanes);
+  std::vector<IgWs> igs(lanes);
+  int32_t* sticky = nullptr;
+  for (int i = 0; i < lanes; ++i) {
+    sets[i] = batch_carve(static_cast<char*>(ws) + (size_t)i * per, per, scene->n, max_pairs);
+    int32_t* own = nullptr;
+    s = ig_prepare(ctx, sets[i].ig, sets[i].ig_bytes, scene->n, scene->k, st, &igs[i], &own);
+    if (s != NGS_OK) return s;
+    if (i == 0) sticky = own;
+  }
   NGS_TRY_HIP(ctx, hipMemsetAsync(ig_raw, 0, (size_t)3 * sizeof(double) * std::max(n_views, 1), st));
-  const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
+  NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
+  for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   // No host synchronisation inside the loop: list overflow is caught on the device (empty
-  // ranges, sticky flag) and reported once the batch has run.
+  // ranges, sticky flag) and reported once the batch has run. View v runs on lane v mod
+  // lanes, which reuses that lane's buffers in stream order.
   for (int v = 0; v < n_views; ++v) {
+    const int i = v % lanes;
+    hipStream_t ls = ctx->lanes[i];
+    const BatchWs& b = sets[i];
+    const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
     const DevCam dc = make_devcam(cams[v], kTile);
-    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
-    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, st));
-    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, w, stats, st));
-    NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_raw + 3 * (size_t)v, stats, sticky, st));
+    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
+    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls));
+    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats, ls));
+    NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v, stats, sticky, ls));
+  }
+  for (int i = 0; i < lanes; ++i) {
+    NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ctx->lanes[i]));
+    NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
   }
   NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, normalisers[0], normalisers[1], normalisers[2], ig->beta_d,
                                         ig->beta_o, ig->outputs, scores, best, st));

@@ -68,7 +68,9 @@ static_assert(kStatTable.d[kStatM1].v == kRecAT && kStatTable.d[kStatYd + 27].u 
 
 __constant__ StatTable c_stats = make_stat_table();
 
-constexpr int kChunk = 16;   // packed rows per reduction round
+// Packed rows per reduction round: 16, or 8 when four lanes share a pixel (16 pixels per
+// wavefront) so that the rows of all 16 wavefronts fit in LDS.
+template <int LPP> constexpr int chunk_rows() { return LPP == 4 ? 8 : 16; }
 
 // Adds R packed rows into this lane's statistics: the scalar statistics (u_a, v_a) and
 // (u_b, v_b), and Z_o for channel zc over the rows of its pixel group. Rows past the
@@ -105,14 +107,14 @@ __device__ __forceinline__ void reduce_rows(const float (*rec)[kRec], const floa
   }
 }
 
-template <int KP>
+template <int KP, int LPP>
 struct IgShared {
   float mx[kBatch], my[kBatch], qa[kBatch], qb[kBatch], qc[kBatch], op[kBatch];
   float z[kBatch], r[kBatch], g[kBatch], b[kBatch], hx[kBatch], hy[kBatch];
   int32_t slot[kBatch];
   float p[kBatch][KP];
-  float rec[kTilePix / kWave][kChunk][kRec];
-  float so[kTilePix / kWave][kChunk][KP + 4];  // padded like the record rows
+  float rec[kTilePix * LPP / kWave][chunk_rows<LPP>()][kRec];
+  float so[kTilePix * LPP / kWave][chunk_rows<LPP>()][KP + 4];  // padded like the record rows
   int flag;
 };
 
@@ -123,20 +125,27 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
          S.my[l] - S.hy[l] <= sy1;
 }
 
-template <int KP>
-__global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
+template <int KP, int LPP>
+__global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_ig_tile(
     int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
     int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
     int64_t* __restrict__ stats) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  IgShared<KP>& S = *reinterpret_cast<IgShared<KP>*>(smem_raw);
+  IgShared<KP, LPP>& S = *reinterpret_cast<IgShared<KP, LPP>*>(smem_raw);
+  constexpr int kThreads = kTilePix * LPP;
+  constexpr int kChunk = chunk_rows<LPP>();
+  constexpr int KL = KP / LPP;           // object channels held per lane
+  constexpr int kRowsW = kWave / LPP / kTile;  // pixel rows per wavefront
+  // lanes of the wavefront that are the first of their pixel
+  constexpr uint64_t kH0 = LPP == 1 ? ~0ull : (LPP == 2 ? 0x5555555555555555ull : 0x1111111111111111ull);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int py = ty * kTile + (threadIdx.x / kTile);
+  const int pix = threadIdx.x / LPP, h = threadIdx.x % LPP;  // pixel, and part of its channels
+  const int px = tx * kTile + (pix & (kTile - 1));
+  const int py = ty * kTile + (pix / kTile);
   const bool inside = px < cam.width && py < cam.height;
   const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -148,9 +157,9 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
   const int sB = kWave + lane;
   const int ua = c_stats.d[lane].u, va = c_stats.d[lane].v;
   const int ub = sB < kStatScalar ? c_stats.d[sB].u : 0, vb = sB < kStatScalar ? c_stats.d[sB].v : 0;
-  // pixel-centre bounds of this wavefront's 16 x 4 strip
+  // pixel-centre bounds of this wavefront's 16 x kRowsW strip
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
-  const float sy0 = (float)(ty * kTile + wave * (kWave / kTile)) + 0.5f, sy1 = sy0 + (float)(kWave / kTile - 1);
+  const float sy0 = (float)(ty * kTile + wave * kRowsW) + 0.5f, sy1 = sy0 + (float)(kRowsW - 1);
 
   // ---- pass 1: front to back, final transmittance and last contributor -----------------
   float T = 1.f;
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
   const int tile_last = S.flag;
   if (stats) {
     // contributing (pixel, Gaussian) pairs P
-    int tot = nc;
+    int tot = h == 0 ? nc : 0;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     if (lane == 0 && tot) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)tot);
     if (threadIdx.x == 0 && tile_last >= 0)
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
   __syncthreads();
   if (threadIdx.x == 0) S.flag = 0;
   __syncthreads();
-  for (int i = (int)start + threadIdx.x; i <= tile_last; i += kTilePix)
+  for (int i = (int)start + threadIdx.x; i <= tile_last; i += kThreads)
     if (slot_of[gids[i]] >= 0) S.flag = 1;
   __syncthreads();
   if (S.flag == 0) return;
@@ -213,10 +222,10 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
   const float t_final = T;
   float Tc = T;
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Sd = 0.f;
-  float So[KP];
+  float So[KL];  // channels h * KL ... (h + 1) * KL - 1 of the object suffix
 #pragma unroll
-  for (int c = 0; c < KP; ++c) So[c] = 0.f;
-  if (obj_eq2) So[0] = t_final;  // S~ = S_o + T_final e_0
+  for (int c = 0; c < KL; ++c) So[c] = 0.f;
+  if (obj_eq2 && h == 0) So[0] = t_final;  // S~ = S_o + T_final e_0
   for (int hi = tile_last + 1; hi > (int)start; hi -= kBatch) {
     const int lo = max((int)start, hi - kBatch);
     const int cnt = hi - lo;
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
       S.r[j] = rgb[g]; S.g[j] = rgb[n + g]; S.b[j] = rgb[2 * n + g];
       conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
     }
-    for (int idx = threadIdx.x; idx < cnt * KP; idx += kTilePix) {
+    for (int idx = threadIdx.x; idx < cnt * KP; idx += kThreads) {
       const int j = idx / KP, c = idx % KP;
       S.p[j][c] = (c < k) ? prob[(size_t)gids[lo + j] * k + c] : 0.f;
     }
@@ -282,11 +291,13 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
             wd = S.z[j] * Tg - Sd * om;
             nrgb = wr * wr + wg * wg + wb * wb;
 #pragma unroll
-            for (int c = 0; c < KP; ++c) {
-              const float w = S.p[j][c] * Tg - So[c] * om;
+            for (int c = 0; c < KL; ++c) {
+              const float w = S.p[j][h * KL + c] * Tg - So[c] * om;
               no += w * w;
             }
           }
+#pragma unroll
+          for (int off = 1; off < LPP; off <<= 1) no += __shfl_xor(no, off);
           const float ao = a * om, wd2 = wd * wd;
 #pragma unroll
           for (int i = 0; i < 6; ++i) {
@@ -299,10 +310,13 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
           rv[kRecAW] = a * wr; rv[kRecAW + 1] = a * wg; rv[kRecAW + 2] = a * wb; rv[kRecAW + 3] = a * wd;
           rv[kRecAT] = a * Tg; rv[kRecA] = a;
         }
-        const int cnt = __popcll(cmask);
-        const uint64_t below = (1ull << lane) - 1ull;
-        const int rank = __popcll(cmask & below);       // among contributing lanes
-        const int nrank = __popcll(~cmask & below);     // among the others
+        // pixels (first lanes) that contribute; ranks of this lane's pixel among them and
+        // among the others
+        const uint64_t pmask = cmask & kH0;
+        const int cnt = __popcll(pmask);
+        const uint64_t below = (1ull << (lane - h)) - 1ull;
+        const int rank = __popcll(pmask & below);
+        const int nrank = __popcll(~pmask & kH0 & below);
         float (*rec)[kRec] = S.rec[wave];
         float (*sov)[KP + 4] = S.so[wave];
         float accA = 0.f, accB = 0.f, z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -313,12 +327,14 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
           const int R = m > kChunk / 2 ? kChunk : kChunk / 2;
           const int row = contrib ? rank - c0 : m + nrank;
           if (contrib ? (row >= 0 && row < m) : (row < R)) {
-            float* dst = rec[row];
+            if (h == 0) {
+              float* dst = rec[row];
 #pragma unroll
-            for (int e = 0; e < kRec; e += 4) *reinterpret_cast<float4*>(dst + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
-            float* srow = sov[row];
+              for (int e = 0; e < kRec; e += 4) *reinterpret_cast<float4*>(dst + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
+            }
+            float* srow = sov[row] + h * KL;
 #pragma unroll
-            for (int c = 0; c < KP; c += 4) *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
+            for (int c = 0; c < KL; c += 4) *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
@@ -348,7 +364,7 @@ __global__ __launch_bounds__(kTilePix, 3) void k_ig_tile(
         Sr += S.r[j] * a; Sg += S.g[j] * a; Sb += S.b[j] * a;
         Sd += S.z[j] * a;
 #pragma unroll
-        for (int c = 0; c < KP; ++c) So[c] += S.p[j][c] * a;
+        for (int c = 0; c < KL; ++c) So[c] += S.p[j][h * KL + c] * a;
         Tc = Tg;
       }
     }
@@ -423,13 +439,14 @@ __global__ __launch_bounds__(256) void k_ig_zero(float4* __restrict__ acc, const
     acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int KP>
+template <int KP, int LPP>
 hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                        const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
-  const size_t shm = sizeof(IgShared<KP>);
+  const size_t shm = sizeof(IgShared<KP, LPP>);
+  static_assert(sizeof(IgShared<KP, LPP>) <= 65536, "IG kernel LDS");
   ProfScope ps(kProfIgTiles, st);
-  hipLaunchKernelGGL(k_ig_tile<KP>, dim3(ntiles), dim3(kTilePix), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
+  hipLaunchKernelGGL((k_ig_tile<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
                      stats);
   return hipGetLastError();
@@ -476,11 +493,11 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (s.k <= 4) return launch_ig_k<4>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 8) return launch_ig_k<8>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 16) return launch_ig_k<16>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 32) return launch_ig_k<32>(s, p, l, cam, rc, ig, w, stats, st);
-  return launch_ig_k<64>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 4) return launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 8) return launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 16) return launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 32) return launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  return launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, stats, st);
 }
 
 }  // namespace ngs
