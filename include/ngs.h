@@ -104,14 +104,15 @@ typedef struct {
   int32_t mode;
 } ngs_ig_params;
 
-/* Per-view projection (one entry per Gaussian). rect is inclusive tile bounds
- * (x0, y0, x1, y1); count = number of tiles (0: culled). zkey = bits of float32(Z). */
+/* Per-view projection (one entry per Gaussian). rect holds each Gaussian's inclusive
+ * tile bounds (x0, y0, x1, y1) together (8 bytes, 8-byte aligned; a culled Gaussian has
+ * (0, 0, -1, -1)); count = number of tiles (0: culled). zkey = bits of float32(Z). */
 typedef struct {
   float* mean2d;    /* [2][n] */
   float* conic;     /* [3][n] Q = Sigma2^-1: xx, xy, yy */
   float* depth;     /* [n] camera-space Z */
   uint32_t* zkey;   /* [n] */
-  int16_t* rect;    /* [4][n] */
+  int16_t* rect;    /* [n][4] */
   uint32_t* count;  /* [n] */
 } ngs_projected;
 

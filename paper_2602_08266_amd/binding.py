@@ -285,7 +285,7 @@ def ngs_project(ctx: Context, scene: DeviceScene, cam: ngs_camera, rp: ngs_raste
                     torch.empty((3, n), dtype=torch.float32, device=dev),
                     torch.empty(n, dtype=torch.float32, device=dev),
                     torch.empty(n, dtype=torch.int32, device=dev),
-                    torch.empty((4, n), dtype=torch.int16, device=dev),
+                    torch.empty((n, 4), dtype=torch.int16, device=dev),
                     torch.empty(n, dtype=torch.int32, device=dev))
     sc, pc = scene.c(), out.c()
     _check("ngs_project", lib().ngs_project(ctx.handle, _ref(sc), _ref(cam), _ref(rp), _ref(pc), _stream()), ctx)

@@ -94,29 +94,49 @@ struct RectU {
   float inv_w;
 };
 
-__device__ __forceinline__ void part_lane_load(int n, int r, const uint32_t* __restrict__ order,
-                                               const uint32_t* __restrict__ count, const int16_t* __restrict__ rect,
-                                               uint32_t* gid, int* x0, int* y0, int* w, int* area) {
-  *gid = 0u; *x0 = 0; *y0 = 0; *w = 1; *area = 0;
+// A lane's Gaussian of rank r: gid, tile origin packed as x0 | y0 << 16, width, area and
+// 1 / width (area 0 past n or for a culled Gaussian).
+struct RectL {
+  uint32_t gid, org;
+  int w, area;
+  float inv_w;
+};
+
+__device__ __forceinline__ RectL part_lane_load(int n, int r, const uint32_t* __restrict__ order,
+                                                const int16_t* __restrict__ rect) {
+  RectL l{0u, 0u, 1, 0, 1.f};
   if (r < n) {
     const uint32_t g = order[r];
-    *gid = g;
-    *x0 = rect[g];
-    *y0 = rect[n + g];
-    *w = rect[2 * n + g] - *x0 + 1;
-    *area = (int)count[g];
+    const short4 b = reinterpret_cast<const short4*>(rect)[g];
+    l.gid = g;
+    l.org = (uint32_t)(uint16_t)b.x | ((uint32_t)(uint16_t)b.y << 16);
+    l.w = b.z - b.x + 1;
+    l.area = b.z >= b.x ? l.w * (b.w - b.y + 1) : 0;
+    l.w = l.area > 0 ? l.w : 1;
+    l.inv_w = 1.f / (float)l.w;
   }
+  return l;
 }
 
-__device__ __forceinline__ RectU part_bcast(uint32_t gid, int x0, int y0, int w, int area, int q) {
+__device__ __forceinline__ RectU part_bcast(const RectL& l, int q) {
   RectU u;
-  u.gid = (uint32_t)__builtin_amdgcn_readlane((int)gid, q);
-  u.x0 = __builtin_amdgcn_readlane(x0, q);
-  u.y0 = __builtin_amdgcn_readlane(y0, q);
-  u.w = __builtin_amdgcn_readlane(w, q);
-  u.area = __builtin_amdgcn_readlane(area, q);
-  u.inv_w = 1.f / (float)u.w;
+  u.gid = (uint32_t)__builtin_amdgcn_readlane((int)l.gid, q);
+  const uint32_t org = (uint32_t)__builtin_amdgcn_readlane((int)l.org, q);
+  u.x0 = (int)(org & 0xFFFFu);
+  u.y0 = (int)(org >> 16);
+  u.w = __builtin_amdgcn_readlane(l.w, q);
+  u.area = __builtin_amdgcn_readlane(l.area, q);
+  u.inv_w = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, l.inv_w), q));
   return u;
+}
+
+// Rank chunk of partition block b. Workgroups are dealt to the 8 XCDs round robin, so
+// block b runs on XCD b % 8; giving each XCD a contiguous range of chunks keeps adjacent
+// pieces of every tile's output segment (and of the count table) in one L2.
+__device__ __forceinline__ int part_chunk(int b, int nblk) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, q = nblk / kXcd, r = nblk % kXcd;
+  return x * q + min(x, r) + b / kXcd;
 }
 
 // Tile of entry j (row-major) of the rect. (j + 0.5) / w lies at least 0.5 / w from an
@@ -132,25 +152,23 @@ __device__ __forceinline__ int part_tile(const RectU& u, int j, int tiles_x) {
 // broadcast from that lane) and spreads its lanes over the Gaussian's tiles, which are
 // distinct, adding to the per-tile counters with LDS atomics.
 __global__ __launch_bounds__(kWave) void k_part_hist(int n, const uint32_t* __restrict__ order,
-                                                     const uint32_t* __restrict__ count,
                                                      const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                      uint32_t* __restrict__ hist, int nblk) {
   __shared__ uint32_t cnt[NGS_MAX_TILES];
   const int lane = threadIdx.x;
+  const int chunk = part_chunk(blockIdx.x, nblk);
   for (int t = lane; t < ntiles; t += kWave) cnt[t] = 0u;
   __syncthreads();
-  const int r0 = blockIdx.x * kPartRanks;
+  const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
-    uint32_t gid;
-    int x0, y0, w, area;
-    part_lane_load(n, r0 + sub + lane, order, count, rect, &gid, &x0, &y0, &w, &area);
+    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
     for (int q = 0; q < kWave; ++q) {
-      const RectU u = part_bcast(gid, x0, y0, w, area, q);
+      const RectU u = part_bcast(l, q);
       for (int j = lane; j < u.area; j += kWave) atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
     }
   }
   __syncthreads();
-  for (int t = lane; t < ntiles; t += kWave) hist[(size_t)t * nblk + blockIdx.x] = cnt[t];
+  for (int t = lane; t < ntiles; t += kWave) hist[(size_t)t * nblk + chunk] = cnt[t];
 }
 
 // Pass b1: per tile, exclusive scan of its counts across blocks (in place); totals.
@@ -219,22 +237,20 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
 // depth order and its LDS atomics execute in program order, so each tile's running
 // position advances in depth order: the pass is stable.
 __global__ __launch_bounds__(kWave) void k_part_scatter(int n, const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ count,
                                                         const int16_t* __restrict__ rect, int tiles_x, int ntiles,
                                                         const uint32_t* __restrict__ hist, int nblk,
                                                         const uint32_t* __restrict__ ranges, int64_t capacity,
                                                         uint32_t* __restrict__ gids_out) {
   __shared__ uint32_t cnt[NGS_MAX_TILES];
   const int lane = threadIdx.x;
-  for (int t = lane; t < ntiles; t += kWave) cnt[t] = ranges[t] + hist[(size_t)t * nblk + blockIdx.x];
+  const int chunk = part_chunk(blockIdx.x, nblk);
+  for (int t = lane; t < ntiles; t += kWave) cnt[t] = ranges[t] + hist[(size_t)t * nblk + chunk];
   __syncthreads();
-  const int r0 = blockIdx.x * kPartRanks;
+  const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
-    uint32_t gid;
-    int x0, y0, w, area;
-    part_lane_load(n, r0 + sub + lane, order, count, rect, &gid, &x0, &y0, &w, &area);
+    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
     for (int q = 0; q < kWave; ++q) {
-      const RectU u = part_bcast(gid, x0, y0, w, area, q);
+      const RectU u = part_bcast(l, q);
       for (int j = lane; j < u.area; j += kWave) {
         const uint32_t pos = atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
         if ((int64_t)pos < capacity) gids_out[pos] = u.gid;
@@ -329,8 +345,8 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.count, p.rect, cam.tiles_x, ntiles,
-                       w.phist, nblk);
+    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, cam.tiles_x, ntiles, w.phist,
+                       nblk);
   }
   {
     ProfScope ps(kProfTileScan, st);
@@ -340,7 +356,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   }
   {
     ProfScope ps(kProfTileScatter, st);
-    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.count, p.rect, cam.tiles_x, ntiles,
+    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, cam.tiles_x, ntiles,
                        w.phist, nblk, out.ranges, out.capacity, out.gids);
   }
   if (out.keys) {

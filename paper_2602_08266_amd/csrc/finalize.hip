@@ -345,13 +345,15 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   }
   const int nst = stat_len(k);
   for (int slot = blockIdx.x; slot < used; slot += gridDim.x) {
+    // a Gaussian that reached a tile but no pixel has no statistics (sum a^2 = 0): its gain
+    // is zero and its row is not read
+    const float a2f = acc[(size_t)slot * astride + kStatYd + tri_idx(6, 6, 7)];
+    if (!(a2f > 0.f)) continue;
     __syncthreads();
     const int g = gid_of[slot];
     for (int s = threadIdx.x; s < nst; s += kFinThreads) S.st[s] = (double)acc[(size_t)slot * astride + s];
     __syncthreads();
-    // a Gaussian that reached a tile but no pixel has no statistics: its gain is zero
     const double a2 = S.st[kStatYd + tri_idx(6, 6, 7)];
-    if (!(a2 > 0.0)) continue;
     if (threadIdx.x == 0) {
       if (stats) atomicAdd((unsigned long long*)&stats[2], 1ull);
       chain_rule(mean, log_scale, rot, n, g, cam, eps2d, S.P);

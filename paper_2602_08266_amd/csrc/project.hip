@@ -129,10 +129,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   depth[g] = zf;
   zkey[g] = valid ? __float_as_uint(zf) : 0xFFFFFFFFu;
   if (!valid) { x0 = 0; y0 = 0; x1 = -1; y1 = -1; }
-  rect[g] = (int16_t)x0;
-  rect[n + g] = (int16_t)y0;
-  rect[2 * n + g] = (int16_t)x1;
-  rect[3 * n + g] = (int16_t)y1;
+  reinterpret_cast<short4*>(rect)[g] = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
   count[g] = valid ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
 }
 

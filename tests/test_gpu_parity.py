@@ -72,7 +72,7 @@ def test_project_bitexact_keys_and_rects(B, ctx, wl, view):
     assert np.array_equal(cnt > 0, valid)
     zk = pr.zkey.cpu().numpy().view(np.uint32)
     assert np.array_equal(zk[valid], ref["zkey"][valid])
-    rect = pr.rect.cpu().numpy().astype(np.int32)
+    rect = pr.rect.cpu().numpy().astype(np.int32).T  # [n][4] -> [4][n]
     assert np.array_equal(rect[:, valid], ref["rect"][:, valid])
     area = (ref["rect"][2] - ref["rect"][0] + 1) * (ref["rect"][3] - ref["rect"][1] + 1)
     assert np.array_equal(cnt[valid], area[valid])
