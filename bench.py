@@ -35,8 +35,9 @@ def kernel_source_hash(files):
 
 
 # Algorithmic HBM bytes per kernel class, from per-step counts: n Gaussians, k, views V,
-# pairs M (summed over views), walked (tile, list entry) pairs W.
-def algorithmic_bytes(name, n, k, V, M, W):
+# pairs M, walked (tile, list entry) pairs W and touched weighted Gaussians U (all summed
+# over the step's views).
+def algorithmic_bytes(name, n, k, V, M, W, U):
     if name == "project":
         return V * n * (40 + 40)                 # mean, log-scale, quaternion in; 2D mean, conic, depth, key, rect, count out
     if name == "depth_sort_scatter":
@@ -46,12 +47,22 @@ def algorithmic_bytes(name, n, k, V, M, W):
     if name == "count_scan":
         return V * n * 16
     if name == "tile_part_hist":
-        return V * n * 24                        # rank order, offsets, rects of every Gaussian
+        return V * n * 12                        # rank order and the rect of every Gaussian
     if name == "tile_part_scatter":
-        return 4 * M + V * n * 24                # final gid per pair + the same per-Gaussian reads
+        return 4 * M + V * n * 12                # final gid per pair + the same per-Gaussian reads
     if name == "ig_tiles":
-        return W * (4 + 24)                      # list entry + projected geometry per walked entry
+        # list entry + projected geometry per walked entry; object row and statistics
+        # (94 + 6k floats written) of every touched weighted Gaussian
+        return W * (4 + 24) + U * (4 * k + 40) + U * 4 * (94 + 6 * k)
     return None
+
+
+def path_bytes(n, k, V, M, U):
+    """Compulsory HBM bytes of one scoring step (all views): geometry and c_g read, the
+    projection written and read back, every pair emitted once and reordered once, the
+    touched Gaussians' object rows, statistics written and read, and their stored training
+    blocks read (factored object block)."""
+    return V * n * 48 + V * n * 72 + M * 36 + U * (4 * k + 40) + U * 8 * (94 + 6 * k) + U * 8 * (105 + 66 + 68 + 12 * k)
 
 
 KERNEL_FILES = {
@@ -77,19 +88,20 @@ def read_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(workload_name, seed, threads=None):
-    """The FP64 oracle timed on the host on a bounded sample: one candidate view of the
-    workload scored against H_T = lambda I (training blocks would triple the time)."""
+def cpu_baseline(workload_name, seed, views=3, threads=None):
+    """The FP64 oracle timed on the host on a bounded sample: the first `views` candidate
+    views of the workload scored against H_T = lambda I (training blocks would triple the
+    time). Each view's work is split across the oracle's threads."""
     import oracle
     import scenegen
     cfg, scene, cands, train = scenegen.make_workload(workload_name, seed)
     ig = oracle.IGParams(target_id=scene.target)
     th = threads or oracle.default_threads()
     t0 = time.perf_counter()
-    r = oracle.score(scene, [], cands[:1], ig=ig, threads=th)
+    oracle.score(scene, [], cands[:views], ig=ig, threads=th)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "views/s", "cores": th, "kind": "oracle",
-            "sample": f"1 candidate view ({cands[0].width}x{cands[0].height}, {scene.n} Gaussians, k={scene.k}, "
+    return {"value": views / dt, "unit": "views/s", "cores": th, "kind": "oracle",
+            "sample": f"{views} candidate views ({cands[0].width}x{cands[0].height}, {scene.n} Gaussians, k={scene.k}, "
                       f"object-centric), H_T = lambda I, FP64, {dt:.1f} s"}
 
 
@@ -165,12 +177,13 @@ def main():
     # per step counts (stats accumulate over the timed calls)
     M_step = int(st[1]) / K
     W_step = int(st[4]) / K
+    U_step = int(st[2]) / K
     roofline = None
     if prof:
         timed = {k: v for k, v in prof.items() if v[1] > 0}
         dom = max(timed, key=lambda k: timed[k][0])
         ms_tot, launches = timed[dom]
-        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step)
+        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step, U_step)
         if alg is not None:
             per_launch = alg / (launches / K)
             avg_s = ms_tot / launches / 1e3
@@ -192,6 +205,10 @@ def main():
                    "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
                    "views_in_flight": args.in_flight},
         "roofline": roofline,
+        "path": {"algorithmic_bytes_per_view": int(path_bytes(scene.n, scene.k, V, M_step, U_step) / V),
+                 "achieved_GBs": round(path_bytes(scene.n, scene.k, V, M_step, U_step) / (ms_per_step / 1e3) / 1e9, 1),
+                 "frac_of_hbm_peak": round(path_bytes(scene.n, scene.k, V, M_step, U_step) / (ms_per_step / 1e3) / 1e9
+                                           / HBM_PEAK_GBS, 4)},
         "setup_ms": round(setup_ms, 1),
         "pairs_per_view": M_step / V, "walked_entries_per_view": W_step / V,
         "contrib_pairs_per_view": int(st[3]) / K / V, "touched_weighted_per_view": int(st[2]) / K / V,
