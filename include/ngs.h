@@ -169,7 +169,8 @@ typedef struct {
  * [5] views whose slot workspace overflowed. */
 #define NGS_STATS_LEN 6
 
-/* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch.
+/* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch,
+ * 3 = ngs_render_backward.
  * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
  * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
  * at most 16). All host. */
@@ -263,12 +264,37 @@ int32_t ngs_profile_kernels(void);
 const char* ngs_profile_kernel_name(int32_t id);
 ngs_status ngs_profile_read(ngs_ctx* ctx, int32_t id, double* total_ms, int64_t* launches);
 
-/* Backward rasterizer (scene refinement, Sec. III-A.2). Not provided in this version:
- * returns NGS_UNSUPPORTED. */
+/* Loss gradients w.r.t. the rendered images (device FP32, layouts as ngs_image): rgb
+ * [3][H][W], depth [H][W], obj [k][H][W] (w.r.t. O of Eq. 2, or O' of Eq. 1 when
+ * obj_eq2 = 0). A NULL plane counts as zero. */
+typedef struct {
+  const float* rgb;
+  const float* depth;
+  const float* obj;
+} ngs_image_grad;
+
+/* Gradients w.r.t. the scene parameters (device FP32, planes laid out as in ngs_scene:
+ * mean [3][n], log_scale [3][n], rot [4][n] raw quaternion, opacity_logit [n], rgb [3][n],
+ * obj_logit [k][n]); every entry is written. */
+typedef struct {
+  float* mean;
+  float* log_scale;
+  float* rot;
+  float* opacity_logit;
+  float* rgb;
+  float* obj_logit;
+} ngs_scene_grad;
+
+/* Backward rasterizer (scene refinement, Sec. III-A.2; compositing of Eq. 1-2): given dL/d
+ * of the rendered colour, depth and object images of one view, writes dL/d of every
+ * Gaussian parameter. The scene must be prepared (ngs_prepare_scene); proj and lists are
+ * the view's ngs_project / ngs_bin_sort outputs. ws: ngs_workspace_size(3, ...) bytes
+ * (n x (16 + k) FP32 screen-space gradients). Stream-ordered, no host synchronisation. */
 ngs_status ngs_render_backward(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
                                const ngs_tile_lists* lists, const ngs_camera* cam,
-                               const ngs_raster_params* rp, const ngs_image* fwd,
-                               const void* grad_image, void* grad_scene, void* stream);
+                               const ngs_raster_params* rp, int32_t obj_eq2,
+                               const ngs_image_grad* grad_image, ngs_scene_grad* grad_scene,
+                               void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -136,6 +136,7 @@ def lib():
             L.or_pixel_eval_frozen.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_int, P, P]
             L.or_score.argtypes = [P, C.c_int, P, C.c_int, P, P, P, C.c_int, P, P, P, P, P, P]
             L.or_train_blocks.argtypes = [P, C.c_int, P, P, P, C.c_int, C.c_int, P, P, P, P, P]
+            L.or_render_grad.argtypes = [P, P, P, P, C.c_int, P, P, P, P]
             _lib = L
     return _lib
 
@@ -228,6 +229,22 @@ def render(scene, cam, rp: RasterParams = RasterParams(), ig: IGParams = IGParam
     lib().or_render(C.byref(sb.c), C.byref(cc), C.byref(rc), C.byref(igc), int(brute),
                     threads or default_threads(), *[_ptr(out[x]) for x in
                     ("rgb", "depth", "obj", "objp", "t_final", "id", "kbar", "ncontrib", "ambiguous")])
+    return out
+
+
+def render_grad(scene, cam, g_rgb=None, g_depth=None, g_obj=None, rp: RasterParams = RasterParams(),
+                ig: IGParams = IGParams(), threads: Optional[int] = None) -> np.ndarray:
+    """FP64 gradient [n][14 + k] (mu 3, log-scale 3, raw quaternion 4, opacity logit 1, rgb 3,
+    object logits k) of a loss whose gradients w.r.t. the rendered rgb [3][H][W], depth [H][W]
+    and object vector [k][H][W] (O of Eq. 2, or O' when ig.obj_eq2 = 0) are given."""
+    sb = _SceneBuf(scene)
+    d = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    gr, gd, go = d(g_rgb), d(g_depth), d(g_obj)
+    out = np.zeros((sb.n, 14 + sb.k))
+    cc, rc, igc = _cam(cam), rp.c(), ig.c()
+    lib().or_render_grad(C.byref(sb.c), C.byref(cc), C.byref(rc), C.byref(igc), threads or default_threads(),
+                         _ptr(gr) if gr is not None else None, _ptr(gd) if gd is not None else None,
+                         _ptr(go) if go is not None else None, _ptr(out))
     return out
 
 

@@ -863,6 +863,86 @@ int or_render(const or_scene* s, const or_camera* cam, const or_raster* rp, cons
 }
 
 // Per-view information blocks (unweighted A^f_g) of every touched Gaussian.
+// Gradient of a scalar loss through the rendered images (refinement step, Sec. III-A.2,
+// with the compositing of Eq. 1-2): for every Gaussian, grad = sum over pixels and channels
+// of (dL / d out) times the row d out / d theta, theta = (mu 3, log-scale 3, raw quaternion
+// 4, opacity logit 1 | rgb 3 | object logits k). The rows are the ones the information blocks
+// are built from; the object rows enter through d O_m / d alpha and the softmax Jacobian.
+// g_rgb [3][H][W], g_depth [H][W], g_obj [k][H][W] (gradient w.r.t. O of Eq. 2 when
+// obj_eq2, else O'); any may be NULL. grad [n][14 + k] is overwritten.
+int or_render_grad(const or_scene* s, const or_camera* cam, const or_raster* rp, const or_ig* ig, int threads,
+                   const double* g_rgb, const double* g_depth, const double* g_obj, double* grad) {
+  GaussTerms gt = gaussian_terms(*s, *ig);
+  ViewCtx V{s, cam, rp, ig, &gt};
+  view_setup(V);
+  const int n = s->n, k = s->k, W = cam->width, H = cam->height, tile = rp->tile;
+  const size_t HW = (size_t)W * H;
+  const int L = NGEO + 3 + k;
+  std::vector<int> dp_index(n, -1), valid_ids;
+  for (int g = 0; g < n; ++g)
+    if (V.pr[g].valid) { dp_index[g] = (int)valid_ids.size(); valid_ids.push_back(g); }
+  std::vector<DualProj> dp(valid_ids.size());
+  for (size_t i = 0; i < valid_ids.size(); ++i) dp[i] = project_dual(*s, valid_ids[i], *cam, *rp);
+  Features F{s, &V.pr, &gt};
+  const int nrows = V.L.th;
+  std::vector<std::map<int, std::vector<double>>> rowacc(nrows);
+  auto work = [&](int tid, int nth) {
+    PixelWalk Wk;
+    Suffix Sx;
+    Rows R;
+    std::vector<double> go(k);
+    for (int tr = tid; tr < nrows; tr += nth) {
+      auto& acc = rowacc[tr];
+      for (int tx = 0; tx < V.L.tw; ++tx) {
+        const int t = tr * V.L.tw + tx;
+        const int* order = (const int*)&V.L.gids[V.L.start[t]];
+        const size_t len = V.L.end[t] - V.L.start[t];
+        for (int py = tr * tile; py < std::min(H, (tr + 1) * tile); ++py)
+          for (int px = tx * tile; px < std::min(W, (tx + 1) * tile); ++px) {
+            const double x = px + 0.5, y = py + 0.5;
+            const size_t pix = (size_t)py * W + px;
+            walk_pixel(order, len, x, y, V.pr, gt, *rp, Wk);
+            if (Wk.c.empty()) continue;
+            pixel_suffix(Wk, F, Sx);
+            double gc[3];
+            for (int ch = 0; ch < 3; ++ch) gc[ch] = g_rgb ? g_rgb[ch * HW + pix] : 0.0;
+            const double gd = g_depth ? g_depth[pix] : 0.0;
+            for (int m = 0; m < k; ++m) go[m] = g_obj ? g_obj[m * HW + pix] : 0.0;
+            for (int ci = 0; ci < (int)Wk.c.size(); ++ci) {
+              const int g = Wk.c[ci].gid;
+              pixel_rows(Wk, Sx, ci, x, y, F, dp, dp_index, *ig, false, R);
+              std::vector<double>& v = acc[g];
+              if (v.empty()) v.assign(L, 0.0);
+              double wo_dot = 0.0;
+              for (int m = 0; m < k; ++m) wo_dot += go[m] * R.wo[m];
+              for (int i = 0; i < NGEO; ++i) {
+                double a = gd * R.d[i] + wo_dot * R.gvec[i];
+                for (int ch = 0; ch < 3; ++ch) a += gc[ch] * R.rgb[ch][i];
+                v[i] += a;
+              }
+              for (int ch = 0; ch < 3; ++ch) v[NGEO + ch] += gc[ch] * R.rgb[ch][NGEO + ch];
+              const double* pg = &gt.p[(size_t)g * k];
+              double dot = 0.0;
+              for (int m = 0; m < k; ++m) dot += go[m] * pg[m];
+              for (int j = 0; j < k; ++j) v[NGEO + 3 + j] += R.a * pg[j] * (go[j] - dot);
+            }
+          }
+      }
+    }
+  };
+  threads = std::max(1, threads);
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < threads; ++t) th.emplace_back(work, t, threads);
+    for (auto& x : th) x.join();
+  }
+  std::fill(grad, grad + (size_t)n * L, 0.0);
+  for (int tr = 0; tr < nrows; ++tr)
+    for (auto& kv : rowacc[tr])
+      for (int i = 0; i < L; ++i) grad[(size_t)kv.first * L + i] += kv.second[i];
+  return 0;
+}
+
 void* or_view_blocks(const or_scene* s, const or_camera* cam, const or_raster* rp, const or_ig* ig, int threads) {
   GaussTerms gt = gaussian_terms(*s, *ig);
   ViewCtx V{s, cam, rp, ig, &gt};

@@ -77,6 +77,14 @@ class ngs_hessian(C.Structure):
                 ("h_rgb", P), ("h_d", P), ("h_o", P), ("logdet", P)]
 
 
+class ngs_image_grad(C.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("obj", P)]
+
+
+class ngs_scene_grad(C.Structure):
+    _fields_ = [("mean", P), ("log_scale", P), ("rot", P), ("opacity_logit", P), ("rgb", P), ("obj_logit", P)]
+
+
 class ngs_dims(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("width", C.c_int64), ("height", C.c_int64),
                 ("max_pairs", C.c_int64), ("max_slots", C.c_int64), ("views_in_flight", C.c_int64)]
@@ -109,7 +117,7 @@ def lib():
         L.ngs_hessian_reset.argtypes = [P, P, i32, P]
         L.ngs_hessian_finalize.argtypes = [P, P, P]
         L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
-        L.ngs_render_backward.argtypes = [P] * 10
+        L.ngs_render_backward.argtypes = [P, P, P, P, P, P, i32, P, P, P, C.c_size_t, P]
         L.ngs_profile_enable.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
         L.ngs_profile_kernel_name.argtypes = [i32]
@@ -329,6 +337,65 @@ def ngs_render(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLis
     return out
 
 
+def ngs_render_backward(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLists, cam: ngs_camera,
+                        rp: ngs_raster_params, g_rgb: Optional[torch.Tensor] = None,
+                        g_depth: Optional[torch.Tensor] = None, g_obj: Optional[torch.Tensor] = None,
+                        obj_eq2: bool = True, ws: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+    """dL/d(scene parameters) from dL/d(rendered rgb [3][H][W], depth [H][W], obj [k][H][W])."""
+    n, k, dev = max(scene.n, 1), scene.k, scene.device
+    f = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+    out = dict(mean=f(3, n), log_scale=f(3, n), rot=f(4, n), opacity_logit=f(n), rgb=f(3, n), obj_logit=f(k, n))
+    gi = [None if x is None else x.detach().to(torch.float32).contiguous() for x in (g_rgb, g_depth, g_obj)]
+    if ws is None:
+        ws = _bytes(workspace_size(3, scene.n, scene.k), dev)
+    img = ngs_image_grad(*[_p(x) for x in gi])
+    sgr = ngs_scene_grad(*[_p(out[x]) for x in ("mean", "log_scale", "rot", "opacity_logit", "rgb", "obj_logit")])
+    sc, pc, lc = scene.c(), proj.c(), lists.c()
+    _check("ngs_render_backward", lib().ngs_render_backward(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam),
+                                                            _ref(rp), int(bool(obj_eq2)), _ref(img), _ref(sgr),
+                                                            _p(ws), ws.numel(), _stream()), ctx)
+    return out
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable tile rasterizer of one view: scene parameter tensors (float32 SoA on the
+    GPU: mean [3][n], log_scale [3][n], rot [4][n], opacity_logit [n], rgb [3][n], obj_logit
+    [k][n]) -> rgb [3][H][W], depth [H][W], obj [k][H][W] (O of Eq. 2). Forward and backward
+    run in libngs; the lists are rebuilt from the current parameters on every forward."""
+
+    @staticmethod
+    def forward(fctx, mean, log_scale, rot, opacity_logit, rgb, obj_logit, ctx, cam, rp, capacity):
+        ds = DeviceScene.__new__(DeviceScene)
+        ds.n, ds.k, ds.device = int(mean.shape[1]), int(obj_logit.shape[0]), str(mean.device)
+        c = lambda t: t.detach().to(torch.float32).contiguous()
+        ds.mean, ds.log_scale, ds.rot = c(mean), c(log_scale), c(rot)
+        ds.opacity_logit, ds.rgb, ds.obj_logit = c(opacity_logit), c(rgb), c(obj_logit)
+        n = max(ds.n, 1)
+        ds.prob = torch.empty((n, ds.k), dtype=torch.float32, device=ds.device)
+        ds.opacity = torch.empty(n, dtype=torch.float32, device=ds.device)
+        ds.kappa, ds.conf = torch.empty_like(ds.opacity), torch.empty_like(ds.opacity)
+        ds.label = torch.empty(n, dtype=torch.int32, device=ds.device)
+        ngs_prepare_scene(ctx, ds, ig_params())
+        proj = ngs_project(ctx, ds, cam, rp)
+        lists = ngs_bin_sort(ctx, ds, proj, cam, rp, capacity=capacity)
+        img = ngs_render(ctx, ds, proj, lists, cam, rp, want_obj=True)
+        fctx.state = (ctx, ds, proj, lists, cam, rp)
+        return img["rgb"], img["depth"], img["obj"]
+
+    @staticmethod
+    def backward(fctx, g_rgb, g_depth, g_obj):
+        ctx, ds, proj, lists, cam, rp = fctx.state
+        g = ngs_render_backward(ctx, ds, proj, lists, cam, rp, g_rgb, g_depth, g_obj, obj_eq2=True)
+        return g["mean"], g["log_scale"], g["rot"], g["opacity_logit"], g["rgb"], g["obj_logit"], None, None, None, None
+
+
+def render(mean, log_scale, rot, opacity_logit, rgb, obj_logit, ctx: Context, cam: ngs_camera,
+           rp: Optional[ngs_raster_params] = None, capacity: int = 1 << 24):
+    """Autograd entry of the rasterizer (see RenderFunction)."""
+    return RenderFunction.apply(mean, log_scale, rot, opacity_logit, rgb, obj_logit, ctx, cam,
+                                rp if rp is not None else raster_params(), capacity)
+
+
 class IgWorkspace:
     def __init__(self, scene: DeviceScene, max_slots: int = 1 << 16):
         self.buf = _bytes(workspace_size(1, scene.n, scene.k, max_slots=max_slots), scene.device)
@@ -446,7 +513,29 @@ class NbvScorer:
         self.norm = self.ig_train.mean(axis=0)
         return self.norm
 
-    def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None):
+    def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None, scaled: bool = True):
+        """Scores the candidates. scaled=False drops the Eq. 10 normalisation (normalisers 1)."""
         if self.ws is None:
             self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
-        return ngs_score_batch(self.ctx, self.scene, self.h, self.norm, cams, self.rp, self.ig, self.ws, stats)
+        norm = self.norm if scaled else [1.0, 1.0, 1.0]
+        return ngs_score_batch(self.ctx, self.scene, self.h, norm, cams, self.rp, self.ig, self.ws, stats)
+
+    def greedy(self, train_cams: Sequence[ngs_camera], cand_cams: Sequence[ngs_camera], steps: int,
+               follow: Optional[Sequence[int]] = None, scaled: bool = True):
+        """Greedy next-best-view sequence without retraining: each step scores the remaining
+        candidates against the training set, then moves the chosen one (the argmax, or
+        follow[step] when given) into the training set, so its information joins H_T and the
+        Eq. 10 normalisers of the next step. Returns one dict per step."""
+        chosen: list = []
+        remaining = list(range(len(cand_cams)))
+        out = []
+        for s in range(min(steps, len(cand_cams))):
+            self.setup(list(train_cams) + [cand_cams[i] for i in chosen])
+            scores, best, raw = self.score([cand_cams[i] for i in remaining], scaled=scaled)
+            b = remaining[int(best.item())]
+            pick = b if follow is None else int(follow[s])
+            out.append({"remaining": list(remaining), "scores": scores.cpu().numpy(), "raw": raw.cpu().numpy(),
+                        "best": b, "norm": self.norm.copy()})
+            chosen.append(pick)
+            remaining.remove(pick)
+        return out

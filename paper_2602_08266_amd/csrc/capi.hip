@@ -235,6 +235,7 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
     case 0: *bytes = bin_ws_bytes(d->n, d->max_pairs); return NGS_OK;
     case 1: *bytes = igb; return NGS_OK;
     case 2: *bytes = (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + igb); return NGS_OK;
+    case 3: *bytes = bwd_ws_bytes(d->n, d->k); return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
 }
@@ -457,10 +458,21 @@ ngs_status ngs_profile_read(ngs_ctx* ctx, int32_t id, double* total_ms, int64_t*
 
 ngs_status ngs_render_backward(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
                                const ngs_tile_lists* lists, const ngs_camera* cam, const ngs_raster_params* rp,
-                               const ngs_image* fwd, const void* grad_image, void* grad_scene, void* stream) {
-  (void)ctx; (void)scene; (void)proj; (void)lists; (void)cam; (void)rp; (void)fwd; (void)grad_image;
-  (void)grad_scene; (void)stream;
-  return NGS_UNSUPPORTED;
+                               int32_t obj_eq2, const ngs_image_grad* grad_image, ngs_scene_grad* grad_scene,
+                               void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !grad_image || !grad_scene) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s == NGS_OK) s = check_cam(cam, rp);
+  if (s == NGS_OK) s = check_proj(proj);
+  if (s == NGS_OK) s = check_lists(lists);
+  if (s != NGS_OK) return s;
+  const ngs_scene_grad& o = *grad_scene;
+  if (!o.mean || !o.log_scale || !o.rot || !o.opacity_logit || !o.rgb || !o.obj_logit) return NGS_INVALID_ARG;
+  if (!ws || ws_bytes < bwd_ws_bytes(scene->n, scene->k)) return NGS_WORKSPACE_TOO_SMALL;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, launch_render_backward(*scene, *proj, *lists, make_devcam(*cam, kTile), *rp, obj_eq2 ? 1 : 0,
+                                          *grad_image, o, ws, (hipStream_t)stream));
+  return NGS_OK;
 }
 
 }  // extern "C"

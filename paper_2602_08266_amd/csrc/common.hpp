@@ -97,7 +97,7 @@ inline RasterConst make_raster(const ngs_raster_params& r) {
 enum ProfId {
   kProfPrepare = 0, kProfProject, kProfDepthHist, kProfDepthScan, kProfDepthScatter, kProfCountScan,
   kProfEmit, kProfRanges, kProfKeys64, kProfRender, kProfIgTiles, kProfIgFinalize, kProfHessianLogdet,
-  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfKernels
+  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfBwdTiles, kProfBwdParams, kProfKernels
 };
 class ProfScope {
  public:
@@ -175,6 +175,11 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
                               double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);
 hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st);
+// Backward rasterizer (backward.hip).
+size_t bwd_ws_bytes(int64_t n, int64_t k);
+hipError_t launch_render_backward(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
+                                  const DevCam& cam, const ngs_raster_params& rp, int obj_eq2,
+                                  const ngs_image_grad& gi, const ngs_scene_grad& out, void* ws, hipStream_t st);
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
                                 float beta_d, float beta_o, uint32_t outputs, float* scores,
                                 int32_t* best, hipStream_t st);

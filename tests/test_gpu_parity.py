@@ -204,6 +204,40 @@ def test_score_pipeline_tiny(B, ctx, target):
     log(f"  best gpu {int(best.item())} oracle {ref.best}; stats {st}")
 
 
+@pytest.mark.parametrize("target", [-1, 3])
+def test_greedy_nbv_sequence_tiny(B, ctx, target):
+    """Three greedy steps: each chosen view joins the training set (H_T and normalisers are
+    rebuilt) before the remaining candidates are rescored; the GPU follows the oracle's picks
+    so that every step compares the same candidate set."""
+    log(f"test_greedy_nbv_sequence tiny target {target}")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = B.DeviceScene(scene, "cuda")
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(target_id=target), max_pairs=1 << 18,
+                         max_slots=1 << 14, store_capacity=1 << 14)
+    oig = oracle.IGParams(target_id=target)
+    chosen, remaining, picks, refs = [], list(range(len(cands))), [], []
+    for step in range(3):
+        ref = oracle.score(scene, list(train) + [cands[i] for i in chosen], [cands[i] for i in remaining], ig=oig)
+        assert ref.status == 0
+        refs.append((list(remaining), ref))
+        pick = remaining[ref.best]
+        picks.append(pick)
+        chosen.append(pick)
+        remaining.remove(pick)
+    seq = scorer.greedy([B.camera(c) for c in train], [B.camera(c) for c in cands], 3, follow=picks)
+    for step, (rem, ref) in enumerate(refs):
+        got = seq[step]
+        assert got["remaining"] == rem
+        check_gain(got["norm"], ref.norm, f"step {step} normalisers")
+        for v in range(len(rem)):
+            check_gain(got["raw"][v], ref.ig_cand[v], f"step {step} candidate {rem[v]}")
+        assert np.allclose(got["scores"].astype(np.float64), ref.scores, rtol=2e-3)
+        top = np.sort(ref.scores[:, 3])
+        if len(top) > 1 and (top[-1] - top[-2]) / abs(top[-1]) > 1e-3:
+            assert got["best"] == picks[step]
+        log(f"  step {step}: pick {picks[step]} gpu best {got['best']}")
+
+
 def test_abi_errors(B, ctx):
     log("test_abi_errors")
     import ctypes as C
@@ -235,4 +269,4 @@ def test_abi_errors(B, ctx):
     with pytest.raises(B.NgsError) as e:
         B.ngs_info_gain(ctx, ds, pr, lists, cam, rp, B.ig_params(), None, tiny_ws)
     assert e.value.status == B.NGS_WORKSPACE_TOO_SMALL
-    assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, None, None, None, None) == B.NGS_UNSUPPORTED
+    assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, 0, None, None, None, 0, None) == B.NGS_INVALID_ARG

@@ -378,6 +378,76 @@ def test_jacobian_rows_match_finite_differences(eq2):
     assert checked > 50
 
 
+# ------------------------------------------------------------------------------------------
+# Gradient through the rendered images (refinement step)
+# ------------------------------------------------------------------------------------------
+
+_GRAD_PARAMS = [("mean", i) for i in range(3)] + [("log_scale", i) for i in range(3)] + \
+               [("rot", i) for i in range(4)] + [("opacity_logit", None)] + [("rgb", i) for i in range(3)]
+
+
+def _loss(sc, cam, g, ig):
+    img = oracle.render(sc, cam, ig=ig)
+    return (np.sum(g["rgb"] * img["rgb"]) + np.sum(g["depth"] * img["depth"]) + np.sum(g["obj"] * img["obj" if ig.obj_eq2 else "objp"]),
+            img["ncontrib"])
+
+
+@pytest.mark.parametrize("eq2", [1, 0])
+def test_render_grad_matches_finite_differences(eq2):
+    """grad of L = <g, render(theta)> against FP64 central differences of the full renderer
+    (samples whose contributor counts change under the step are skipped)."""
+    k = 4
+    sc = small_scene(k=k)
+    cam = axis_camera(W=32, H=32, f=40.0)
+    ig = oracle.IGParams(obj_eq2=eq2)
+    rng = np.random.default_rng(11)
+    g = dict(rgb=rng.normal(size=(3, 32, 32)), depth=rng.normal(size=(32, 32)), obj=rng.normal(size=(k, 32, 32)))
+    grad = oracle.render_grad(sc, cam, g["rgb"], g["depth"], g["obj"], ig=ig)
+    assert grad.shape == (sc.n, 14 + k)
+    _, nc0 = _loss(sc, cam, g, ig)
+    params = _GRAD_PARAMS + [("obj_logit", m) for m in range(k)]
+    checked = skipped = 0
+    for gi in range(sc.n):
+        for j, (name, idx) in enumerate(params):
+            base = getattr(sc, name)
+            val = base[gi] if base.ndim == 1 else base[idx, gi]
+            h = 1e-6 * max(1.0, abs(val))
+            lp, ncp = _loss(_perturbed(sc, name, idx, gi, h), cam, g, ig)
+            lm, ncm = _loss(_perturbed(sc, name, idx, gi, -h), cam, g, ig)
+            if not (np.array_equal(ncp, nc0) and np.array_equal(ncm, nc0)):
+                skipped += 1
+                continue
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grad[gi, j]) <= 1e-5 * max(1.0, abs(grad[gi, j])), (name, idx, gi, fd, grad[gi, j])
+            checked += 1
+    assert checked >= 0.9 * (checked + skipped) and checked > 80
+
+
+def test_render_grad_is_sum_of_row_products():
+    """The gradient is the sum over pixels of the (separately pinned) Jacobian rows times the
+    image gradient; a plain loop over every pixel of a small image."""
+    k = 4
+    sc = small_scene(k=k, seed=5)
+    cam = axis_camera(W=20, H=20, f=30.0)
+    ig = oracle.IGParams()
+    rng = np.random.default_rng(3)
+    gr, gd, go = rng.normal(size=(3, 20, 20)), rng.normal(size=(20, 20)), rng.normal(size=(k, 20, 20))
+    grad = oracle.render_grad(sc, cam, gr, gd, go, ig=ig)
+    ref = np.zeros_like(grad)
+    for py in range(20):
+        for px in range(20):
+            rows = oracle.pixel_rows(sc, cam, px, py, ig=ig)
+            for ci, gi in enumerate(rows["gids"]):
+                for ch in range(3):
+                    ref[gi, :11] += gr[ch, py, px] * rows["rgb"][ci][ch, :11]
+                    ref[gi, 11 + ch] += gr[ch, py, px] * rows["rgb"][ci][ch, 11 + ch]
+                ref[gi, :11] += gd[py, px] * rows["d"][ci]
+                ref[gi, :11] += go[:, py, px] @ rows["o"][ci][:, :11]
+                ref[gi, 14:] += go[:, py, px] @ rows["o"][ci][:, 11:]
+    assert np.abs(ref).max() > 0
+    assert np.allclose(grad, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
 def test_blocks_are_sums_of_row_outer_products():
     k = 4
     sc = small_scene(k=k, n=5)
