@@ -105,6 +105,84 @@ def cpu_baseline(workload_name, seed, views=3, threads=None):
                       f"object-centric), H_T = lambda I, FP64, {dt:.1f} s"}
 
 
+def run_backward(args):
+    """Refinement step: for every view, render the scene (projection, binning, compositing),
+    an L1 colour + L1 depth + cross-entropy object loss against targets rendered from a
+    perturbed copy of the scene, and the backward rasterizer."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2602_08266_amd import binding as B
+
+    torch.cuda.set_device(0)
+    cfg, scene, cands, train = scenegen.make_workload("diff", args.seed, n_views=args.views)
+    V = len(cands)
+    ctx = B.Context(0)
+    rp = B.raster_params()
+    cams = [B.camera(c) for c in cands]
+    rng = np.random.default_rng(args.seed + 17)
+    t = lambda a, grad=False: torch.as_tensor(np.asarray(a, np.float32), device="cuda").contiguous().requires_grad_(grad)
+    tgt = [t(scene.mean + rng.normal(0, 0.005, scene.mean.shape)), t(scene.log_scale), t(scene.rot),
+           t(scene.opacity_logit + rng.normal(0, 0.3, scene.opacity_logit.shape)), t(scene.rgb), t(scene.obj_logit)]
+    targets = []
+    with torch.no_grad():
+        for c in cams:
+            rgb, depth, obj = B.render(*tgt, ctx, c, rp, 48 << 20)
+            targets.append((rgb.clone(), depth.clone(), obj.argmax(0)))
+    params = [t(scene.mean, True), t(scene.log_scale, True), t(scene.rot, True), t(scene.opacity_logit, True),
+              t(scene.rgb, True), t(scene.obj_logit, True)]
+
+    def step():
+        for p in params:
+            p.grad = None
+        total = 0.0
+        for c, (trgb, tdep, tlab) in zip(cams, targets):
+            rgb, depth, obj = B.render(*params, ctx, c, rp, 48 << 20)
+            loss = (rgb - trgb).abs().mean() + (depth - tdep).abs().mean() + torch.nn.functional.nll_loss(
+                torch.log(obj.clamp_min(1e-6)).unsqueeze(0), tlab.unsqueeze(0))
+            loss.backward()
+            total += float(loss.detach())
+        return total
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    B.ngs_profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = B.ngs_profile_read(ctx)
+    B.ngs_profile_enable(ctx, False)
+    K = args.steps
+    timed = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(timed, key=lambda k: timed[k][0])
+    ms_tot, launches = timed[dom]
+    n, k, HW = scene.n, scene.k, cands[0].width * cands[0].height
+    # compulsory bytes of one backward launch: the image gradients, the per-Gaussian screen
+    # gradient rows (zeroed, written, read) and the parameter gradients written
+    alg = {"bwd_tiles": HW * (4 + k) * 4 + n * (16 + k) * 4, "bwd_params": n * (16 + k) * 4 + n * (14 + k) * 4}.get(dom)
+    avg_s = ms_tot / launches / 1e3
+    roof = ({"bound": "hbm", "achieved": round(alg / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(alg)} if alg else
+            {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None, "kernel": dom,
+             "avg_launch_us": round(avg_s * 1e6, 2)})
+    print(json.dumps({
+        "metric": "views/s of the differentiable rasterizer (forward + loss + backward), 500k Gaussians 640x480",
+        "value": round(V * K / dt, 2), "unit": "views/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / K, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"diff: {n} Gaussians, k={k}, {V} views at {cands[0].width}x{cands[0].height}, "
+                               "targets from a perturbed copy (mu + N(0, 5 mm), opacity logit + N(0, 0.3))",
+                   "loss": "L1 rgb + L1 depth + object cross-entropy"},
+        "roofline": roof, "loss": round(loss, 6),
+        "kernels_ms_per_step": {kk: round(v[0] / K, 3) for kk, v in sorted(prof.items(), key=lambda x: -x[1][0])
+                                if v[1] > 0}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +194,8 @@ def main():
     ap.add_argument("--in-flight", type=int, default=8, help="candidate views scored concurrently")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
+    ap.add_argument("--backward", action="store_true",
+                    help="time the differentiable rasterizer (forward + loss + backward) on the 500k-Gaussian workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (for scaling rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -133,6 +213,9 @@ def main():
         print("bench.py measures one GPU only: the scorer is not sharded across GPUs in this build "
               "(views would be split across GPUs with one all-gather of the scores).", file=sys.stderr)
         sys.exit(2)
+    if args.backward:
+        run_backward(args)
+        return
 
     import numpy as np
     import torch
