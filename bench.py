@@ -183,6 +183,89 @@ def run_backward(args):
                                 if v[1] > 0}}), flush=True)
 
 
+def run_surrogate(args):
+    """Learned view scorer on the surrogate workload (1M Gaussians, k = 64, 2048 candidates at
+    80x60 per scene, whole-scene confidence): exact labels from ngs_score_batch on seeded
+    training scenes, training with the library's BF16 kernels, then on held-out scenes the
+    ranking agreement with the exact scores and the throughput of both scorers."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2602_08266_amd import binding as B
+    from paper_2602_08266_amd import surrogate as SG
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    log = lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush())
+    nv = args.views or 2048
+    xs, ys, scene_of = [], [], []
+    t_feat = t_exact = 0.0
+    seeds = list(range(args.sur_scenes)) + [1000 + i for i in range(args.sur_test_scenes)]
+    for i, seed in enumerate(seeds):
+        cfg, scene, cands, train = scenegen.make_workload("surrogate", seed, n_views=nv)
+        s = SG.scene_samples(ctx, scene, cands, train, views_in_flight=8)
+        xs.append(s.x)
+        ys.append(s.y)
+        scene_of.append(np.full(nv, seed))
+        if i >= args.sur_scenes:
+            t_feat += s.seconds_features
+            t_exact += s.seconds_exact
+        log(f"scene {seed}: features {s.seconds_features:.2f} s, exact {s.seconds_exact:.2f} s")
+        del scene
+    ntr = args.sur_scenes * nv
+    x = torch.cat(xs, dim=1)
+    y = torch.cat(ys)
+    del xs
+    mu, sd = float(y[:ntr].mean()), float(y[:ntr].std())
+    yn = (y - mu) / sd
+    net = B.Surrogate(ctx, seed=args.seed, max_batch=256)
+    B.ngs_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = SG.train(net, x[:, :ntr].contiguous(), yn[:ntr].contiguous(), epochs=args.sur_epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    prof = B.ngs_profile_read(ctx)
+    B.ngs_profile_enable(ctx, False)
+    xt = x[:, ntr:].contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = SG.predict(net, xt)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    ag = SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:])
+    ptr = SG.predict(net, x[:, :min(ntr, 8192)].contiguous())
+    ag_train = SG.agreement(ptr.cpu().numpy(), y[:min(ntr, 8192)].cpu().numpy(),
+                            np.concatenate(scene_of)[:min(ntr, 8192)])
+    # matrix-core work of training: 2 flops per multiply-add of every GEMM of forward and backward
+    per_view_fwd = sum(2 * co * ci * 9 * ho * wo for (ci, co, _), (ho, wo) in
+                       zip(B.SUR_SHAPES[:4], [(30, 40), (15, 20), (8, 10), (4, 5)])) + 2 * (128 * 128 + 128)
+    steps = args.sur_epochs * (ntr // 256)
+    gemm_ms, gemm_n = prof.get("sur_gemm", (0.0, 0))
+    gemm_tflops = 3 * per_view_fwd * 256 * steps / (gemm_ms / 1e3) / 1e12 if gemm_ms > 0 else None
+    nt = args.sur_test_scenes * nv
+    sur_views_s = nt / (t_feat + t_net)
+    exact_views_s = nt / t_exact
+    print(json.dumps({
+        "metric": "candidate views scored/sec, learned surrogate (80x60 feature maps + BF16 network) vs exact IG",
+        "value": round(sur_views_s, 2), "unit": "views/s", "n_gpus": 1, "higher_is_better": True,
+        "vs_baseline": None, "dtype": "bf16 network / f32 features", "data": "synthetic",
+        "config": {"workload": f"surrogate: 1M Gaussians, k=64, {nv} candidates at 80x60 per scene, whole-scene "
+                               f"confidence; {args.sur_scenes} training scenes ({ntr} pairs), "
+                               f"{args.sur_test_scenes} held-out scenes",
+                   "network": "4 conv 3x3 s2 (4-32-64-128-128) + avg pool + FC 128-128-1, BF16 MFMA, FP32 accumulate"},
+        "exact_views_s": round(exact_views_s, 2), "speedup": round(sur_views_s / exact_views_s, 3),
+        "surrogate_feature_s": round(t_feat, 3), "surrogate_network_s": round(t_net, 4), "exact_s": round(t_exact, 3),
+        "agreement_heldout": ag.__dict__, "agreement_train": ag_train.__dict__,
+        "train": {"pairs": ntr, "epochs": args.sur_epochs, "seconds": round(t_train, 2),
+                  "loss_per_epoch": [round(h, 4) for h in hist], "label_mean": mu, "label_std": sd},
+        "roofline": {"bound": "mfma", "kernel": "sur_gemm",
+                     "achieved": round(gemm_tflops, 2) if gemm_tflops else None, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(gemm_tflops / 2500.0, 5) if gemm_tflops else None, "traffic": None,
+                     "avg_launch_us": round(gemm_ms / gemm_n * 1e3, 2) if gemm_n else None}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +279,11 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
     ap.add_argument("--backward", action="store_true",
                     help="time the differentiable rasterizer (forward + loss + backward) on the 500k-Gaussian workload")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="train the learned view scorer on exact scores of seeded scenes and compare it with exact scoring")
+    ap.add_argument("--sur-scenes", type=int, default=12, help="training scenes (2048 views each)")
+    ap.add_argument("--sur-test-scenes", type=int, default=2)
+    ap.add_argument("--sur-epochs", type=int, default=15)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (for scaling rocprofv3 FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -215,6 +303,9 @@ def main():
         sys.exit(2)
     if args.backward:
         run_backward(args)
+        return
+    if args.surrogate:
+        run_surrogate(args)
         return
 
     import numpy as np

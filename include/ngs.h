@@ -170,7 +170,7 @@ typedef struct {
 #define NGS_STATS_LEN 6
 
 /* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch,
- * 3 = ngs_render_backward.
+ * 3 = ngs_render_backward, 4 = ngs_sur_render_features (ngs_surrogate.h).
  * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
  * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
  * at most 16). All host. */

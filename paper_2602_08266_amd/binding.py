@@ -25,7 +25,8 @@ EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_bin_sort", "ngs_render",
            "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_kernels", "ngs_profile_kernel_name",
-           "ngs_profile_read"]
+           "ngs_profile_read", "ngs_sur_workspace_size", "ngs_sur_sync_bf16", "ngs_sur_forward", "ngs_sur_backward",
+           "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_render_features", "ngs_gemm_bf16"]
 
 
 class NgsError(RuntimeError):
@@ -85,6 +86,15 @@ class ngs_scene_grad(C.Structure):
     _fields_ = [("mean", P), ("log_scale", P), ("rot", P), ("opacity_logit", P), ("rgb", P), ("obj_logit", P)]
 
 
+SUR_LAYERS, SUR_WIDTH, SUR_IN = 6, 128, (4, 60, 80)
+# (in, out, kernel taps) of the surrogate's layers: four 3x3 convolutions, two fully connected
+SUR_SHAPES = [(4, 32, 9), (32, 64, 9), (64, 128, 9), (128, 128, 9), (128, 128, 1), (128, 1, 1)]
+
+
+class ngs_sur_params(C.Structure):
+    _fields_ = [("w", P * SUR_LAYERS), ("b", P * SUR_LAYERS), ("w_bf16", P * SUR_LAYERS)]
+
+
 class ngs_dims(C.Structure):
     _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("width", C.c_int64), ("height", C.c_int64),
                 ("max_pairs", C.c_int64), ("max_slots", C.c_int64), ("views_in_flight", C.c_int64)]
@@ -118,6 +128,15 @@ def lib():
         L.ngs_hessian_finalize.argtypes = [P, P, P]
         L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_render_backward.argtypes = [P, P, P, P, P, P, i32, P, P, P, C.c_size_t, P]
+        L.ngs_sur_workspace_size.argtypes = [i32, C.POINTER(C.c_size_t)]
+        L.ngs_sur_sync_bf16.argtypes = [P, P, P]
+        L.ngs_sur_forward.argtypes = [P, P, P, i32, P, P, C.c_size_t, P]
+        L.ngs_sur_backward.argtypes = [P, P, P, i32, P, P, P, C.c_size_t, P]
+        L.ngs_sur_mse.argtypes = [P, P, P, i32, P, P, P]
+        L.ngs_sur_adam.argtypes = [P, P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, i32, P]
+        L.ngs_sur_features.argtypes = [P, P, i32, i32, i32, C.c_float, P, i32, i32, P]
+        L.ngs_sur_render_features.argtypes = [P, P, P, i32, P, C.c_float, P, P, P, C.c_size_t, P]
+        L.ngs_gemm_bf16.argtypes = [P, i32, i32, i32, i32, i32, P, i32, P, i32, P, i32, C.c_float, P]
         L.ngs_profile_enable.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
         L.ngs_profile_kernel_name.argtypes = [i32]
@@ -394,6 +413,137 @@ def render(mean, log_scale, rot, opacity_logit, rgb, obj_logit, ctx: Context, ca
     """Autograd entry of the rasterizer (see RenderFunction)."""
     return RenderFunction.apply(mean, log_scale, rot, opacity_logit, rgb, obj_logit, ctx, cam,
                                 rp if rp is not None else raster_params(), capacity)
+
+
+def ngs_gemm_bf16(ctx: Context, a: torch.Tensor, b: torch.Tensor, trans_a: bool = False, trans_b: bool = False,
+                  c: Optional[torch.Tensor] = None, beta: float = 0.0) -> torch.Tensor:
+    """c = op(a) op(b) (+ beta c) with BF16 operands (torch.bfloat16) and FP32 output."""
+    assert a.dtype == torch.bfloat16 and b.dtype == torch.bfloat16
+    a, b = a.contiguous(), b.contiguous()
+    m, k = (a.shape[1], a.shape[0]) if trans_a else (a.shape[0], a.shape[1])
+    kb, n = (b.shape[1], b.shape[0]) if trans_b else (b.shape[0], b.shape[1])
+    assert k == kb
+    if c is None:
+        c = torch.zeros((m, n), dtype=torch.float32, device=a.device)
+    _check("ngs_gemm_bf16", lib().ngs_gemm_bf16(ctx.handle, int(trans_a), int(trans_b), m, n, k, _p(a), a.shape[1],
+                                                _p(b), b.shape[1], _p(c), c.shape[1], float(beta), _stream()), ctx)
+    return c
+
+
+class Surrogate:
+    """The learned view scorer's parameters, gradients and Adam moments (torch tensors on the
+    GPU; every pass runs in libngs)."""
+
+    def __init__(self, ctx: Context, device: str = "cuda", seed: int = 0, max_batch: int = 256):
+        self.ctx, self.device, self.max_batch = ctx, device, max_batch
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        self.w, self.b = [], []
+        for (ci, co, taps) in SUR_SHAPES:
+            fan_in = ci * taps
+            self.w.append((torch.randn((co, ci * taps), generator=g) * (2.0 / fan_in) ** 0.5).to(device))
+            self.b.append(torch.zeros(co, device=device))
+        self.wb = [torch.empty(w.shape, dtype=torch.bfloat16, device=device) for w in self.w]
+        self.gw = [torch.zeros_like(w) for w in self.w]
+        self.gb = [torch.zeros_like(x) for x in self.b]
+        self.mw = [torch.zeros_like(w) for w in self.w]
+        self.mb = [torch.zeros_like(x) for x in self.b]
+        self.vw = [torch.zeros_like(w) for w in self.w]
+        self.vb = [torch.zeros_like(x) for x in self.b]
+        self.step = 0
+        self.ws = _bytes(self.workspace_size(max_batch), device)
+        self.sync()
+
+    @staticmethod
+    def workspace_size(batch: int) -> int:
+        v = C.c_size_t()
+        _check("ngs_sur_workspace_size", lib().ngs_sur_workspace_size(batch, C.byref(v)))
+        return int(v.value)
+
+    def _c(self, w, b, wb=None) -> ngs_sur_params:
+        s = ngs_sur_params()
+        for l in range(SUR_LAYERS):
+            s.w[l], s.b[l] = _p(w[l]), _p(b[l])
+            s.w_bf16[l] = _p(wb[l]) if wb is not None else None
+        return s
+
+    def params(self) -> ngs_sur_params:
+        return self._c(self.w, self.b, self.wb)
+
+    def sync(self):
+        p = self.params()
+        _check("ngs_sur_sync_bf16", lib().ngs_sur_sync_bf16(self.ctx.handle, _ref(p), _stream()), self.ctx)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """x [4][B][60][80] FP32 -> predictions [B]."""
+        B = int(x.shape[1])
+        assert B <= self.max_batch and tuple(x.shape[2:]) == SUR_IN[1:] and x.shape[0] == 4
+        x = x.contiguous()
+        pred = torch.empty(B, dtype=torch.float32, device=self.device)
+        p = self.params()
+        _check("ngs_sur_forward", lib().ngs_sur_forward(self.ctx.handle, _ref(p), _p(x), B, _p(pred), _p(self.ws),
+                                                        self.ws.numel(), _stream()), self.ctx)
+        return pred
+
+    def backward(self, x: torch.Tensor, dpred: torch.Tensor):
+        """Gradients (into self.gw, self.gb) of the last forward on x."""
+        B = int(x.shape[1])
+        p, g = self.params(), self._c(self.gw, self.gb)
+        _check("ngs_sur_backward", lib().ngs_sur_backward(self.ctx.handle, _ref(p), _p(x), B, _p(dpred.contiguous()),
+                                                          _ref(g), _p(self.ws), self.ws.numel(), _stream()), self.ctx)
+
+    def mse(self, pred: torch.Tensor, target: torch.Tensor):
+        B = int(pred.shape[0])
+        dpred = torch.empty_like(pred)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check("ngs_sur_mse", lib().ngs_sur_mse(self.ctx.handle, _p(pred), _p(target.contiguous()), B, _p(dpred),
+                                                _p(loss), _stream()), self.ctx)
+        return loss, dpred
+
+    def adam(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        p, g = self.params(), self._c(self.gw, self.gb)
+        m, v = self._c(self.mw, self.mb), self._c(self.vw, self.vb)
+        _check("ngs_sur_adam", lib().ngs_sur_adam(self.ctx.handle, _ref(p), _ref(g), _ref(m), _ref(v), lr, beta1, beta2,
+                                                  eps, self.step, _stream()), self.ctx)
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float = 1e-3) -> torch.Tensor:
+        pred = self.forward(x)
+        loss, dpred = self.mse(pred, target)
+        self.backward(x, dpred)
+        self.adam(lr)
+        return loss
+
+
+def ngs_sur_features(ctx: Context, img: Dict[str, torch.Tensor], k: int, depth_scale: float, x: torch.Tensor,
+                     index: int):
+    """Writes view `index`'s four input channels from an ngs_render output into x [4][B][60][80]."""
+    H, W = img["depth"].shape
+    im = ngs_image(_p(img["rgb"]), _p(img["depth"]), None, _p(img["t_final"]), _p(img["mean_conf"]),
+                   _p(img["argmax_id"]), None)
+    _check("ngs_sur_features", lib().ngs_sur_features(ctx.handle, _ref(im), W, H, k, float(depth_scale), _p(x),
+                                                      int(x.shape[1]), index, _stream()), ctx)
+
+
+class FeatureRenderer:
+    """Batched 80x60 feature maps of many candidates (ngs_sur_render_features)."""
+
+    def __init__(self, ctx: Context, scene: DeviceScene, max_pairs: int = 1 << 23, views_in_flight: int = 0):
+        self.ctx, self.scene = ctx, scene
+        self.dims = ngs_dims(scene.n, scene.k, SUR_IN[2], SUR_IN[1], max_pairs, 0, views_in_flight)
+        self.buf = _bytes(workspace_size(4, scene.n, scene.k, max_pairs=max_pairs, views_in_flight=views_in_flight),
+                          scene.device)
+
+    def __call__(self, cams: Sequence[ngs_camera], rp: ngs_raster_params, depth_scale: float,
+                 x: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nv = len(cams)
+        if x is None:
+            x = torch.empty((4, nv, SUR_IN[1], SUR_IN[2]), dtype=torch.float32, device=self.scene.device)
+        arr = (ngs_camera * nv)(*cams)
+        sc = self.scene.c()
+        _check("ngs_sur_render_features", lib().ngs_sur_render_features(
+            self.ctx.handle, _ref(sc), arr, nv, _ref(rp), float(depth_scale), _p(x), _ref(self.dims), _p(self.buf),
+            self.buf.numel(), _stream()), self.ctx)
+        return x
 
 
 class IgWorkspace:

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libngs.so")
-SOURCES = ["project.hip", "sort.hip", "bin.hip", "render.hip", "info_gain.hip", "finalize.hip", "backward.hip", "prof.hip",
+SOURCES = ["project.hip", "sort.hip", "bin.hip", "render.hip", "info_gain.hip", "finalize.hip", "backward.hip", "surrogate.hip",
+           "prof.hip",
            "capi.hip"]
 ARCH = os.environ.get("NGS_OFFLOAD_ARCH", "gfx950")
 

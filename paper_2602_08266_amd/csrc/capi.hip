@@ -153,6 +153,25 @@ ngs_status ensure_lanes(ngs_ctx* ctx, int want) {
   return NGS_OK;
 }
 
+// One 80 x 60 render (rgb, depth, t_final, mean_conf, argmax id) for the feature maps.
+size_t feat_img_bytes() {
+  const size_t hw = (size_t)NGS_SUR_IN_W * NGS_SUR_IN_H;
+  return 7 * al(hw * 4);
+}
+
+ngs_image feat_img_carve(char* p) {
+  const size_t hw = (size_t)NGS_SUR_IN_W * NGS_SUR_IN_H;
+  ngs_image im{};
+  im.rgb = (float*)p; p += 3 * al(hw * 4);
+  im.depth = (float*)p; p += al(hw * 4);
+  im.t_final = (float*)p; p += al(hw * 4);
+  im.mean_conf = (float*)p; p += al(hw * 4);
+  im.argmax_id = (int32_t*)p;
+  im.obj = nullptr;
+  im.n_contrib = nullptr;
+  return im;
+}
+
 BatchWs batch_carve(void* ws, size_t ws_bytes, int64_t n, int64_t max_pairs) {
   const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
   char* p = static_cast<char*>(ws);
@@ -236,6 +255,8 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
     case 1: *bytes = igb; return NGS_OK;
     case 2: *bytes = (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + igb); return NGS_OK;
     case 3: *bytes = bwd_ws_bytes(d->n, d->k); return NGS_OK;
+    case 4: *bytes = kIgHeader + (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + feat_img_bytes());
+      return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
 }
@@ -472,6 +493,145 @@ ngs_status ngs_render_backward(ngs_ctx* ctx, const ngs_scene* scene, const ngs_p
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
   NGS_TRY_HIP(ctx, launch_render_backward(*scene, *proj, *lists, make_devcam(*cam, kTile), *rp, obj_eq2 ? 1 : 0,
                                           *grad_image, o, ws, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+// ---- learned view scorer ----------------------------------------------------------------
+
+namespace {
+bool sur_params_ok(const ngs_sur_params* p, bool need_bf16) {
+  if (!p) return false;
+  for (int l = 0; l < NGS_SUR_LAYERS; ++l)
+    if (!p->w[l] || !p->b[l] || (need_bf16 && !p->w_bf16[l])) return false;
+  return true;
+}
+}  // namespace
+
+ngs_status ngs_sur_workspace_size(int32_t batch, size_t* bytes) {
+  if (batch < 1 || !bytes) return NGS_INVALID_ARG;
+  *bytes = sur_workspace_bytes(batch);
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_sync_bf16(ngs_ctx* ctx, const ngs_sur_params* params, void* stream) {
+  if (!ctx || !sur_params_ok(params, true)) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_sync_bf16(*params, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_forward(ngs_ctx* ctx, const ngs_sur_params* params, const float* x, int32_t batch, float* pred,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !sur_params_ok(params, true) || !x || !pred || batch < 1) return NGS_INVALID_ARG;
+  if (!ws || ws_bytes < sur_workspace_bytes(batch)) return NGS_WORKSPACE_TOO_SMALL;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_forward(*params, x, batch, pred, ws, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_backward(ngs_ctx* ctx, const ngs_sur_params* params, const float* x, int32_t batch,
+                            const float* dpred, ngs_sur_params* grads, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !sur_params_ok(params, true) || !sur_params_ok(grads, false) || !dpred || batch < 1)
+    return NGS_INVALID_ARG;
+  if (!ws || ws_bytes < sur_workspace_bytes(batch)) return NGS_WORKSPACE_TOO_SMALL;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_backward(*params, x, batch, dpred, *grads, ws, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_mse(ngs_ctx* ctx, const float* pred, const float* target, int32_t batch, float* dpred, float* loss,
+                       void* stream) {
+  if (!ctx || !pred || !target || !dpred || batch < 1) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_mse(pred, target, batch, dpred, loss, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_adam(ngs_ctx* ctx, ngs_sur_params* params, const ngs_sur_params* g, ngs_sur_params* m,
+                        ngs_sur_params* v, float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (!ctx || !sur_params_ok(params, true) || !sur_params_ok(g, false) || !sur_params_ok(m, false) ||
+      !sur_params_ok(v, false) || step < 1)
+    return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_adam(*params, *g, *m, *v, lr, beta1, beta2, eps, step, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_features(ngs_ctx* ctx, const ngs_image* img, int32_t width, int32_t height, int32_t k,
+                            float depth_scale, float* x, int32_t batch, int32_t index, void* stream) {
+  if (!ctx || !img || !img->depth || !img->t_final || !img->argmax_id || !img->mean_conf || !x) return NGS_INVALID_ARG;
+  if (width != NGS_SUR_IN_W || height != NGS_SUR_IN_H || k < 1 || !(depth_scale > 0.f) || index < 0 ||
+      index >= batch)
+    return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_features(*img, width, height, k, depth_scale, x, batch, index, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,
+                                   const ngs_raster_params* rp, float depth_scale, float* x, const ngs_dims* dims,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !cams || n_views < 1 || !x || !dims || !(depth_scale > 0.f)) return NGS_INVALID_ARG;
+  if (dims->n != scene->n || dims->k != scene->k || dims->max_pairs < 1) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s != NGS_OK) return s;
+  for (int v = 0; v < n_views; ++v) {
+    s = check_cam(&cams[v], rp);
+    if (s != NGS_OK) return s;
+    if (cams[v].width != NGS_SUR_IN_W || cams[v].height != NGS_SUR_IN_H) return NGS_INVALID_ARG;
+  }
+  size_t need = 0;
+  s = ngs_workspace_size(4, dims, &need);
+  if (s != NGS_OK) return s;
+  if (!ws || ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const int lanes = std::max(1, std::min(views_in_flight(dims), n_views));
+  s = ensure_lanes(ctx, lanes);
+  if (s != NGS_OK) return s;
+  int32_t* sticky = static_cast<int32_t*>(ws);
+  NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, kIgHeader, st));
+  const size_t per = (need - kIgHeader) / (size_t)views_in_flight(dims);
+  char* base = static_cast<char*>(ws) + kIgHeader;
+  std::vector<BatchWs> sets(lanes);
+  std::vector<ngs_image> imgs(lanes);
+  const size_t fixed = al(batch_fixed_bytes(scene->n, dims->max_pairs));
+  for (int i = 0; i < lanes; ++i) {
+    sets[i] = batch_carve(base + (size_t)i * per, fixed, scene->n, dims->max_pairs);
+    imgs[i] = feat_img_carve(base + (size_t)i * per + fixed);
+  }
+  NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
+  for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
+  const RasterConst rc = make_raster(*rp);
+  for (int v = 0; v < n_views; ++v) {
+    const int i = v % lanes;
+    hipStream_t ls = ctx->lanes[i];
+    const BatchWs& b = sets[i];
+    const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
+    const DevCam dc = make_devcam(cams[v], kTile);
+    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
+    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, ls));
+    NGS_TRY_HIP(ctx, launch_render(*scene, b.proj, b.lists, dc, rc, imgs[i], ls));
+    NGS_TRY_HIP(ctx, sur_features(imgs[i], NGS_SUR_IN_W, NGS_SUR_IN_H, scene->k, depth_scale, x, n_views, v, ls));
+  }
+  for (int i = 0; i < lanes; ++i) {
+    NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ctx->lanes[i]));
+    NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
+  }
+  int64_t of = 0;
+  s = read_i64(ctx, sticky, 4, st, &of);
+  if (s != NGS_OK) return s;
+  return of ? NGS_CAPACITY : NGS_OK;
+}
+
+ngs_status ngs_gemm_bf16(ngs_ctx* ctx, int32_t trans_a, int32_t trans_b, int32_t m, int32_t n, int32_t k,
+                         const uint16_t* a, int32_t lda, const uint16_t* b, int32_t ldb, float* c, int32_t ldc,
+                         float beta, void* stream) {
+  if (!ctx || !a || !b || !c || m < 0 || n < 0 || k < 0) return NGS_INVALID_ARG;
+  if (ldc < n || lda < (trans_a ? m : k) || ldb < (trans_b ? k : n)) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_gemm(trans_a != 0, trans_b != 0, m, n, k, a, lda, b, ldb, c, ldc, beta, (hipStream_t)stream));
   return NGS_OK;
 }
 

@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "../../include/ngs.h"
+#include "../../include/ngs_surrogate.h"
 
 namespace ngs {
 
@@ -97,7 +98,8 @@ inline RasterConst make_raster(const ngs_raster_params& r) {
 enum ProfId {
   kProfPrepare = 0, kProfProject, kProfDepthHist, kProfDepthScan, kProfDepthScatter, kProfCountScan,
   kProfEmit, kProfRanges, kProfKeys64, kProfRender, kProfIgTiles, kProfIgFinalize, kProfHessianLogdet,
-  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfBwdTiles, kProfBwdParams, kProfKernels
+  kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfBwdTiles, kProfBwdParams, kProfSurGemm, kProfSurForward,
+  kProfSurBackward, kProfKernels
 };
 class ProfScope {
  public:
@@ -180,6 +182,19 @@ size_t bwd_ws_bytes(int64_t n, int64_t k);
 hipError_t launch_render_backward(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                                   const DevCam& cam, const ngs_raster_params& rp, int obj_eq2,
                                   const ngs_image_grad& gi, const ngs_scene_grad& out, void* ws, hipStream_t st);
+// Learned view scorer (surrogate.hip).
+size_t sur_workspace_bytes(int batch);
+hipError_t sur_gemm(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                    float* C, int ldc, float beta, hipStream_t st);
+hipError_t sur_sync_bf16(const ngs_sur_params& p, hipStream_t st);
+hipError_t sur_forward(const ngs_sur_params& p, const float* x, int B, float* pred, void* ws, hipStream_t st);
+hipError_t sur_backward(const ngs_sur_params& p, const float* x, int B, const float* dpred, const ngs_sur_params& g,
+                        void* ws, hipStream_t st);
+hipError_t sur_mse(const float* pred, const float* target, int B, float* dpred, float* loss, hipStream_t st);
+hipError_t sur_adam(const ngs_sur_params& p, const ngs_sur_params& g, const ngs_sur_params& m,
+                    const ngs_sur_params& v, float lr, float b1, float b2, float eps, int step, hipStream_t st);
+hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
+                        hipStream_t st);
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
                                 float beta_d, float beta_o, uint32_t outputs, float* scores,
                                 int32_t* best, hipStream_t st);

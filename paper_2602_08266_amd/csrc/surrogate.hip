@@ -1,0 +1,435 @@
+// surrogate.hip -- learned view scorer: a small convolutional network that predicts a view's
+// next-best-view score from low-resolution rendered feature maps (depth, final transmittance,
+// argmax object id, mean confidence). Not part of the paper: an addition whose ranking is
+// judged by, and falls back to, the exact information gain.
+//
+// Network (fixed): four 3x3 convolutions with stride 2 and padding 1 (4 -> 32 -> 64 -> 128 ->
+// 128 channels, 60x80 -> 30x40 -> 15x20 -> 8x10 -> 4x5), ReLU, global average pool, then
+// 128 -> 128 (ReLU) -> 1. Activations are channel-major [C][B][H][W]. Every convolution and
+// fully connected layer is a GEMM on BF16 operands with FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16): forward Z = W * col(X); backward dW = dZ * col(X)^T and
+// col(dX) = W^T * dZ. The BF16 rounding points are the GEMM operands: weights, the im2col of
+// activations, the pooled and hidden activations, and the pre-activation gradients.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace ngs {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ---- GEMM: C[M][N] = op(A)[M][K] * op(B)[K][N] + beta * C, BF16 in, FP32 out ----------
+// op(A) = A (row-major, lda) or A^T (A stored [K][M]); op(B) = B ([K][N]) or B^T ([N][K]).
+// 64 x 64 block tile, K step 32, four wavefronts each owning a 32 x 32 quarter as 2 x 2
+// MFMA tiles of 16 x 16. For v_mfma_f32_16x16x32_bf16 lane l supplies row (l mod 16) of A
+// and column (l mod 16) of B at k = 8 (l / 16) ... +7, and receives C rows 4 (l / 16) ... +3
+// of column (l mod 16).
+constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
+                                                   const uint16_t* __restrict__ B, int ldb, float* __restrict__ C,
+                                                   int ldc, float beta) {
+  __shared__ __align__(16) uint16_t As[kGM][kGK + kGPad];
+  __shared__ __align__(16) uint16_t Bs[kGN][kGK + kGPad];
+  const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+    for (int e = tid; e < kGM * kGK; e += 256) {
+      const int mm = TA ? e % kGM : e / kGK, kk = TA ? e / kGM : e % kGK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      uint16_t v = 0;
+      if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+      As[mm][kk] = v;
+    }
+    for (int e = tid; e < kGN * kGK; e += 256) {
+      const int nn = TB ? e / kGK : e % kGN, kk = TB ? e % kGK : e / kGN;
+      const int gn = n0 + nn, gk = k0 + kk;
+      uint16_t v = 0;
+      if (gn < N && gk < K) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+    const int kb = 8 * (lane >> 4);
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + mi * 16 + (lane & 15)][kb]);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + ni * 16 + (lane & 15)][kb]);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mi][ni], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + i;
+        const int col = n0 + wn * 32 + ni * 16 + (lane & 15);
+        if (row < M && col < N) {
+          float* c = C + (size_t)row * ldc + col;
+          *c = acc[mi][ni][i] + (beta != 0.f ? beta * *c : 0.f);
+        }
+      }
+}
+
+hipError_t gemm(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                float* C, int ldc, float beta, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  ProfScope ps(kProfSurGemm, st);
+  const dim3 grid((N + kGN - 1) / kGN, (M + kGM - 1) / kGM);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  return hipGetLastError();
+}
+
+// ---- elementwise kernels --------------------------------------------------------------------
+constexpr int kEw = 256;
+inline dim3 ew_grid(size_t n) { return dim3((unsigned)std::min<size_t>((n + kEw - 1) / kEw, 65536)); }
+
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = to_bf16(x[i]);
+}
+
+// col[(c * 9 + kh * 3 + kw)][(b * Ho + ho) * Wo + wo] = x[c][b][ho s - 1 + kh][wo s - 1 + kw] (0 outside)
+__global__ void k_im2col(const float* __restrict__ x, int C, int B, int H, int W, int s, int Ho, int Wo,
+                         uint16_t* __restrict__ col) {
+  const size_t N = (size_t)B * Ho * Wo, total = (size_t)C * 9 * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(i / N);
+    const size_t nn = i % N;
+    const int c = row / 9, kh = (row % 9) / 3, kw = row % 3;
+    const int b = (int)(nn / ((size_t)Ho * Wo));
+    const int r = (int)(nn % ((size_t)Ho * Wo));
+    const int h = (r / Wo) * s - 1 + kh, w = (r % Wo) * s - 1 + kw;
+    float v = 0.f;
+    if (h >= 0 && h < H && w >= 0 && w < W) v = x[(((size_t)c * B + b) * H + h) * W + w];
+    col[i] = to_bf16(v);
+  }
+}
+
+// dx[c][b][h][w] = sum over the (kh, kw, ho, wo) that read x[c][b][h][w] of dcol
+__global__ void k_col2im(const float* __restrict__ dcol, int C, int B, int H, int W, int s, int Ho, int Wo,
+                         float* __restrict__ dx) {
+  const size_t N = (size_t)B * Ho * Wo, total = (size_t)C * B * H * W;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int w = (int)(i % W), h = (int)((i / W) % H);
+    const int b = (int)((i / ((size_t)W * H)) % B), c = (int)(i / ((size_t)W * H * B));
+    float v = 0.f;
+    for (int kh = 0; kh < 3; ++kh) {
+      const int hh = h + 1 - kh;
+      if (hh < 0 || hh % s) continue;
+      const int ho = hh / s;
+      if (ho >= Ho) continue;
+      for (int kw = 0; kw < 3; ++kw) {
+        const int ww = w + 1 - kw;
+        if (ww < 0 || ww % s) continue;
+        const int wo = ww / s;
+        if (wo >= Wo) continue;
+        v += dcol[(size_t)(c * 9 + kh * 3 + kw) * N + ((size_t)b * Ho + ho) * Wo + wo];
+      }
+    }
+    dx[i] = v;
+  }
+}
+
+// y[r][j] += bias[r]; optional ReLU; optional BF16 copy
+__global__ void k_bias_act(float* __restrict__ y, const float* __restrict__ bias, int rows, size_t cols, int relu,
+                           uint16_t* __restrict__ yb) {
+  const size_t total = (size_t)rows * cols;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    float v = y[i] + bias[i / cols];
+    if (relu) v = fmaxf(v, 0.f);
+    y[i] = v;
+    if (yb) yb[i] = to_bf16(v);
+  }
+}
+
+// dz = dy * (y > 0) (BF16 copy for the GEMMs), db[r] = sum_j dz[r][j]; one block per row
+__global__ __launch_bounds__(256) void k_act_bwd(const float* __restrict__ dy, const float* __restrict__ y,
+                                                 size_t cols, int relu, uint16_t* __restrict__ dzb,
+                                                 float* __restrict__ db) {
+  __shared__ float red[256];
+  const int r = blockIdx.x;
+  float acc = 0.f;
+  for (size_t j = threadIdx.x; j < cols; j += 256) {
+    const size_t i = (size_t)r * cols + j;
+    const float v = (!relu || y[i] > 0.f) ? dy[i] : 0.f;
+    dzb[i] = to_bf16(v);
+    acc += v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[r] = red[0];
+}
+
+// p[c][b] = mean over s of x[c][b][s] (FP32 and BF16)
+__global__ void k_pool_fwd(const float* __restrict__ x, int C, int B, int S, float* __restrict__ p,
+                           uint16_t* __restrict__ pb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C * B) return;
+  float v = 0.f;
+  for (int s = 0; s < S; ++s) v += x[(size_t)i * S + s];
+  v /= (float)S;
+  p[i] = v;
+  pb[i] = to_bf16(v);
+}
+
+__global__ void k_pool_bwd(const float* __restrict__ dp, int C, int B, int S, float* __restrict__ dx) {
+  const size_t total = (size_t)C * B * S;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+    dx[i] = dp[i / S] / (float)S;
+}
+
+// loss = mean (pred - t)^2, dpred = 2 (pred - t) / B (single block)
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ pred, const float* __restrict__ t, int B,
+                                             float* __restrict__ dpred, float* __restrict__ loss) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < B; i += 256) {
+    const float d = pred[i] - t[i];
+    dpred[i] = 2.f * d / (float)B;
+    acc += d * d;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) *loss = red[0] / (float)B;
+}
+
+// Adam with bias correction; refreshes the BF16 copy of the weight
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       size_t n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       uint16_t* __restrict__ wb) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = to_bf16(wi);
+  }
+}
+
+// Input channels of view `index` from its 80x60-class render: depth / depth_scale,
+// final transmittance, argmax object id / k, mean confidence.
+__global__ void k_features(const float* __restrict__ depth, const float* __restrict__ tfin,
+                           const int32_t* __restrict__ id, const float* __restrict__ kbar, int HW, int B, int index,
+                           float inv_depth, float inv_k, float* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW) return;
+  x[((size_t)0 * B + index) * HW + i] = depth[i] * inv_depth;
+  x[((size_t)1 * B + index) * HW + i] = tfin[i];
+  x[((size_t)2 * B + index) * HW + i] = (float)id[i] * inv_k;
+  x[((size_t)3 * B + index) * HW + i] = kbar[i];
+}
+
+// ---- network shape and workspace ------------------------------------------------------------
+struct ConvShape { int ci, co, h, w, ho, wo; };
+constexpr ConvShape kConv[4] = {{4, 32, 60, 80, 30, 40}, {32, 64, 30, 40, 15, 20}, {64, 128, 15, 20, 8, 10},
+                                {128, 128, 8, 10, 4, 5}};
+constexpr int kWidth = NGS_SUR_WIDTH;
+
+struct SurWs {
+  uint16_t* col[4];  // im2col of each conv input [ci * 9][B ho wo]
+  float* act[4];     // post-ReLU conv outputs [co][B ho wo]
+  float* pool;       // [128][B]
+  uint16_t* poolb;
+  float* hid;        // [128][B]
+  uint16_t* hidb;
+  float* pred;       // [B] (fc2 output before the caller's copy)
+  float* dz;         // FP32 gradient scratch, the largest activation
+  uint16_t* dzb;     // its BF16 copy
+  float* dcol;       // [ci * 9][B ho wo] of the largest layer
+  float* dact;       // gradient of the current layer input
+  uint16_t* xb;      // unused (kept aligned)
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t sur_ws_bytes(int B) {
+  size_t s = 0;
+  size_t max_act = 0, max_col = 0;
+  for (int l = 0; l < 4; ++l) {
+    const size_t n = (size_t)B * kConv[l].ho * kConv[l].wo;
+    s += al((size_t)kConv[l].ci * 9 * n * 2) + al((size_t)kConv[l].co * n * 4);
+    max_act = std::max(max_act, (size_t)kConv[l].co * n);
+    max_act = std::max(max_act, (size_t)kConv[l].ci * B * kConv[l].h * kConv[l].w);
+    max_col = std::max(max_col, (size_t)kConv[l].ci * 9 * n);
+  }
+  s += 2 * (al((size_t)kWidth * B * 4) + al((size_t)kWidth * B * 2)) + al((size_t)B * 4);
+  s += al(max_act * 4) + al(max_act * 2) + al(max_col * 4) + al(max_act * 4);
+  return s;
+}
+
+SurWs sur_ws_carve(void* ws, int B) {
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t b) { char* r = p; p += al(b); return r; };
+  SurWs w;
+  size_t max_act = 0, max_col = 0;
+  for (int l = 0; l < 4; ++l) {
+    const size_t n = (size_t)B * kConv[l].ho * kConv[l].wo;
+    w.col[l] = (uint16_t*)take((size_t)kConv[l].ci * 9 * n * 2);
+    w.act[l] = (float*)take((size_t)kConv[l].co * n * 4);
+    max_act = std::max(max_act, (size_t)kConv[l].co * n);
+    max_act = std::max(max_act, (size_t)kConv[l].ci * B * kConv[l].h * kConv[l].w);
+    max_col = std::max(max_col, (size_t)kConv[l].ci * 9 * n);
+  }
+  w.pool = (float*)take((size_t)kWidth * B * 4);
+  w.poolb = (uint16_t*)take((size_t)kWidth * B * 2);
+  w.hid = (float*)take((size_t)kWidth * B * 4);
+  w.hidb = (uint16_t*)take((size_t)kWidth * B * 2);
+  w.pred = (float*)take((size_t)B * 4);
+  w.dz = (float*)take(max_act * 4);
+  w.dzb = (uint16_t*)take(max_act * 2);
+  w.dcol = (float*)take(max_col * 4);
+  w.dact = (float*)take(max_act * 4);
+  w.xb = nullptr;
+  return w;
+}
+
+// weight elements of layer l (conv 0..3, fc 4..5) and its output width
+inline size_t layer_w(int l) {
+  if (l < 4) return (size_t)kConv[l].co * kConv[l].ci * 9;
+  return l == 4 ? (size_t)kWidth * kWidth : (size_t)kWidth;
+}
+inline int layer_out(int l) { return l < 4 ? kConv[l].co : (l == 4 ? kWidth : 1); }
+
+#define SUR_TRY(expr)                      \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return e_;       \
+  } while (0)
+
+}  // namespace
+
+size_t sur_workspace_bytes(int batch) { return sur_ws_bytes(batch); }
+
+hipError_t sur_gemm(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                    float* C, int ldc, float beta, hipStream_t st) {
+  return gemm(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, beta, st);
+}
+
+hipError_t sur_sync_bf16(const ngs_sur_params& p, hipStream_t st) {
+  for (int l = 0; l < NGS_SUR_LAYERS; ++l) {
+    const size_t n = layer_w(l);
+    hipLaunchKernelGGL(k_to_bf16, ew_grid(n), dim3(kEw), 0, st, p.w[l], p.w_bf16[l], n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t sur_forward(const ngs_sur_params& p, const float* x, int B, float* pred, void* ws, hipStream_t st) {
+  ProfScope ps(kProfSurForward, st);
+  SurWs w = sur_ws_carve(ws, B);
+  const float* in = x;
+  for (int l = 0; l < 4; ++l) {
+    const ConvShape& c = kConv[l];
+    const size_t n = (size_t)B * c.ho * c.wo;
+    hipLaunchKernelGGL(k_im2col, ew_grid((size_t)c.ci * 9 * n), dim3(kEw), 0, st, in, c.ci, B, c.h, c.w, 2, c.ho,
+                       c.wo, w.col[l]);
+    SUR_TRY(hipGetLastError());
+    SUR_TRY(gemm(false, false, c.co, (int)n, c.ci * 9, p.w_bf16[l], c.ci * 9, w.col[l], (int)n, w.act[l], (int)n,
+                 0.f, st));
+    hipLaunchKernelGGL(k_bias_act, ew_grid((size_t)c.co * n), dim3(kEw), 0, st, w.act[l], p.b[l], c.co, n, 1,
+                       (uint16_t*)nullptr);
+    in = w.act[l];
+  }
+  const int S = kConv[3].ho * kConv[3].wo;
+  hipLaunchKernelGGL(k_pool_fwd, dim3((kWidth * B + 255) / 256), dim3(256), 0, st, w.act[3], kWidth, B, S, w.pool,
+                     w.poolb);
+  SUR_TRY(gemm(false, false, kWidth, B, kWidth, p.w_bf16[4], kWidth, w.poolb, B, w.hid, B, 0.f, st));
+  hipLaunchKernelGGL(k_bias_act, ew_grid((size_t)kWidth * B), dim3(kEw), 0, st, w.hid, p.b[4], kWidth, (size_t)B, 1,
+                     w.hidb);
+  SUR_TRY(gemm(false, false, 1, B, kWidth, p.w_bf16[5], kWidth, w.hidb, B, w.pred, B, 0.f, st));
+  hipLaunchKernelGGL(k_bias_act, ew_grid((size_t)B), dim3(kEw), 0, st, w.pred, p.b[5], 1, (size_t)B, 0,
+                     (uint16_t*)nullptr);
+  SUR_TRY(hipMemcpyAsync(pred, w.pred, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  return hipGetLastError();
+}
+
+hipError_t sur_backward(const ngs_sur_params& p, const float* x, int B, const float* dpred, const ngs_sur_params& g,
+                        void* ws, hipStream_t st) {
+  ProfScope ps(kProfSurBackward, st);
+  SurWs w = sur_ws_carve(ws, B);
+  // fc2: dz = dpred (no activation)
+  hipLaunchKernelGGL(k_act_bwd, dim3(1), dim3(256), 0, st, dpred, w.pred, (size_t)B, 0, w.dzb, g.b[5]);
+  SUR_TRY(gemm(false, true, 1, kWidth, B, w.dzb, B, w.hidb, B, g.w[5], kWidth, 0.f, st));          // dW = dz hid^T
+  SUR_TRY(gemm(true, false, kWidth, B, 1, p.w_bf16[5], kWidth, w.dzb, B, w.dact, B, 0.f, st));      // dhid = W^T dz
+  // fc1
+  hipLaunchKernelGGL(k_act_bwd, dim3(kWidth), dim3(256), 0, st, w.dact, w.hid, (size_t)B, 1, w.dzb, g.b[4]);
+  SUR_TRY(gemm(false, true, kWidth, kWidth, B, w.dzb, B, w.poolb, B, g.w[4], kWidth, 0.f, st));
+  SUR_TRY(gemm(true, false, kWidth, B, kWidth, p.w_bf16[4], kWidth, w.dzb, B, w.dz, B, 0.f, st));   // dpool
+  const int S = kConv[3].ho * kConv[3].wo;
+  hipLaunchKernelGGL(k_pool_bwd, ew_grid((size_t)kWidth * B * S), dim3(kEw), 0, st, w.dz, kWidth, B, S, w.dact);
+  for (int l = 3; l >= 0; --l) {
+    const ConvShape& c = kConv[l];
+    const size_t n = (size_t)B * c.ho * c.wo;
+    hipLaunchKernelGGL(k_act_bwd, dim3(c.co), dim3(256), 0, st, w.dact, w.act[l], n, 1, w.dzb, g.b[l]);
+    SUR_TRY(hipGetLastError());
+    SUR_TRY(gemm(false, true, c.co, c.ci * 9, (int)n, w.dzb, (int)n, w.col[l], (int)n, g.w[l], c.ci * 9, 0.f, st));
+    if (l == 0) break;
+    SUR_TRY(gemm(true, false, c.ci * 9, (int)n, c.co, p.w_bf16[l], c.ci * 9, w.dzb, (int)n, w.dcol, (int)n, 0.f, st));
+    hipLaunchKernelGGL(k_col2im, ew_grid((size_t)c.ci * B * c.h * c.w), dim3(kEw), 0, st, w.dcol, c.ci, B, c.h, c.w,
+                       2, c.ho, c.wo, w.dact);
+  }
+  (void)x;
+  return hipGetLastError();
+}
+
+hipError_t sur_mse(const float* pred, const float* target, int B, float* dpred, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, pred, target, B, dpred, loss);
+  return hipGetLastError();
+}
+
+hipError_t sur_adam(const ngs_sur_params& p, const ngs_sur_params& g, const ngs_sur_params& m,
+                    const ngs_sur_params& v, float lr, float b1, float b2, float eps, int step, hipStream_t st) {
+  const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+  for (int l = 0; l < NGS_SUR_LAYERS; ++l) {
+    const size_t nw = layer_w(l), nb = (size_t)layer_out(l);
+    hipLaunchKernelGGL(k_adam, ew_grid(nw), dim3(kEw), 0, st, p.w[l], g.w[l], m.w[l], v.w[l], nw, lr, b1, b2, eps, c1,
+                       c2, p.w_bf16[l]);
+    hipLaunchKernelGGL(k_adam, ew_grid(nb), dim3(kEw), 0, st, p.b[l], g.b[l], m.b[l], v.b[l], nb, lr, b1, b2, eps, c1,
+                       c2, (uint16_t*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
+                        hipStream_t st) {
+  const int HW = W * H;
+  hipLaunchKernelGGL(k_features, dim3((HW + 255) / 256), dim3(256), 0, st, img.depth, img.t_final, img.argmax_id,
+                     img.mean_conf, HW, B, index, 1.f / depth_scale, 1.f / (float)k, x);
+  return hipGetLastError();
+}
+
+}  // namespace ngs

@@ -1,15 +1,15 @@
 """CPU-side checks of the boundary: the built library loads and exports every entry point
-declared in include/ngs.h (no compute call: there is no GPU here)."""
+declared in include/*.h (no compute call: there is no GPU here)."""
 import ctypes
 import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ngs.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include"))) if f.endswith(".h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "\n".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:ngs_status|const char\*|int32_t)\s+(ngs_\w+)\s*\(", src, flags=re.M)))
 
