@@ -70,16 +70,28 @@ ngs_status ngs_sur_adam(ngs_ctx* ctx, ngs_sur_params* params, const ngs_sur_para
 ngs_status ngs_sur_features(ngs_ctx* ctx, const ngs_image* img, int32_t width, int32_t height, int32_t k,
                             float depth_scale, float* x, int32_t batch, int32_t index, void* stream);
 
+/* Per-Gaussian novelty against a training store (device, out [n] FP32):
+ * out[g] = c_g * (1/3) sum_f exp(-(logdet H_T,g,f - d_f ln lambda) / d_f) over the outputs
+ * f = rgb, depth, object (d_f = 14, 11, 11 + k; Eq. 9 blocks with the prior lambda I), i.e. the
+ * confidence of Eq. 7 / 12 times the mean reciprocal geometric-mean eigenvalue of H_T / lambda:
+ * c_g for a Gaussian no training view touched (or h NULL), smaller the better it is observed.
+ * lambda_prior must be the one the store was built with. The scene must be prepared.
+ * An input the surrogate's feature render averages (not part of the paper's method). */
+ngs_status ngs_sur_novelty(ngs_ctx* ctx, const ngs_scene* scene, const ngs_hessian* h, float lambda_prior,
+                           float* out, void* stream);
+
 /* Feature maps of n_views candidates (every camera 80 x 60) in one call: per view, projection,
  * binning and compositing (as ngs_project, ngs_bin_sort, ngs_render) and the four input
- * channels into x [4][n_views][60][80] (as ngs_sur_features, depth / depth_scale). Views run
+ * channels into x [4][n_views][60][80] (as ngs_sur_features, depth / depth_scale). With
+ * weight (device [n], may be NULL) the fourth channel averages weight[g] along each ray
+ * where ngs_render averages kappa (e.g. the output of ngs_sur_novelty). Views run
  * dims->views_in_flight at a time on the context's streams, like ngs_score_batch; no host
  * synchronisation except one at the end. The scene must be prepared. ws:
  * ngs_workspace_size(4, dims) bytes. NGS_CAPACITY if a view has more pairs than
  * dims->max_pairs. */
 ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,
-                                   const ngs_raster_params* rp, float depth_scale, float* x, const ngs_dims* dims,
-                                   void* ws, size_t ws_bytes, void* stream);
+                                   const ngs_raster_params* rp, const float* weight, float depth_scale, float* x,
+                                   const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream);
 
 /* c [m][n] = op(a) op(b) + beta c with BF16 a, b (raw 16-bit words) and FP32 c on the matrix
  * cores. op(a) = a [m][k] (lda) or, with trans_a, a^T of a [k][m]; op(b) = b [k][n] (ldb) or,

@@ -26,7 +26,7 @@ EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs
            "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_kernels", "ngs_profile_kernel_name",
            "ngs_profile_read", "ngs_sur_workspace_size", "ngs_sur_sync_bf16", "ngs_sur_forward", "ngs_sur_backward",
-           "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_render_features", "ngs_gemm_bf16"]
+           "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_novelty", "ngs_sur_render_features", "ngs_gemm_bf16"]
 
 
 class NgsError(RuntimeError):
@@ -135,7 +135,8 @@ def lib():
         L.ngs_sur_mse.argtypes = [P, P, P, i32, P, P, P]
         L.ngs_sur_adam.argtypes = [P, P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, i32, P]
         L.ngs_sur_features.argtypes = [P, P, i32, i32, i32, C.c_float, P, i32, i32, P]
-        L.ngs_sur_render_features.argtypes = [P, P, P, i32, P, C.c_float, P, P, P, C.c_size_t, P]
+        L.ngs_sur_novelty.argtypes = [P, P, P, C.c_float, P, P]
+        L.ngs_sur_render_features.argtypes = [P, P, P, i32, P, P, C.c_float, P, P, P, C.c_size_t, P]
         L.ngs_gemm_bf16.argtypes = [P, i32, i32, i32, i32, i32, P, i32, P, i32, P, i32, C.c_float, P]
         L.ngs_profile_enable.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
@@ -534,16 +535,27 @@ class FeatureRenderer:
                           scene.device)
 
     def __call__(self, cams: Sequence[ngs_camera], rp: ngs_raster_params, depth_scale: float,
-                 x: Optional[torch.Tensor] = None) -> torch.Tensor:
+                 x: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None) -> torch.Tensor:
         nv = len(cams)
         if x is None:
             x = torch.empty((4, nv, SUR_IN[1], SUR_IN[2]), dtype=torch.float32, device=self.scene.device)
         arr = (ngs_camera * nv)(*cams)
         sc = self.scene.c()
         _check("ngs_sur_render_features", lib().ngs_sur_render_features(
-            self.ctx.handle, _ref(sc), arr, nv, _ref(rp), float(depth_scale), _p(x), _ref(self.dims), _p(self.buf),
+            self.ctx.handle, _ref(sc), arr, nv, _ref(rp), _p(weight), float(depth_scale), _p(x), _ref(self.dims),
+            _p(self.buf),
             self.buf.numel(), _stream()), self.ctx)
         return x
+
+
+def ngs_sur_novelty(ctx: Context, scene: DeviceScene, h: Optional[Hessian], lambda_prior: float) -> torch.Tensor:
+    """Per-Gaussian confidence x novelty against the training store h (see ngs_surrogate.h)."""
+    out = torch.empty(max(scene.n, 1), dtype=torch.float32, device=scene.device)
+    sc = scene.c()
+    hc = h.c() if h is not None else None
+    _check("ngs_sur_novelty", lib().ngs_sur_novelty(ctx.handle, _ref(sc), _ref(hc) if hc is not None else None,
+                                                    float(lambda_prior), _p(out), _stream()), ctx)
+    return out
 
 
 class IgWorkspace:

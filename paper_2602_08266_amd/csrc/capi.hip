@@ -17,6 +17,8 @@ struct ngs_ctx {
   std::vector<hipStream_t> lanes;
   std::vector<hipEvent_t> lane_done;
   hipEvent_t fork = nullptr;
+  // ngs_sur_render_features: the two halves of its double-buffered view groups are free again
+  hipEvent_t half_done[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -137,6 +139,8 @@ int views_in_flight(const ngs_dims* d) {
 // Creates the context's in-flight streams and events up to `want`.
 ngs_status ensure_lanes(ngs_ctx* ctx, int want) {
   if (!ctx->fork) NGS_TRY_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  for (hipEvent_t& e : ctx->half_done)
+    if (!e) NGS_TRY_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   while ((int)ctx->lanes.size() < want) {
     hipStream_t s = nullptr;
     NGS_TRY_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -224,6 +228,8 @@ ngs_status ngs_destroy(ngs_ctx* ctx) {
   for (hipStream_t s : ctx->lanes) (void)hipStreamDestroy(s);
   for (hipEvent_t e : ctx->lane_done) (void)hipEventDestroy(e);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  for (hipEvent_t e : ctx->half_done)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return NGS_OK;
@@ -255,7 +261,8 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
     case 1: *bytes = igb; return NGS_OK;
     case 2: *bytes = (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + igb); return NGS_OK;
     case 3: *bytes = bwd_ws_bytes(d->n, d->k); return NGS_OK;
-    case 4: *bytes = kIgHeader + (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + feat_img_bytes());
+    case 4: *bytes = kIgHeader + 2 * (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) +
+                                                                       feat_img_bytes());
       return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
@@ -564,13 +571,24 @@ ngs_status ngs_sur_features(ngs_ctx* ctx, const ngs_image* img, int32_t width, i
       index >= batch)
     return NGS_INVALID_ARG;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  NGS_TRY_HIP(ctx, sur_features(*img, width, height, k, depth_scale, x, batch, index, (hipStream_t)stream));
+  NGS_TRY_HIP(ctx, sur_features(*img, width, height, k, depth_scale, x, batch, index, 1, 0, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_sur_novelty(ngs_ctx* ctx, const ngs_scene* scene, const ngs_hessian* h, float lambda_prior,
+                           float* out, void* stream) {
+  if (!ctx || !out || !(lambda_prior > 0.f)) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, true);
+  if (s != NGS_OK) return s;
+  if (h && (!h->slot_of || !h->logdet || h->capacity < 1 || h->k != scene->k)) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  NGS_TRY_HIP(ctx, sur_novelty(*scene, h, lambda_prior, out, (hipStream_t)stream));
   return NGS_OK;
 }
 
 ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,
-                                   const ngs_raster_params* rp, float depth_scale, float* x, const ngs_dims* dims,
-                                   void* ws, size_t ws_bytes, void* stream) {
+                                   const ngs_raster_params* rp, const float* weight, float depth_scale, float* x,
+                                   const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !cams || n_views < 1 || !x || !dims || !(depth_scale > 0.f)) return NGS_INVALID_ARG;
   if (dims->n != scene->n || dims->k != scene->k || dims->max_pairs < 1) return NGS_INVALID_ARG;
   ngs_status s = check_scene(scene, true);
@@ -586,38 +604,46 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
   if (!ws || ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  const int lanes = std::max(1, std::min(views_in_flight(dims), n_views));
-  s = ensure_lanes(ctx, lanes);
+  // Views go in groups of G: each view of a group is projected and binned on its own context
+  // stream, then one render launch composites the whole group (grid.y = view) and one launch
+  // writes its feature channels, both on `stream`. Groups alternate between two halves of
+  // the buffer sets, so binning of the next group overlaps the render of this one.
+  const int G = std::max(1, std::min(views_in_flight(dims), n_views));
+  s = ensure_lanes(ctx, G);
   if (s != NGS_OK) return s;
   int32_t* sticky = static_cast<int32_t*>(ws);
   NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, kIgHeader, st));
-  const size_t per = (need - kIgHeader) / (size_t)views_in_flight(dims);
+  const size_t per = (need - kIgHeader) / (2 * (size_t)views_in_flight(dims));
   char* base = static_cast<char*>(ws) + kIgHeader;
-  std::vector<BatchWs> sets(lanes);
-  std::vector<ngs_image> imgs(lanes);
   const size_t fixed = al(batch_fixed_bytes(scene->n, dims->max_pairs));
-  for (int i = 0; i < lanes; ++i) {
-    sets[i] = batch_carve(base + (size_t)i * per, fixed, scene->n, dims->max_pairs);
-    imgs[i] = feat_img_carve(base + (size_t)i * per + fixed);
-  }
   NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
-  for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
+  for (int i = 0; i < G; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   const RasterConst rc = make_raster(*rp);
-  for (int v = 0; v < n_views; ++v) {
-    const int i = v % lanes;
-    hipStream_t ls = ctx->lanes[i];
-    const BatchWs& b = sets[i];
-    const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
-    const DevCam dc = make_devcam(cams[v], kTile);
-    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
-    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, ls));
-    NGS_TRY_HIP(ctx, launch_render(*scene, b.proj, b.lists, dc, rc, imgs[i], ls));
-    NGS_TRY_HIP(ctx, sur_features(imgs[i], NGS_SUR_IN_W, NGS_SUR_IN_H, scene->k, depth_scale, x, n_views, v, ls));
-  }
-  for (int i = 0; i < lanes; ++i) {
-    NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ctx->lanes[i]));
-    NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
+  ngs_scene ws_scene = *scene;  // the render averages `weight` where it would average kappa
+  if (weight) ws_scene.kappa = const_cast<float*>(weight);
+  for (int q = 0, v0 = 0; v0 < n_views; ++q, v0 += G) {
+    const int g = std::min(G, n_views - v0);
+    const int half = q & 1;
+    for (int i = 0; i < g; ++i) {
+      hipStream_t ls = ctx->lanes[i];
+      if (q >= 2) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ls, ctx->half_done[half], 0));
+      const BatchWs b = batch_carve(base + (size_t)(half * G + i) * per, fixed, scene->n, dims->max_pairs);
+      const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
+      const DevCam dc = make_devcam(cams[v0 + i], kTile);
+      NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
+      NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, ls));
+      NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ls));
+      NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
+    }
+    char* first = base + (size_t)(half * G) * per;
+    const BatchWs b0 = batch_carve(first, fixed, scene->n, dims->max_pairs);
+    const ngs_image img0 = feat_img_carve(first + fixed);
+    const DevCam dc0 = make_devcam(cams[v0], kTile);  // every view is 80 x 60: one tile grid
+    NGS_TRY_HIP(ctx, launch_render_views(ws_scene, b0.proj, b0.lists, dc0, rc, img0, g, per, st));
+    NGS_TRY_HIP(ctx, sur_features(img0, NGS_SUR_IN_W, NGS_SUR_IN_H, scene->k, depth_scale, x, n_views, v0, g, per,
+                                  st));
+    NGS_TRY_HIP(ctx, hipEventRecord(ctx->half_done[half], st));
   }
   int64_t of = 0;
   s = read_i64(ctx, sticky, 4, st, &of);

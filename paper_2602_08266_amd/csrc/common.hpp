@@ -156,6 +156,11 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
 hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                          const DevCam& cam, const RasterConst& rc, const ngs_image& img,
                          hipStream_t st);
+// Views of one size in one launch (grid.y = view); view v's projection, lists and images lie
+// v * stride bytes past those passed.
+hipError_t launch_render_views(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+                               const RasterConst& rc, const ngs_image& img, int views, size_t stride,
+                               hipStream_t st);
 
 // Information gain (info_gain.hip, finalize.hip).
 struct IgWs {
@@ -193,8 +198,9 @@ hipError_t sur_backward(const ngs_sur_params& p, const float* x, int B, const fl
 hipError_t sur_mse(const float* pred, const float* target, int B, float* dpred, float* loss, hipStream_t st);
 hipError_t sur_adam(const ngs_sur_params& p, const ngs_sur_params& g, const ngs_sur_params& m,
                     const ngs_sur_params& v, float lr, float b1, float b2, float eps, int step, hipStream_t st);
+hipError_t sur_novelty(const ngs_scene& s, const ngs_hessian* h, float lambda, float* out, hipStream_t st);
 hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
-                        hipStream_t st);
+                        int views, size_t set_stride, hipStream_t st);
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
                                 float beta_d, float beta_o, uint32_t outputs, float* scores,
                                 int32_t* best, hipStream_t st);

@@ -5,6 +5,8 @@
 // (SoA scalars plus the k-long probability rows). A pixel leaves the walk at the first
 // Gaussian that would drop its transmittance below t_min; a wavefront stops issuing once
 // all its lanes have left, and the workgroup stops loading batches once all 256 have.
+// Several views of one size can share a launch (grid.y = view): their per-view buffers
+// (projection, lists, images) sit at a fixed byte stride from the first view's.
 #include "common.hpp"
 
 namespace ngs {
@@ -21,7 +23,23 @@ __global__ __launch_bounds__(kTilePix) void k_render(int n, int k, const uint32_
                                                      const float* __restrict__ kappa, float* __restrict__ out_rgb,
                                                      float* __restrict__ out_depth, float* __restrict__ out_obj,
                                                      float* __restrict__ out_t, float* __restrict__ out_conf,
-                                                     int32_t* __restrict__ out_id, int32_t* __restrict__ out_nc) {
+                                                     int32_t* __restrict__ out_id, int32_t* __restrict__ out_nc,
+                                                     size_t set_stride) {
+  if (blockIdx.y) {
+    const size_t so = (size_t)blockIdx.y * set_stride;
+    gids = (const uint32_t*)((const char*)gids + so);
+    ranges = (const uint32_t*)((const char*)ranges + so);
+    mean2d = (const float*)((const char*)mean2d + so);
+    conic = (const float*)((const char*)conic + so);
+    depth = (const float*)((const char*)depth + so);
+    if (out_rgb) out_rgb = (float*)((char*)out_rgb + so);
+    if (out_depth) out_depth = (float*)((char*)out_depth + so);
+    if (out_obj) out_obj = (float*)((char*)out_obj + so);
+    if (out_t) out_t = (float*)((char*)out_t + so);
+    if (out_conf) out_conf = (float*)((char*)out_conf + so);
+    if (out_id) out_id = (int32_t*)((char*)out_id + so);
+    if (out_nc) out_nc = (int32_t*)((char*)out_nc + so);
+  }
   __shared__ float s_mx[kBatch], s_my[kBatch], s_qa[kBatch], s_qb[kBatch], s_qc[kBatch], s_op[kBatch];
   __shared__ float s_z[kBatch], s_r[kBatch], s_g[kBatch], s_b[kBatch], s_kap[kBatch], s_hx[kBatch], s_hy[kBatch];
   __shared__ float s_p[kBatch][KP];
@@ -115,24 +133,31 @@ __global__ __launch_bounds__(kTilePix) void k_render(int n, int k, const uint32_
 
 template <int KP>
 hipError_t launch_render_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
-                           const RasterConst& rc, const ngs_image& img, hipStream_t st) {
+                           const RasterConst& rc, const ngs_image& img, int views, size_t stride, hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   ProfScope ps(kProfRender, st);
-  hipLaunchKernelGGL(k_render<KP>, dim3(ntiles), dim3(kTilePix), 0, st, s.n, s.k, l.gids, l.ranges, cam, rc,
+  hipLaunchKernelGGL(k_render<KP>, dim3(ntiles, views), dim3(kTilePix), 0, st, s.n, s.k, l.gids, l.ranges, cam, rc,
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, s.kappa, img.rgb, img.depth, img.obj,
-                     img.t_final, img.mean_conf, img.argmax_id, img.n_contrib);
+                     img.t_final, img.mean_conf, img.argmax_id, img.n_contrib, stride);
   return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t launch_render_views(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+                               const RasterConst& rc, const ngs_image& img, int views, size_t stride,
+                               hipStream_t st) {
+  if (views < 1) return hipSuccess;
+  if (s.k <= 4) return launch_render_k<4>(s, p, l, cam, rc, img, views, stride, st);
+  if (s.k <= 8) return launch_render_k<8>(s, p, l, cam, rc, img, views, stride, st);
+  if (s.k <= 16) return launch_render_k<16>(s, p, l, cam, rc, img, views, stride, st);
+  if (s.k <= 32) return launch_render_k<32>(s, p, l, cam, rc, img, views, stride, st);
+  return launch_render_k<64>(s, p, l, cam, rc, img, views, stride, st);
+}
+
 hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                          const RasterConst& rc, const ngs_image& img, hipStream_t st) {
-  if (s.k <= 4) return launch_render_k<4>(s, p, l, cam, rc, img, st);
-  if (s.k <= 8) return launch_render_k<8>(s, p, l, cam, rc, img, st);
-  if (s.k <= 16) return launch_render_k<16>(s, p, l, cam, rc, img, st);
-  if (s.k <= 32) return launch_render_k<32>(s, p, l, cam, rc, img, st);
-  return launch_render_k<64>(s, p, l, cam, rc, img, st);
+  return launch_render_views(s, p, l, cam, rc, img, 1, 0, st);
 }
 
 }  // namespace ngs

@@ -33,34 +33,38 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 // 64 x 64 block tile, K step 32, four wavefronts each owning a 32 x 32 quarter as 2 x 2
 // MFMA tiles of 16 x 16. For v_mfma_f32_16x16x32_bf16 lane l supplies row (l mod 16) of A
 // and column (l mod 16) of B at k = 8 (l / 16) ... +7, and receives C rows 4 (l / 16) ... +3
-// of column (l mod 16).
+// of column (l mod 16). Long-K products with few output tiles (the weight gradients, whose K
+// is batch x pixels) split K over grid.z: each split writes its partial tile to a workspace
+// slab and a second kernel sums the slabs in split order, so results do not depend on timing.
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;
+constexpr int kMaxSplits = 64;
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
                                                    const uint16_t* __restrict__ B, int ldb, float* __restrict__ C,
-                                                   int ldc, float beta) {
+                                                   int ldc, float beta, int kchunk, float* __restrict__ part) {
   __shared__ __align__(16) uint16_t As[kGM][kGK + kGPad];
   __shared__ __align__(16) uint16_t Bs[kGN][kGK + kGPad];
   const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += kGK) {
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
     for (int e = tid; e < kGM * kGK; e += 256) {
       const int mm = TA ? e % kGM : e / kGK, kk = TA ? e / kGM : e % kGK;
       const int gm = m0 + mm, gk = k0 + kk;
       uint16_t v = 0;
-      if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+      if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
       As[mm][kk] = v;
     }
     for (int e = tid; e < kGN * kGK; e += 256) {
       const int nn = TB ? e / kGK : e % kGN, kk = TB ? e % kGK : e / kGN;
       const int gn = n0 + nn, gk = k0 + kk;
       uint16_t v = 0;
-      if (gn < N && gk < K) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+      if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
       Bs[nn][kk] = v;
     }
     __syncthreads();
@@ -85,21 +89,57 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
         const int row = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + i;
         const int col = n0 + wn * 32 + ni * 16 + (lane & 15);
         if (row < M && col < N) {
-          float* c = C + (size_t)row * ldc + col;
-          *c = acc[mi][ni][i] + (beta != 0.f ? beta * *c : 0.f);
+          if (part) {
+            part[((size_t)blockIdx.z * M + row) * N + col] = acc[mi][ni][i];
+          } else {
+            float* c = C + (size_t)row * ldc + col;
+            *c = acc[mi][ni][i] + (beta != 0.f ? beta * *c : 0.f);
+          }
         }
       }
 }
 
+__global__ void k_splitk_reduce(const float* __restrict__ part, int splits, int M, int N, float* __restrict__ C,
+                                int ldc, float beta) {
+  const size_t MN = (size_t)M * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < MN; i += (size_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * MN + i];
+    float* c = C + (i / N) * (size_t)ldc + (i % N);
+    *c = s + (beta != 0.f ? beta * *c : 0.f);
+  }
+}
+
+// Splits of K for an M x N x K product: enough workgroups to cover the chip twice, each split
+// at least 8 K steps long.
+int splitk_for(int M, int N, int K) {
+  const int tiles = ((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN);
+  if (tiles >= 512) return 1;
+  int s = std::min(kMaxSplits, (512 + tiles - 1) / tiles);
+  s = std::min(s, std::max(1, K / (8 * kGK)));
+  return std::max(s, 1);
+}
+
+// part: workspace for split-K partials (splitk_for(M, N, K) * M * N floats), or NULL for a
+// single pass.
 hipError_t gemm(bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
-                float* C, int ldc, float beta, hipStream_t st) {
+                float* C, int ldc, float beta, hipStream_t st, float* part = nullptr) {
   if (M <= 0 || N <= 0) return hipSuccess;
   ProfScope ps(kProfSurGemm, st);
-  const dim3 grid((N + kGN - 1) / kGN, (M + kGM - 1) / kGM);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
-  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta);
+  const int splits = part ? splitk_for(M, N, K) : 1;
+  const int kchunk = splits > 1 ? ((K + splits - 1) / splits + kGK - 1) / kGK * kGK : std::max(K, 1);
+  const int used = splits > 1 ? (K + kchunk - 1) / kchunk : 1;
+  float* pp = used > 1 ? part : nullptr;
+  const dim3 grid((N + kGN - 1) / kGN, (M + kGM - 1) / kGM, used);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta, kchunk, pp);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta, kchunk, pp);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta, kchunk, pp);
+  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, beta, kchunk, pp);
+  if (pp) {
+    const size_t mn = (size_t)M * N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)std::min<size_t>((mn + 255) / 256, 4096)), dim3(256), 0, st,
+                       pp, used, M, N, C, ldc, beta);
+  }
   return hipGetLastError();
 }
 
@@ -244,14 +284,41 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
 // Input channels of view `index` from its 80x60-class render: depth / depth_scale,
 // final transmittance, argmax object id / k, mean confidence.
 __global__ void k_features(const float* __restrict__ depth, const float* __restrict__ tfin,
-                           const int32_t* __restrict__ id, const float* __restrict__ kbar, int HW, int B, int index,
-                           float inv_depth, float inv_k, float* __restrict__ x) {
+                           const int32_t* __restrict__ id, const float* __restrict__ kbar, int HW, int B, int index0,
+                           float inv_depth, float inv_k, size_t set_stride, float* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= HW) return;
+  // view index0 + blockIdx.y reads the image set blockIdx.y * set_stride bytes past the first
+  const size_t so = (size_t)blockIdx.y * set_stride;
+  depth = (const float*)((const char*)depth + so);
+  tfin = (const float*)((const char*)tfin + so);
+  id = (const int32_t*)((const char*)id + so);
+  kbar = (const float*)((const char*)kbar + so);
+  const int index = index0 + (int)blockIdx.y;
   x[((size_t)0 * B + index) * HW + i] = depth[i] * inv_depth;
   x[((size_t)1 * B + index) * HW + i] = tfin[i];
   x[((size_t)2 * B + index) * HW + i] = (float)id[i] * inv_k;
   x[((size_t)3 * B + index) * HW + i] = kbar[i];
+}
+
+// Novelty of every Gaussian against the training information: for each output f with block
+// dimension d_f, the geometric mean eigenvalue of H_T,g,f relative to the prior lambda,
+// exp((logdet H_T,g,f - d_f ln lambda) / d_f), is 1 for a Gaussian no training view touched
+// and grows with what the views observed; its reciprocal, averaged over the three outputs and
+// scaled by the confidence c_g, is the weight the feature render averages along each ray.
+__global__ void k_novelty(int n, int k, const float* __restrict__ conf, const int32_t* __restrict__ slot_of,
+                          const double* __restrict__ logdet, int capacity, double ln_lambda, float* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int s = slot_of ? slot_of[g] : -1;
+  double nu = 1.0;
+  if (s >= 0 && s < capacity) {
+    const double d[3] = {14.0, 11.0, 11.0 + (double)k};
+    nu = 0.0;
+    for (int f = 0; f < 3; ++f) nu += exp(-(logdet[(size_t)f * capacity + s] - d[f] * ln_lambda) / d[f]);
+    nu *= 1.0 / 3.0;
+  }
+  out[g] = (float)((double)conf[g] * nu);
 }
 
 // ---- network shape and workspace ------------------------------------------------------------
@@ -273,7 +340,15 @@ struct SurWs {
   float* dcol;       // [ci * 9][B ho wo] of the largest layer
   float* dact;       // gradient of the current layer input
   uint16_t* xb;      // unused (kept aligned)
+  float* part;       // split-K partials of the weight-gradient products
 };
+
+// Largest split-K slab set of a weight-gradient product (co x ci*9 per layer, 128 x 128, 1 x 128).
+size_t part_floats() {
+  size_t m = (size_t)kWidth * kWidth;
+  for (int l = 0; l < 4; ++l) m = std::max(m, (size_t)kConv[l].co * kConv[l].ci * 9);
+  return (size_t)kMaxSplits * m;
+}
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -289,6 +364,7 @@ size_t sur_ws_bytes(int B) {
   }
   s += 2 * (al((size_t)kWidth * B * 4) + al((size_t)kWidth * B * 2)) + al((size_t)B * 4);
   s += al(max_act * 4) + al(max_act * 2) + al(max_col * 4) + al(max_act * 4);
+  s += al(part_floats() * 4);
   return s;
 }
 
@@ -315,6 +391,7 @@ SurWs sur_ws_carve(void* ws, int B) {
   w.dcol = (float*)take(max_col * 4);
   w.dact = (float*)take(max_act * 4);
   w.xb = nullptr;
+  w.part = (float*)take(part_floats() * 4);
   return w;
 }
 
@@ -332,6 +409,13 @@ inline int layer_out(int l) { return l < 4 ? kConv[l].co : (l == 4 ? kWidth : 1)
   } while (0)
 
 }  // namespace
+
+hipError_t sur_novelty(const ngs_scene& s, const ngs_hessian* h, float lambda, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_novelty, dim3((s.n + 255) / 256), dim3(256), 0, st, s.n, s.k, s.conf,
+                     h ? h->slot_of : nullptr, h ? h->logdet : nullptr, h ? h->capacity : 0,
+                     log((double)lambda), out);
+  return hipGetLastError();
+}
 
 size_t sur_workspace_bytes(int batch) { return sur_ws_bytes(batch); }
 
@@ -383,11 +467,11 @@ hipError_t sur_backward(const ngs_sur_params& p, const float* x, int B, const fl
   SurWs w = sur_ws_carve(ws, B);
   // fc2: dz = dpred (no activation)
   hipLaunchKernelGGL(k_act_bwd, dim3(1), dim3(256), 0, st, dpred, w.pred, (size_t)B, 0, w.dzb, g.b[5]);
-  SUR_TRY(gemm(false, true, 1, kWidth, B, w.dzb, B, w.hidb, B, g.w[5], kWidth, 0.f, st));          // dW = dz hid^T
+  SUR_TRY(gemm(false, true, 1, kWidth, B, w.dzb, B, w.hidb, B, g.w[5], kWidth, 0.f, st, w.part));          // dW = dz hid^T
   SUR_TRY(gemm(true, false, kWidth, B, 1, p.w_bf16[5], kWidth, w.dzb, B, w.dact, B, 0.f, st));      // dhid = W^T dz
   // fc1
   hipLaunchKernelGGL(k_act_bwd, dim3(kWidth), dim3(256), 0, st, w.dact, w.hid, (size_t)B, 1, w.dzb, g.b[4]);
-  SUR_TRY(gemm(false, true, kWidth, kWidth, B, w.dzb, B, w.poolb, B, g.w[4], kWidth, 0.f, st));
+  SUR_TRY(gemm(false, true, kWidth, kWidth, B, w.dzb, B, w.poolb, B, g.w[4], kWidth, 0.f, st, w.part));
   SUR_TRY(gemm(true, false, kWidth, B, kWidth, p.w_bf16[4], kWidth, w.dzb, B, w.dz, B, 0.f, st));   // dpool
   const int S = kConv[3].ho * kConv[3].wo;
   hipLaunchKernelGGL(k_pool_bwd, ew_grid((size_t)kWidth * B * S), dim3(kEw), 0, st, w.dz, kWidth, B, S, w.dact);
@@ -396,7 +480,8 @@ hipError_t sur_backward(const ngs_sur_params& p, const float* x, int B, const fl
     const size_t n = (size_t)B * c.ho * c.wo;
     hipLaunchKernelGGL(k_act_bwd, dim3(c.co), dim3(256), 0, st, w.dact, w.act[l], n, 1, w.dzb, g.b[l]);
     SUR_TRY(hipGetLastError());
-    SUR_TRY(gemm(false, true, c.co, c.ci * 9, (int)n, w.dzb, (int)n, w.col[l], (int)n, g.w[l], c.ci * 9, 0.f, st));
+    SUR_TRY(gemm(false, true, c.co, c.ci * 9, (int)n, w.dzb, (int)n, w.col[l], (int)n, g.w[l], c.ci * 9, 0.f, st,
+                 w.part));
     if (l == 0) break;
     SUR_TRY(gemm(true, false, c.ci * 9, (int)n, c.co, p.w_bf16[l], c.ci * 9, w.dzb, (int)n, w.dcol, (int)n, 0.f, st));
     hipLaunchKernelGGL(k_col2im, ew_grid((size_t)c.ci * B * c.h * c.w), dim3(kEw), 0, st, w.dcol, c.ci, B, c.h, c.w,
@@ -425,10 +510,11 @@ hipError_t sur_adam(const ngs_sur_params& p, const ngs_sur_params& g, const ngs_
 }
 
 hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
-                        hipStream_t st) {
+                        int views, size_t set_stride, hipStream_t st) {
   const int HW = W * H;
-  hipLaunchKernelGGL(k_features, dim3((HW + 255) / 256), dim3(256), 0, st, img.depth, img.t_final, img.argmax_id,
-                     img.mean_conf, HW, B, index, 1.f / depth_scale, 1.f / (float)k, x);
+  if (views < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((HW + 255) / 256, views), dim3(256), 0, st, img.depth, img.t_final,
+                     img.argmax_id, img.mean_conf, HW, B, index, 1.f / depth_scale, 1.f / (float)k, set_stride, x);
   return hipGetLastError();
 }
 

@@ -2,10 +2,12 @@
 all its passes run in libngs; see include/ngs_surrogate.h).
 
 A sample is one candidate view of a seeded scene: its four 80x60 feature maps (depth, final
-transmittance, argmax object id, mean confidence, from ngs_render) and, as the label, the
-view's exact next-best-view score (Eq. 11 of the paper on Eq. 10-normalised gains, whole-scene
-confidence Eq. 7, four training views per scene) from ngs_score_batch. The surrogate ranks
-candidates; the exact scorer re-scores its best ones and stays the judge.
+transmittance, argmax object id, and the ray average of confidence x novelty against the
+training information, from the library's feature render) and, as the label, the view's exact
+next-best-view score (Eq. 11 of the paper on Eq. 10-normalised gains, whole-scene confidence
+Eq. 7, four training views per scene) from ngs_score_batch. The surrogate ranks candidates;
+the exact scorer re-scores its best ones and stays the judge. Without the novelty channel the
+maps say nothing about what the training views already observed, which the gain depends on.
 """
 from __future__ import annotations
 
@@ -28,29 +30,36 @@ class SceneSamples:
     raw: torch.Tensor     # [V][3] exact gains IG_rgb, IG_d, IG_o
     seconds_features: float
     seconds_exact: float
+    seconds_rescore: float  # exact scoring of `rescore` of the candidates in one batch
 
 
 def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views_in_flight: int = 4,
-                  max_pairs: int = 1 << 23) -> SceneSamples:
+                  max_pairs: int = 1 << 23, rescore: int = 32, feature_in_flight: int = 16) -> SceneSamples:
     """Feature maps and exact scores of every candidate of one scene."""
     ds = B.DeviceScene(scene, "cuda")
     rp = B.raster_params()
     ig = B.ig_params(target_id=-1)
     B.ngs_prepare_scene(ctx, ds, ig)
     cams = [B.camera(c) for c in cands]
-    fr = B.FeatureRenderer(ctx, ds, max_pairs=max_pairs, views_in_flight=views_in_flight)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x = fr(cams, rp, DEPTH_SCALE)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
     scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=max_pairs, max_slots=max(scene.n, 1 << 16),
                          store_capacity=max(scene.n, 1 << 16), views_in_flight=views_in_flight)
     scorer.setup([B.camera(c) for c in train])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     scores, best, raw = scorer.score(cams)
     torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fr = B.FeatureRenderer(ctx, ds, max_pairs=max_pairs, views_in_flight=feature_in_flight)
+    torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return SceneSamples(x, scores[:, 3].clone(), raw.clone(), t1 - t0, t2 - t1)
+    nov = B.ngs_sur_novelty(ctx, ds, scorer.h, ig.lambda_prior)
+    x = fr(cams, rp, DEPTH_SCALE, weight=nov)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    scorer.score(cams[:rescore])
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    return SceneSamples(x, scores[:, 3].clone(), raw.clone(), t3 - t2, t1 - t0, t4 - t3)
 
 
 def train(net: B.Surrogate, x: torch.Tensor, y: torch.Tensor, epochs: int = 12, batch: int = 256,
@@ -82,36 +91,53 @@ def predict(net: B.Surrogate, x: torch.Tensor, batch: int = 256) -> torch.Tensor
 
 @dataclass
 class Agreement:
-    top5_in_steps: float      # fraction of 32-candidate steps whose exact best is in the surrogate's top 5
-    top1_in_steps: float
-    fallback_best: float      # fraction of steps where re-scoring the surrogate's top 5 finds the exact best
-    full_top32_hit: float     # per scene: exact best among the surrogate's 32 best of all candidates
-    spearman: float
-    regret: float             # mean relative score loss of the fallback pick vs the exact best
+    """Ranking agreement of the surrogate with the exact scores on held-out scenes. The
+    pipeline ranks a candidate set with the surrogate, re-scores its `rescore` best exactly and
+    takes the exact argmax among them."""
+    top5_full: float          # per scene (all candidates): the pipeline's pick is in the exact top 5
+    best_full: float          # ... and is the exact best
+    top5_subsets: float       # the same over disjoint random subsets of `subset` candidates
+    best_subsets: float
+    top5_in_steps: float      # 32-candidate subsets: the exact best is in the surrogate's own top 5
+    spearman: float           # mean per-scene rank correlation of predicted and exact scores
+    regret: float             # mean relative score lost by the pipeline's pick (subsets)
+    sets_full: int
+    sets_subsets: int
 
 
-def agreement(pred: np.ndarray, exact: np.ndarray, scene_of: np.ndarray, step: int = 32, seed: int = 0) -> Agreement:
+def pipeline_pick(pred: np.ndarray, exact: np.ndarray, rescore: int) -> int:
+    top = np.argsort(-pred, kind="stable")[:rescore]
+    return int(top[np.argmax(exact[top])])
+
+
+def agreement(pred: np.ndarray, exact: np.ndarray, scene_of: np.ndarray, rescore: int = 32, subset: int = 256,
+              seed: int = 0) -> Agreement:
+    from scipy.stats import spearmanr
     rng = np.random.default_rng(seed)
-    t5 = t1 = fb = 0
-    regret = []
-    steps = 0
-    hits, nsc = 0, 0
+    full5 = fullb = sub5 = subb = st5 = 0
+    nfull = nsub = nst = 0
+    regret, rho = [], []
     for s in np.unique(scene_of):
         idx = np.where(scene_of == s)[0]
         p, e = pred[idx], exact[idx]
-        nsc += 1
-        hits += int(np.argmax(e) in np.argsort(-p)[:32])
+        rank = np.argsort(-e, kind="stable")
+        pick = pipeline_pick(p, e, rescore)
+        full5 += int(pick in rank[:5])
+        fullb += int(pick == rank[0])
+        nfull += 1
+        rho.append(spearmanr(p, e)[0])
         perm = rng.permutation(len(idx))
-        for q in range(0, len(perm) - step + 1, step):
-            c = perm[q:q + step]
-            best = c[np.argmax(e[c])]
-            order = c[np.argsort(-p[c])]
-            t5 += int(best in order[:5])
-            t1 += int(best == order[0])
-            pick = order[:5][np.argmax(e[order[:5]])]
-            fb += int(pick == best)
-            regret.append((e[best] - e[pick]) / max(abs(e[best]), 1e-12))
-            steps += 1
-    from scipy.stats import spearmanr
-    rho = float(np.mean([spearmanr(pred[scene_of == s], exact[scene_of == s])[0] for s in np.unique(scene_of)]))
-    return Agreement(t5 / steps, t1 / steps, fb / steps, hits / nsc, rho, float(np.mean(regret)))
+        for q in range(0, len(perm) - subset + 1, subset):
+            c = perm[q:q + subset]
+            pk = c[pipeline_pick(p[c], e[c], rescore)]
+            r = c[np.argsort(-e[c], kind="stable")]
+            sub5 += int(pk in r[:5])
+            subb += int(pk == r[0])
+            regret.append((e[r[0]] - e[pk]) / max(abs(e[r[0]]), 1e-12))
+            nsub += 1
+        for q in range(0, len(perm) - 32 + 1, 32):
+            c = perm[q:q + 32]
+            st5 += int(c[np.argmax(e[c])] in c[np.argsort(-p[c], kind="stable")[:5]])
+            nst += 1
+    return Agreement(full5 / nfull, fullb / nfull, sub5 / max(nsub, 1), subb / max(nsub, 1), st5 / max(nst, 1),
+                     float(np.mean(rho)), float(np.mean(regret)) if regret else 0.0, nfull, nsub)

@@ -148,3 +148,89 @@ def test_training_reduces_loss(B, ctx):
         last = float(net.train_step(x, y, lr=1e-3))
     log(f"  loss {first:.4f} -> {last:.4f}")
     assert last < first / 5
+
+
+def test_novelty_matches_definition(B, ctx):
+    """ngs_sur_novelty on a synthetic store: untouched Gaussians keep c_g, touched ones get c_g
+    times the mean over the three outputs of exp(-(logdet - d ln lambda) / d)."""
+    import torch
+    import scenegen
+    log("test_novelty_matches_definition")
+    scene = scenegen.make_scene(3000, 8, 16, seed=4)
+    ds = B.DeviceScene(scene, "cuda")
+    lam = 0.1
+    B.ngs_prepare_scene(ctx, ds, B.ig_params(lambda_prior=lam))
+    rng = np.random.default_rng(6)
+    h = B.Hessian(scene.n, scene.k, 1000)
+    touched = rng.choice(scene.n, 1000, replace=False)
+    slot_of = np.full(scene.n, -1, np.int32)
+    slot_of[touched] = np.arange(1000, dtype=np.int32)
+    d = np.array([14.0, 11.0, 11.0 + scene.k])
+    ld = d[:, None] * np.log(lam) + rng.uniform(0, 30, (3, 1000))
+    h.slot_of.copy_(torch.tensor(slot_of))
+    h.logdet.copy_(torch.tensor(ld))
+    got = B.ngs_sur_novelty(ctx, ds, h, lam).cpu().numpy().astype(np.float64)
+    conf = ds.conf.cpu().numpy().astype(np.float64)
+    nu = np.ones(scene.n)
+    nu[touched] = np.mean(np.exp(-(ld - d[:, None] * np.log(lam)) / d[:, None]), axis=0)
+    assert np.allclose(got, conf * nu, rtol=1e-6, atol=1e-12)
+    none = B.ngs_sur_novelty(ctx, ds, None, lam).cpu().numpy()
+    assert np.array_equal(none, ds.conf.cpu().numpy())
+
+
+def feature_workload(n_views):
+    import scenegen
+    scene = scenegen.make_scene(3000, 8, 16, seed=2)
+    cfg = scenegen.SceneConfig("feat", 3000, 8, 16, n_views, ((80, 60, n_views),), 525.0, (0.6, 0.6))
+    cands, _ = scenegen.make_cameras(cfg, 2)
+    return scene, cands
+
+
+def test_feature_maps_match_oracle(B, ctx):
+    """ngs_sur_render_features (groups of 4 views in flight, a ragged last group, both buffer
+    halves reused) against the FP64 oracle render of every view: depth / scale, final
+    transmittance, argmax id / k and the mean confidence, to the rendered-channel protocol."""
+    import oracle
+    from parity_util import check_channel
+    log("test_feature_maps_match_oracle")
+    scene, cands = feature_workload(21)
+    ds = B.DeviceScene(scene, "cuda")
+    B.ngs_prepare_scene(ctx, ds, B.ig_params())
+    ds_scale = 0.6
+    fr = B.FeatureRenderer(ctx, ds, max_pairs=1 << 18, views_in_flight=4)
+    x = fr([B.camera(c) for c in cands], B.raster_params(), ds_scale).cpu().numpy()
+    assert np.isfinite(x).all()
+    for v, cam in enumerate(cands):
+        ref = oracle.render(scene, cam)
+        amb = ref["ambiguous"].astype(bool)
+        check_channel("depth", x[0, v], ref["depth"] / ds_scale, amb, 1.0 / ds_scale)
+        check_channel("t_final", x[1, v], ref["t_final"], amb, 1.0)
+        check_channel("mean_conf", x[3, v], ref["kbar"], amb, 1.0)
+        srt = np.sort(ref["obj"], axis=0)
+        firm = (~amb) & (srt[-1] - srt[-2] > 1e-5)
+        assert np.array_equal(x[2, v][firm], ref["id"][firm] / np.float32(scene.k)), f"view {v}: argmax ids differ"
+
+
+def test_feature_maps_weighted_match_single_view_path(B, ctx):
+    """With a per-Gaussian weight, the grouped multi-view launches give bit for bit what
+    ngs_render + ngs_sur_features give one view at a time on a scene whose kappa is that weight."""
+    import torch
+    log("test_feature_maps_weighted_match_single_view_path")
+    scene, cands = feature_workload(11)
+    ds = B.DeviceScene(scene, "cuda")
+    B.ngs_prepare_scene(ctx, ds, B.ig_params())
+    w = torch.tensor(np.random.default_rng(3).uniform(0, 2, scene.n).astype(np.float32), device="cuda")
+    rp = B.raster_params()
+    fr = B.FeatureRenderer(ctx, ds, max_pairs=1 << 18, views_in_flight=3)
+    x = fr([B.camera(c) for c in cands], rp, 0.6, weight=w)
+    ds_w = B.DeviceScene(scene, "cuda")
+    B.ngs_prepare_scene(ctx, ds_w, B.ig_params())
+    ds_w.kappa.copy_(w)
+    ref = torch.zeros_like(x)
+    for v, cam in enumerate(cands):
+        c = B.camera(cam)
+        pr = B.ngs_project(ctx, ds_w, c, rp)
+        lists = B.ngs_bin_sort(ctx, ds_w, pr, c, rp, capacity=1 << 18)
+        img = B.ngs_render(ctx, ds_w, pr, lists, c, rp, want_obj=False)
+        B.ngs_sur_features(ctx, img, scene.k, 0.6, ref, v)
+    assert torch.equal(x, ref)
