@@ -241,11 +241,11 @@ def run_surrogate(args):
     t_net = time.perf_counter() - t0
     ag = SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:],
                       rescore=args.sur_rescore)
+    ag_budget = {r: SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:],
+                                 rescore=r).__dict__ for r in (32, 64, 128, 256)}
     if args.sur_dump:
         np.savez(args.sur_dump, pred=pred.cpu().numpy(), exact=y[ntr:].cpu().numpy(),
                  scene=np.concatenate(scene_of)[ntr:], raw=torch.cat(raws)[ntr:].cpu().numpy())
-    ag64 = SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:],
-                        rescore=2 * args.sur_rescore)
     ptr = SG.predict(net, x[:, :min(ntr, 4 * nv)].contiguous())
     ag_train = SG.agreement(ptr.cpu().numpy(), y[:min(ntr, 4 * nv)].cpu().numpy(),
                             np.concatenate(scene_of)[:min(ntr, 4 * nv)])
@@ -272,7 +272,7 @@ def run_surrogate(args):
         "surrogate_feature_s": round(t_feat, 3), "surrogate_network_s": round(t_net, 4),
         "surrogate_rescore_s": round(t_rescore, 3), "exact_s": round(t_exact, 3),
         "rescore": args.sur_rescore, "agreement_heldout": ag.__dict__,
-        "agreement_heldout_rescore_x2": ag64.__dict__, "agreement_train": ag_train.__dict__,
+        "agreement_heldout_by_rescore": ag_budget, "agreement_train": ag_train.__dict__,
         "train": {"pairs": ntr, "epochs": args.sur_epochs, "seconds": round(t_train, 2),
                   "loss_per_epoch": [round(h, 4) for h in hist], "label_mean": mu, "label_std": sd},
         "roofline": {"bound": "mfma", "kernel": "sur_gemm",
@@ -294,12 +294,17 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
     ap.add_argument("--backward", action="store_true",
                     help="time the differentiable rasterizer (forward + loss + backward) on the 500k-Gaussian workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing the alternatives on 32 candidates first")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the second timed region, which replays the batch captured in a HIP graph")
     ap.add_argument("--surrogate", action="store_true",
                     help="train the learned view scorer on exact scores of seeded scenes and compare it with exact scoring")
     ap.add_argument("--sur-scenes", type=int, default=24, help="training scenes (2048 views each)")
-    ap.add_argument("--sur-test-scenes", type=int, default=6)
+    ap.add_argument("--sur-test-scenes", type=int, default=8)
     ap.add_argument("--sur-epochs", type=int, default=20)
-    ap.add_argument("--sur-rescore", type=int, default=32, help="candidates the exact scorer re-scores per scene")
+    ap.add_argument("--sur-rescore", type=int, default=128,
+                    help="candidates (of each scene's 2048) the exact scorer re-scores")
     ap.add_argument("--sur-dump", default="", help="write held-out predictions and exact scores (.npz)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (for scaling rocprofv3 FETCH/WRITE_SIZE)")
@@ -346,6 +351,11 @@ def main():
     norm = scorer.setup([B.camera(c) for c in train])
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
+    tune = None
+    if not args.no_autotune:
+        from paper_2602_08266_amd import autotune
+        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32,
+                                   log=lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush()))
     stats = torch.zeros(6, dtype=torch.int64, device="cuda:0")
     for _ in range(args.warmup):
         scorer.score(cam_c, stats)
@@ -362,6 +372,22 @@ def main():
     prof = B.ngs_profile_read(ctx) if not args.no_profile else {}
     B.ngs_profile_enable(ctx, False)
     st = stats.cpu().numpy()
+    graph = None
+    if not args.no_graph:
+        # the same batch captured once into a HIP graph, replayed with one launch per step
+        g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.ws, normalisers=norm)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        gbest = int(g.best.item())
+        graph = {"views_per_s": round(V * args.steps / gdt, 2), "ms_per_step": round(gdt * 1e3 / args.steps, 3),
+                 "overflow": int(g.overflow.item()), "best_view": gbest,
+                 "max_rel_diff_vs_eager": float(((g.ig_raw - raw).abs() / raw.abs().clamp_min(1e-300)).max())}
+        g.close()
     K = args.steps
     ms_per_step = dt * 1e3 / K
     value = V * K / dt
@@ -394,7 +420,7 @@ def main():
                                f"{V} candidate views at {cands[0].width}x{cands[0].height}, object-centric target "
                                f"{scene.target}, radius U{list(cfg.radius)} m, 4 training views",
                    "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
-                   "views_in_flight": args.in_flight},
+                   "views_in_flight": scorer.views_in_flight, "ig_lanes_per_pixel": B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"]},
         "roofline": roofline,
         "path": {"algorithmic_bytes_per_view": int(path_bytes(scene.n, scene.k, V, M_step, U_step) / V),
                  "achieved_GBs": round(path_bytes(scene.n, scene.k, V, M_step, U_step) / (ms_per_step / 1e3) / 1e9, 1),
@@ -406,7 +432,10 @@ def main():
         "best_view": int(best.item()), "normalisers": [float(x) for x in norm],
         "kernels_ms_per_step": {k: round(v[0] / K, 3) for k, v in sorted(prof.items(), key=lambda x: -x[1][0])
                                 if v[1] > 0},
-        "surrogate": None,
+        "graph": graph,
+        "autotune": None if tune is None else {"views_in_flight": tune.views_in_flight,
+                                               "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
+                                               "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
     }
     if not args.no_cpu_baseline:
         sys.stderr.write("timing the CPU oracle on one view...\n")

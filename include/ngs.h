@@ -254,6 +254,45 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
                            int32_t* best, double* ig_raw, int64_t* stats, const ngs_dims* dims,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* Launch shapes of a context (all calls on it that follow use them; zero fields = defaults).
+ * ig_lanes_per_pixel: lanes of the information-gain tile kernel per pixel, 1, 2 or 4: the
+ * object channels of a pixel are split over that many lanes, the workgroup has 256 times as
+ * many lanes, and a reduction round stages 16 packed rows per wavefront in LDS (8 with 4
+ * lanes). Allowed: k <= 8: 1, 2; k <= 32: 1, 2, 4; k <= 64: 1, 2. Default: 1 for k <= 8,
+ * else 2. A value not allowed for the scene's k makes ngs_info_gain, ngs_score_batch and
+ * ngs_score_graph_create return NGS_INVALID_ARG. Results agree across shapes to rounding.
+ * The autotuner of the Python package picks these and views_in_flight by timing. */
+typedef struct {
+  int32_t ig_lanes_per_pixel;
+} ngs_tuning;
+ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* tuning);
+ngs_status ngs_get_tuning(const ngs_ctx* ctx, ngs_tuning* tuning);
+
+/* The same batch captured once into a HIP graph and replayed with one launch per batch.
+ * ngs_score_graph_create records everything ngs_score_batch enqueues for these arguments
+ * (per view on the context's streams: projection, binning, information gain, finalisation;
+ * then the combination and argmax) into one graph, instantiates it and returns it in *out;
+ * nothing runs. ngs_score_graph_launch replays it on `stream` with a single hipGraphLaunch.
+ * Bound by value at capture: the cameras, n_views, rp, ig and dims. Bound by address: the
+ * scene arrays, the store h, the workspace and every output, whose contents may change
+ * between replays (a refined scene, a grown training store) but not their addresses or
+ * sizes. Differences from ngs_score_batch: normalisers is DEVICE memory (FP64 [3]) read at
+ * every replay, so the caller can update it between replays; it is not checked, enabled
+ * outputs need positive values. overflow (device int32 [1]) is set to 1 by a replay in which
+ * some view exceeded dims->max_pairs or dims->max_slots (that view's gains are then not
+ * valid) and to 0 otherwise; stats, when given, only accumulates (stats[0] is not written).
+ * The graph contains kernel nodes and event dependencies only (no memset or memcpy nodes),
+ * no host synchronisation. Replays, and other calls that use the same workspace or context,
+ * must not overlap. ngs_score_graph_destroy frees the graph, not the buffers. */
+typedef struct ngs_score_graph ngs_score_graph;
+ngs_status ngs_score_graph_create(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                                  const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
+                                  const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw,
+                                  int64_t* stats, int32_t* overflow, const ngs_dims* dims, void* ws, size_t ws_bytes,
+                                  ngs_score_graph** out);
+ngs_status ngs_score_graph_launch(ngs_score_graph* graph, void* stream);
+ngs_status ngs_score_graph_destroy(ngs_score_graph* graph);
+
 /* Optional kernel timing: while enabled, every kernel the library launches is bracketed
  * by two hipEvents recorded on its launch stream. ngs_profile_read synchronises the
  * recorded events and returns the total milliseconds and launch count of kernel class id

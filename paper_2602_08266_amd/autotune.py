@@ -1,0 +1,106 @@
+"""Autotuner of the batched scorer's launch shapes.
+
+It times ngs_score_batch on a sample of the real candidate set for every pair of
+views_in_flight (buffer sets and context streams kept busy at once) and lanes per pixel of the
+information-gain tile kernel (which sets its workgroup size and the packed rows it stages in LDS
+per reduction round), keeps the fastest, and applies it to the context (ngs_set_tuning) and to
+the scorer's workspace. Results may be cached in a JSON file keyed by the device, the scene
+size and the resolution mix of the sample.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import binding as B
+
+VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16)
+
+
+def lpp_choices(k: int) -> Tuple[int, ...]:
+    """Lanes per pixel the library accepts for object vectors of length k."""
+    if k <= 8:
+        return (1, 2)
+    if k <= 32:
+        return (1, 2, 4)
+    return (1, 2)
+
+
+@dataclass
+class TuneResult:
+    views_in_flight: int
+    ig_lanes_per_pixel: int
+    ms_per_view: float
+    table: List[Dict] = field(default_factory=list)
+
+
+def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max_slots: int) -> str:
+    res: Dict[str, int] = {}
+    for c in cams:
+        r = f"{c.width}x{c.height}"
+        res[r] = res.get(r, 0) + 1
+    dev = torch.cuda.get_device_name(torch.cuda.current_device()) if torch.cuda.is_available() else "none"
+    return json.dumps({"dev": dev, "n": scene.n, "k": scene.k, "res": sorted(res.items()), "pairs": max_pairs,
+                       "slots": max_slots}, sort_keys=True)
+
+
+def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera], sample: int = 32,
+               reps: int = 2, vif: Sequence[int] = VIEWS_IN_FLIGHT, lpps: Optional[Sequence[int]] = None,
+               cache: Optional[str] = None, log=None) -> TuneResult:
+    """Times every (views_in_flight, lanes per pixel) pair on `sample` evenly spaced candidates
+    (after one untimed batch), best of `reps`; applies the winner to ctx and scorer."""
+    step = max(1, len(cams) // sample)
+    sub = list(cams[::step][:sample])
+    key = _key(scorer.scene, sub, scorer.max_pairs, scorer.max_slots)
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            hit = json.load(f).get(key)
+        if hit:
+            res = TuneResult(hit["views_in_flight"], hit["ig_lanes_per_pixel"], hit["ms_per_view"], hit["table"])
+            apply(ctx, scorer, res)
+            return res
+    lpps = tuple(lpps) if lpps else lpp_choices(scorer.scene.k)
+    table = []
+    best = None
+    for lpp in lpps:
+        B.ngs_set_tuning(ctx, lpp)
+        for v in vif:
+            scorer.views_in_flight = v
+            scorer.ws = None  # resized for v buffer sets on the next score()
+            scorer.score(sub)
+            torch.cuda.synchronize()
+            t = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                scorer.score(sub)
+                torch.cuda.synchronize()
+                t = min(t, time.perf_counter() - t0)
+            ms = t / len(sub) * 1e3
+            table.append({"views_in_flight": v, "ig_lanes_per_pixel": lpp, "ms_per_view": round(ms, 4)})
+            if log:
+                log(f"autotune: views_in_flight {v:2d}, lanes per pixel {lpp}: {ms:.3f} ms/view")
+            if best is None or ms < best[0]:
+                best = (ms, v, lpp)
+    scorer.ws = None
+    res = TuneResult(best[1], best[2], best[0], table)
+    apply(ctx, scorer, res)
+    if cache:
+        data = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+        data[key] = res.__dict__
+        with open(cache, "w") as f:
+            json.dump(data, f, indent=1)
+    return res
+
+
+def apply(ctx: B.Context, scorer: B.NbvScorer, res: TuneResult):
+    B.ngs_set_tuning(ctx, res.ig_lanes_per_pixel)
+    scorer.views_in_flight = res.views_in_flight
+    scorer.ws = None

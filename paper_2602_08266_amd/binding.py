@@ -24,6 +24,8 @@ STATS_LEN = 6
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_bin_sort", "ngs_render",
            "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
+           "ngs_score_graph_create", "ngs_score_graph_launch", "ngs_score_graph_destroy", "ngs_set_tuning",
+           "ngs_get_tuning",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_kernels", "ngs_profile_kernel_name",
            "ngs_profile_read", "ngs_sur_workspace_size", "ngs_sur_sync_bf16", "ngs_sur_forward", "ngs_sur_backward",
            "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_novelty", "ngs_sur_render_features", "ngs_gemm_bf16"]
@@ -127,6 +129,12 @@ def lib():
         L.ngs_hessian_reset.argtypes = [P, P, i32, P]
         L.ngs_hessian_finalize.argtypes = [P, P, P]
         L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_score_graph_create.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, C.c_size_t,
+                                             C.POINTER(P)]
+        L.ngs_score_graph_launch.argtypes = [P, P]
+        L.ngs_set_tuning.argtypes = [P, P]
+        L.ngs_get_tuning.argtypes = [P, P]
+        L.ngs_score_graph_destroy.argtypes = [P]
         L.ngs_render_backward.argtypes = [P, P, P, P, P, P, i32, P, P, P, C.c_size_t, P]
         L.ngs_sur_workspace_size.argtypes = [i32, C.POINTER(C.c_size_t)]
         L.ngs_sur_sync_bf16.argtypes = [P, P, P]
@@ -611,6 +619,69 @@ def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], norm
                                                     _p(ig_raw), _p(stats), _ref(ws.dims), _p(ws.buf), ws.buf.numel(),
                                                     _stream()), ctx)
     return scores[:nv], best, ig_raw[:nv]
+
+
+class ngs_tuning(C.Structure):
+    _fields_ = [("ig_lanes_per_pixel", C.c_int32)]
+
+
+def ngs_set_tuning(ctx: Context, ig_lanes_per_pixel: int = 0):
+    t = ngs_tuning(int(ig_lanes_per_pixel))
+    _check("ngs_set_tuning", lib().ngs_set_tuning(ctx.handle, _ref(t)), ctx)
+
+
+def ngs_get_tuning(ctx: Context) -> Dict[str, int]:
+    t = ngs_tuning()
+    _check("ngs_get_tuning", lib().ngs_get_tuning(ctx.handle, _ref(t)), ctx)
+    return {"ig_lanes_per_pixel": int(t.ig_lanes_per_pixel)}
+
+
+class ScoreGraph:
+    """A scoring batch captured into a HIP graph (ngs_score_graph_create) and replayed with
+    one launch. It binds the cameras and parameters by value and the scene, the store h, the
+    workspace and its own output tensors by address: after the scene or h change in place, or
+    `normalisers` (a device tensor) is updated, replay() scores against the new contents."""
+
+    def __init__(self, ctx: Context, scene: DeviceScene, h: Optional[Hessian], cams: Sequence[ngs_camera],
+                 rp: ngs_raster_params, ig: ngs_ig_params, ws: ScoreWorkspace, normalisers=(1.0, 1.0, 1.0),
+                 stats: Optional[torch.Tensor] = None):
+        nv = len(cams)
+        dev = scene.device
+        self.ctx, self.scene, self.h, self.ws, self.stats = ctx, scene, h, ws, stats
+        self.norm = torch.tensor([float(x) for x in normalisers], dtype=torch.float64, device=dev)
+        self.scores = torch.empty((nv, 4), dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+        self.ig_raw = torch.empty((nv, 3), dtype=torch.float64, device=dev)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
+        arr = (ngs_camera * max(nv, 1))(*cams)
+        sc = scene.c()
+        hc = h.c() if h is not None else None
+        self._rp, self._ig = rp, ig
+        handle = C.c_void_p()
+        torch.cuda.synchronize()
+        _check("ngs_score_graph_create", lib().ngs_score_graph_create(
+            ctx.handle, _ref(sc), _ref(hc) if hc is not None else None, _p(self.norm), arr, nv, _ref(rp), _ref(ig),
+            _p(self.scores), _p(self.best), _p(self.ig_raw), _p(stats), _p(self.overflow), _ref(ws.dims), _p(ws.buf),
+            ws.buf.numel(), C.byref(handle)), ctx)
+        self.handle = handle
+
+    def replay(self, normalisers=None):
+        """One launch of the whole batch on the current stream; returns (scores, best, ig_raw)."""
+        if normalisers is not None:
+            self.norm.copy_(torch.tensor([float(x) for x in normalisers], dtype=torch.float64))
+        _check("ngs_score_graph_launch", lib().ngs_score_graph_launch(self.handle, _stream()), self.ctx)
+        return self.scores, self.best, self.ig_raw
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ngs_score_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16,

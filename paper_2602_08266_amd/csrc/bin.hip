@@ -330,7 +330,7 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, w.blocksum, nb, w.offsets + n);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, w.offsets, n, w.blocksum);
   } else {
-    e = hipMemsetAsync(w.offsets, 0, 8, st);
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(w.offsets), 0u, 2, st);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -339,9 +339,10 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const uint32_t* order = w.dvals[1];
-  hipError_t e = hipMemcpyAsync(out.n_pairs, w.offsets + n, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+  hipError_t e = launch_copy_u32(reinterpret_cast<uint32_t*>(out.n_pairs),
+                                 reinterpret_cast<const uint32_t*>(w.offsets + n), 2, st);
   if (e != hipSuccess) return e;
-  if (n == 0) return hipMemsetAsync(out.ranges, 0, sizeof(uint32_t) * 2 * (size_t)ntiles, st);
+  if (n == 0) return launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st);
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);

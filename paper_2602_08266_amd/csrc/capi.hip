@@ -19,6 +19,7 @@ struct ngs_ctx {
   hipEvent_t fork = nullptr;
   // ngs_sur_render_features: the two halves of its double-buffered view groups are free again
   hipEvent_t half_done[2] = {nullptr, nullptr};
+  ngs_tuning tuning{};  // launch shapes (ngs_set_tuning); zero = defaults
 };
 
 namespace {
@@ -95,7 +96,7 @@ ngs_status ig_prepare(ngs_ctx* ctx, void* ws, size_t ws_bytes, int64_t n, int64_
   if (slots < 1) return NGS_WORKSPACE_TOO_SMALL;
   *sticky = static_cast<int32_t*>(ws);
   *w = ig_ws_carve(static_cast<char*>(ws) + kIgHeader, n, k, slots);
-  NGS_TRY_HIP(ctx, hipMemsetAsync(*sticky, 0, kIgHeader, st));
+  NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(*sticky), 0u, kIgHeader / 4, st));
   return NGS_OK;
 }
 
@@ -367,6 +368,7 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
     return NGS_INVALID_ARG;
   if (ig->mode == NGS_MODE_SCORE && !ig_out) return NGS_INVALID_ARG;
   if (h && (h->k != scene->k || (h->capacity > 0 && !h->logdet))) return NGS_INVALID_ARG;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
   if (!ws) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
@@ -376,7 +378,8 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
   if (s != NGS_OK) return s;
   if (ig_out) NGS_TRY_HIP(ctx, hipMemsetAsync(ig_out, 0, 3 * sizeof(double), st));
   const DevCam dc = make_devcam(*cam, kTile);
-  NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, dc, make_raster(*rp), *ig, w, stats, st));
+  NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, dc, make_raster(*rp), *ig, w, stats, ctx->tuning.ig_lanes_per_pixel,
+                                   st));
   NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_out ? ig_out : nullptr, stats, sticky, st));
   int64_t of = 0;
   s = read_i64(ctx, sticky, 4, st, &of);
@@ -388,11 +391,14 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
   return NGS_OK;
 }
 
-ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
-                           const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
-                           const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw, int64_t* stats,
-                           const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream) {
-  if (!ctx || !normalisers || !cams || n_views < 0 || !scores || !best || !ig_raw || !dims) return NGS_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Checks shared by ngs_score_batch and ngs_score_graph_create.
+ngs_status check_batch(const ngs_scene* scene, ngs_hessian* h, const ngs_camera* cams, int32_t n_views,
+                       const ngs_raster_params* rp, const ngs_ig_params* ig, const ngs_dims* dims, void* ws,
+                       size_t ws_bytes) {
   if (dims->n != scene->n || dims->k != scene->k || dims->max_pairs < 1 || dims->max_slots < 1) return NGS_INVALID_ARG;
   ngs_status s = check_scene(scene, true);
   if (s == NGS_OK) s = check_ig(ig);
@@ -403,19 +409,27 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     s = check_cam(&cams[v], rp);
     if (s != NGS_OK) return s;
   }
-  for (int f = 0; f < 3; ++f)
-    if (((ig->outputs >> f) & 1u) && !(normalisers[f] > 0.0)) return NGS_DEGENERATE;
   if (!ws) return NGS_WORKSPACE_TOO_SMALL;
-  hipStream_t st = (hipStream_t)stream;
-  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
   size_t need = 0;
   s = ngs_workspace_size(2, dims, &need);
   if (s != NGS_OK) return s;
-  if (ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
+  return ws_bytes < need ? NGS_WORKSPACE_TOO_SMALL : NGS_OK;
+}
+
+// Enqueues a whole scoring batch on `st` and the context streams, with no host
+// synchronisation and no memset or memcpy nodes, so that it can also be captured into a
+// graph. Normalisers come from nf_dev (device) when given, else from nf_host. *sticky_out
+// receives the device flag that a list or slot overflow raises.
+ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* nf_host,
+                               const double* nf_dev, const ngs_camera* cams, int32_t n_views,
+                               const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores, int32_t* best,
+                               double* ig_raw, int64_t* stats, const ngs_dims* dims, void* ws, hipStream_t st,
+                               int32_t** sticky_out) {
+  size_t need = 0;
+  ngs_status s = ngs_workspace_size(2, dims, &need);
+  if (s != NGS_OK) return s;
   const int64_t max_pairs = dims->max_pairs;
   const int lanes = std::max(1, std::min(views_in_flight(dims), n_views));
-  s = ensure_lanes(ctx, lanes);
-  if (s != NGS_OK) return s;
   // one buffer set per in-flight view; the first set's IG header holds the sticky overflow
   // flag that every set reports into
   const size_t per = need / (size_t)views_in_flight(dims);
@@ -429,12 +443,13 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     if (s != NGS_OK) return s;
     if (i == 0) sticky = own;
   }
-  NGS_TRY_HIP(ctx, hipMemsetAsync(ig_raw, 0, (size_t)3 * sizeof(double) * std::max(n_views, 1), st));
+  *sticky_out = sticky;
+  NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ig_raw), 0u, (size_t)6 * std::max(n_views, 1), st));
   NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
   for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
-  // No host synchronisation inside the loop: list overflow is caught on the device (empty
-  // ranges, sticky flag) and reported once the batch has run. View v runs on lane v mod
-  // lanes, which reuses that lane's buffers in stream order.
+  // List overflow is caught on the device (empty ranges, sticky flag) and reported once the
+  // batch has run. View v runs on lane v mod lanes, which reuses that lane's buffers in
+  // stream order.
   for (int v = 0; v < n_views; ++v) {
     const int i = v % lanes;
     hipStream_t ls = ctx->lanes[i];
@@ -444,15 +459,49 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
     NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls));
-    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats, ls));
+    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats,
+                                     ctx->tuning.ig_lanes_per_pixel, ls));
     NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v, stats, sticky, ls));
   }
   for (int i = 0; i < lanes; ++i) {
     NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ctx->lanes[i]));
     NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
   }
-  NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, normalisers[0], normalisers[1], normalisers[2], ig->beta_d,
-                                        ig->beta_o, ig->outputs, scores, best, st));
+  const double n0 = nf_host ? nf_host[0] : 1.0, n1 = nf_host ? nf_host[1] : 1.0, n2 = nf_host ? nf_host[2] : 1.0;
+  NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, n0, n1, n2, nf_dev, ig->beta_d, ig->beta_o, ig->outputs,
+                                        scores, best, st));
+  return NGS_OK;
+}
+
+}  // namespace
+
+struct ngs_score_graph {
+  ngs_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                           const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
+                           const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw, int64_t* stats,
+                           const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !normalisers || !cams || n_views < 0 || !scores || !best || !ig_raw || !dims || !scene || !rp || !ig)
+    return NGS_INVALID_ARG;
+  ngs_status s = check_batch(scene, h, cams, n_views, rp, ig, dims, ws, ws_bytes);
+  if (s != NGS_OK) return s;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  for (int f = 0; f < 3; ++f)
+    if (((ig->outputs >> f) & 1u) && !(normalisers[f] > 0.0)) return NGS_DEGENERATE;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  s = ensure_lanes(ctx, std::max(1, std::min(views_in_flight(dims), n_views)));
+  if (s != NGS_OK) return s;
+  int32_t* sticky = nullptr;
+  s = enqueue_score_batch(ctx, scene, h, normalisers, nullptr, cams, n_views, rp, ig, scores, best, ig_raw, stats,
+                          dims, ws, st, &sticky);
+  if (s != NGS_OK) return s;
   int64_t of = 0;
   s = read_i64(ctx, sticky, 4, st, &of);
   if (s != NGS_OK) return s;
@@ -465,6 +514,93 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, 4, st));
     return NGS_CAPACITY;
   }
+  return NGS_OK;
+}
+
+ngs_status ngs_score_graph_create(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                                  const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
+                                  const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw,
+                                  int64_t* stats, int32_t* overflow, const ngs_dims* dims, void* ws, size_t ws_bytes,
+                                  ngs_score_graph** out) {
+  if (!out) return NGS_INVALID_ARG;
+  *out = nullptr;
+  if (!ctx || !normalisers || !cams || n_views < 1 || !scores || !best || !ig_raw || !overflow || !dims || !scene ||
+      !rp || !ig)
+    return NGS_INVALID_ARG;
+  ngs_status s = check_batch(scene, h, cams, n_views, rp, ig, dims, ws, ws_bytes);
+  if (s != NGS_OK) return s;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  s = ensure_lanes(ctx, std::max(1, std::min(views_in_flight(dims), n_views)));
+  if (s != NGS_OK) return s;
+  hipStream_t cs = nullptr;
+  NGS_TRY_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const bool prof = prof_suspend();
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    int32_t* sticky = nullptr;
+    s = enqueue_score_batch(ctx, scene, h, nullptr, normalisers, cams, n_views, rp, ig, scores, best, ig_raw, stats,
+                            dims, ws, cs, &sticky);
+    if (s == NGS_OK) {
+      e = launch_copy_u32(reinterpret_cast<uint32_t*>(overflow), reinterpret_cast<const uint32_t*>(sticky), 1, cs);
+      if (e != hipSuccess) s = NGS_HIP_ERROR;
+    }
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);  // always ends the capture
+    if (s == NGS_OK && e2 != hipSuccess) { e = e2; s = NGS_HIP_ERROR; }
+  } else {
+    s = NGS_HIP_ERROR;
+  }
+  prof_resume(prof);
+  (void)hipStreamDestroy(cs);
+  if (s != NGS_OK) {
+    if (e != hipSuccess) ctx->last_hip = (int32_t)e;
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    ctx->last_hip = (int32_t)e;
+    (void)hipGraphDestroy(graph);
+    return NGS_HIP_ERROR;
+  }
+  ngs_score_graph* g = new ngs_score_graph;
+  g->ctx = ctx;
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return NGS_OK;
+}
+
+ngs_status ngs_score_graph_launch(ngs_score_graph* g, void* stream) {
+  if (!g || !g->exec) return NGS_INVALID_ARG;
+  NGS_TRY_HIP(g->ctx, hipSetDevice(g->ctx->device));
+  NGS_TRY_HIP(g->ctx, hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return NGS_OK;
+}
+
+ngs_status ngs_score_graph_destroy(ngs_score_graph* g) {
+  if (!g) return NGS_INVALID_ARG;
+  (void)hipSetDevice(g->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return NGS_OK;
+}
+
+ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* t) {
+  if (!ctx || !t) return NGS_INVALID_ARG;
+  if (t->ig_lanes_per_pixel != 0 && t->ig_lanes_per_pixel != 1 && t->ig_lanes_per_pixel != 2 &&
+      t->ig_lanes_per_pixel != 4)
+    return NGS_INVALID_ARG;
+  ctx->tuning = *t;
+  return NGS_OK;
+}
+
+ngs_status ngs_get_tuning(const ngs_ctx* ctx, ngs_tuning* t) {
+  if (!ctx || !t) return NGS_INVALID_ARG;
+  *t = ctx->tuning;
   return NGS_OK;
 }
 

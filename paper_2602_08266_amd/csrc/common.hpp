@@ -111,6 +111,9 @@ class ProfScope {
   void* a_;
 };
 void prof_enable(bool on);
+// Pause timing without clearing what was recorded (graph capture records no profiling events).
+bool prof_suspend();
+void prof_resume(bool on);
 void prof_read(int id, double* ms, int64_t* count);
 const char* prof_name(int id);
 
@@ -133,6 +136,9 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, ui
 hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st);
+// Device-to-device copy of n 32-bit words by a kernel (graph-capturable like the fills: the
+// scoring path records no memset or memcpy nodes).
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st);
 
 // Binning (bin.hip).
 struct BinWs {
@@ -175,9 +181,12 @@ struct IgWs {
 int ig_stat_stride(int64_t k);
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
+// lpp: lanes per pixel of the tile kernel (1, 2 or 4; 0 = the default for k); it sets the
+// workgroup size and the rows per LDS reduction round. ig_lpp_valid tells which k allow which.
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
-                           const IgWs& w, int64_t* stats, hipStream_t st);
+                           const IgWs& w, int64_t* stats, int lpp, hipStream_t st);
+bool ig_lpp_valid(int64_t k, int lpp);
 hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
                               double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);
@@ -202,7 +211,7 @@ hipError_t sur_novelty(const ngs_scene& s, const ngs_hessian* h, float lambda, f
 hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
                         int views, size_t set_stride, hipStream_t st);
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
-                                float beta_d, float beta_o, uint32_t outputs, float* scores,
+                                const double* nf_dev, float beta_d, float beta_o, uint32_t outputs, float* scores,
                                 int32_t* best, hipStream_t st);
 
 }  // namespace ngs

@@ -387,14 +387,17 @@ __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, i
 }
 
 // Eq. 10 normalisation, Eq. 11 combination and the argmax of Eq. 5 (lowest index on ties).
+// The normalisers come from nf_dev (device, three doubles) when it is given, else by value.
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ ig_raw, int nv, double n0, double n1,
-                                                 double n2, double bd, double bo, uint32_t outputs,
-                                                 float* __restrict__ scores, int32_t* __restrict__ best) {
+                                                 double n2, const double* __restrict__ nf_dev, double bd, double bo,
+                                                 uint32_t outputs, float* __restrict__ scores,
+                                                 int32_t* __restrict__ best) {
   __shared__ double sv[256];
   __shared__ int si[256];
   double bv = -INFINITY;
   int bi = -1;
-  const double nf[3] = {n0, n1, n2}, beta[3] = {1.0, bd, bo};
+  const double nf[3] = {nf_dev ? nf_dev[0] : n0, nf_dev ? nf_dev[1] : n1, nf_dev ? nf_dev[2] : n2};
+  const double beta[3] = {1.0, bd, bo};
   for (int v = threadIdx.x; v < nv; v += 256) {
     double tot = 0.0;
     for (int f = 0; f < 3; ++f) {
@@ -447,10 +450,11 @@ hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_p
   return hipGetLastError();
 }
 
-hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2, float beta_d,
-                                float beta_o, uint32_t outputs, float* scores, int32_t* best, hipStream_t st) {
+hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
+                                const double* nf_dev, float beta_d, float beta_o, uint32_t outputs, float* scores,
+                                int32_t* best, hipStream_t st) {
   ProfScope ps(kProfCombine, st);
-  hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st, ig_raw, n_views, n0, n1, n2, (double)beta_d,
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st, ig_raw, n_views, n0, n1, n2, nf_dev, (double)beta_d,
                      (double)beta_o, outputs, scores, best);
   return hipGetLastError();
 }

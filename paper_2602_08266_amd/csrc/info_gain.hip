@@ -477,7 +477,7 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
 }
 
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
-                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats,
+                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                            hipStream_t st) {
   {
     ProfScope ps(kProfFill, st);
@@ -493,11 +493,26 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (s.k <= 4) return launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 8) return launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 16) return launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 32) return launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, stats, st);
-  return launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  // lanes per pixel (ig_lpp_valid): 0 picks the default of each object-vector width
+  if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, stats, st)
+                                : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 8) return lpp == 2 ? launch_ig_k<8, 2>(s, p, l, cam, rc, ig, w, stats, st)
+                                : launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 16) return lpp == 1 ? launch_ig_k<16, 1>(s, p, l, cam, rc, ig, w, stats, st)
+                        : lpp == 4 ? launch_ig_k<16, 4>(s, p, l, cam, rc, ig, w, stats, st)
+                                   : launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, cam, rc, ig, w, stats, st)
+                        : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, cam, rc, ig, w, stats, st)
+                                   : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, stats, st)
+                  : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, stats, st);
+}
+
+bool ig_lpp_valid(int64_t k, int lpp) {
+  if (lpp == 0) return true;
+  if (k <= 8) return lpp == 1 || lpp == 2;
+  if (k <= 32) return lpp == 1 || lpp == 2 || lpp == 4;
+  return lpp == 1 || lpp == 2;
 }
 
 }  // namespace ngs

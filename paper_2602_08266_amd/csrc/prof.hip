@@ -79,6 +79,18 @@ void prof_enable(bool on) {
   g_on = on;
 }
 
+bool prof_suspend() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const bool was = g_on;
+  g_on = false;
+  return was;
+}
+
+void prof_resume(bool on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_on = on;
+}
+
 void prof_read(int id, double* ms, int64_t* count) {
   std::lock_guard<std::mutex> lk(g_mu);
   drain_locked();

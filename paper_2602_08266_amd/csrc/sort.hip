@@ -161,6 +161,10 @@ __global__ void k_fill_i32(int32_t* v, int32_t x, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = x;
 }
+__global__ void k_copy_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
 
 }  // namespace
 
@@ -176,6 +180,12 @@ hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st) {
   if (!n) return hipSuccess;
   ProfScope ps(kProfFill, st);
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  ProfScope ps(kProfFill, st);
+  hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st) {

@@ -270,3 +270,45 @@ def test_abi_errors(B, ctx):
         B.ngs_info_gain(ctx, ds, pr, lists, cam, rp, B.ig_params(), None, tiny_ws)
     assert e.value.status == B.NGS_WORKSPACE_TOO_SMALL
     assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, 0, None, None, None, 0, None) == B.NGS_INVALID_ARG
+
+
+@pytest.mark.parametrize("k,lpp", [(16, 1), (16, 2), (16, 4), (64, 1), (64, 2)])
+def test_info_gain_every_launch_shape(B, ctx, k, lpp):
+    """Every lanes-per-pixel shape the autotuner may pick (ngs_set_tuning) scores a small
+    scene with a training store to the oracle's gains (1e-3 relative)."""
+    log(f"test_info_gain_every_launch_shape k={k} lpp={lpp}")
+    scene = scenegen.make_scene(3000, 8, k, seed=21)
+    cfg = scenegen.SceneConfig("shape", 3000, 8, k, 4, ((128, 96, 4),), 500.0, (0.6, 0.6))
+    cands, train = scenegen.make_cameras(cfg, 21)
+    ds = B.DeviceScene(scene, "cuda")
+    ref = oracle.score(scene, train, cands)
+    assert ref.status == 0
+    B.ngs_set_tuning(ctx, lpp)
+    try:
+        assert B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"] == lpp
+        scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
+                             store_capacity=1 << 14, views_in_flight=2)
+        norm = scorer.setup([B.camera(c) for c in train])
+        check_gain(norm, ref.norm, "normalisers")
+        scores, best, raw = scorer.score([B.camera(c) for c in cands])
+        for v in range(len(cands)):
+            check_gain(raw[v].cpu().numpy(), ref.ig_cand[v], f"view {v}")
+    finally:
+        B.ngs_set_tuning(ctx, 0)
+
+
+def test_tuning_rejects_shapes_the_width_does_not_allow(B, ctx):
+    log("test_tuning_rejects_shapes")
+    scene = scenegen.make_scene(500, 8, 64, seed=3)
+    ds = B.DeviceScene(scene, "cuda")
+    with pytest.raises(B.NgsError):
+        B.ngs_set_tuning(ctx, 3)
+    B.ngs_set_tuning(ctx, 4)
+    try:
+        scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 16, max_slots=1 << 12,
+                             store_capacity=1 << 12)
+        cam = scenegen.look_at(np.array([0.6, 0.0, 0.3]), 64, 48, 60.0)
+        with pytest.raises(B.NgsError):
+            scorer.setup([B.camera(cam)])
+    finally:
+        B.ngs_set_tuning(ctx, 0)
