@@ -295,7 +295,11 @@ def main():
     ap.add_argument("--backward", action="store_true",
                     help="time the differentiable rasterizer (forward + loss + backward) on the 500k-Gaussian workload")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shapes instead of timing the alternatives on 32 candidates first")
+                    help="use --in-flight and --ig-lpp instead of the autotuned launch shapes")
+    ap.add_argument("--retune", default="", metavar="CACHE",
+                    help="time every launch shape on 32 candidates (ignoring the package's tuning cache) and "
+                         "write the result to CACHE")
+    ap.add_argument("--ig-lpp", type=int, default=0, help="with --no-autotune: lanes per pixel of the IG kernel")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the second timed region, which replays the batch captured in a HIP graph")
     ap.add_argument("--surrogate", action="store_true",
@@ -353,9 +357,16 @@ def main():
     setup_ms = (time.perf_counter() - t0) * 1e3
     tune = None
     if not args.no_autotune:
+        # launch shapes from the package's tuning cache for this device and workload, else
+        # (or with --retune) timed now on 32 of the candidates
         from paper_2602_08266_amd import autotune
-        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32,
+        if args.retune and os.path.exists(args.retune):
+            os.remove(args.retune)
+        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32, cache=args.retune or autotune.CACHE,
+                                   write_cache=bool(args.retune),
                                    log=lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush()))
+    elif args.ig_lpp:
+        B.ngs_set_tuning(ctx, args.ig_lpp)
     stats = torch.zeros(6, dtype=torch.int64, device="cuda:0")
     for _ in range(args.warmup):
         scorer.score(cam_c, stats)
@@ -433,7 +444,7 @@ def main():
         "kernels_ms_per_step": {k: round(v[0] / K, 3) for k, v in sorted(prof.items(), key=lambda x: -x[1][0])
                                 if v[1] > 0},
         "graph": graph,
-        "autotune": None if tune is None else {"views_in_flight": tune.views_in_flight,
+        "autotune": None if tune is None else {"cached": tune.cached, "views_in_flight": tune.views_in_flight,
                                                "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
                                                "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
     }

@@ -20,6 +20,7 @@ import torch
 from . import binding as B
 
 VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16)
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
 def lpp_choices(k: int) -> Tuple[int, ...]:
@@ -37,6 +38,7 @@ class TuneResult:
     ig_lanes_per_pixel: int
     ms_per_view: float
     table: List[Dict] = field(default_factory=list)
+    cached: bool = False
 
 
 def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max_slots: int) -> str:
@@ -44,16 +46,19 @@ def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max
     for c in cams:
         r = f"{c.width}x{c.height}"
         res[r] = res.get(r, 0) + 1
-    dev = torch.cuda.get_device_name(torch.cuda.current_device()) if torch.cuda.is_available() else "none"
+    dev = (torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+           if torch.cuda.is_available() else "none")
     return json.dumps({"dev": dev, "n": scene.n, "k": scene.k, "res": sorted(res.items()), "pairs": max_pairs,
                        "slots": max_slots}, sort_keys=True)
 
 
 def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera], sample: int = 32,
                reps: int = 2, vif: Sequence[int] = VIEWS_IN_FLIGHT, lpps: Optional[Sequence[int]] = None,
-               cache: Optional[str] = None, log=None) -> TuneResult:
+               cache: Optional[str] = None, write_cache: bool = True, log=None) -> TuneResult:
     """Times every (views_in_flight, lanes per pixel) pair on `sample` evenly spaced candidates
-    (after one untimed batch), best of `reps`; applies the winner to ctx and scorer."""
+    (after one untimed batch), best of `reps`; applies the winner to ctx and scorer. With a
+    cache file, a stored result for the same device, scene size and resolution mix is applied
+    without timing; new results are added to it when write_cache is set."""
     step = max(1, len(cams) // sample)
     sub = list(cams[::step][:sample])
     key = _key(scorer.scene, sub, scorer.max_pairs, scorer.max_slots)
@@ -61,7 +66,8 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
         with open(cache) as f:
             hit = json.load(f).get(key)
         if hit:
-            res = TuneResult(hit["views_in_flight"], hit["ig_lanes_per_pixel"], hit["ms_per_view"], hit["table"])
+            res = TuneResult(hit["views_in_flight"], hit["ig_lanes_per_pixel"], hit["ms_per_view"], hit["table"],
+                             cached=True)
             apply(ctx, scorer, res)
             return res
     lpps = tuple(lpps) if lpps else lpp_choices(scorer.scene.k)
@@ -89,12 +95,12 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
     scorer.ws = None
     res = TuneResult(best[1], best[2], best[0], table)
     apply(ctx, scorer, res)
-    if cache:
+    if cache and write_cache:
         data = {}
         if os.path.exists(cache):
             with open(cache) as f:
                 data = json.load(f)
-        data[key] = res.__dict__
+        data[key] = {k: v for k, v in res.__dict__.items() if k != "cached"}
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return res

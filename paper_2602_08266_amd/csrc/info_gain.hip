@@ -210,13 +210,19 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
       atomicAdd((unsigned long long*)&stats[4], (unsigned long long)(tile_last - (int)start + 1));
   }
   if (tile_last < 0) return;
+  // Nearest weighted entry: pass 2 ends there, because entries in front of it only feed the
+  // suffixes of entries further in front, none of which writes a record.
   __syncthreads();
-  if (threadIdx.x == 0) S.flag = 0;
+  if (threadIdx.x == 0) S.flag = INT_MAX;
   __syncthreads();
   for (int i = (int)start + threadIdx.x; i <= tile_last; i += kThreads)
-    if (slot_of[gids[i]] >= 0) S.flag = 1;
+    if (slot_of[gids[i]] >= 0) {
+      atomicMin(&S.flag, i);
+      break;  // a lane's later indices are larger
+    }
   __syncthreads();
-  if (S.flag == 0) return;
+  const int first_w = S.flag;
+  if (first_w > tile_last) return;
 
   // ---- pass 2: back to front ------------------------------------------------------------
   const float t_final = T;
@@ -226,8 +232,8 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
 #pragma unroll
   for (int c = 0; c < KL; ++c) So[c] = 0.f;
   if (obj_eq2 && h == 0) So[0] = t_final;  // S~ = S_o + T_final e_0
-  for (int hi = tile_last + 1; hi > (int)start; hi -= kBatch) {
-    const int lo = max((int)start, hi - kBatch);
+  for (int hi = tile_last + 1; hi > first_w; hi -= kBatch) {
+    const int lo = max(first_w, hi - kBatch);
     const int cnt = hi - lo;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
