@@ -4,13 +4,18 @@
 // two stages, because all pairs of one Gaussian share its depth bits:
 //   1. depth digits: the n Gaussians are sorted by their 32-bit depth key (4 passes over n
 //      entries instead of over the M >> n pairs); gid order breaks ties (stable LSD);
-//   2. one stable counting pass on the tile digit (<= 12 bits) over the pairs, fused with
-//      their generation: each single-wavefront block takes 512 consecutive depth ranks one
-//      Gaussian at a time (its lanes spread over that Gaussian's rect), counts its pairs per
-//      tile (pass a), and after a scan over blocks and tiles (pass b) writes each pair's gid
-//      at its final position (pass c); per-tile positions advance in depth order.
+//   2. the tile digit in two stable counting levels fused with the pairs' generation:
+//      level 1 places one entry per (row of tiles, Gaussian) - gid and the Gaussian's tile
+//      span x0, w - into per-row segments in depth order (single-wavefront blocks of 512
+//      consecutive depth ranks; count, scan over blocks, scatter); level 2 splits every
+//      row's segment into chunks and places each entry's pairs into the row's tiles (count
+//      per (tile, chunk), scan over the row's chunks, scatter). A scatter takes 64 entries
+//      at a time, one per lane in depth order, and for each row (tile) they cover ranks the
+//      covering lanes with a ballot, so every level is stable and each write is a run.
 // The result equals a sort of (tile << 32 | depth bits) with ties broken by gid; the
-// per-tile ranges fall out of the scan, and no pair array other than the output is written.
+// per-tile ranges fall out of the scan. A single level over all tiles (a block writing ~10
+// pairs into each of ~1,200 tiles) left thousands of half-written lines per block in the
+// L2 and wrote ~8x the pairs' bytes to HBM; level 2's blocks touch only one row's tiles.
 #include "common.hpp"
 
 namespace ngs {
@@ -85,7 +90,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
   }
 }
 
-constexpr int kPartRanks = 512;  // depth ranks per partition block (one wavefront)
+constexpr int kPartRanks = 512;  // depth ranks per level-1 partition block (one wavefront)
+constexpr int kChunk2 = 1024;    // least row entries per level-2 chunk
+constexpr int kHist2 = 1 << 22;  // level-2 count table entries (tiles_x * chunks)
+constexpr int kGrid2 = 2048;     // persistent level-2 blocks
 
 // One Gaussian's rect as seen by the whole wavefront: lane q's values broadcast.
 struct RectU {
@@ -147,31 +155,7 @@ __device__ __forceinline__ int part_tile(const RectU& u, int j, int tiles_x) {
   return (u.y0 + row) * tiles_x + u.x0 + (j - row * u.w);
 }
 
-// Pass a: pairs per (tile, block), tile-major: hist[t * nblk + block]. Each lane loads one
-// Gaussian of the current 64 ranks; the wavefront then takes them one at a time (values
-// broadcast from that lane) and spreads its lanes over the Gaussian's tiles, which are
-// distinct, adding to the per-tile counters with LDS atomics.
-__global__ __launch_bounds__(kWave) void k_part_hist(int n, const uint32_t* __restrict__ order,
-                                                     const int16_t* __restrict__ rect, int tiles_x, int ntiles,
-                                                     uint32_t* __restrict__ hist, int nblk) {
-  __shared__ uint32_t cnt[NGS_MAX_TILES];
-  const int lane = threadIdx.x;
-  const int chunk = part_chunk(blockIdx.x, nblk);
-  for (int t = lane; t < ntiles; t += kWave) cnt[t] = 0u;
-  __syncthreads();
-  const int r0 = chunk * kPartRanks;
-  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
-    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
-    for (int q = 0; q < kWave; ++q) {
-      const RectU u = part_bcast(l, q);
-      for (int j = lane; j < u.area; j += kWave) atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
-    }
-  }
-  __syncthreads();
-  for (int t = lane; t < ntiles; t += kWave) hist[(size_t)t * nblk + chunk] = cnt[t];
-}
-
-// Pass b1: per tile, exclusive scan of its counts across blocks (in place); totals.
+// Per row of a (row, block) count table: exclusive scan across blocks (in place); totals.
 __global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ hist, int nblk,
                                                         uint32_t* __restrict__ tot) {
   __shared__ uint32_t sm[256];
@@ -195,12 +179,14 @@ __global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ h
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Pass b2: tile starts (exclusive scan of the totals) -> ranges; an empty tile gets
-// start = end = the number of pairs in lower tiles. If the pairs exceed the list capacity,
-// every range is left empty and *overflow is raised (the scatter then writes nothing).
+// Tile starts (exclusive scan of the per-tile totals) -> ranges; an empty tile gets
+// start = end = the number of pairs in lower tiles. If the pairs (m_total, the count scan's
+// total) exceed the list capacity, every range is left empty and *overflow is raised (the
+// scatters then write nothing).
 __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict__ tot, int ntiles,
                                                      uint32_t* __restrict__ ranges, int64_t capacity,
-                                                     int32_t* __restrict__ overflow, int64_t* __restrict__ stats) {
+                                                     int32_t* __restrict__ overflow, int64_t* __restrict__ stats,
+                                                     const uint64_t* __restrict__ m_total) {
   __shared__ uint32_t sm[256];
   constexpr int kPer = NGS_MAX_TILES / 256;
   const int t0 = threadIdx.x * kPer;
@@ -218,7 +204,7 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
     sm[threadIdx.x] += add;
     __syncthreads();
   }
-  const uint32_t total = sm[255];
+  const uint64_t total = *m_total;
   const bool over = (int64_t)total > capacity;
   const uint32_t excl = sm[threadIdx.x] - run;
   for (int j = 0; j < kPer; ++j)
@@ -232,30 +218,263 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
   }
 }
 
-// Pass c: every pair goes to ranges[tile] + (pairs of lower blocks for the tile) + (earlier
-// pairs of this block for the tile). The wavefront takes its Gaussians one at a time in
-// depth order and its LDS atomics execute in program order, so each tile's running
-// position advances in depth order: the pass is stable.
-__global__ __launch_bounds__(kWave) void k_part_scatter(int n, const uint32_t* __restrict__ order,
-                                                        const int16_t* __restrict__ rect, int tiles_x, int ntiles,
-                                                        const uint32_t* __restrict__ hist, int nblk,
-                                                        const uint32_t* __restrict__ ranges, int64_t capacity,
-                                                        uint32_t* __restrict__ gids_out) {
+// ---- level 1: rows ------------------------------------------------------------------------
+// Pass 1a: row entries per (row, block), row-major: rhist[r * nblk + block]. Counting needs
+// no order, so each lane adds its own Gaussian's rows.
+__global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* __restrict__ order,
+                                                    const int16_t* __restrict__ rect, int rows,
+                                                    uint32_t* __restrict__ rhist, int nblk) {
   __shared__ uint32_t cnt[NGS_MAX_TILES];
   const int lane = threadIdx.x;
   const int chunk = part_chunk(blockIdx.x, nblk);
-  for (int t = lane; t < ntiles; t += kWave) cnt[t] = ranges[t] + hist[(size_t)t * nblk + chunk];
+  for (int t = lane; t < rows; t += kWave) cnt[t] = 0u;
   __syncthreads();
   const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
     const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
-    for (int q = 0; q < kWave; ++q) {
-      const RectU u = part_bcast(l, q);
-      for (int j = lane; j < u.area; j += kWave) {
-        const uint32_t pos = atomicAdd(&cnt[part_tile(u, j, tiles_x)], 1u);
-        if ((int64_t)pos < capacity) gids_out[pos] = u.gid;
-      }
+    const int y0 = (int)(l.org >> 16), h = l.area / l.w;
+    for (int j = 0; j < h; ++j) atomicAdd(&cnt[y0 + j], 1u);
+  }
+  __syncthreads();
+  for (int t = lane; t < rows; t += kWave) rhist[(size_t)t * nblk + chunk] = cnt[t];
+}
+
+// Pass 1b (one block): row starts, the level-2 chunking and the overflow decision.
+// meta: [0] M (all pairs), [1] entries per level-2 chunk K2, [2] chunks NC, [3] over.
+// K2 keeps the level-2 count table within kHist2 entries: tiles_x * NC <= kHist2.
+__global__ __launch_bounds__(256) void k_row_starts(const uint32_t* __restrict__ rtot, int rows, int tiles_x,
+                                                    const uint64_t* __restrict__ m_total, int64_t capacity,
+                                                    uint32_t* __restrict__ rstart, uint32_t* __restrict__ nch,
+                                                    uint32_t* __restrict__ cp, uint32_t* __restrict__ meta) {
+  __shared__ uint32_t sm[256];
+  __shared__ uint32_t k2_sh;
+  constexpr int kPer = NGS_MAX_TILES / 256;
+  const int t0 = threadIdx.x * kPer;
+  const uint64_t M = *m_total;
+  const bool over = (int64_t)M > capacity;
+  // row starts
+  uint32_t v[kPer];
+  uint32_t run = 0;
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = run;
+    run += (t0 + j < rows && !over) ? rtot[t0 + j] : 0u;
+  }
+  sm[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sm[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint32_t m1 = sm[255];
+  const uint32_t excl = sm[threadIdx.x] - run;
+  for (int j = 0; j < kPer; ++j)
+    if (t0 + j < rows) rstart[t0 + j] = excl + v[j];
+  if (threadIdx.x == 0) {
+    const uint64_t room = (uint64_t)kHist2 / (uint64_t)tiles_x - (uint64_t)rows;  // >= 1, see kHist2
+    const uint64_t k2 = ((uint64_t)m1 + room - 1) / room;
+    k2_sh = (uint32_t)(k2 > (uint64_t)kChunk2 ? k2 : (uint64_t)kChunk2);
+  }
+  __syncthreads();
+  const uint32_t K2 = k2_sh;
+  __syncthreads();
+  // chunks per row and their exclusive scan
+  run = 0;
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = run;
+    run += (t0 + j < rows && !over) ? (rtot[t0 + j] + K2 - 1) / K2 : 0u;
+  }
+  sm[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sm[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint32_t excl2 = sm[threadIdx.x] - run;
+  for (int j = 0; j < kPer; ++j)
+    if (t0 + j < rows) {
+      cp[t0 + j] = excl2 + v[j];
+      nch[t0 + j] = (!over) ? (rtot[t0 + j] + K2 - 1) / K2 : 0u;
     }
+  if (threadIdx.x == 0) {
+    cp[rows] = sm[255];
+    meta[0] = (uint32_t)min(M, (uint64_t)0xFFFFFFFFu);
+    meta[1] = K2;
+    meta[2] = sm[255];
+    meta[3] = over ? 1u : 0u;
+  }
+}
+
+// Wave-wide min and max.
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Places the current 64 entries (lane order = depth order) of one segment family: for every
+// bin c in [lo, hi], the lanes whose span [b0, b0 + len) covers c take consecutive positions
+// cnt[c] + (covering lanes below them), and cnt[c] advances by their number. No atomics:
+// ballots give the ranks, and each bin's writes are one coalesced run.
+template <class Emit>
+__device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int lo, int hi, int lane, Emit emit) {
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int c = lo; c <= hi; ++c) {
+    const bool cover = len > 0 && b0 <= c && c < b0 + len;
+    const uint64_t m = __ballot(cover);
+    if (!m) continue;
+    const uint32_t base = cnt[c];
+    if (cover) emit(c, base + (uint32_t)__popcll(m & below));
+    if (lane == 0) cnt[c] = base + (uint32_t)__popcll(m);
+  }
+}
+
+// Pass 1c: every Gaussian's row entries {gid, x0 | w << 16} to their row segments, in depth
+// order within a row.
+__global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* __restrict__ order,
+                                                       const int16_t* __restrict__ rect, int rows,
+                                                       const uint32_t* __restrict__ rhist, int nblk,
+                                                       const uint32_t* __restrict__ rstart,
+                                                       const uint32_t* __restrict__ meta, uint2* __restrict__ rl) {
+  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  if (meta[3]) return;
+  const int lane = threadIdx.x;
+  const int chunk = part_chunk(blockIdx.x, nblk);
+  for (int t = lane; t < rows; t += kWave) cnt[t] = rstart[t] + rhist[(size_t)t * nblk + chunk];
+  __syncthreads();
+  const int r0 = chunk * kPartRanks;
+  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
+    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
+    const int y0 = (int)(l.org >> 16), h = l.area / l.w;
+    const int lo = wave_min(h > 0 ? y0 : INT_MAX), hi = wave_max(h > 0 ? y0 + h - 1 : -1);
+    const uint2 e = make_uint2(l.gid, (l.org & 0xFFFFu) | ((uint32_t)l.w << 16));
+    place_batch(cnt, y0, h, lo, hi, lane, [&](int, uint32_t pos) { rl[pos] = e; });
+  }
+}
+
+// ---- level 2: tiles within a row ----------------------------------------------------------
+// Chunk ci of the level-2 work: row (binary search over the chunk prefix) and its entries.
+struct Chunk2 {
+  int row;
+  uint32_t begin, end;  // entry range in the row list
+  uint32_t idx;         // chunk index within the row
+};
+
+__device__ __forceinline__ Chunk2 chunk2_of(uint32_t ci, int rows, const uint32_t* __restrict__ cp,
+                                            const uint32_t* __restrict__ rstart, const uint32_t* __restrict__ rtot,
+                                            uint32_t K2) {
+  int lo = 0, hi = rows - 1;  // last row with cp[row] <= ci
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cp[mid] <= ci) lo = mid; else hi = mid - 1;
+  }
+  Chunk2 c;
+  c.row = lo;
+  c.idx = ci - cp[lo];
+  c.begin = rstart[lo] + c.idx * K2;
+  c.end = min(c.begin + K2, rstart[lo] + rtot[lo]);
+  return c;
+}
+
+// Pass 2a: pairs per (tile, chunk); the table of row r holds tiles_x rows of nch[r] chunk
+// counts at tiles_x * cp[r]. Persistent: blocks stride over the chunks.
+__global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* __restrict__ rl, int rows, int tiles_x,
+                                                      const uint32_t* __restrict__ rstart,
+                                                      const uint32_t* __restrict__ rtot, const uint32_t* __restrict__ cp,
+                                                      const uint32_t* __restrict__ nch, const uint32_t* __restrict__ meta,
+                                                      uint32_t* __restrict__ hist2) {
+  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  if (meta[3]) return;
+  const uint32_t K2 = meta[1], NC = meta[2];
+  const int lane = threadIdx.x;
+  for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
+    const Chunk2 c = chunk2_of(ci, rows, cp, rstart, rtot, K2);
+    for (int t = lane; t < tiles_x; t += kWave) cnt[t] = 0u;
+    __syncthreads();
+    for (uint32_t i = c.begin + lane; i < c.end; i += kWave) {
+      const uint32_t xw = rl[i].y;
+      const int x0 = (int)(xw & 0xFFFFu), w = (int)(xw >> 16);
+      for (int j = 0; j < w; ++j) atomicAdd(&cnt[x0 + j], 1u);
+    }
+    __syncthreads();
+    uint32_t* dst = hist2 + (size_t)tiles_x * cp[c.row];
+    const uint32_t nc = nch[c.row];
+    for (int t = lane; t < tiles_x; t += kWave) dst[(size_t)t * nc + c.idx] = cnt[t];
+    __syncthreads();
+  }
+}
+
+// Pass 2b: per tile, exclusive scan of its counts across its row's chunks (in place); totals.
+__global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* __restrict__ hist2, int tiles_x,
+                                                    const uint32_t* __restrict__ cp, const uint32_t* __restrict__ nch,
+                                                    const uint32_t* __restrict__ meta, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t sm[256];
+  const int tile = blockIdx.x;
+  const int r = tile / tiles_x, x = tile % tiles_x;
+  const int nc = meta[3] ? 0 : (int)nch[r];
+  uint32_t* row = hist2 + (size_t)tiles_x * cp[r] + (size_t)x * nc;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nc; b0 += 256) {
+    const int i = b0 + threadIdx.x;
+    const uint32_t v = (i < nc) ? row[i] : 0u;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t add = (threadIdx.x >= (unsigned)off) ? sm[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sm[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nc) row[i] = carry + sm[threadIdx.x] - v;
+    carry += sm[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[tile] = carry;
+}
+
+// Pass 2c: each chunk's entries, in order, to their tiles: ranges[tile] + (pairs of earlier
+// chunks of the row for the tile) + (earlier pairs of this chunk). Entries of a row are in
+// depth order and place_batch keeps lane order within a tile: stable. A block keeps at most
+// tiles_x output runs open, so the L2 completes their lines.
+__global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict__ rl, int rows, int tiles_x,
+                                                         const uint32_t* __restrict__ rstart,
+                                                         const uint32_t* __restrict__ rtot,
+                                                         const uint32_t* __restrict__ cp,
+                                                         const uint32_t* __restrict__ nch,
+                                                         const uint32_t* __restrict__ meta,
+                                                         const uint32_t* __restrict__ hist2,
+                                                         const uint32_t* __restrict__ ranges, int64_t capacity,
+                                                         uint32_t* __restrict__ gids_out) {
+  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  if (meta[3]) return;
+  const uint32_t K2 = meta[1], NC = meta[2];
+  const int lane = threadIdx.x;
+  for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
+    const Chunk2 c = chunk2_of(ci, rows, cp, rstart, rtot, K2);
+    const uint32_t* h = hist2 + (size_t)tiles_x * cp[c.row];
+    const uint32_t nc = nch[c.row];
+    const int tbase = c.row * tiles_x;
+    for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
+    __syncthreads();
+    for (uint32_t i0 = c.begin; i0 < c.end; i0 += kWave) {
+      const uint32_t i = i0 + lane;
+      uint2 e = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
+      if (i < c.end) e = rl[i];
+      const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
+      const int lo = wave_min(w > 0 ? x0 : INT_MAX), hi = wave_max(w > 0 ? x0 + w - 1 : -1);
+      place_batch(cnt, x0, w, lo, hi, lane, [&](int, uint32_t pos) {
+        if ((int64_t)pos < capacity) gids_out[pos] = e.x;
+      });
+    }
+    __syncthreads();
   }
 }
 
@@ -277,10 +496,10 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ ran
 //   ptot: u32 [4096]
 //   hist: u32 [256][blocks(n)], rowtot: u32 [256]   radix-sort scratch
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
-  (void)max_pairs;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   const size_t nb = sort_blocks_for(nn);
   const size_t nblk = (nn + kPartRanks - 1) / kPartRanks;
+  const size_t mp = (size_t)std::max<int64_t>(max_pairs, 1);
   size_t b = 0;
   b += 4 * align_up(nn * 4, 256);
   b += align_up((nn + 1) * 8, 256);
@@ -289,14 +508,18 @@ size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
   b += align_up((size_t)NGS_MAX_TILES * 4, 256);
   b += align_up(256 * nb * 4, 256);
   b += align_up(256 * 4, 256);
+  b += align_up(mp * 8, 256);                          // row entries
+  b += align_up((size_t)kHist2 * 4, 256);              // level-2 counts
+  b += 4 * align_up(((size_t)NGS_MAX_TILES + 1) * 4, 256);  // rtot, rstart, nch, cp
+  b += align_up(16, 256);                              // meta
   return b;
 }
 
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
-  (void)max_pairs;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   const size_t nb = sort_blocks_for(nn);
   const size_t nblk = (nn + kPartRanks - 1) / kPartRanks;
+  const size_t mp = (size_t)std::max<int64_t>(max_pairs, 1);
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += align_up(bytes, 256); return r; };
   BinWs w;
@@ -309,6 +532,13 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
   w.sort.hist = (uint32_t*)take(256 * nb * 4);
   w.sort.rowtot = (uint32_t*)take(256 * 4);
   w.sort.max_blocks = nb;
+  w.rl = (uint2*)take(mp * 8);
+  w.hist2 = (uint32_t*)take((size_t)kHist2 * 4);
+  w.rtot = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
+  w.rstart = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
+  w.nch = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
+  w.cp = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
+  w.meta = (uint32_t*)take(16);
   return w;
 }
 
@@ -338,27 +568,44 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
 hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
+  const int rows = cam.tiles_y, tx = cam.tiles_x;
   const uint32_t* order = w.dvals[1];
-  hipError_t e = launch_copy_u32(reinterpret_cast<uint32_t*>(out.n_pairs),
-                                 reinterpret_cast<const uint32_t*>(w.offsets + n), 2, st);
+  const uint64_t* m_total = w.offsets + n;
+  hipError_t e = launch_copy_u32(reinterpret_cast<uint32_t*>(out.n_pairs), reinterpret_cast<const uint32_t*>(m_total),
+                                 2, st);
   if (e != hipSuccess) return e;
   if (n == 0) return launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st);
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_part_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, cam.tiles_x, ntiles, w.phist,
-                       nblk);
+    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk);
   }
   {
     ProfScope ps(kProfTileScan, st);
-    hipLaunchKernelGGL(k_part_scan_rows, dim3(ntiles), dim3(256), 0, st, w.phist, nblk, w.ptot);
-    hipLaunchKernelGGL(k_part_ranges, dim3(1), dim3(256), 0, st, w.ptot, ntiles, out.ranges, out.capacity, overflow,
-                       stats);
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(rows), dim3(256), 0, st, w.phist, nblk, w.rtot);
+    hipLaunchKernelGGL(k_row_starts, dim3(1), dim3(256), 0, st, w.rtot, rows, tx, m_total, out.capacity, w.rstart,
+                       w.nch, w.cp, w.meta);
   }
   {
     ProfScope ps(kProfTileScatter, st);
-    hipLaunchKernelGGL(k_part_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, cam.tiles_x, ntiles,
-                       w.phist, nblk, out.ranges, out.capacity, out.gids);
+    hipLaunchKernelGGL(k_row_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
+                       w.rstart, w.meta, w.rl);
+  }
+  {
+    ProfScope ps(kProfTileHist, st);
+    hipLaunchKernelGGL(k_tile2_hist, dim3(kGrid2), dim3(kWave), 0, st, w.rl, rows, tx, w.rstart, w.rtot, w.cp, w.nch,
+                       w.meta, w.hist2);
+  }
+  {
+    ProfScope ps(kProfTileScan, st);
+    hipLaunchKernelGGL(k_tile2_scan, dim3(ntiles), dim3(256), 0, st, w.hist2, tx, w.cp, w.nch, w.meta, w.ptot);
+    hipLaunchKernelGGL(k_part_ranges, dim3(1), dim3(256), 0, st, w.ptot, ntiles, out.ranges, out.capacity, overflow,
+                       stats, m_total);
+  }
+  {
+    ProfScope ps(kProfTileScatter, st);
+    hipLaunchKernelGGL(k_tile2_scatter, dim3(kGrid2), dim3(kWave), 0, st, w.rl, rows, tx, w.rstart, w.rtot, w.cp,
+                       w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
   }
   if (out.keys) {
     ProfScope ps(kProfKeys64, st);

@@ -147,9 +147,13 @@ struct BinWs {
   uint32_t* dvals[2];   // gids ping-pong [n]
   uint64_t* offsets;    // [n + 1] exclusive scan of tile counts in depth order
   uint64_t* blocksum;   // scan partials
-  uint32_t* phist;      // pairs per (tile, partition block) [4096][ceil(n / 256)]
+  uint32_t* phist;      // level 1: row entries per (row, block) [4096][ceil(n / 512)]
   uint32_t* ptot;       // pairs per tile [4096]
   SortWs sort;
+  uint2* rl;            // level 1 output: {gid, x0 | w << 16} per (row, Gaussian) [max_pairs]
+  uint32_t* hist2;      // level 2: pairs per (tile, chunk), row by row
+  uint32_t *rtot, *rstart, *nch, *cp;  // per row: entries, start, chunks, chunk prefix [4097]
+  uint32_t* meta;       // M, entries per chunk, chunks, overflow
 };
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);
