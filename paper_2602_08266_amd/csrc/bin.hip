@@ -91,9 +91,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
 }
 
 constexpr int kPartRanks = 512;  // depth ranks per level-1 partition block (one wavefront)
-constexpr int kChunk2 = 1024;    // least row entries per level-2 chunk
+constexpr int kChunk2 = 512;     // least row entries per level-2 chunk
 constexpr int kHist2 = 1 << 22;  // level-2 count table entries (tiles_x * chunks)
-constexpr int kGrid2 = 2048;     // persistent level-2 blocks
+constexpr int kGrid2 = 8192;     // persistent level-2 blocks
 
 // One Gaussian's rect as seen by the whole wavefront: lane q's values broadcast.
 struct RectU {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
 __global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* __restrict__ order,
                                                     const int16_t* __restrict__ rect, int rows,
                                                     uint32_t* __restrict__ rhist, int nblk) {
-  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  extern __shared__ uint32_t cnt[];  // [rows]
   const int lane = threadIdx.x;
   const int chunk = part_chunk(blockIdx.x, nblk);
   for (int t = lane; t < rows; t += kWave) cnt[t] = 0u;
@@ -337,26 +337,59 @@ __device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int 
   }
 }
 
+// The same with the counters in registers: lane l holds bin l in cr[0] and bin 64 + l in
+// cr[1] (NR = 2), read with readlane at the (uniform) bin; for at most 64 NR bins.
+template <int NR, class Emit>
+__device__ __forceinline__ void place_batch_reg(uint32_t (&cr)[NR], int b0, int len, int lo, int hi, int lane,
+                                                Emit emit) {
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int c = lo; c <= hi; ++c) {
+    const bool cover = len > 0 && b0 <= c && c < b0 + len;
+    const uint64_t m = __ballot(cover);
+    if (!m) continue;
+    const int src = c & (kWave - 1);
+    const bool hi_half = NR > 1 && c >= kWave;
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(hi_half ? cr[NR - 1] : cr[0]), src);
+    if (cover) emit(c, base + (uint32_t)__popcll(m & below));
+    if (lane == src) {
+      if (hi_half) cr[NR - 1] = base + (uint32_t)__popcll(m);
+      else cr[0] = base + (uint32_t)__popcll(m);
+    }
+  }
+}
+
 // Pass 1c: every Gaussian's row entries {gid, x0 | w << 16} to their row segments, in depth
-// order within a row.
+// order within a row. NR > 0: counters in registers (rows <= 64 NR), else in LDS.
+template <int NR>
 __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* __restrict__ order,
                                                        const int16_t* __restrict__ rect, int rows,
                                                        const uint32_t* __restrict__ rhist, int nblk,
                                                        const uint32_t* __restrict__ rstart,
                                                        const uint32_t* __restrict__ meta, uint2* __restrict__ rl) {
-  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  extern __shared__ uint32_t cnt[];  // [rows] when NR == 0
   if (meta[3]) return;
   const int lane = threadIdx.x;
   const int chunk = part_chunk(blockIdx.x, nblk);
-  for (int t = lane; t < rows; t += kWave) cnt[t] = rstart[t] + rhist[(size_t)t * nblk + chunk];
-  __syncthreads();
+  uint32_t cr[NR > 0 ? NR : 1];
+  if constexpr (NR > 0) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int t = i * kWave + lane;
+      cr[i] = t < rows ? rstart[t] + rhist[(size_t)t * nblk + chunk] : 0u;
+    }
+  } else {
+    for (int t = lane; t < rows; t += kWave) cnt[t] = rstart[t] + rhist[(size_t)t * nblk + chunk];
+    __syncthreads();
+  }
   const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
     const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
     const int y0 = (int)(l.org >> 16), h = l.area / l.w;
     const int lo = wave_min(h > 0 ? y0 : INT_MAX), hi = wave_max(h > 0 ? y0 + h - 1 : -1);
     const uint2 e = make_uint2(l.gid, (l.org & 0xFFFFu) | ((uint32_t)l.w << 16));
-    place_batch(cnt, y0, h, lo, hi, lane, [&](int, uint32_t pos) { rl[pos] = e; });
+    auto emit = [&](int, uint32_t pos) { rl[pos] = e; };
+    if constexpr (NR > 0) place_batch_reg<NR>(cr, y0, h, lo, hi, lane, emit);
+    else place_batch(cnt, y0, h, lo, hi, lane, emit);
   }
 }
 
@@ -368,17 +401,18 @@ struct Chunk2 {
   uint32_t idx;         // chunk index within the row
 };
 
-__device__ __forceinline__ Chunk2 chunk2_of(uint32_t ci, int rows, const uint32_t* __restrict__ cp,
+// cpl: the block's LDS copy of the chunk prefix.
+__device__ __forceinline__ Chunk2 chunk2_of(uint32_t ci, int rows, const uint32_t* cpl,
                                             const uint32_t* __restrict__ rstart, const uint32_t* __restrict__ rtot,
                                             uint32_t K2) {
-  int lo = 0, hi = rows - 1;  // last row with cp[row] <= ci
+  int lo = 0, hi = rows - 1;  // last row with cpl[row] <= ci
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (cp[mid] <= ci) lo = mid; else hi = mid - 1;
+    if (cpl[mid] <= ci) lo = mid; else hi = mid - 1;
   }
   Chunk2 c;
   c.row = lo;
-  c.idx = ci - cp[lo];
+  c.idx = ci - cpl[lo];
   c.begin = rstart[lo] + c.idx * K2;
   c.end = min(c.begin + K2, rstart[lo] + rtot[lo]);
   return c;
@@ -391,12 +425,17 @@ __global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* __restrict__ 
                                                       const uint32_t* __restrict__ rtot, const uint32_t* __restrict__ cp,
                                                       const uint32_t* __restrict__ nch, const uint32_t* __restrict__ meta,
                                                       uint32_t* __restrict__ hist2) {
-  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  extern __shared__ uint32_t lds2[];  // cnt [tiles_x], chunk prefix [rows]
+  uint32_t* cnt = lds2;
+  uint32_t* cpl = lds2 + tiles_x;
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
   const int lane = threadIdx.x;
+  if (blockIdx.x >= NC) return;
+  for (int r = lane; r < rows; r += kWave) cpl[r] = cp[r];
   for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
-    const Chunk2 c = chunk2_of(ci, rows, cp, rstart, rtot, K2);
+    __syncthreads();
+    const Chunk2 c = chunk2_of(ci, rows, cpl, rstart, rtot, K2);
     for (int t = lane; t < tiles_x; t += kWave) cnt[t] = 0u;
     __syncthreads();
     for (uint32_t i = c.begin + lane; i < c.end; i += kWave) {
@@ -442,8 +481,10 @@ __global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* __restrict__ hist2
 
 // Pass 2c: each chunk's entries, in order, to their tiles: ranges[tile] + (pairs of earlier
 // chunks of the row for the tile) + (earlier pairs of this chunk). Entries of a row are in
-// depth order and place_batch keeps lane order within a tile: stable. A block keeps at most
-// tiles_x output runs open, so the L2 completes their lines.
+// depth order and the placement keeps lane order within a tile: stable. A block keeps at most
+// tiles_x output runs open, so the L2 completes their lines. NR > 0: counters in registers
+// (tiles_x <= 64 NR), else in LDS.
+template <int NR>
 __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict__ rl, int rows, int tiles_x,
                                                          const uint32_t* __restrict__ rstart,
                                                          const uint32_t* __restrict__ rtot,
@@ -453,28 +494,43 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict
                                                          const uint32_t* __restrict__ hist2,
                                                          const uint32_t* __restrict__ ranges, int64_t capacity,
                                                          uint32_t* __restrict__ gids_out) {
-  __shared__ uint32_t cnt[NGS_MAX_TILES];
+  extern __shared__ uint32_t lds2[];  // cnt [tiles_x] (NR == 0), chunk prefix [rows]
+  uint32_t* cnt = lds2;
+  uint32_t* cpl = lds2 + (NR > 0 ? 0 : tiles_x);
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
   const int lane = threadIdx.x;
+  if (blockIdx.x >= NC) return;
+  for (int r = lane; r < rows; r += kWave) cpl[r] = cp[r];
   for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
-    const Chunk2 c = chunk2_of(ci, rows, cp, rstart, rtot, K2);
+    __syncthreads();
+    const Chunk2 c = chunk2_of(ci, rows, cpl, rstart, rtot, K2);
     const uint32_t* h = hist2 + (size_t)tiles_x * cp[c.row];
     const uint32_t nc = nch[c.row];
     const int tbase = c.row * tiles_x;
-    for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
-    __syncthreads();
+    uint32_t cr[NR > 0 ? NR : 1];
+    if constexpr (NR > 0) {
+#pragma unroll
+      for (int i2 = 0; i2 < NR; ++i2) {
+        const int t = i2 * kWave + lane;
+        cr[i2] = t < tiles_x ? ranges[tbase + t] + h[(size_t)t * nc + c.idx] : 0u;
+      }
+    } else {
+      for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
+      __syncthreads();
+    }
     for (uint32_t i0 = c.begin; i0 < c.end; i0 += kWave) {
       const uint32_t i = i0 + lane;
       uint2 e = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
       if (i < c.end) e = rl[i];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
       const int lo = wave_min(w > 0 ? x0 : INT_MAX), hi = wave_max(w > 0 ? x0 + w - 1 : -1);
-      place_batch(cnt, x0, w, lo, hi, lane, [&](int, uint32_t pos) {
+      auto emit = [&](int, uint32_t pos) {
         if ((int64_t)pos < capacity) gids_out[pos] = e.x;
-      });
+      };
+      if constexpr (NR > 0) place_batch_reg<NR>(cr, x0, w, lo, hi, lane, emit);
+      else place_batch(cnt, x0, w, lo, hi, lane, emit);
     }
-    __syncthreads();
   }
 }
 
@@ -578,7 +634,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk);
+    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), rows * 4, st, n, order, p.rect, rows, w.phist, nblk);
   }
   {
     ProfScope ps(kProfTileScan, st);
@@ -588,13 +644,20 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   }
   {
     ProfScope ps(kProfTileScatter, st);
-    hipLaunchKernelGGL(k_row_scatter, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
-                       w.rstart, w.meta, w.rl);
+    if (rows <= kWave)
+      hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
+                         w.rstart, w.meta, w.rl);
+    else if (rows <= 2 * kWave)
+      hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
+                         w.rstart, w.meta, w.rl);
+    else
+      hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk), dim3(kWave), rows * 4, st, n, order, p.rect, rows, w.phist,
+                         nblk, w.rstart, w.meta, w.rl);
   }
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_tile2_hist, dim3(kGrid2), dim3(kWave), 0, st, w.rl, rows, tx, w.rstart, w.rtot, w.cp, w.nch,
-                       w.meta, w.hist2);
+    hipLaunchKernelGGL(k_tile2_hist, dim3(kGrid2), dim3(kWave), (tx + rows) * 4, st, w.rl, rows, tx, w.rstart, w.rtot,
+                       w.cp, w.nch, w.meta, w.hist2);
   }
   {
     ProfScope ps(kProfTileScan, st);
@@ -604,8 +667,15 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
   }
   {
     ProfScope ps(kProfTileScatter, st);
-    hipLaunchKernelGGL(k_tile2_scatter, dim3(kGrid2), dim3(kWave), 0, st, w.rl, rows, tx, w.rstart, w.rtot, w.cp,
-                       w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+    if (tx <= kWave)
+      hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+    else if (tx <= 2 * kWave)
+      hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+    else
+      hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(kGrid2), dim3(kWave), (tx + rows) * 4, st, w.rl, rows, tx,
+                         w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
   }
   if (out.keys) {
     ProfScope ps(kProfKeys64, st);

@@ -100,6 +100,27 @@ def test_bin_sort_bitexact(B, ctx, wl, view):
     assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
 
 
+@pytest.mark.parametrize("w,h", [(2304, 64), (64, 1100), (64, 2100), (1300, 40)])
+def test_bin_sort_bitexact_tile_grid_shapes(B, ctx, w, h):
+    """Tile grids that take the other counter paths of the two-level partition: more than
+    128 tiles per row (LDS counters), 65-128 rows and more than 128 rows (register pairs and
+    LDS for the row level), 82 tiles per row (two registers per lane)."""
+    log(f"test_bin_sort tile grid {w}x{h}")
+    scene = scenegen.make_scene(20000, 8, 16, seed=31)
+    cam = scenegen.look_at(np.array([0.55, -0.25, 0.35]), w, h, 0.9 * max(w, h))
+    ds = device_scene(B, ctx, scene)
+    rp = B.raster_params()
+    c = B.camera(cam)
+    pr = B.ngs_project(ctx, ds, c, rp)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=16, want_keys=True)
+    ref = oracle.tile_lists(scene, cam)
+    m = int(lists.n_pairs.item())
+    assert m == ref["m"] and m > 0
+    assert np.array_equal(lists.gids[:m].cpu().numpy().view(np.uint32), ref["gids"])
+    assert np.array_equal(lists.keys[:m].cpu().numpy().view(np.uint64), ref["keys"])
+    assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+
+
 def render_gpu(B, ctx, ds, cam, want_obj=True):
     rp = B.raster_params()
     c = B.camera(cam)
