@@ -162,30 +162,38 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   const float sy0 = (float)(ty * kTile + wave * kRowsW) + 0.5f, sy1 = sy0 + (float)(kRowsW - 1);
 
   // ---- pass 1: front to back, final transmittance and last contributor -----------------
+  // Each wavefront walks on its own: lane l holds batch entry l in registers, the walk reads
+  // an entry's values with readlane, and a wavefront stops once all its pixels are done.
   float T = 1.f;
   int last = -1, nc = 0;
   bool done = !inside;
-  for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
-    if (__syncthreads_and(done)) break;
-    const int cnt = (int)min((uint32_t)kBatch, end - b0);
-    if ((int)threadIdx.x < cnt) {
-      const uint32_t g = gids[b0 + threadIdx.x];
-      const int j = threadIdx.x;
-      S.mx[j] = mean2d[g]; S.my[j] = mean2d[n + g];
-      S.qa[j] = conic[g]; S.qb[j] = conic[n + g]; S.qc[j] = conic[2 * n + g];
-      S.op[j] = opacity[g];
-      conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
+  for (uint32_t b0 = start; b0 < end; b0 += kWave) {
+    if (__ballot(!done) == 0ull) break;
+    const int cnt = (int)min((uint32_t)kWave, end - b0);
+    float emx = 0.f, emy = 0.f, eqa = 0.f, eqb = 0.f, eqc = 0.f, eop = 0.f, ehx = -1.f, ehy = -1.f;
+    if (lane < cnt) {
+      const uint32_t g = gids[b0 + lane];
+      emx = mean2d[g]; emy = mean2d[n + g];
+      eqa = conic[g]; eqb = conic[n + g]; eqc = conic[2 * n + g];
+      eop = opacity[g];
+      conic_extent(eqa, eqb, eqc, rc.cutoff_q, &ehx, &ehy);
     }
-    __syncthreads();
-    uint64_t live = __ballot(reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
+    uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
+                             emy - ehy <= sy1);
     if (!done) {
       while (live) {
         const int j = __ffsll((unsigned long long)live) - 1;
         live &= live - 1;
-        const float dx = fxp - S.mx[j], dy = fyp - S.my[j];
-        const float q = conic_q(S.qa[j], S.qb[j], S.qc[j], dx, dy);
+        const float mxj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emx), j));
+        const float myj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emy), j));
+        const float qaj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqa), j));
+        const float qbj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqb), j));
+        const float qcj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqc), j));
+        const float opj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eop), j));
+        const float dx = fxp - mxj, dy = fyp - myj;
+        const float q = conic_q(qaj, qbj, qcj, dx, dy);
         if (q > rc.cutoff_q) continue;
-        const float alpha = fminf(rc.alpha_max, gauss_alpha(S.op[j], q));
+        const float alpha = fminf(rc.alpha_max, gauss_alpha(opj, q));
         if (alpha < rc.alpha_min) continue;
         const float Tn = transmit(T, alpha);
         if (Tn < rc.t_min) { done = true; break; }
