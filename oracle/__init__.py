@@ -64,7 +64,7 @@ class _IG(C.Structure):
     _fields_ = [("lambda_prior", C.c_double), ("alpha_obj", C.c_double), ("alpha_opa", C.c_double),
                 ("beta_d", C.c_double), ("beta_o", C.c_double), ("target_id", C.c_int32),
                 ("outputs", C.c_int32), ("conf_on_train", C.c_int32), ("obj_eq2", C.c_int32),
-                ("level", C.c_int32)]
+                ("level", C.c_int32), ("criterion", C.c_int32)]
 
 
 def _f32(x) -> float:
@@ -102,11 +102,12 @@ class IGParams:
     conf_on_train: int = 1
     obj_eq2: int = 1
     level: int = 2
+    criterion: int = 0  # 0: log det (Eq. 6); 1: trace(H^-1)^-1 (the alternative f of Sec. III-B)
 
     def c(self) -> _IG:
         return _IG(_f32(self.lambda_prior), _f32(self.alpha_obj), _f32(self.alpha_opa), _f32(self.beta_d),
                    _f32(self.beta_o), self.target_id, self.outputs, self.conf_on_train, self.obj_eq2,
-                   self.level)
+                   self.level, self.criterion)
 
 
 def lib():
@@ -132,9 +133,11 @@ def lib():
             L.or_blocks_free.argtypes = [P]
             L.or_logdet.argtypes = [C.c_int, P]
             L.or_logdet.restype = C.c_double
+            L.or_trace_inv.argtypes = [C.c_int, P]
+            L.or_trace_inv.restype = C.c_double
             L.or_pixel_rows.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_int, P, P, P, P]
             L.or_pixel_eval_frozen.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_int, P, P]
-            L.or_score.argtypes = [P, C.c_int, P, C.c_int, P, P, P, C.c_int, P, P, P, P, P, P]
+            L.or_score.argtypes = [P, C.c_int, P, C.c_int, P, P, P, C.c_int, P, P, P, P, P, P, P]
             L.or_train_blocks.argtypes = [P, C.c_int, P, P, P, C.c_int, C.c_int, P, P, P, P, P]
             L.or_render_grad.argtypes = [P, P, P, P, C.c_int, P, P, P, P]
             _lib = L
@@ -284,6 +287,12 @@ def logdet(A: np.ndarray) -> float:
     return float(lib().or_logdet(A.shape[0], _ptr(A)))
 
 
+def trace_inv(A: np.ndarray) -> float:
+    """trace(A^-1) of an SPD matrix by the oracle's Cholesky."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    return float(lib().or_trace_inv(A.shape[0], _ptr(A)))
+
+
 def pixel_rows(scene, cam, px: int, py: int, rp: RasterParams = RasterParams(), ig: IGParams = IGParams(),
                cap: int = 512):
     """Jacobian rows of every channel at one pixel, for each contributor front to back."""
@@ -320,6 +329,7 @@ class ScoreResult:
     scores: np.ndarray     # [V][4] normalised rgb, depth, object, combined (Eq. 11)
     best: int
     stats: np.ndarray      # [V][2] touched Gaussians U, contributing pairs P
+    trace_total: np.ndarray = None  # [3] S_T of the trace criterion (0 for log det)
 
 
 def score(scene, train_cams, cand_cams, rp: RasterParams = RasterParams(), ig: IGParams = IGParams(),
@@ -331,9 +341,10 @@ def score(scene, train_cams, cand_cams, rp: RasterParams = RasterParams(), ig: I
     rc, igc = rp.c(), ig.c()
     igt = np.zeros((max(nt, 1), 3)); igcand = np.zeros((max(nc, 1), 3)); norm = np.zeros(3)
     sc = np.zeros((max(nc, 1), 4)); best = C.c_int32(-1); stats = np.zeros((max(nc, 1), 2), np.int64)
+    tt = np.zeros(3)
     st = lib().or_score(C.byref(sb.c), nt, tc, nc, cc, C.byref(rc), C.byref(igc), threads or default_threads(),
-                        _ptr(igt), _ptr(igcand), _ptr(norm), _ptr(sc), C.byref(best), _ptr(stats))
-    return ScoreResult(int(st), igt[:nt], igcand[:nc], norm, sc[:nc], int(best.value), stats[:nc])
+                        _ptr(igt), _ptr(igcand), _ptr(norm), _ptr(sc), C.byref(best), _ptr(stats), _ptr(tt))
+    return ScoreResult(int(st), igt[:nt], igcand[:nc], norm, sc[:nc], int(best.value), stats[:nc], tt)
 
 
 def train_blocks(scene, train_cams, query: Sequence[int], rp: RasterParams = RasterParams(),

@@ -96,6 +96,7 @@ struct or_ig {
   int32_t conf_on_train;  // 1: H_T = lambda I + c_g sum_t A_t; 0: H_T = lambda I + sum_t A_t
   int32_t obj_eq2;        // 1: object output is O (Eq. 2); 0: O' (Eq. 1)
   int32_t level;          // 1: dense object rows; 2: block expansion of the object rows
+  int32_t criterion;      // 0: f = log det H (Eq. 6); 1: f = trace(H^-1)^-1 (Sec. III-B)
 };
 
 }  // extern "C"
@@ -689,11 +690,42 @@ double chol_logdet(const double* A, int l) {
   return ld;
 }
 
+// trace(A^-1) of an SPD l x l matrix: A = L L^T, A^-1 = L^-T L^-1, so the trace is the sum
+// of the squared entries of L^-1 (textbook Cholesky and forward substitution, column by column).
+double chol_trace_inv(const double* A, int l) {
+  std::vector<double> L((size_t)l * l, 0.0);
+  for (int j = 0; j < l; ++j) {
+    double d = A[(size_t)j * l + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * l + k] * L[(size_t)j * l + k];
+    if (!(d > 0.0)) return NAN;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * l + j] = ljj;
+    for (int i = j + 1; i < l; ++i) {
+      double v = A[(size_t)i * l + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * l + k] * L[(size_t)j * l + k];
+      L[(size_t)i * l + j] = v / ljj;
+    }
+  }
+  double tr = 0.0;
+  std::vector<double> x(l);
+  for (int c = 0; c < l; ++c) {  // column c of L^-1: solve L x = e_c
+    for (int i = 0; i < l; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * l + k] * x[k];
+      x[i] = v / L[(size_t)i * l + i];
+      tr += x[i] * x[i];
+    }
+  }
+  return tr;
+}
+
 inline int block_len(int f, int k) { return f == 0 ? 14 : (f == 1 ? NGEO : NGEO + k); }
 inline const std::vector<double>& block_of(const Blocks& b, int f) { return f == 0 ? b.rgb : (f == 1 ? b.d : b.o); }
 inline std::vector<double>& block_of(Blocks& b, int f) { return f == 0 ? b.rgb : (f == 1 ? b.d : b.o); }
 
-// IG_f(T, c) = sum_g [logdet(H_T,g + c_g A_c,g) - logdet(H_T,g)] (Eqs. 5, 6, 9).
+// IG_f(T, c) = sum_g [logdet(H_T,g + c_g A_c,g) - logdet(H_T,g)] (Eqs. 5, 6, 9). With the
+// trace criterion the per-Gaussian term is the reduction of the covariance trace,
+// trace(H_T,g^-1) - trace((H_T,g + c_g A_c,g)^-1), and out[] holds its sum R_f.
 void info_gain(const BlocksResult& cand, const std::map<int, Blocks>& HT, const GaussTerms& gt,
                const or_ig& ig, int k, double out[3], std::vector<std::array<double, 3>>* per_g) {
   out[0] = out[1] = out[2] = 0.0;
@@ -714,7 +746,8 @@ void info_gain(const BlocksResult& cand, const std::map<int, Blocks>& HT, const 
       }
       const std::vector<double>& A = block_of(cand.blocks[i], f);
       for (size_t e = 0; e < M.size(); ++e) M[e] = Hm[e] + cg * A[e];
-      const double d = chol_logdet(M.data(), l) - chol_logdet(Hm.data(), l);
+      const double d = ig.criterion == 1 ? chol_trace_inv(Hm.data(), l) - chol_trace_inv(M.data(), l)
+                                         : chol_logdet(M.data(), l) - chol_logdet(Hm.data(), l);
       out[f] += d;
       if (per_g) (*per_g)[i][f] = d;
     }
@@ -962,6 +995,7 @@ int or_blocks_get(void* h, int64_t i, int32_t* gid, double* a_rgb, double* a_d, 
 void or_blocks_free(void* h) { delete static_cast<BlocksResult*>(h); }
 
 double or_logdet(int l, const double* A) { return chol_logdet(A, l); }
+double or_trace_inv(int l, const double* A) { return chol_trace_inv(A, l); }
 
 // Jacobian rows at pixel (px, py) for every contributor, front to back. Returns the number
 // of contributors (rows written only when it is <= cap): contrib [cap] gids, rows_rgb
@@ -1029,7 +1063,8 @@ int or_pixel_eval_frozen(const or_scene* s, const or_camera* cam, const or_raste
 // normaliser is not positive (scores then hold the raw gains only).
 int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or_camera* cand,
              const or_raster* rp, const or_ig* ig, int threads, double* ig_train, double* ig_cand,
-             double* norm, double* scores, int32_t* best, int64_t* stats /*[nc][2]: U, pairs*/) {
+             double* norm, double* scores, int32_t* best, int64_t* stats /*[nc][2]: U, pairs*/,
+             double* trace_total /*[3] S_T of the trace criterion, may be NULL*/) {
   GaussTerms gt = gaussian_terms(*s, *ig);
   const int k = s->k;
   std::vector<BlocksResult> tv;
@@ -1039,12 +1074,25 @@ int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or
     tv.push_back(view_blocks(V, threads));
   }
   std::map<int, Blocks> HT = build_train(tv, gt, *ig, k);
+  // trace criterion: f(V) = 1 / S_V with S_V = sum over all n Gaussians of trace(H_V,g^-1)
+  // (block diagonal H; a Gaussian no training view touched has H_T,g = lambda I), so
+  // f(T + c) - f(T) = 1 / (S_T - R) - 1 / S_T = R / (S_T (S_T - R)) for the reduction R.
+  double st[3] = {0, 0, 0};
+  if (ig->criterion == 1)
+    for (int f = 0; f < 3; ++f) {
+      const int l = block_len(f, k);
+      for (const auto& kv : HT) st[f] += chol_trace_inv(block_of(kv.second, f).data(), l);
+      st[f] += (double)(s->n - (int64_t)HT.size()) * l / ig->lambda_prior;
+    }
+  auto gain = [&](int f, double r) { return ig->criterion == 1 ? r / (st[f] * (st[f] - r)) : r; };
   double nf[3] = {0, 0, 0};
   for (int t = 0; t < nt; ++t) {
     double o[3];
     info_gain(tv[t], HT, gt, *ig, k, o, nullptr);
-    for (int f = 0; f < 3; ++f) { ig_train[3 * t + f] = o[f]; nf[f] += o[f] / nt; }
+    for (int f = 0; f < 3; ++f) { ig_train[3 * t + f] = o[f]; nf[f] += gain(f, o[f]) / nt; }
   }
+  if (trace_total)
+    for (int f = 0; f < 3; ++f) trace_total[f] = st[f];
   tv.clear();
   for (int f = 0; f < 3; ++f) norm[f] = nf[f];
   int status = 0;
@@ -1063,7 +1111,7 @@ int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or
     double tot = 0.0;
     for (int f = 0; f < 3; ++f) {
       ig_cand[3 * c + f] = o[f];
-      const double v = (status == 0 && ((ig->outputs >> f) & 1)) ? o[f] / nf[f] : 0.0;
+      const double v = (status == 0 && ((ig->outputs >> f) & 1)) ? gain(f, o[f]) / nf[f] : 0.0;
       scores[4 * c + f] = v;
       tot += beta[f] * v;
     }

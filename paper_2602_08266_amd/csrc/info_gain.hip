@@ -234,6 +234,10 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
 
   // ---- pass 2: back to front ------------------------------------------------------------
   const float t_final = T;
+  // the wavefront's last contributor: entries behind it contribute to none of its pixels
+  int wave_last = last;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
   float Tc = T;
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Sd = 0.f;
   float So[KL];  // channels h * KL ... (h + 1) * KL - 1 of the object suffix
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
       S.p[j][c] = (c < k) ? prob[(size_t)gids[lo + j] * k + c] : 0.f;
     }
     __syncthreads();
-    uint64_t live = __ballot(reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
+    uint64_t live = __ballot(lo + lane <= wave_last && reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
     while (live) {
       const int j = 63 - __clzll((long long)live);
       live &= ~(1ull << j);

@@ -587,3 +587,52 @@ def test_normalisation_eq10_and_argmax(tiny):
     tot = r.scores[:, 0] + 10.0 * r.scores[:, 1] + r.scores[:, 2]
     assert np.allclose(r.scores[:, 3], tot, rtol=1e-14)
     assert r.best == int(np.argmax(r.scores[:, 3]))
+
+
+def test_trace_inv_matches_lapack_and_sherman_morrison():
+    """trace(A^-1) of the oracle's Cholesky against numpy's inverse, and the closed form of a
+    rank-one update of the prior: trace((lam I + a v v^T)^-1) = l / lam - a |v|^2 / (lam (lam + a |v|^2))."""
+    rng = np.random.default_rng(8)
+    for l in (14, 11, 43, 75):
+        X = rng.normal(size=(l, 2 * l)) * np.exp(rng.uniform(-3, 3, size=(l, 1)))
+        A = X @ X.T + 0.1 * np.eye(l)
+        ref = np.trace(np.linalg.inv(A))
+        assert abs(oracle.trace_inv(A) - ref) <= 1e-9 * ref
+        v = rng.normal(size=l)
+        lam, a = 0.1, 3.7
+        cf = l / lam - a * (v @ v) / (lam * (lam + a * (v @ v)))
+        assert abs(oracle.trace_inv(lam * np.eye(l) + a * np.outer(v, v)) - cf) <= 1e-10 * cf
+    assert math.isnan(oracle.trace_inv(-np.eye(3)))
+
+
+def test_trace_criterion_rebuilt_with_numpy(tiny):
+    """Trace criterion (f = trace(H^-1)^-1 on the block-diagonal H): per candidate the oracle's raw
+    value is the reduction R_f = sum_g [trace(H_T,g^-1) - trace((H_T,g + c_g A_g)^-1)] and the
+    scores use f(T + c) - f(T) = R / (S (S - R)), S = sum over all n Gaussians of trace(H_T,g^-1);
+    rebuilt here with numpy inverses from the separately pinned blocks."""
+    cfg, scene, cands, train = tiny
+    for target in (-1, 3):
+        ig = oracle.IGParams(target_id=target, criterion=1)
+        r = oracle.score(scene, train, train + cands[:3], ig=ig)
+        assert r.status == 0
+        gt = oracle.gaussian_terms(scene, ig)
+        # S_T from every Gaussian's training block (prior only when untouched)
+        H_all = oracle.train_blocks(scene, train, np.arange(scene.n, dtype=np.int32), ig=ig)
+        S = np.array([sum(np.trace(np.linalg.inv(H_all[key][g])) for g in range(scene.n))
+                      for key in ("rgb", "d", "o")])
+        assert np.allclose(r.trace_total, S, rtol=1e-10)
+        for c, cam in enumerate(train + cands[:3]):
+            vb = oracle.view_blocks(scene, cam, ig=ig)
+            H = oracle.train_blocks(scene, train, vb.gids, ig=ig)
+            ref = np.zeros(3)
+            for i, g in enumerate(vb.gids):
+                cg = gt["conf"][g]
+                for f, (A, Hf) in enumerate(((vb.rgb[i], H["rgb"][i]), (vb.d[i], H["d"][i]), (vb.o[i], H["o"][i]))):
+                    ref[f] += np.trace(np.linalg.inv(Hf)) - np.trace(np.linalg.inv(Hf + cg * A))
+            assert np.allclose(r.ig_cand[c], ref, rtol=1e-8, atol=1e-12 * S.max()), (target, c)
+            assert np.all(r.ig_cand[c] >= -1e-12 * S)
+        gains = r.ig_cand / (S * (S - r.ig_cand))
+        t = len(train)
+        assert np.allclose(r.norm, gains[:t].mean(0), rtol=1e-12)
+        assert np.allclose(r.scores[:, :3], gains / r.norm, rtol=1e-12)
+        assert r.best == int(np.argmax(r.scores[:, 3]))
