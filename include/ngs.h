@@ -94,7 +94,17 @@ typedef struct {
  * from Sec. IV-A.2; lambda_prior adds lambda*I to every block of H (a reading: the
  * paper is silent on regularisation); target_id < 0 scores the whole scene (Eq. 7),
  * otherwise Eq. 12 for that object; conf_on_train = 1 weights training views by c_g
- * too (Eq. 9 read for every view); obj_eq2 = 1 differentiates O of Eq. 2 (else O'). */
+ * too (Eq. 9 read for every view); obj_eq2 = 1 differentiates O of Eq. 2 (else O').
+ * criterion selects f (Sec. III-B): 0 = log det H (Eq. 6, the paper's choice); 1 = the
+ * trace-based f(V) = trace(H_V^-1)^-1 on the same block-diagonal H. With 1 the raw gain of
+ * a view is the covariance-trace reduction R_f = sum_g [trace(H_T,g^-1) -
+ * trace((H_T,g + c_g A_g)^-1)] and ngs_score_batch turns it into f(T + c) - f(T) =
+ * R / (S (S - R)) with trace_total[f] = S = sum over all n Gaussians of trace(H_T,g^-1)
+ * (n - stored slots times l_f / lambda for Gaussians without a stored block); the
+ * normalisers must then be means of that converted quantity over the training views.
+ * Ablation switches of the paper's Table III: the object output (bit 2 of outputs), the
+ * confidence (alpha_obj = alpha_opa = 0 gives c_g = 1, or the target indicator with
+ * Eq. 12), and the Eq. 10 scaling (normalisers 1 with fixed beta weights). */
 typedef struct {
   float lambda_prior, alpha_obj, alpha_opa, beta_d, beta_o;
   int32_t target_id;
@@ -102,6 +112,8 @@ typedef struct {
   int32_t conf_on_train;
   int32_t obj_eq2;
   int32_t mode;
+  int32_t criterion;
+  double trace_total[3];
 } ngs_ig_params;
 
 /* Per-view projection (one entry per Gaussian). rect holds each Gaussian's inclusive
@@ -160,6 +172,8 @@ typedef struct {
   double* h_d;
   double* h_o;
   double* logdet;      /* [3][capacity] */
+  double* trinv;       /* [3][capacity] trace(H_T,g^-1), filled by ngs_hessian_finalize when
+                          not NULL; needed by the trace criterion */
 } ngs_hessian;
 
 /* Per-view statistics the kernels add into (device, int64 [6], caller-zeroed):
@@ -219,7 +233,8 @@ ngs_status ngs_render(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected*
 /* Information of one view (Eq. 6, block diagonal per Gaussian, Sec. III-B.1) with the
  * per-output parameter subsets of Sec. III-B.3 (rgb: 14, depth: 11, object: 11 + k).
  * SCORE mode: ig_out[3] (device, FP64) = IG_f(T, c) = sum_g logdet(H_T,g + c_g A_g) -
- * logdet(H_T,g) (Eq. 5, 6, 9); h may be NULL (H_T = lambda I). ACCUMULATE mode: adds
+ * logdet(H_T,g) (Eq. 5, 6, 9), or with ig->criterion = 1 the trace reduction R_f (see
+ * ngs_ig_params; h->trinv then required); h may be NULL (H_T = lambda I). ACCUMULATE mode: adds
  * w_g A_g into h (w_g = c_g, or 1 when conf_on_train = 0); call ngs_hessian_finalize
  * after the last training view. stats (device int64 [NGS_STATS_LEN]) may be NULL.
  * ws: ngs_workspace_size(1, ...) bytes; its slot capacity (max_slots) must cover every
@@ -231,7 +246,8 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
 
 /* Clears a training store (slot_of = -1, n_slots = 0). */
 ngs_status ngs_hessian_reset(ngs_ctx* ctx, ngs_hessian* h, int32_t n, void* stream);
-/* Computes logdet of every stored block after the last ACCUMULATE view. Syncs; fails
+/* Computes logdet (and trace of the inverse, when h->trinv is given) of every stored
+ * block after the last ACCUMULATE view. Syncs; fails
  * with NGS_CAPACITY (needed slots in *n_slots) if a training view overflowed. */
 ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream);
 

@@ -11,6 +11,7 @@ import os
 from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -59,7 +60,8 @@ class ngs_raster_params(C.Structure):
 class ngs_ig_params(C.Structure):
     _fields_ = [("lambda_prior", C.c_float), ("alpha_obj", C.c_float), ("alpha_opa", C.c_float),
                 ("beta_d", C.c_float), ("beta_o", C.c_float), ("target_id", C.c_int32), ("outputs", C.c_uint32),
-                ("conf_on_train", C.c_int32), ("obj_eq2", C.c_int32), ("mode", C.c_int32)]
+                ("conf_on_train", C.c_int32), ("obj_eq2", C.c_int32), ("mode", C.c_int32),
+                ("criterion", C.c_int32), ("trace_total", C.c_double * 3)]
 
 
 class ngs_projected(C.Structure):
@@ -77,7 +79,7 @@ class ngs_image(C.Structure):
 
 class ngs_hessian(C.Structure):
     _fields_ = [("k", C.c_int32), ("capacity", C.c_int32), ("slot_of", P), ("n_slots", P), ("gid_of", P),
-                ("h_rgb", P), ("h_d", P), ("h_o", P), ("logdet", P)]
+                ("h_rgb", P), ("h_d", P), ("h_o", P), ("logdet", P), ("trinv", P)]
 
 
 class ngs_image_grad(C.Structure):
@@ -189,9 +191,10 @@ def raster_params(tile=16, z_near=0.05, eps2d=0.3, cutoff_q=9.0, alpha_min=1.0 /
 
 
 def ig_params(lambda_prior=0.1, alpha_obj=0.3, alpha_opa=0.3, beta_d=10.0, beta_o=1.0, target_id=-1,
-              outputs=7, conf_on_train=1, obj_eq2=1, mode=MODE_SCORE) -> ngs_ig_params:
+              outputs=7, conf_on_train=1, obj_eq2=1, mode=MODE_SCORE, criterion=0) -> ngs_ig_params:
+    """criterion: 0 = log det (Eq. 6), 1 = trace(H^-1)^-1 (trace_total is filled by NbvScorer.setup)."""
     return ngs_ig_params(lambda_prior, alpha_obj, alpha_opa, beta_d, beta_o, target_id, outputs, conf_on_train,
-                         obj_eq2, mode)
+                         obj_eq2, mode, criterion, (C.c_double * 3)(0.0, 0.0, 0.0))
 
 
 def camera(cam) -> ngs_camera:
@@ -288,10 +291,11 @@ class Hessian:
         self.h_d = torch.zeros((cap, 66), dtype=torch.float64, device=device)
         self.h_o = torch.zeros((cap, 68 + 12 * k), dtype=torch.float64, device=device)
         self.logdet = torch.zeros((3, cap), dtype=torch.float64, device=device)
+        self.trinv = torch.zeros((3, cap), dtype=torch.float64, device=device)
 
     def c(self) -> ngs_hessian:
         return ngs_hessian(self.k, self.capacity, _p(self.slot_of), _p(self.n_slots), _p(self.gid_of),
-                           _p(self.h_rgb), _p(self.h_d), _p(self.h_o), _p(self.logdet))
+                           _p(self.h_rgb), _p(self.h_d), _p(self.h_o), _p(self.logdet), _p(self.trinv))
 
 
 def workspace_size(op: int, n: int, k: int, width: int = 0, height: int = 0, max_pairs: int = 0,
@@ -743,7 +747,19 @@ class NbvScorer:
             proj, lists = self._view(cam)
             gains.append(ngs_info_gain(self.ctx, self.scene, proj, lists, cam, self.rp, sc, self.h, self.igws))
         self.ig_train = torch.stack(gains).cpu().numpy()
-        self.norm = self.ig_train.mean(axis=0)
+        if self.ig.criterion == 1:
+            # S_f = sum over all Gaussians of trace(H_T,g^-1): stored slots from the store, the
+            # rest carry the prior lambda I; the normalisers average f(T + t) - f(T) = R/(S(S - R))
+            used = min(int(self.h.n_slots.item()), self.h.capacity)
+            lam = float(np.float32(self.ig.lambda_prior))
+            dims = np.array([14.0, 11.0, 11.0 + self.scene.k])
+            st = self.h.trinv[:, :used].sum(dim=1).cpu().numpy() + (self.scene.n - used) * dims / lam
+            self.ig.trace_total = (C.c_double * 3)(*[float(x) for x in st])
+            self.trace_total = st
+            conv = self.ig_train / (st * (st - self.ig_train))
+            self.norm = conv.mean(axis=0)
+        else:
+            self.norm = self.ig_train.mean(axis=0)
         return self.norm
 
     def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None, scaled: bool = True):

@@ -74,6 +74,7 @@ ngs_status check_ig(const ngs_ig_params* ig) {
   if (!ig) return NGS_INVALID_ARG;
   if (!(ig->lambda_prior > 0.f) || ig->outputs == 0u || (ig->outputs & ~7u)) return NGS_INVALID_ARG;
   if (ig->mode != NGS_MODE_SCORE && ig->mode != NGS_MODE_ACCUMULATE) return NGS_INVALID_ARG;
+  if (ig->criterion != 0 && ig->criterion != 1) return NGS_INVALID_ARG;
   return NGS_OK;
 }
 
@@ -368,6 +369,7 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
     return NGS_INVALID_ARG;
   if (ig->mode == NGS_MODE_SCORE && !ig_out) return NGS_INVALID_ARG;
   if (h && (h->k != scene->k || (h->capacity > 0 && !h->logdet))) return NGS_INVALID_ARG;
+  if (ig->criterion == 1 && ig->mode == NGS_MODE_SCORE && h && h->capacity > 0 && !h->trinv) return NGS_INVALID_ARG;
   if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
   if (!ws) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
@@ -405,6 +407,11 @@ ngs_status check_batch(const ngs_scene* scene, ngs_hessian* h, const ngs_camera*
   if (s != NGS_OK) return s;
   if (ig->mode != NGS_MODE_SCORE) return NGS_INVALID_ARG;
   if (h && h->k != scene->k) return NGS_INVALID_ARG;
+  if (ig->criterion == 1) {
+    if (h && h->capacity > 0 && !h->trinv) return NGS_INVALID_ARG;
+    for (int f = 0; f < 3; ++f)
+      if (((ig->outputs >> f) & 1u) && !(ig->trace_total[f] > 0.0)) return NGS_INVALID_ARG;
+  }
   for (int v = 0; v < n_views; ++v) {
     s = check_cam(&cams[v], rp);
     if (s != NGS_OK) return s;
@@ -468,8 +475,7 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
   }
   const double n0 = nf_host ? nf_host[0] : 1.0, n1 = nf_host ? nf_host[1] : 1.0, n2 = nf_host ? nf_host[2] : 1.0;
-  NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, n0, n1, n2, nf_dev, ig->beta_d, ig->beta_o, ig->outputs,
-                                        scores, best, st));
+  NGS_TRY_HIP(ctx, launch_score_combine(ig_raw, n_views, n0, n1, n2, nf_dev, *ig, scores, best, st));
   return NGS_OK;
 }
 

@@ -216,7 +216,7 @@ hipError_t sur_novelty(const ngs_scene& s, const ngs_hessian* h, float lambda, f
 hipError_t sur_features(const ngs_image& img, int W, int H, int k, float depth_scale, float* x, int B, int index,
                         int views, size_t set_stride, hipStream_t st);
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
-                                const double* nf_dev, float beta_d, float beta_o, uint32_t outputs, float* scores,
-                                int32_t* best, hipStream_t st);
+                                const double* nf_dev, const ngs_ig_params& ig, float* scores, int32_t* best,
+                                hipStream_t st);
 
 }  // namespace ngs

@@ -148,7 +148,57 @@ __device__ void block_sum4(FinShared& S, double (&v)[4]) {
 
 // log det of the object block held as (G, E, tau) with p = S.p (see the file header).
 // G (11 x 11, full) and E (11 x k) are in S; tau > 0.
-__device__ double object_logdet(FinShared& S, int k, double lambda, double tau) {
+// trace(A^-1 K) for the packed upper triangle A of an SPD l x l matrix (l <= 14) and K (l x l
+// row-major, NULL = identity): Cholesky A = L L^T into work, then per column of K a forward
+// and a back substitution; thread 0 computes in FP64, every thread returns the value.
+// work holds l * l + 1 doubles.
+static_assert(NGS_MAX_K * kNGeo >= 2 * kNGeo * kNGeo + 1 && NGS_MAX_K * kNGeo >= 14 * 14 + 1,
+              "S.F doubles as the scratch of trace_inv_prod");
+__device__ double trace_inv_prod(const double* A, int l, const double* K, double* work) {
+  if (threadIdx.x == 0) {
+    double* L = work;
+    bool bad = false;
+    for (int j = 0; j < l && !bad; ++j) {
+      double d = A[tri_idx(j, j, l)];
+      for (int q = 0; q < j; ++q) d -= L[j * l + q] * L[j * l + q];
+      if (!(d > 0.0)) { bad = true; break; }
+      const double ljj = sqrt(d);
+      L[j * l + j] = ljj;
+      for (int i = j + 1; i < l; ++i) {
+        double v = A[tri_idx(j, i, l)];
+        for (int q = 0; q < j; ++q) v -= L[i * l + q] * L[j * l + q];
+        L[i * l + j] = v / ljj;
+      }
+    }
+    double tr = 0.0;
+    if (!bad) {
+      double y[kSmallL];
+      for (int c = 0; c < l; ++c) {
+        for (int i = 0; i < l; ++i) {
+          double v = K ? K[i * l + c] : (i == c ? 1.0 : 0.0);
+          for (int q = 0; q < i; ++q) v -= L[i * l + q] * y[q];
+          y[i] = v / L[i * l + i];
+        }
+        for (int i = l - 1; i >= 0; --i) {
+          double v = y[i];
+          for (int q = i + 1; q < l; ++q) v -= L[q * l + i] * y[q];
+          y[i] = v / L[i * l + i];
+        }
+        tr += y[c];
+      }
+    }
+    work[l * l] = bad ? __builtin_nan("") : tr;
+  }
+  __syncthreads();
+  const double r = work[l * l];
+  __syncthreads();
+  return r;
+}
+
+// The object block [[G, E S], [S E^T, D]], D = lambda I + tau S S, reduced to its Schur
+// complement: fills S.X = D^-1 F (F = S E^T) and S.A = G - F^T X (packed, 11 x 11), and
+// returns logdet D in *ld_d and, when trd is given, trace(D^-1) in *trd (Woodbury).
+__device__ void object_schur(FinShared& S, int k, double lambda, double tau, double* ld_d, double* trd) {
   // F = S E^T (k x 11): F[c][r] = p_c (E[r][c] - (E p)_r)
   for (int r = threadIdx.x; r < kNGeo; r += kFinThreads) {
     double v = 0.0;
@@ -177,11 +227,28 @@ __device__ double object_logdet(FinShared& S, int k, double lambda, double tau) 
   block_sum4(S, acc);
   block_sum4(S, zs);
   const double z00 = acc[0], z01 = acc[1], z11 = acc[2], sp = acc[3];
+  // trace(D^-1) = sum Delta^-1 - trace(W Y), W = B^-1 tau C, Y = U^T Delta^-2 U
+  double ty[4] = {0.0, 0.0, 0.0, 0.0};
+  if (trd) {
+    for (int c = threadIdx.x; c < k; c += kFinThreads) {
+      const double pc = S.p[c], p2 = pc * pc, di = S.dinv[c], di2 = di * di;
+      ty[0] += di;
+      ty[1] += p2 * di2;
+      ty[2] += p2 * pc * di2;
+      ty[3] += p2 * p2 * di2;
+    }
+    block_sum4(S, ty);
+  }
   // B = I + tau C Z
   const double b00 = 1.0 + tau * (sp * z00 - z01), b01 = tau * (sp * z01 - z11);
   const double b10 = -tau * z00, b11 = 1.0 - tau * z01;
   const double detb = b00 * b11 - b01 * b10;
-  const double ld_d = zs[0] + log(detb);
+  *ld_d = zs[0] + log(detb);
+  if (trd) {
+    const double w00 = tau * (b11 * sp + b01) / detb, w01 = -tau * b11 / detb;
+    const double w10 = -tau * (b10 * sp + b00) / detb, w11 = tau * b10 / detb;
+    *trd = ty[0] - (w00 * ty[1] + (w01 + w10) * ty[2] + w11 * ty[3]);
+  }
   // V = U^T Delta^-1 F (2 x 11); W = B^-1 tau C V; X = Delta^-1 (F - U W)
   for (int e = threadIdx.x; e < 2 * kNGeo; e += kFinThreads) {
     const int q = e / kNGeo, r = e % kNGeo;
@@ -215,7 +282,26 @@ __device__ double object_logdet(FinShared& S, int k, double lambda, double tau) 
     S.A[tri_idx(r, q, kNGeo)] = v;
   }
   __syncthreads();
+}
+
+__device__ double object_logdet(FinShared& S, int k, double lambda, double tau) {
+  double ld_d;
+  object_schur(S, k, lambda, tau, &ld_d, nullptr);
   return ld_d + ldl_logdet<kSmallL>(S.A, kNGeo, S.row);
+}
+
+// trace of the object block's inverse from its Schur complement Sigma (in S.A after
+// object_schur): trace(M^-1) = trace(D^-1) + trace(Sigma^-1 (I + X^T X)). Uses S.F as scratch.
+__device__ double object_trinv_after_schur(FinShared& S, int k, double trd) {
+  double* K = &S.F[0][0];
+  for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
+    const int r = e / kNGeo, q = e % kNGeo;
+    double v = r == q ? 1.0 : 0.0;
+    for (int c = 0; c < k; ++c) v += S.X[c][r] * S.X[c][q];
+    K[e] = v;
+  }
+  __syncthreads();
+  return trd + trace_inv_prod(S.A, kNGeo, K, K + kNGeo * kNGeo);
 }
 
 __device__ __forceinline__ int block_dim(int f) { return f == 0 ? 14 : kNGeo; }
@@ -224,7 +310,8 @@ __device__ __forceinline__ int store_len(int f, int k) { return f == 0 ? 105 : (
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
     const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
-    uint32_t outputs, int mode, int conf_on_train, const float* __restrict__ acc, int astride, int max_slots,
+    uint32_t outputs, int mode, int conf_on_train, int criterion, const float* __restrict__ acc, int astride,
+    int max_slots,
     const int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots, const int32_t* __restrict__ overflow,
     ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
   __shared__ FinShared S;
@@ -303,7 +390,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
           for (int e = threadIdx.x; e < tl; e += kFinThreads) hblk[e] = S.A[e];
           continue;
         }
-        ld_m = ldl_logdet<kSmallL>(S.A, l, S.row);
+        ld_m = criterion == 1 ? trace_inv_prod(S.A, l, nullptr, &S.F[0][0]) : ldl_logdet<kSmallL>(S.A, l, S.row);
       } else {
         // ---- object block as (G, E, tau) ----
         load_sym(S, kStatYo, 6);
@@ -347,12 +434,24 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
             for (int c = threadIdx.x; c < k; c += kFinThreads) hblk[kObjE + kNGeo * k + c] = S.p[c];
           continue;
         }
-        ld_m = object_logdet(S, k, lambda, S.tau);
+        if (criterion == 1) {
+          double ld_d, trd;
+          object_schur(S, k, lambda, S.tau, &ld_d, &trd);
+          ld_m = object_trinv_after_schur(S, k, trd);
+        } else {
+          ld_m = object_logdet(S, k, lambda, S.tau);
+        }
       }
-      // ---- SCORE: gain = logdet M - logdet H_T ----
+      // ---- SCORE: gain = logdet M - logdet H_T, or (trace criterion) the reduction of the
+      // covariance trace, trace(H_T^-1) - trace(M^-1) ----
       const int l = f == 2 ? kNGeo + k : block_dim(f);
-      const double ld_h = hs >= 0 ? h.logdet[(size_t)f * h.capacity + hs] : (double)l * log(lambda);
-      if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], ld_m - ld_h);
+      if (criterion == 1) {
+        const double tr_h = hs >= 0 ? h.trinv[(size_t)f * h.capacity + hs] : (double)l / lambda;
+        if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], tr_h - ld_m);
+      } else {
+        const double ld_h = hs >= 0 ? h.logdet[(size_t)f * h.capacity + hs] : (double)l * log(lambda);
+        if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], ld_m - ld_h);
+      }
     }
   }
 }
@@ -371,6 +470,10 @@ __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, i
         for (int e = threadIdx.x; e < tri_len(block_dim(f)); e += kFinThreads) S.A[e] = hblk[e];
         __syncthreads();
         ld = ldl_logdet<kSmallL>(S.A, block_dim(f), S.row);
+        if (h.trinv) {
+          const double tr = trace_inv_prod(S.A, block_dim(f), nullptr, &S.F[0][0]);
+          if (threadIdx.x == 0) h.trinv[(size_t)f * h.capacity + slot] = tr;
+        }
       } else {
         for (int e = threadIdx.x; e < kNGeo * kNGeo; e += kFinThreads) {
           const int i = e / kNGeo, c = e % kNGeo;
@@ -379,7 +482,13 @@ __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, i
         for (int e = threadIdx.x; e < kNGeo * k; e += kFinThreads) S.E[e / k][e % k] = hblk[kObjE + e];
         for (int c = threadIdx.x; c < k; c += kFinThreads) S.p[c] = hblk[kObjE + kNGeo * k + c];
         __syncthreads();
-        ld = object_logdet(S, k, hblk[kObjLam], hblk[kObjTau]);
+        double ld_d, trd;
+        object_schur(S, k, hblk[kObjLam], hblk[kObjTau], &ld_d, h.trinv ? &trd : nullptr);
+        ld = ld_d + ldl_logdet<kSmallL>(S.A, kNGeo, S.row);
+        if (h.trinv) {
+          const double tr = object_trinv_after_schur(S, k, trd);
+          if (threadIdx.x == 0) h.trinv[(size_t)f * h.capacity + slot] = tr;
+        }
       }
       if (threadIdx.x == 0) h.logdet[(size_t)f * h.capacity + slot] = ld;
     }
@@ -388,20 +497,25 @@ __global__ __launch_bounds__(kFinThreads) void k_hessian_logdet(ngs_hessian h, i
 
 // Eq. 10 normalisation, Eq. 11 combination and the argmax of Eq. 5 (lowest index on ties).
 // The normalisers come from nf_dev (device, three doubles) when it is given, else by value.
+// With the trace criterion the raw values are covariance-trace reductions R, turned into the
+// set function's difference 1 / (S - R) - 1 / S = R / (S (S - R)) with the training totals S.
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ ig_raw, int nv, double n0, double n1,
                                                  double n2, const double* __restrict__ nf_dev, double bd, double bo,
-                                                 uint32_t outputs, float* __restrict__ scores,
-                                                 int32_t* __restrict__ best) {
+                                                 uint32_t outputs, int criterion, double st0, double st1, double st2,
+                                                 float* __restrict__ scores, int32_t* __restrict__ best) {
   __shared__ double sv[256];
   __shared__ int si[256];
   double bv = -INFINITY;
   int bi = -1;
   const double nf[3] = {nf_dev ? nf_dev[0] : n0, nf_dev ? nf_dev[1] : n1, nf_dev ? nf_dev[2] : n2};
   const double beta[3] = {1.0, bd, bo};
+  const double st[3] = {st0, st1, st2};
   for (int v = threadIdx.x; v < nv; v += 256) {
     double tot = 0.0;
     for (int f = 0; f < 3; ++f) {
-      const double s = ((outputs >> f) & 1u) ? ig_raw[3 * v + f] / nf[f] : 0.0;
+      const double r = ig_raw[3 * v + f];
+      const double g = criterion == 1 ? r / (st[f] * (st[f] - r)) : r;
+      const double s = ((outputs >> f) & 1u) ? g / nf[f] : 0.0;
       scores[4 * v + f] = (float)s;
       tot += beta[f] * s;
     }
@@ -436,7 +550,7 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
   ProfScope ps(kProfIgFinalize, st);
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
                      s.prob, cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
-                     w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats,
+                     ig.criterion, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats,
                      sticky);
   return hipGetLastError();
 }
@@ -451,11 +565,12 @@ hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_p
 }
 
 hipError_t launch_score_combine(const double* ig_raw, int n_views, double n0, double n1, double n2,
-                                const double* nf_dev, float beta_d, float beta_o, uint32_t outputs, float* scores,
-                                int32_t* best, hipStream_t st) {
+                                const double* nf_dev, const ngs_ig_params& ig, float* scores, int32_t* best,
+                                hipStream_t st) {
   ProfScope ps(kProfCombine, st);
-  hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st, ig_raw, n_views, n0, n1, n2, nf_dev, (double)beta_d,
-                     (double)beta_o, outputs, scores, best);
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(256), 0, st, ig_raw, n_views, n0, n1, n2, nf_dev, (double)ig.beta_d,
+                     (double)ig.beta_o, ig.outputs, ig.criterion, ig.trace_total[0], ig.trace_total[1],
+                     ig.trace_total[2], scores, best);
   return hipGetLastError();
 }
 

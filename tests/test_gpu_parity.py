@@ -333,3 +333,36 @@ def test_tuning_rejects_shapes_the_width_does_not_allow(B, ctx):
             scorer.setup([B.camera(cam)])
     finally:
         B.ngs_set_tuning(ctx, 0)
+
+
+@pytest.mark.parametrize("wl,target", [("tiny", -1), ("tiny", 3), ("k64", -1)])
+def test_trace_criterion_matches_oracle(B, ctx, wl, target):
+    """The trace-based f of Sec. III-B (criterion 1): training totals S, the raw covariance-
+    trace reductions, the Eq. 10 normalisers of the converted gains, the scores and the argmax
+    against the oracle. k64 takes the factored object block at k = 64."""
+    log(f"test_trace_criterion {wl} target {target}")
+    if wl == "tiny":
+        cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    else:
+        scene = scenegen.make_scene(3000, 8, 64, seed=23)
+        cfg = scenegen.SceneConfig("k64", 3000, 8, 64, 4, ((128, 96, 4),), 500.0, (0.6, 0.6))
+        cands, train = scenegen.make_cameras(cfg, 23)
+    cands = cands[:5]
+    ds = B.DeviceScene(scene, "cuda")
+    ig = B.ig_params(target_id=target, criterion=1)
+    ref = oracle.score(scene, train, cands, ig=oracle.IGParams(target_id=target, criterion=1))
+    assert ref.status == 0
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=1 << 18, max_slots=1 << 14,
+                         store_capacity=1 << 14)
+    norm = scorer.setup([B.camera(c) for c in train])
+    assert np.allclose(scorer.trace_total, ref.trace_total, rtol=1e-6)
+    for t in range(len(train)):
+        check_gain(scorer.ig_train[t], ref.ig_train[t], f"training view {t}")
+    check_gain(norm, ref.norm, "normalisers")
+    scores, best, raw = scorer.score([B.camera(c) for c in cands])
+    for v in range(len(cands)):
+        check_gain(raw[v].cpu().numpy(), ref.ig_cand[v], f"candidate {v}")
+    assert np.allclose(scores.cpu().numpy().astype(np.float64), ref.scores, rtol=2e-3)
+    top = np.sort(ref.scores[:, 3])
+    if (top[-1] - top[-2]) / abs(top[-1]) > 1e-3:
+        assert int(best.item()) == ref.best
