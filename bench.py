@@ -242,7 +242,7 @@ def run_surrogate(args):
     ag = SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:],
                       rescore=args.sur_rescore)
     ag_budget = {r: SG.agreement(pred.cpu().numpy(), y[ntr:].cpu().numpy(), np.concatenate(scene_of)[ntr:],
-                                 rescore=r).__dict__ for r in (32, 64, 128, 256)}
+                                 rescore=r).__dict__ for r in (32, 64, 128, 256, 512)}
     if args.sur_dump:
         np.savez(args.sur_dump, pred=pred.cpu().numpy(), exact=y[ntr:].cpu().numpy(),
                  scene=np.concatenate(scene_of)[ntr:], raw=torch.cat(raws)[ntr:].cpu().numpy())
@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--sur-scenes", type=int, default=24, help="training scenes (2048 views each)")
     ap.add_argument("--sur-test-scenes", type=int, default=8)
     ap.add_argument("--sur-epochs", type=int, default=20)
-    ap.add_argument("--sur-rescore", type=int, default=128,
+    ap.add_argument("--sur-rescore", type=int, default=256,
                     help="candidates (of each scene's 2048) the exact scorer re-scores")
     ap.add_argument("--sur-dump", default="", help="write held-out predictions and exact scores (.npz)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

@@ -84,9 +84,10 @@ ngs_status ngs_sur_novelty(ngs_ctx* ctx, const ngs_scene* scene, const ngs_hessi
  * binning and compositing (as ngs_project, ngs_bin_sort, ngs_render) and the four input
  * channels into x [4][n_views][60][80] (as ngs_sur_features, depth / depth_scale). With
  * weight (device [n], may be NULL) the fourth channel averages weight[g] along each ray
- * where ngs_render averages kappa (e.g. the output of ngs_sur_novelty). Views run
- * dims->views_in_flight at a time on the context's streams, like ngs_score_batch; no host
- * synchronisation except one at the end. The scene must be prepared. ws:
+ * where ngs_render averages kappa (e.g. the output of ngs_sur_novelty). Views go in groups
+ * of dims->views_in_flight (default 8, at most 32): each view of a group is projected and
+ * binned on its own context stream, then one render launch composites the whole group; no
+ * host synchronisation except one at the end. The scene must be prepared. ws:
  * ngs_workspace_size(4, dims) bytes. NGS_CAPACITY if a view has more pairs than
  * dims->max_pairs. */
 ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,

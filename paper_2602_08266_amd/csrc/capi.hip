@@ -133,9 +133,10 @@ size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
 
 constexpr int kDefaultInFlight = 8;
 constexpr int kMaxInFlight = 16;
+constexpr int kMaxFeatureGroup = 32;  // views per grouped render launch of the feature maps
 
-int views_in_flight(const ngs_dims* d) {
-  return d->views_in_flight <= 0 ? kDefaultInFlight : (int)std::min<int64_t>(d->views_in_flight, kMaxInFlight);
+int views_in_flight(const ngs_dims* d, int cap = kMaxInFlight) {
+  return d->views_in_flight <= 0 ? kDefaultInFlight : (int)std::min<int64_t>(d->views_in_flight, cap);
 }
 
 // Creates the context's in-flight streams and events up to `want`.
@@ -263,8 +264,9 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
     case 1: *bytes = igb; return NGS_OK;
     case 2: *bytes = (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) + igb); return NGS_OK;
     case 3: *bytes = bwd_ws_bytes(d->n, d->k); return NGS_OK;
-    case 4: *bytes = kIgHeader + 2 * (size_t)views_in_flight(d) * al(batch_fixed_bytes(d->n, d->max_pairs) +
-                                                                       feat_img_bytes());
+    case 4:
+      *bytes = kIgHeader + 2 * (size_t)views_in_flight(d, kMaxFeatureGroup) *
+                               al(batch_fixed_bytes(d->n, d->max_pairs) + feat_img_bytes());
       return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
@@ -750,12 +752,12 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
   // stream, then one render launch composites the whole group (grid.y = view) and one launch
   // writes its feature channels, both on `stream`. Groups alternate between two halves of
   // the buffer sets, so binning of the next group overlaps the render of this one.
-  const int G = std::max(1, std::min(views_in_flight(dims), n_views));
+  const int G = std::max(1, std::min(views_in_flight(dims, kMaxFeatureGroup), n_views));
   s = ensure_lanes(ctx, G);
   if (s != NGS_OK) return s;
   int32_t* sticky = static_cast<int32_t*>(ws);
   NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, kIgHeader, st));
-  const size_t per = (need - kIgHeader) / (2 * (size_t)views_in_flight(dims));
+  const size_t per = (need - kIgHeader) / (2 * (size_t)views_in_flight(dims, kMaxFeatureGroup));
   char* base = static_cast<char*>(ws) + kIgHeader;
   const size_t fixed = al(batch_fixed_bytes(scene->n, dims->max_pairs));
   NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));

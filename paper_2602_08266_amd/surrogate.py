@@ -34,7 +34,7 @@ class SceneSamples:
 
 
 def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views_in_flight: int = 4,
-                  max_pairs: int = 1 << 23, rescore: int = 32, feature_in_flight: int = 16) -> SceneSamples:
+                  max_pairs: int = 1 << 23, rescore: int = 32, feature_in_flight: int = 32) -> SceneSamples:
     """Feature maps and exact scores of every candidate of one scene."""
     ds = B.DeviceScene(scene, "cuda")
     rp = B.raster_params()
