@@ -18,9 +18,13 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
+from . import autotune as AT
 from . import binding as B
 
 DEPTH_SCALE = 0.6  # m: candidate radius of the surrogate workload
+
+# launch shapes of the exact scorer, tuned once per process and scene size / resolution
+_TUNED = {}
 
 
 @dataclass
@@ -33,7 +37,7 @@ class SceneSamples:
     seconds_rescore: float  # exact scoring of `rescore` of the candidates in one batch
 
 
-def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views_in_flight: int = 4,
+def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views_in_flight: int = 8,
                   max_pairs: int = 1 << 23, rescore: int = 32, feature_in_flight: int = 32) -> SceneSamples:
     """Feature maps and exact scores of every candidate of one scene."""
     ds = B.DeviceScene(scene, "cuda")
@@ -44,6 +48,11 @@ def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views
     scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=max_pairs, max_slots=max(scene.n, 1 << 16),
                          store_capacity=max(scene.n, 1 << 16), views_in_flight=views_in_flight)
     scorer.setup([B.camera(c) for c in train])
+    key = (scene.n, scene.k, cams[0].width, cams[0].height)
+    if key not in _TUNED:
+        _TUNED[key] = AT.tune_score(ctx, scorer, cams, sample=64, vif=(8, 12, 16))
+    else:
+        AT.apply(ctx, scorer, _TUNED[key])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     scores, best, raw = scorer.score(cams)
