@@ -181,6 +181,7 @@ struct IgWs {
   int32_t* gid_of;      // [max_slots]
   int32_t* n_slots;     // [1]
   int32_t* overflow;    // [1]
+  double* pmat;         // [max_slots][7][11] chain-rule matrix P of each slot (finalize)
   int64_t max_slots;
 };
 int ig_stat_stride(int64_t k);

@@ -307,13 +307,36 @@ __device__ double object_trinv_after_schur(FinShared& S, int k, double trd) {
 __device__ __forceinline__ int block_dim(int f) { return f == 0 ? 14 : kNGeo; }
 __device__ __forceinline__ int store_len(int f, int k) { return f == 0 ? 105 : (f == 1 ? 66 : kObjE + 12 * k); }
 
+// The chain-rule matrix P (d(m, Q, l, Z)/d theta, FP64) of every slot with statistics, one
+// thread per slot, into the workspace: the straight-line FP64 code would otherwise set the
+// register budget of the whole finalize kernel.
+__global__ __launch_bounds__(64) void k_fin_chain(int n, const float* __restrict__ mean,
+                                                  const float* __restrict__ log_scale, const float* __restrict__ rot,
+                                                  DevCam cam, double eps2d, const float* __restrict__ acc, int astride,
+                                                  int max_slots, const int32_t* __restrict__ gid_of,
+                                                  const int32_t* __restrict__ n_slots, double* __restrict__ pmat) {
+  const int used = min(*n_slots, max_slots);
+  for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < used; slot += gridDim.x * blockDim.x) {
+    const float a2f = acc[(size_t)slot * astride + kStatYd + tri_idx(6, 6, 7)];
+    if (!(a2f > 0.f)) continue;
+    double P[7][kNGeo];
+    chain_rule(mean, log_scale, rot, n, gid_of[slot], cam, eps2d, P);
+    double* dst = pmat + (size_t)slot * 7 * kNGeo;
+    for (int i = 0; i < 7; ++i)
+      for (int j = 0; j < kNGeo; ++j) dst[i * kNGeo + j] = P[i][j];
+  }
+}
+
+// TRACE: the trace criterion (reductions of trace(H^-1)); else log-det gains.
+template <bool TRACE>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
     const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
     uint32_t outputs, int mode, int conf_on_train, int criterion, const float* __restrict__ acc, int astride,
     int max_slots,
     const int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots, const int32_t* __restrict__ overflow,
-    ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky) {
+    ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky,
+    const double* __restrict__ pmat) {
   __shared__ FinShared S;
   const int used = min(*n_slots, max_slots);
   if (blockIdx.x == 0 && threadIdx.x == 0 && *overflow) {
@@ -331,9 +354,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     for (int s = threadIdx.x; s < nst; s += kFinThreads) S.st[s] = (double)acc[(size_t)slot * astride + s];
     __syncthreads();
     const double a2 = S.st[kStatYd + tri_idx(6, 6, 7)];
+    for (int e = threadIdx.x; e < 7 * kNGeo; e += kFinThreads) S.P[e / kNGeo][e % kNGeo] = pmat[(size_t)slot * 7 * kNGeo + e];
     if (threadIdx.x == 0) {
       if (stats) atomicAdd((unsigned long long*)&stats[2], 1ull);
-      chain_rule(mean, log_scale, rot, n, g, cam, eps2d, S.P);
       S.hs = has_h ? h.slot_of[g] : -1;
       S.hs_new = 0;
     }
@@ -390,7 +413,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
           for (int e = threadIdx.x; e < tl; e += kFinThreads) hblk[e] = S.A[e];
           continue;
         }
-        ld_m = criterion == 1 ? trace_inv_prod(S.A, l, nullptr, &S.F[0][0]) : ldl_logdet<kSmallL>(S.A, l, S.row);
+        if constexpr (TRACE) ld_m = trace_inv_prod(S.A, l, nullptr, &S.F[0][0]);
+        else ld_m = ldl_logdet<kSmallL>(S.A, l, S.row);
       } else {
         // ---- object block as (G, E, tau) ----
         load_sym(S, kStatYo, 6);
@@ -434,7 +458,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
             for (int c = threadIdx.x; c < k; c += kFinThreads) hblk[kObjE + kNGeo * k + c] = S.p[c];
           continue;
         }
-        if (criterion == 1) {
+        if constexpr (TRACE) {
           double ld_d, trd;
           object_schur(S, k, lambda, S.tau, &ld_d, &trd);
           ld_m = object_trinv_after_schur(S, k, trd);
@@ -445,7 +469,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       // ---- SCORE: gain = logdet M - logdet H_T, or (trace criterion) the reduction of the
       // covariance trace, trace(H_T^-1) - trace(M^-1) ----
       const int l = f == 2 ? kNGeo + k : block_dim(f);
-      if (criterion == 1) {
+      if constexpr (TRACE) {
         const double tr_h = hs >= 0 ? h.trinv[(size_t)f * h.capacity + hs] : (double)l / lambda;
         if (threadIdx.x == 0 && cg != 0.0) atomicAdd(&ig_out[f], tr_h - ld_m);
       } else {
@@ -548,10 +572,14 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
   if (h) hh = *h;
   const int blocks = (int)std::min<int64_t>(w.max_slots, 4096);
   ProfScope ps(kProfIgFinalize, st);
-  hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
-                     s.prob, cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
-                     ig.criterion, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0, ig_out, stats,
-                     sticky);
+  hipLaunchKernelGGL(k_fin_chain, dim3((unsigned)std::min<int64_t>((w.max_slots + 63) / 64, 2048)), dim3(64), 0, st,
+                     s.n, s.mean, s.log_scale, s.rot, cam, (double)rp.eps2d, w.acc, w.astride, (int)w.max_slots,
+                     w.gid_of, w.n_slots, w.pmat);
+  auto fin = ig.criterion == 1 ? k_finalize<true> : k_finalize<false>;
+  hipLaunchKernelGGL(fin, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf, s.prob,
+                     cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
+                     ig.criterion, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0,
+                     ig_out, stats, sticky, (const double*)w.pmat);
   return hipGetLastError();
 }
 

@@ -477,7 +477,7 @@ int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   return al((size_t)ig_stat_stride(k) * (size_t)max_slots * 4) + al((size_t)std::max<int64_t>(n, 1) * 4) +
-         al((size_t)max_slots * 4) + al(8);
+         al((size_t)max_slots * 4) + al(8) + al((size_t)max_slots * 7 * kNGeo * 8);
 }
 
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
@@ -488,8 +488,9 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   w.acc = (float*)p; p += al((size_t)w.astride * (size_t)max_slots * 4);
   w.slot_of = (int32_t*)p; p += al((size_t)std::max<int64_t>(n, 1) * 4);
   w.gid_of = (int32_t*)p; p += al((size_t)max_slots * 4);
-  w.n_slots = (int32_t*)p;
+  w.n_slots = (int32_t*)p; p += al(8);
   w.overflow = w.n_slots + 1;
+  w.pmat = (double*)p;
   w.max_slots = max_slots;
   return w;
 }
