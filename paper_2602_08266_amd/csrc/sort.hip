@@ -13,8 +13,8 @@ namespace {
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTileElems = kSortThreads * kSortItems;  // 4096 keys per block
+constexpr int kSortItems = 8;
+constexpr int kSortTileElems = kSortThreads * kSortItems;  // 2048 keys per block
 constexpr int kWavesPerBlock = kSortThreads / kWave;
 
 __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
                                                           const uint32_t* __restrict__ hist, size_t nblocks,
                                                           const uint32_t* __restrict__ rowtot,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  // The block's 4096 pairs are first ranked into digit order in LDS (stable), then streamed
+  // The block's 2048 pairs are first ranked into digit order in LDS (stable), then streamed
   // out: consecutive lanes write consecutive positions of each digit's run.
   __shared__ uint32_t sm[kSortThreads];
   __shared__ uint32_t gbase[kRadix];           // global position of this block's first key of digit d
