@@ -179,7 +179,9 @@ typedef struct {
 /* Per-view statistics the kernels add into (device, int64 [6], caller-zeroed):
  * [0] views, [1] pairs M, [2] Gaussians with a nonzero weight that contribute to at
  *     least one pixel U,
- * [3] contributing (pixel, Gaussian) pairs P, [4] walked (tile, entry) pairs,
+ * [3] contributing (pixel, Gaussian) pairs P, [4] walked (tile, entry) pairs, both over
+ *     the tiles the information walk visits (with a target object only the tiles that the
+ *     rect of a weighted Gaussian reaches; the others add nothing to any statistic),
  * [5] views whose slot workspace overflowed. */
 #define NGS_STATS_LEN 6
 

@@ -84,7 +84,7 @@ constexpr size_t kIgHeader = 256;
 int64_t ig_slots_for(size_t ws_bytes, int64_t n, int64_t k) {
   if (ws_bytes < kIgHeader) return 0;
   const size_t per = (size_t)ig_stat_stride(k) * 4 + 4 + 7 * kNGeo * 8;
-  const size_t fixed = al((size_t)std::max<int64_t>(n, 1) * 4) + 4 * kAlign;
+  const size_t fixed = al((size_t)std::max<int64_t>(n, 1) * 4) + al((size_t)NGS_MAX_TILES * 4) + 4 * kAlign;
   if (ws_bytes < kIgHeader + fixed) return 0;
   int64_t s = (int64_t)((ws_bytes - kIgHeader - fixed) / per);
   while (s > 0 && kIgHeader + ig_ws_bytes(n, k, s) > ws_bytes) --s;

@@ -182,6 +182,7 @@ struct IgWs {
   int32_t* n_slots;     // [1]
   int32_t* overflow;    // [1]
   double* pmat;         // [max_slots][7][11] chain-rule matrix P of each slot (finalize)
+  int32_t* tflag;       // [NGS_MAX_TILES] tiles reached by a slotted Gaussian's rect
   int64_t max_slots;
 };
 int ig_stat_stride(int64_t k);

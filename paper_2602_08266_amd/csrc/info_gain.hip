@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
     int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
-    int64_t* __restrict__ stats) {
+    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   IgShared<KP, LPP>& S = *reinterpret_cast<IgShared<KP, LPP>*>(smem_raw);
   constexpr int kThreads = kTilePix * LPP;
@@ -142,6 +142,8 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   constexpr uint64_t kH0 = LPP == 1 ? ~0ull : (LPP == 2 ? 0x5555555555555555ull : 0x1111111111111111ull);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
+  // no weighted Gaussian reaches this tile: nothing of it enters a statistic
+  if (tflag && tflag[tile] == 0) return;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int pix = threadIdx.x / LPP, h = threadIdx.x % LPP;  // pixel, and part of its channels
   const int px = tx * kTile + (pix & (kTile - 1));
@@ -389,21 +391,29 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   }
 }
 
-__global__ void k_ig_clear(int32_t* n_slots, int32_t* overflow) {
-  *n_slots = 0;
-  *overflow = 0;
+__global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots, int32_t* overflow, int32_t* tflag, int ntiles) {
+  if (threadIdx.x == 0) {
+    *n_slots = 0;
+    *overflow = 0;
+  }
+  if (tflag)
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) tflag[i] = 0;
 }
 
 // Slot of every Gaussian for this view: a fresh slot for each one that has a nonzero
 // confidence weight and reaches a tile, -1 otherwise. Each 256-thread block covers
 // kAssignPer x 256 Gaussians (coalesced), ranks its selected ones with a block scan and
-// takes its slots with a single counter update.
+// takes its slots with a single counter update. With tflag, every slotted Gaussian also marks
+// the tiles of its rect, so that the tile kernel can leave the other tiles at once; the cost
+// is the rect areas of the slotted Gaussians, small when only one object carries weight.
 constexpr int kAssignPer = 16;
 
 __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restrict__ conf,
                                                    const uint32_t* __restrict__ count, int32_t* __restrict__ slot_of,
                                                    int32_t* __restrict__ gid_of, int32_t* __restrict__ n_slots,
-                                                   int32_t* __restrict__ overflow, int max_slots) {
+                                                   int32_t* __restrict__ overflow, int max_slots,
+                                                   const int16_t* __restrict__ rect, int32_t* __restrict__ tflag,
+                                                   int tiles_x, int tiles_y) {
   __shared__ int wsum[256 / kWave];
   __shared__ int base_sh;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -431,6 +441,7 @@ __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restric
   __syncthreads();
   int slot = base_sh + x - c;
   for (int w = 0; w < wave; ++w) slot += wsum[w];
+  uint32_t slotted = 0u;
 #pragma unroll
   for (int i = 0; i < kAssignPer; ++i) {
     const int g = g0 + i * 256;
@@ -441,10 +452,27 @@ __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restric
       slot_of[g] = slot;
       gid_of[slot] = g;
       ++slot;
+      slotted |= 1u << i;
     } else {
       slot_of[g] = -1;
       atomicOr(overflow, 1);
       ++slot;
+    }
+  }
+  if (!tflag) return;
+  // the wavefront marks the rects of its slotted Gaussians together, one Gaussian at a time
+  for (int i = 0; i < kAssignPer; ++i) {
+    uint64_t m = __ballot((slotted >> i) & 1u);
+    while (m) {
+      const int j = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int g = blockIdx.x * (256 * kAssignPer) + wave * kWave + j + i * 256;
+      const short4 r = *reinterpret_cast<const short4*>(rect + 4 * (size_t)g);
+      const int x0 = max((int)r.x, 0), y0 = max((int)r.y, 0);
+      const int x1 = min((int)r.z, tiles_x - 1), y1 = min((int)r.w, tiles_y - 1);
+      if (x1 < x0 || y1 < y0) continue;
+      const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
+      for (int t = lane; t < area; t += kWave) tflag[(y0 + t / w) * tiles_x + x0 + t % w] = 1;
     }
   }
 }
@@ -459,14 +487,15 @@ __global__ __launch_bounds__(256) void k_ig_zero(float4* __restrict__ acc, const
 
 template <int KP, int LPP>
 hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
-                       const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, hipStream_t st) {
+                       const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, const int32_t* tflag, int64_t* stats,
+                       hipStream_t st) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const size_t shm = sizeof(IgShared<KP, LPP>);
   static_assert(sizeof(IgShared<KP, LPP>) <= 65536, "IG kernel LDS");
   ProfScope ps(kProfIgTiles, st);
   hipLaunchKernelGGL((k_ig_tile<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
-                     stats);
+                     stats, tflag);
   return hipGetLastError();
 }
 
@@ -477,7 +506,7 @@ int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   return al((size_t)ig_stat_stride(k) * (size_t)max_slots * 4) + al((size_t)std::max<int64_t>(n, 1) * 4) +
-         al((size_t)max_slots * 4) + al(8) + al((size_t)max_slots * 7 * kNGeo * 8);
+         al((size_t)max_slots * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al((size_t)max_slots * 7 * kNGeo * 8);
 }
 
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
@@ -490,6 +519,7 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   w.gid_of = (int32_t*)p; p += al((size_t)max_slots * 4);
   w.n_slots = (int32_t*)p; p += al(8);
   w.overflow = w.n_slots + 1;
+  w.tflag = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * 4);
   w.pmat = (double*)p;
   w.max_slots = max_slots;
   return w;
@@ -498,33 +528,37 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                            hipStream_t st) {
+  // Tile flags only pay when few Gaussians carry weight (one target object, Eq. 12); with
+  // whole-scene confidence nearly every tile holds a weighted Gaussian.
+  int32_t* tflag = ig.target_id >= 0 ? w.tflag : nullptr;
+  const int ntiles = cam.tiles_x * cam.tiles_y;
   {
     ProfScope ps(kProfFill, st);
-    hipLaunchKernelGGL(k_ig_clear, dim3(1), dim3(1), 0, st, w.n_slots, w.overflow);
+    hipLaunchKernelGGL(k_ig_clear, dim3(1), dim3(256), 0, st, w.n_slots, w.overflow, tflag, ntiles);
   }
   {
     ProfScope ps(kProfIgAssign, st);
     const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
     hipLaunchKernelGGL(k_ig_assign, dim3(nb), dim3(256), 0, st, s.n, s.conf, p.count, w.slot_of, w.gid_of,
-                       w.n_slots, w.overflow, (int)w.max_slots);
+                       w.n_slots, w.overflow, (int)w.max_slots, p.rect, tflag, cam.tiles_x, cam.tiles_y);
     hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
                        (int)w.max_slots, w.astride);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // lanes per pixel (ig_lpp_valid): 0 picks the default of each object-vector width
-  if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, stats, st)
-                                : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 8) return lpp == 2 ? launch_ig_k<8, 2>(s, p, l, cam, rc, ig, w, stats, st)
-                                : launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 16) return lpp == 1 ? launch_ig_k<16, 1>(s, p, l, cam, rc, ig, w, stats, st)
-                        : lpp == 4 ? launch_ig_k<16, 4>(s, p, l, cam, rc, ig, w, stats, st)
-                                   : launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, stats, st);
-  if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, cam, rc, ig, w, stats, st)
-                        : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, cam, rc, ig, w, stats, st)
-                                   : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, stats, st);
-  return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, stats, st)
-                  : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, stats, st);
+  if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                                : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+  if (s.k <= 8) return lpp == 2 ? launch_ig_k<8, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                                : launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+  if (s.k <= 16) return lpp == 1 ? launch_ig_k<16, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                        : lpp == 4 ? launch_ig_k<16, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                                   : launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+  if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                        : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                                   : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+  return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                  : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
 }
 
 bool ig_lpp_valid(int64_t k, int lpp) {
