@@ -220,26 +220,43 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
       atomicAdd((unsigned long long*)&stats[4], (unsigned long long)(tile_last - (int)start + 1));
   }
   if (tile_last < 0) return;
-  // Nearest weighted entry: pass 2 ends there, because entries in front of it only feed the
-  // suffixes of entries further in front, none of which writes a record.
+  // the wavefront's last contributor: entries behind it contribute to none of its pixels
+  int wave_last = last;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
+  // The wavefront's nearest weighted entry whose box reaches its strip: its part of pass 2
+  // ends there, because entries in front of it only feed the suffixes of entries further in
+  // front, none of which writes a record for its pixels. The tile's pass 2 ends at the
+  // nearest over its wavefronts.
   __syncthreads();
   if (threadIdx.x == 0) S.flag = INT_MAX;
   __syncthreads();
-  for (int i = (int)start + threadIdx.x; i <= tile_last; i += kThreads)
-    if (slot_of[gids[i]] >= 0) {
-      atomicMin(&S.flag, i);
-      break;  // a lane's later indices are larger
+  int wave_first = INT_MAX;
+  for (int b0 = (int)start; b0 <= wave_last; b0 += kWave) {
+    const int i = b0 + lane;
+    bool hit = false;
+    if (i <= wave_last) {
+      const uint32_t g = gids[i];
+      if (slot_of[g] >= 0) {
+        float hx, hy;
+        conic_extent(conic[g], conic[n + g], conic[2 * n + g], rc.cutoff_q, &hx, &hy);
+        const float mx = mean2d[g], my = mean2d[n + g];
+        hit = mx + hx >= sx0 && mx - hx <= sx1 && my + hy >= sy0 && my - hy <= sy1;
+      }
     }
+    const uint64_t hm = __ballot(hit);
+    if (hm) {
+      wave_first = b0 + __ffsll((unsigned long long)hm) - 1;
+      break;
+    }
+  }
+  if (lane == 0 && wave_first != INT_MAX) atomicMin(&S.flag, wave_first);
   __syncthreads();
   const int first_w = S.flag;
   if (first_w > tile_last) return;
 
   // ---- pass 2: back to front ------------------------------------------------------------
   const float t_final = T;
-  // the wavefront's last contributor: entries behind it contribute to none of its pixels
-  int wave_last = last;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
   float Tc = T;
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Sd = 0.f;
   float So[KL];  // channels h * KL ... (h + 1) * KL - 1 of the object suffix
@@ -265,7 +282,8 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
       S.p[j][c] = (c < k) ? prob[(size_t)gids[lo + j] * k + c] : 0.f;
     }
     __syncthreads();
-    uint64_t live = __ballot(lo + lane <= wave_last && reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
+    uint64_t live =
+        __ballot(lo + lane <= wave_last && lo + lane >= wave_first && reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
     while (live) {
       const int j = 63 - __clzll((long long)live);
       live &= ~(1ull << j);
