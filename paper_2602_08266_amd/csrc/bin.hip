@@ -186,7 +186,8 @@ __global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ h
 __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict__ tot, int ntiles,
                                                      uint32_t* __restrict__ ranges, int64_t capacity,
                                                      int32_t* __restrict__ overflow, int64_t* __restrict__ stats,
-                                                     const uint64_t* __restrict__ m_total) {
+                                                     const uint64_t* __restrict__ m_total,
+                                                     const int32_t* __restrict__ keep) {
   __shared__ uint32_t sm[256];
   constexpr int kPer = NGS_MAX_TILES / 256;
   const int t0 = threadIdx.x * kPer;
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
   for (int j = 0; j < kPer; ++j)
     if (t0 + j < ntiles) {
       ranges[t0 + j] = over ? 0u : excl + v[j];
-      ranges[ntiles + t0 + j] = over ? 0u : excl + v[j] + tot[t0 + j];
+      ranges[ntiles + t0 + j] = over ? 0u : excl + v[j] + (keep && keep[t0 + j] == 0 ? 0u : tot[t0 + j]);
     }
   if (threadIdx.x == 0) {
     if (over && overflow) atomicOr(overflow, 1);
@@ -324,10 +325,14 @@ __device__ __forceinline__ int wave_max(int v) {
 // bin c in [lo, hi], the lanes whose span [b0, b0 + len) covers c take consecutive positions
 // cnt[c] + (covering lanes below them), and cnt[c] advances by their number. No atomics:
 // ballots give the ranks, and each bin's writes are one coalesced run.
-template <class Emit>
-__device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int lo, int hi, int lane, Emit emit) {
+// Bins for which keep(c) is false are passed over: nothing is written for them and their
+// counters stay as they were.
+template <class Emit, class Keep>
+__device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int lo, int hi, int lane, Emit emit,
+                                            Keep keep) {
   const uint64_t below = (1ull << lane) - 1ull;
   for (int c = lo; c <= hi; ++c) {
+    if (!keep(c)) continue;
     const bool cover = len > 0 && b0 <= c && c < b0 + len;
     const uint64_t m = __ballot(cover);
     if (!m) continue;
@@ -339,11 +344,12 @@ __device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int 
 
 // The same with the counters in registers: lane l holds bin l in cr[0] and bin 64 + l in
 // cr[1] (NR = 2), read with readlane at the (uniform) bin; for at most 64 NR bins.
-template <int NR, class Emit>
+template <int NR, class Emit, class Keep>
 __device__ __forceinline__ void place_batch_reg(uint32_t (&cr)[NR], int b0, int len, int lo, int hi, int lane,
-                                                Emit emit) {
+                                                Emit emit, Keep keep) {
   const uint64_t below = (1ull << lane) - 1ull;
   for (int c = lo; c <= hi; ++c) {
+    if (!keep(c)) continue;
     const bool cover = len > 0 && b0 <= c && c < b0 + len;
     const uint64_t m = __ballot(cover);
     if (!m) continue;
@@ -388,8 +394,9 @@ __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* __
     const int lo = wave_min(h > 0 ? y0 : INT_MAX), hi = wave_max(h > 0 ? y0 + h - 1 : -1);
     const uint2 e = make_uint2(l.gid, (l.org & 0xFFFFu) | ((uint32_t)l.w << 16));
     auto emit = [&](int, uint32_t pos) { rl[pos] = e; };
-    if constexpr (NR > 0) place_batch_reg<NR>(cr, y0, h, lo, hi, lane, emit);
-    else place_batch(cnt, y0, h, lo, hi, lane, emit);
+    const auto all = [](int) { return true; };
+    if constexpr (NR > 0) place_batch_reg<NR>(cr, y0, h, lo, hi, lane, emit, all);
+    else place_batch(cnt, y0, h, lo, hi, lane, emit, all);
   }
 }
 
@@ -493,7 +500,8 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict
                                                          const uint32_t* __restrict__ meta,
                                                          const uint32_t* __restrict__ hist2,
                                                          const uint32_t* __restrict__ ranges, int64_t capacity,
-                                                         uint32_t* __restrict__ gids_out) {
+                                                         uint32_t* __restrict__ gids_out,
+                                                         const int32_t* __restrict__ keep) {
   extern __shared__ uint32_t lds2[];  // cnt [tiles_x] (NR == 0), chunk prefix [rows]
   uint32_t* cnt = lds2;
   uint32_t* cpl = lds2 + (NR > 0 ? 0 : tiles_x);
@@ -509,11 +517,13 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict
     const uint32_t nc = nch[c.row];
     const int tbase = c.row * tiles_x;
     uint32_t cr[NR > 0 ? NR : 1];
+    uint64_t km[NR > 0 ? NR : 1];  // wanted tiles of the row, bit t % 64 of word t / 64
     if constexpr (NR > 0) {
 #pragma unroll
       for (int i2 = 0; i2 < NR; ++i2) {
         const int t = i2 * kWave + lane;
         cr[i2] = t < tiles_x ? ranges[tbase + t] + h[(size_t)t * nc + c.idx] : 0u;
+        km[i2] = __ballot(t < tiles_x && (!keep || keep[tbase + t] != 0));
       }
     } else {
       for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
@@ -528,8 +538,13 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict
       auto emit = [&](int, uint32_t pos) {
         if ((int64_t)pos < capacity) gids_out[pos] = e.x;
       };
-      if constexpr (NR > 0) place_batch_reg<NR>(cr, x0, w, lo, hi, lane, emit);
-      else place_batch(cnt, x0, w, lo, hi, lane, emit);
+      if constexpr (NR > 0) {
+        const auto kept = [&](int t) { return ((NR > 1 && t >= kWave ? km[NR - 1] : km[0]) >> (t & (kWave - 1))) & 1ull; };
+        place_batch_reg<NR>(cr, x0, w, lo, hi, lane, emit, kept);
+      } else {
+        const auto kept = [&](int t) { return !keep || keep[tbase + t] != 0; };
+        place_batch(cnt, x0, w, lo, hi, lane, emit, kept);
+      }
     }
   }
 }
@@ -622,7 +637,8 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
 }
 
 hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
-                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st) {
+                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
+                             const int32_t* keep) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int rows = cam.tiles_y, tx = cam.tiles_x;
   const uint32_t* order = w.dvals[1];
@@ -663,19 +679,19 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, c
     ProfScope ps(kProfTileScan, st);
     hipLaunchKernelGGL(k_tile2_scan, dim3(ntiles), dim3(256), 0, st, w.hist2, tx, w.cp, w.nch, w.meta, w.ptot);
     hipLaunchKernelGGL(k_part_ranges, dim3(1), dim3(256), 0, st, w.ptot, ntiles, out.ranges, out.capacity, overflow,
-                       stats, m_total);
+                       stats, m_total, keep);
   }
   {
     ProfScope ps(kProfTileScatter, st);
     if (tx <= kWave)
       hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
-                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
     else if (tx <= 2 * kWave)
       hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
-                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
     else
       hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(kGrid2), dim3(kWave), (tx + rows) * 4, st, w.rl, rows, tx,
-                         w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids);
+                         w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
   }
   if (out.keys) {
     ProfScope ps(kProfKeys64, st);

@@ -467,9 +467,12 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     const DevCam dc = make_devcam(cams[v], kTile);
     NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls));
-    NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats,
-                                     ctx->tuning.ig_lanes_per_pixel, ls));
+    // slots first: with a target object only the lists of tiles that a weighted Gaussian
+    // reaches are written, the only ones the information walk reads
+    NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, *ig, igs[i], ls));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i])));
+    NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats,
+                                    ctx->tuning.ig_lanes_per_pixel, ls));
     NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v, stats, sticky, ls));
   }
   for (int i = 0; i < lanes; ++i) {

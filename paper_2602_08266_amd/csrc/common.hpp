@@ -159,9 +159,12 @@ size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);
 hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st);
 // Pairs beyond out.capacity are not written: the ranges are left empty and *overflow (may
-// be NULL) is raised; stats[1] (may be NULL) accumulates the pair count.
+// be NULL) is raised; stats[1] (may be NULL) accumulates the pair count. keep (may be NULL:
+// every tile) flags the tiles whose lists are wanted: the others get empty ranges and none of
+// their gids is written, while the wanted lists and M stay those of the full binning.
 hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
-                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st);
+                             const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
+                             const int32_t* keep = nullptr);
 
 // Rendering (render.hip).
 hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
@@ -193,6 +196,15 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
                            const IgWs& w, int64_t* stats, int lpp, hipStream_t st);
+// The two halves of launch_ig_tiles: slot assignment (and, with a target object, the flags of
+// the tiles that a slotted Gaussian's rect reaches; see ig_tile_flags), then the tile walk.
+hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const DevCam& cam, const ngs_ig_params& ig,
+                            const IgWs& w, hipStream_t st);
+hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+                          const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
+                          hipStream_t st);
+// Tile flags of w when launch_ig_assign fills them (a target object), else nullptr.
+const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w);
 bool ig_lpp_valid(int64_t k, int lpp);
 hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,

@@ -543,12 +543,15 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   return w;
 }
 
-hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
-                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
-                           hipStream_t st) {
+const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w) {
   // Tile flags only pay when few Gaussians carry weight (one target object, Eq. 12); with
   // whole-scene confidence nearly every tile holds a weighted Gaussian.
-  int32_t* tflag = ig.target_id >= 0 ? w.tflag : nullptr;
+  return ig.target_id >= 0 ? w.tflag : nullptr;
+}
+
+hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const DevCam& cam, const ngs_ig_params& ig,
+                            const IgWs& w, hipStream_t st) {
+  int32_t* tflag = const_cast<int32_t*>(ig_tile_flags(ig, w));
   const int ntiles = cam.tiles_x * cam.tiles_y;
   {
     ProfScope ps(kProfFill, st);
@@ -562,8 +565,13 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
     hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
                        (int)w.max_slots, w.astride);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+                          const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
+                          hipStream_t st) {
+  const int32_t* tflag = ig_tile_flags(ig, w);
   // lanes per pixel (ig_lpp_valid): 0 picks the default of each object-vector width
   if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
                                 : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);
@@ -577,6 +585,14 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
                                    : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
   return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
                   : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+}
+
+hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
+                           hipStream_t st) {
+  hipError_t e = launch_ig_assign(s, p, cam, ig, w, st);
+  if (e != hipSuccess) return e;
+  return launch_ig_walk(s, p, l, cam, rc, ig, w, stats, lpp, st);
 }
 
 bool ig_lpp_valid(int64_t k, int lpp) {
