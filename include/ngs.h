@@ -189,7 +189,7 @@ typedef struct {
  * 3 = ngs_render_backward, 4 = ngs_sur_render_features (ngs_surrogate.h).
  * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
  * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
- * at most 16; at most 32 for op 4, where it is the views per grouped render). All host. */
+ * at most 32; at most 32 for op 4, where it is the views per grouped render). All host. */
 typedef struct {
   int64_t n, k, width, height, max_pairs, max_slots, views_in_flight;
 } ngs_dims;

@@ -19,7 +19,7 @@ import torch
 
 from . import binding as B
 
-VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16)
+VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16, 24, 32)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 

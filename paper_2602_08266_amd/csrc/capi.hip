@@ -132,7 +132,7 @@ size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
 }
 
 constexpr int kDefaultInFlight = 8;
-constexpr int kMaxInFlight = 16;
+constexpr int kMaxInFlight = 32;
 constexpr int kMaxFeatureGroup = 32;  // views per grouped render launch of the feature maps
 
 int views_in_flight(const ngs_dims* d, int cap = kMaxInFlight) {
