@@ -50,7 +50,7 @@ def scene_samples(ctx: B.Context, scene, cands: Sequence, train: Sequence, views
     scorer.setup([B.camera(c) for c in train])
     key = (scene.n, scene.k, cams[0].width, cams[0].height)
     if key not in _TUNED:
-        _TUNED[key] = AT.tune_score(ctx, scorer, cams, sample=64, vif=(8, 12, 16))
+        _TUNED[key] = AT.tune_score(ctx, scorer, cams, sample=64, vif=(8, 16, 32))
     else:
         AT.apply(ctx, scorer, _TUNED[key])
     torch.cuda.synchronize()
