@@ -72,12 +72,12 @@ __constant__ StatTable c_stats = make_stat_table();
 // wavefront) so that the rows of all 16 wavefronts fit in LDS.
 template <int LPP> constexpr int chunk_rows() { return LPP == 4 ? 8 : 16; }
 
-// Adds R packed rows into this lane's statistics: the scalar statistics (u_a, v_a) and
-// (u_b, v_b), and Z_o for channel zc over the rows of its pixel group. Rows past the
-// contributing lanes hold zero records, so no row needs masking.
-template <int R, int KP>
-__device__ __forceinline__ void reduce_rows(const float (*rec)[kRec], const float (*sov)[KP + 4], int ua, int va,
-                                            int ub, int vb, int grp, int zc, float& accA, float& accB,
+// Adds R packed rows (R a multiple of 4) into this lane's statistics: the scalar statistics
+// (u_a, v_a) and (u_b, v_b), and Z_o for channel zc over the rows of its pixel group. Rows past
+// the contributing lanes hold zero records, so no row needs masking.
+template <int KP>
+__device__ __forceinline__ void reduce_rows(int R, const float (*rec)[kRec], const float (*sov)[KP + 4], int ua,
+                                            int va, int ub, int vb, int grp, int zc, float& accA, float& accB,
                                             float (&z)[6]) {
   constexpr int kGroups = kWave / KP;
   constexpr int kStep = 4;  // rows per iteration: enough loads in flight, few registers
@@ -89,12 +89,11 @@ __device__ __forceinline__ void reduce_rows(const float (*rec)[kRec], const floa
       accB += rec[r][ub] * rec[r][vb];
     }
   }
-  constexpr int kRowsPerGroup = (R + kGroups - 1) / kGroups;
-  constexpr int kZStep = kRowsPerGroup < kStep ? kRowsPerGroup : kStep;
+  const int rows_per_group = (R + kGroups - 1) / kGroups;
 #pragma unroll 1
-  for (int t0 = 0; t0 < kRowsPerGroup; t0 += kZStep) {
+  for (int t0 = 0; t0 < rows_per_group; t0 += kStep) {
 #pragma unroll
-    for (int t = t0; t < t0 + kZStep; ++t) {
+    for (int t = t0; t < t0 + kStep; ++t) {
       const int r = t * kGroups + grp;
       if (kGroups > 1 && t * kGroups >= R) break;
       const int rr = r < R ? r : R - 1;
@@ -359,10 +358,10 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
         float (*sov)[KP + 4] = S.so[wave];
         float accA = 0.f, accB = 0.f, z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-          // rows [0, m) take the next contributing lanes; a short last chunk is padded to
-          // R rows with the (zero) records of non-contributing lanes
+          // rows [0, m) take the next contributing lanes; a short last chunk is padded to a
+          // multiple of 4 rows with the (zero) records of non-contributing lanes
           const int m = min(kChunk, cnt - c0);
-          const int R = m > kChunk / 2 ? kChunk : kChunk / 2;
+          const int R = (m + 3) & ~3;
           const int row = contrib ? rank - c0 : m + nrank;
           if (contrib ? (row >= 0 && row < m) : (row < R)) {
             if (h == 0) {
@@ -377,10 +376,7 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          if (R == kChunk)
-            reduce_rows<kChunk, KP>(rec, sov, ua, va, ub, vb, grp, zc, accA, accB, z);
-          else
-            reduce_rows<kChunk / 2, KP>(rec, sov, ua, va, ub, vb, grp, zc, accA, accB, z);
+          reduce_rows<KP>(R, rec, sov, ua, va, ub, vb, grp, zc, accA, accB, z);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
