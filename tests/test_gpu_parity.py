@@ -225,6 +225,41 @@ def test_score_pipeline_tiny(B, ctx, target):
     log(f"  best gpu {int(best.item())} oracle {ref.best}; stats {st}")
 
 
+@pytest.mark.parametrize("target", [3, 17])
+def test_score_batch_filtered_lists_mid(B, ctx, target):
+    """With a target object the batched scorer writes only the lists of tiles that a weighted
+    Gaussian reaches; its gains must equal those of the stand-alone path over complete lists up
+    to the order of FP32 atomic adds. A candidate that looks away from the scene gains exactly
+    zero on both paths."""
+    log(f"test_score_batch_filtered_lists mid target {target}")
+    cfg, scene, cands, train = scenegen.make_workload("mid", 0)
+    ds = B.DeviceScene(scene, "cuda")
+    ig = B.ig_params(target_id=target)
+    rp = B.raster_params()
+    B.ngs_prepare_scene(ctx, ds, ig)
+    away = scenegen.look_at(np.array([3.0, 0.0, 0.2]), 640, 480, 525.0, target=(6.0, 0.0, 0.2))
+    views = [cands[0], cands[5], away, cands[9], cands[30]]
+    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=1 << 24, max_slots=1 << 16, store_capacity=1 << 16,
+                         views_in_flight=2)
+    scorer.setup([B.camera(c) for c in train])
+    _, _, raw = scorer.score([B.camera(c) for c in views])
+    raw = raw.cpu().numpy()
+    ws = B.IgWorkspace(ds, 1 << 16)
+    seen = 0
+    for i, cam in enumerate(views):
+        c = B.camera(cam)
+        pr = B.ngs_project(ctx, ds, c, rp)
+        lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=1 << 24)
+        ref = B.ngs_info_gain(ctx, ds, pr, lists, c, rp, ig, scorer.h, ws).cpu().numpy()
+        log(f"  view {i}: batch {raw[i]} stand-alone {ref}")
+        if cam is away:
+            assert np.all(raw[i] == 0.0) and np.all(ref == 0.0)
+        else:
+            seen += int(np.all(ref > 0.0))
+            assert np.allclose(raw[i], ref, rtol=1e-4, atol=0.0)
+    assert seen >= 2  # the target is in view of most candidates
+
+
 @pytest.mark.parametrize("target", [-1, 3])
 def test_greedy_nbv_sequence_tiny(B, ctx, target):
     """Three greedy steps: each chosen view joins the training set (H_T and normalisers are
