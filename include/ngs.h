@@ -317,6 +317,10 @@ ngs_status ngs_score_graph_destroy(ngs_score_graph* graph);
  * (0 <= id < ngs_profile_kernels()); ngs_profile_kernel_name names the class. Enabling
  * (or disabling) clears the totals. The profile is process-wide. */
 ngs_status ngs_profile_enable(ngs_ctx* ctx, int32_t on);
+/* Like ngs_profile_enable(ctx, 1), but only launches of kernel class id are bracketed, so
+ * that timing one kernel adds no events around the others. NGS_INVALID_ARG for an id out of
+ * range. ngs_profile_enable(ctx, 0) turns it off. */
+ngs_status ngs_profile_enable_class(ngs_ctx* ctx, int32_t id);
 int32_t ngs_profile_kernels(void);
 const char* ngs_profile_kernel_name(int32_t id);
 ngs_status ngs_profile_read(ngs_ctx* ctx, int32_t id, double* total_ms, int64_t* launches);

@@ -27,7 +27,7 @@ EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs
            "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
            "ngs_score_graph_create", "ngs_score_graph_launch", "ngs_score_graph_destroy", "ngs_set_tuning",
            "ngs_get_tuning",
-           "ngs_render_backward", "ngs_profile_enable", "ngs_profile_kernels", "ngs_profile_kernel_name",
+           "ngs_render_backward", "ngs_profile_enable", "ngs_profile_enable_class", "ngs_profile_kernels", "ngs_profile_kernel_name",
            "ngs_profile_read", "ngs_sur_workspace_size", "ngs_sur_sync_bf16", "ngs_sur_forward", "ngs_sur_backward",
            "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_novelty", "ngs_sur_render_features", "ngs_gemm_bf16"]
 
@@ -149,6 +149,7 @@ def lib():
         L.ngs_sur_render_features.argtypes = [P, P, P, i32, P, P, C.c_float, P, P, P, C.c_size_t, P]
         L.ngs_gemm_bf16.argtypes = [P, i32, i32, i32, i32, i32, P, i32, P, i32, P, i32, C.c_float, P]
         L.ngs_profile_enable.argtypes = [P, i32]
+        L.ngs_profile_enable_class.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
         L.ngs_profile_kernel_name.argtypes = [i32]
         L.ngs_profile_kernel_name.restype = C.c_char_p
@@ -693,8 +694,14 @@ def score_workspace(scene: DeviceScene, max_pairs: int, max_slots: int = 1 << 16
     return ScoreWorkspace(scene, max_pairs, max_slots, views_in_flight)
 
 
-def ngs_profile_enable(ctx: Context, on: bool):
-    _check("ngs_profile_enable", lib().ngs_profile_enable(ctx.handle, 1 if on else 0), ctx)
+def ngs_profile_enable(ctx: Context, on: bool, only: Optional[str] = None):
+    """Event timing of every kernel class, or with `only` (a class name) of that class alone."""
+    L = lib()
+    if on and only is not None:
+        names = [L.ngs_profile_kernel_name(i).decode() for i in range(L.ngs_profile_kernels())]
+        _check("ngs_profile_enable_class", L.ngs_profile_enable_class(ctx.handle, names.index(only)), ctx)
+    else:
+        _check("ngs_profile_enable", L.ngs_profile_enable(ctx.handle, 1 if on else 0), ctx)
 
 
 def ngs_profile_read(ctx: Context) -> Dict[str, tuple]:

@@ -621,6 +621,12 @@ ngs_status ngs_profile_enable(ngs_ctx* ctx, int32_t on) {
   return NGS_OK;
 }
 
+ngs_status ngs_profile_enable_class(ngs_ctx* ctx, int32_t id) {
+  if (!ctx || id < 0 || id >= kProfKernels) return NGS_INVALID_ARG;
+  prof_enable(true, id);
+  return NGS_OK;
+}
+
 int32_t ngs_profile_kernels(void) { return kProfKernels; }
 
 const char* ngs_profile_kernel_name(int32_t id) { return prof_name(id); }

@@ -111,7 +111,8 @@ class ProfScope {
   hipStream_t st_;
   void* a_;
 };
-void prof_enable(bool on);
+// only >= 0 restricts the timing to that kernel class (fewer events on the streams)
+void prof_enable(bool on, int only = -1);
 // Pause timing without clearing what was recorded (graph capture records no profiling events).
 bool prof_suspend();
 void prof_resume(bool on);

@@ -18,6 +18,7 @@ struct Rec {
 
 std::mutex g_mu;
 bool g_on = false;
+int g_only = -1;  // >= 0: only this kernel class is timed
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 double g_ms[kProfKernels];
@@ -56,7 +57,7 @@ void drain_locked() {
 }  // namespace
 
 ProfScope::ProfScope(int id, hipStream_t st) : id_(id), st_(st), a_(nullptr) {
-  if (!g_on) return;
+  if (!g_on || (g_only >= 0 && id != g_only)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t a = get_event();
   if (a) (void)hipEventRecord(a, st_);
@@ -72,11 +73,12 @@ ProfScope::~ProfScope() {
   if (g_recs.size() > 65536) drain_locked();
 }
 
-void prof_enable(bool on) {
+void prof_enable(bool on, int only) {
   std::lock_guard<std::mutex> lk(g_mu);
   drain_locked();
   for (int i = 0; i < kProfKernels; ++i) { g_ms[i] = 0.0; g_cnt[i] = 0; }
   g_on = on;
+  g_only = only;
 }
 
 bool prof_suspend() {
