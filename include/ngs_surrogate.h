@@ -2,9 +2,10 @@
  *
  * Not part of arXiv 2602.08266: an addition that predicts a candidate view's next-best-view
  * score (Eq. 11 of the paper, as computed exactly by ngs_score_batch) from four low-resolution
- * rendered feature maps (depth, final transmittance, argmax object id, mean confidence;
- * ngs_render outputs). The exact information gain remains the judge: callers re-score the
- * surrogate's best candidates with ngs_score_batch.
+ * rendered feature maps (depth, final transmittance, argmax object id, and the ray average of
+ * a per-Gaussian weight such as confidence x novelty; ngs_sur_render_features). The exact
+ * information gain makes the final choice: callers re-score the surrogate's best candidates
+ * with ngs_score_batch.
  *
  * Network (fixed): four 3x3 convolutions, stride 2, padding 1, ReLU
  * (4 -> 32 -> 64 -> 128 -> 128 channels; 60x80 -> 30x40 -> 15x20 -> 8x10 -> 4x5), global

@@ -6,7 +6,7 @@ transmittance, argmax object id, and the ray average of confidence x novelty aga
 training information, from the library's feature render) and, as the label, the view's exact
 next-best-view score (Eq. 11 of the paper on Eq. 10-normalised gains, whole-scene confidence
 Eq. 7, four training views per scene) from ngs_score_batch. The surrogate ranks candidates;
-the exact scorer re-scores its best ones and stays the judge. Without the novelty channel the
+the exact scorer re-scores its best ones and makes the final choice. Without the novelty channel the
 maps say nothing about what the training views already observed, which the gain depends on.
 """
 from __future__ import annotations
