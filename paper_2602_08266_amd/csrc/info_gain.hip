@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots, int32_t* ove
 // takes its slots with a single counter update. With tflag, every slotted Gaussian also marks
 // the tiles of its rect, so that the tile kernel can leave the other tiles at once; the cost
 // is the rect areas of the slotted Gaussians, small when only one object carries weight.
-constexpr int kAssignPer = 16;
+constexpr int kAssignPer = 4;
 
 __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restrict__ conf,
                                                    const uint32_t* __restrict__ count, int32_t* __restrict__ slot_of,
