@@ -37,7 +37,7 @@ def kernel_source_hash(files):
 # Algorithmic HBM bytes per kernel class, from per-step counts: n Gaussians, k, views V,
 # pairs M, walked (tile, list entry) pairs W and touched weighted Gaussians U (all summed
 # over the step's views).
-def algorithmic_bytes(name, n, k, V, M, W, U):
+def algorithmic_bytes(name, n, k, V, M, W, U, W2=0):
     if name == "project":
         return V * n * (40 + 40)                 # mean, log-scale, quaternion in; 2D mean, conic, depth, key, rect, count out
     if name == "depth_sort_scatter":
@@ -51,9 +51,13 @@ def algorithmic_bytes(name, n, k, V, M, W, U):
     if name == "tile_part_scatter":
         return 4 * M + V * n * 12                # final gid per pair + the same per-Gaussian reads
     if name == "ig_tiles":
-        # list entry + projected geometry per walked entry; object row and statistics
-        # (94 + 6k floats written) of every touched weighted Gaussian
-        return W * (4 + 24) + U * (4 * k + 40) + U * 4 * (94 + 6 * k)
+        # front-to-back walk: list entry, 2D mean, conic and opacity of every walked entry;
+        # back-to-front walk over the W2 entries from a tile's last contributor to its nearest
+        # weighted one: weight flag, depth, colour and the k-long probability row (the object
+        # suffixes of the weighted Gaussians in front sum the rows of every contributing
+        # Gaussian behind them); the statistics (94 + 6k floats) of every touched weighted
+        # Gaussian written
+        return W * 28 + W2 * (24 + 4 * k) + U * 4 * (94 + 6 * k)
     return None
 
 
@@ -373,7 +377,7 @@ def main():
                                    log=lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush()))
     elif args.ig_lpp:
         B.ngs_set_tuning(ctx, args.ig_lpp)
-    stats = torch.zeros(6, dtype=torch.int64, device="cuda:0")
+    stats = torch.zeros(B.STATS_LEN, dtype=torch.int64, device="cuda:0")
     for _ in range(args.warmup):
         scorer.score(cam_c, stats)
     torch.cuda.synchronize()
@@ -420,10 +424,11 @@ def main():
     M_step = int(st[1]) / K
     W_step = int(st[4]) / K
     U_step = int(st[2]) / K
+    W2_step = int(st[6]) / K
     roofline = None
     if prof and prof.get(dom, (0.0, 0))[1] > 0:
         ms_tot, launches = prof[dom]
-        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step, U_step)
+        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step, U_step, W2_step)
         if alg is not None:
             per_launch = alg / (launches / K)
             avg_s = ms_tot / launches / 1e3
@@ -451,6 +456,7 @@ def main():
                                            / HBM_PEAK_GBS, 4)},
         "setup_ms": round(setup_ms, 1),
         "pairs_per_view": M_step / V, "walked_entries_per_view": W_step / V,
+        "back_to_front_entries_per_view": W2_step / V,
         "contrib_pairs_per_view": int(st[3]) / K / V, "touched_weighted_per_view": int(st[2]) / K / V,
         "best_view": int(best.item()), "normalisers": [float(x) for x in norm],
         "kernels_ms_per_step": {k: round(v[0], 3) for k, v in sorted(breakdown.items(), key=lambda x: -x[1][0])},

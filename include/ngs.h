@@ -176,14 +176,16 @@ typedef struct {
                           not NULL; needed by the trace criterion */
 } ngs_hessian;
 
-/* Per-view statistics the kernels add into (device, int64 [6], caller-zeroed):
+/* Per-view statistics the kernels add into (device, int64 [NGS_STATS_LEN], caller-zeroed):
  * [0] views, [1] pairs M, [2] Gaussians with a nonzero weight that contribute to at
  *     least one pixel U,
  * [3] contributing (pixel, Gaussian) pairs P, [4] walked (tile, entry) pairs, both over
  *     the tiles the information walk visits (with a target object only the tiles that the
  *     rect of a weighted Gaussian reaches; the others add nothing to any statistic),
- * [5] views whose slot workspace overflowed. */
-#define NGS_STATS_LEN 6
+ * [5] views whose slot workspace overflowed,
+ * [6] entries the back-to-front walk stages (per visited tile, from its last contributor
+ *     to its nearest weighted entry that reaches a strip). */
+#define NGS_STATS_LEN 7
 
 /* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch,
  * 3 = ngs_render_backward, 4 = ngs_sur_render_features (ngs_surrogate.h).

@@ -21,7 +21,7 @@ NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
 NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
 MODE_SCORE, MODE_ACCUMULATE = 0, 1
 OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
-STATS_LEN = 6
+STATS_LEN = 7
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_bin_sort", "ngs_render",
            "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
@@ -172,6 +172,15 @@ def _check(fn: str, status: int, ctx=None):
 
 def _p(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stats(t: Optional[torch.Tensor]):
+    """Pointer of a statistics tensor: int64, contiguous, on the GPU, NGS_STATS_LEN long."""
+    if t is None:
+        return None
+    if t.dtype != torch.int64 or not t.is_contiguous() or not t.is_cuda or t.numel() < STATS_LEN:
+        raise ValueError(f"stats must be a contiguous int64 GPU tensor of {STATS_LEN} entries")
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream():
@@ -584,7 +593,7 @@ def ngs_info_gain(ctx: Context, scene: DeviceScene, proj: Projected, lists: Tile
     hc = h.c() if h is not None else None
     _check("ngs_info_gain", lib().ngs_info_gain(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam), _ref(rp),
                                                 _ref(ig), _ref(hc) if hc is not None else None, _p(out),
-                                                _p(stats), _p(ws.buf), ws.buf.numel(), _stream()), ctx)
+                                                _stats(stats), _p(ws.buf), ws.buf.numel(), _stream()), ctx)
     return out
 
 
@@ -621,7 +630,7 @@ def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], norm
     hc = h.c() if h is not None else None
     _check("ngs_score_batch", lib().ngs_score_batch(ctx.handle, _ref(sc), _ref(hc) if hc is not None else None,
                                                     norm, arr, nv, _ref(rp), _ref(ig), _p(scores), _p(best),
-                                                    _p(ig_raw), _p(stats), _ref(ws.dims), _p(ws.buf), ws.buf.numel(),
+                                                    _p(ig_raw), _stats(stats), _ref(ws.dims), _p(ws.buf), ws.buf.numel(),
                                                     _stream()), ctx)
     return scores[:nv], best, ig_raw[:nv]
 
@@ -666,7 +675,7 @@ class ScoreGraph:
         torch.cuda.synchronize()
         _check("ngs_score_graph_create", lib().ngs_score_graph_create(
             ctx.handle, _ref(sc), _ref(hc) if hc is not None else None, _p(self.norm), arr, nv, _ref(rp), _ref(ig),
-            _p(self.scores), _p(self.best), _p(self.ig_raw), _p(stats), _p(self.overflow), _ref(ws.dims), _p(ws.buf),
+            _p(self.scores), _p(self.best), _p(self.ig_raw), _stats(stats), _p(self.overflow), _ref(ws.dims), _p(ws.buf),
             ws.buf.numel(), C.byref(handle)), ctx)
         self.handle = handle
 

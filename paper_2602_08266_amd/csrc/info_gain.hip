@@ -253,6 +253,8 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   __syncthreads();
   const int first_w = S.flag;
   if (first_w > tile_last) return;
+  if (stats && threadIdx.x == 0)
+    atomicAdd((unsigned long long*)&stats[6], (unsigned long long)(tile_last - first_w + 1));
 
   // ---- pass 2: back to front ------------------------------------------------------------
   const float t_final = T;

@@ -210,7 +210,7 @@ def test_score_pipeline_tiny(B, ctx, target):
     for t in range(len(train)):
         check_gain(scorer.ig_train[t], ref.ig_train[t], f"train {t}")
     import torch
-    stats = torch.zeros(6, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(B.STATS_LEN, dtype=torch.int64, device="cuda")
     scores, best, raw = scorer.score([B.camera(c) for c in cands], stats)
     raw = raw.cpu().numpy()
     for v in range(len(cands)):
