@@ -372,8 +372,15 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
               for (int e = 0; e < kRec; e += 4) *reinterpret_cast<float4*>(dst + e) = make_float4(rv[e], rv[e + 1], rv[e + 2], rv[e + 3]);
             }
             float* srow = sov[row] + h * KL;
+            if constexpr (KL % 4 == 0) {
 #pragma unroll
-            for (int c = 0; c < KL; c += 4) *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
+              for (int c = 0; c < KL; c += 4)
+                *reinterpret_cast<float4*>(srow + c) = make_float4(So[c], So[c + 1], So[c + 2], So[c + 3]);
+            } else {
+              // fewer than four channels per lane (k <= 4 with two lanes per pixel)
+#pragma unroll
+              for (int c = 0; c < KL; ++c) srow[c] = So[c];
+            }
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           __builtin_amdgcn_wave_barrier();

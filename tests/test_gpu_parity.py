@@ -225,6 +225,60 @@ def test_score_pipeline_tiny(B, ctx, target):
     log(f"  best gpu {int(best.item())} oracle {ref.best}; stats {st}")
 
 
+def opaque_workload(seed=4):
+    """A tiny-sized scene with opacity logits N(7, 0.5) (sigma about 0.999) seen close up
+    (f = 300 at 128x96), so that sigma exp(-q/2) passes the 0.99 clamp at many pixel centres."""
+    scene = scenegen.make_scene(2000, 8, 16, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    scene.opacity_logit = rng.normal(7.0, 0.5, scene.n).astype(np.float32)
+    cfg = scenegen.SceneConfig("opaque", 2000, 8, 16, 6, ((128, 96, 6),), 300.0 * 640 / 128, (0.6, 0.6))
+    cands, train = scenegen.make_cameras(cfg, seed)
+    return scene, cands, train
+
+
+def clamped_pairs(scene, cam):
+    """(pixel, Gaussian) pairs of the view where the unclamped opacity exceeds alpha_max."""
+    pr = oracle.project(scene, cam)
+    sig = 1.0 / (1.0 + np.exp(-scene.opacity_logit.astype(np.float64)))
+    cnt = 0
+    for g in np.flatnonzero(pr["valid"] & (sig > 0.99)):
+        mx, my = pr["m"][:, g]
+        a, b, c = pr["conic"][:, g]
+        xs = np.arange(max(0, int(mx) - 2), min(cam.width, int(mx) + 3)) + 0.5
+        ys = np.arange(max(0, int(my) - 2), min(cam.height, int(my) + 3)) + 0.5
+        dx, dy = np.meshgrid(xs - mx, ys - my)
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        cnt += int((sig[g] * np.exp(-0.5 * q) > 0.99).sum())
+    return cnt
+
+
+def test_opaque_scene_alpha_clamp_render_and_gain(B, ctx):
+    """Opacities on the 0.99 clamp (Eq. 1 with the 3DGS clamp): k_render's clamped alpha and
+    k_ig_tile's zero opacity derivative at clamped contributors against the oracle."""
+    log("test_opaque_scene_alpha_clamp")
+    scene, cands, train = opaque_workload()
+    ds = device_scene(B, ctx, scene)
+    hits = [clamped_pairs(scene, c) for c in cands[:2]]
+    assert min(hits) > 100, hits
+    for v in range(2):
+        img, _, _ = render_gpu(B, ctx, ds, cands[v])
+        ref = oracle.render(scene, cands[v])
+        st = check_image(img, ref, scene.k, depth_max=1.0)
+        log(f"  view {v}: clamped (pixel, Gaussian) pairs {hits[v]}, {st}")
+    for target in (-1, 3):
+        ig = B.ig_params(target_id=target)
+        scorer = B.NbvScorer(ctx, B.DeviceScene(scene, "cuda"), B.raster_params(), ig, max_pairs=1 << 18,
+                             max_slots=1 << 14, store_capacity=1 << 14)
+        norm = scorer.setup([B.camera(c) for c in train])
+        ref = oracle.score(scene, train, cands, ig=oracle.IGParams(target_id=target))
+        assert ref.status == 0
+        check_gain(norm, ref.norm, f"normalisers target {target}")
+        scores, best, raw = scorer.score([B.camera(c) for c in cands])
+        raw = raw.cpu().numpy()
+        for v in range(len(cands)):
+            check_gain(raw[v], ref.ig_cand[v], f"target {target} candidate {v}")
+
+
 @pytest.mark.parametrize("target", [3, 17])
 def test_score_batch_filtered_lists_mid(B, ctx, target):
     """With a target object the batched scorer writes only the lists of tiles that a weighted
@@ -328,13 +382,15 @@ def test_abi_errors(B, ctx):
     assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, 0, None, None, None, 0, None) == B.NGS_INVALID_ARG
 
 
-@pytest.mark.parametrize("k,lpp", [(16, 1), (16, 2), (16, 4), (64, 1), (64, 2)])
+@pytest.mark.parametrize("k,lpp", [(4, 1), (4, 2), (8, 1), (8, 2), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2),
+                                   (32, 4), (64, 1), (64, 2)])
 def test_info_gain_every_launch_shape(B, ctx, k, lpp):
     """Every lanes-per-pixel shape the autotuner may pick (ngs_set_tuning) scores a small
     scene with a training store to the oracle's gains (1e-3 relative)."""
     log(f"test_info_gain_every_launch_shape k={k} lpp={lpp}")
-    scene = scenegen.make_scene(3000, 8, k, seed=21)
-    cfg = scenegen.SceneConfig("shape", 3000, 8, k, 4, ((128, 96, 4),), 500.0, (0.6, 0.6))
+    clusters = min(8, k)
+    scene = scenegen.make_scene(3000, clusters, k, seed=21)
+    cfg = scenegen.SceneConfig("shape", 3000, clusters, k, 4, ((128, 96, 4),), 500.0, (0.6, 0.6))
     cands, train = scenegen.make_cameras(cfg, 21)
     ds = B.DeviceScene(scene, "cuda")
     ref = oracle.score(scene, train, cands)
