@@ -309,6 +309,133 @@ def test_stop_rule_ends_the_walk():
     assert abs(img["t_final"][24, 32] - tf) < 1e-15
 
 
+def _alpha_clamp_stack(n, sig_l=10.0, s=0.2, z=0.5, f=50.0):
+    """n identical opaque Gaussians on the optical axis, wide enough that sigma exp(-q/2) stays
+    above alpha_max = 0.99 at the pixels next to the centre."""
+    o = np.tile([0.3, -0.2, 1.0], (n, 1))
+    return scenegen.tiny_scene(np.tile([0, 0, z], (n, 1)), np.full((n, 3), math.log(s)),
+                               np.tile([1, 0, 0, 0], (n, 1)), np.full(n, sig_l), np.tile([0.2, 0.5, 0.9], (n, 1)), o)
+
+
+def test_alpha_clamp_closed_form():
+    """Eq. 1 with the 3DGS clamp alpha = min(alpha_max, sigma exp(-q/2)): where the unclamped
+    opacity exceeds 0.99, n stacked Gaussians leave exactly T = (1 - 0.99)^n (t_min lowered so
+    that the stop rule does not end the walk first), and the colour is rgb (1 - T); further out,
+    where the Gaussian is below the clamp, the unclamped closed form holds."""
+    s, z, f, sig_l = 0.2, 0.5, 50.0, 10.0
+    cam = axis_camera(f=f)
+    rp = oracle.RasterParams(t_min=1e-12)
+    amax = f64(0.99)
+    sigma = 1 / (1 + math.exp(-f64(sig_l)))
+    v = f64(f) ** 2 * math.exp(2 * f64(math.log(s))) / f64(z) ** 2 + f64(0.3)
+    for n in (1, 3):
+        img = oracle.render(_alpha_clamp_stack(n, sig_l, s, z, f), cam, rp=rp)
+        clamped = unclamped = 0
+        for (px, py) in [(32, 24), (33, 24), (33, 25), (34, 24), (36, 27), (40, 24)]:
+            r2 = (px + 0.5 - 32) ** 2 + (py + 0.5 - 24) ** 2
+            raw = sigma * math.exp(-0.5 * r2 / v)
+            alpha = min(amax, raw)
+            if raw > amax * (1 + 1e-6):
+                clamped += 1
+            elif raw < amax * (1 - 1e-6):
+                unclamped += 1
+            else:
+                continue
+            tf = (1 - alpha) ** n
+            assert img["ncontrib"][py, px] == n
+            assert abs(img["t_final"][py, px] - tf) <= 1e-12 * tf
+            assert np.allclose(img["rgb"][:, py, px], np.array([f64(c) for c in (0.2, 0.5, 0.9)]) * (1 - tf),
+                               rtol=0, atol=1e-14)
+        assert clamped >= 3 and unclamped >= 1
+    # with the default t_min the second Gaussian would take T below 1e-4: the walk stops at one
+    img = oracle.render(_alpha_clamp_stack(3, sig_l, s, z, f), cam)
+    assert img["ncontrib"][24, 32] == 1
+    assert abs(img["t_final"][24, 32] - (1 - amax)) < 1e-15
+
+
+def test_clamped_contributor_has_zero_geometric_rows():
+    """A contributor whose opacity sits on the clamp has d alpha / d theta = 0: its colour and
+    object rows carry only the direct terms (a and a S_g), its geometric and opacity columns
+    vanish except depth's direct a R[2, :]; FP64 central differences of the frozen compositor
+    agree (the clamp holds under the step)."""
+    k = 3
+    cam = axis_camera(f=50.0)
+    # a wide opaque Gaussian in front (clamped at the centre pixels), a weaker one behind it
+    means = [[0.0, 0.0, 0.5], [0.004, -0.003, 0.6]]
+    ls = [[math.log(0.2)] * 3, [math.log(0.03)] * 3]
+    q = [[1, 0, 0, 0], [0.9, 0.1, -0.2, 0.3]]
+    sc = scenegen.tiny_scene(means, ls, q, [10.0, 0.5], [[0.2, 0.5, 0.9], [0.7, 0.1, 0.4]],
+                             [[0.3, -0.2, 1.0], [1.2, 0.1, -0.5]])
+    sc.mean = np.ascontiguousarray(np.asarray(means, np.float64).T)
+    sc.log_scale = np.ascontiguousarray(np.asarray(ls, np.float64).T)
+    sc.rot = np.ascontiguousarray(np.asarray(q, np.float64).T)
+    sc.opacity_logit = np.array([10.0, 0.5])
+    sc.rgb = np.ascontiguousarray(np.array([[0.2, 0.5, 0.9], [0.7, 0.1, 0.4]]).T)
+    sc.obj_logit = np.ascontiguousarray(np.array([[0.3, -0.2, 1.0], [1.2, 0.1, -0.5]]).T)
+    rp = oracle.RasterParams(t_min=1e-12)
+    ig = oracle.IGParams()
+    px, py = 32, 24
+    rows = oracle.pixel_rows(sc, cam, px, py, rp=rp, ig=ig)
+    assert list(rows["gids"]) == [0, 1]
+    img = oracle.render(sc, cam, rp=rp)
+    a0 = f64(0.99)                                   # alpha of the clamped front Gaussian, T = 1
+    # geometric columns (mu, log-scale, quaternion, opacity logit) of rgb and object rows: zero
+    assert np.all(rows["rgb"][0][:, :11] == 0.0)
+    assert np.all(rows["o"][0][:, :11] == 0.0)
+    # depth: only the direct term a R[2, :] = a (0, 0, 1) on mu
+    assert np.allclose(rows["d"][0][:3], [0.0, 0.0, a0], atol=1e-15) and np.all(rows["d"][0][3:] == 0.0)
+    # colour: a on the diagonal; object logits: a (delta_km - p_m) p_k
+    assert np.allclose(rows["rgb"][0][:, 11:], a0 * np.eye(3), atol=1e-15)
+    p = np.exp(sc.obj_logit[:, 0]); p /= p.sum()
+    assert np.allclose(rows["o"][0][:, 11:], a0 * (np.diag(p) - np.outer(p, p)), atol=1e-15)
+    # the contributor behind it keeps nonzero geometric rows
+    assert np.abs(rows["rgb"][1][:, :11]).max() > 1e-6
+    assert img["ncontrib"][py, px] == 2
+    seq = rows["gids"]
+    params = [("mean", i) for i in range(3)] + [("log_scale", i) for i in range(3)] + \
+             [("rot", i) for i in range(4)] + [("opacity_logit", None)]
+    for j, (name, idx) in enumerate(params):
+        base = getattr(sc, name)
+        val = base[0] if base.ndim == 1 else base[idx, 0]
+        h = 1e-6 * max(1.0, abs(val))
+        fp = oracle.pixel_eval_frozen(_perturbed(sc, name, idx, 0, h), cam, px, py, seq, rp, ig)
+        fm = oracle.pixel_eval_frozen(_perturbed(sc, name, idx, 0, -h), cam, px, py, seq, rp, ig)
+        fd = (fp - fm) / (2 * h)
+        an = np.concatenate([rows["rgb"][0][:, j], [rows["d"][0][j]], rows["o"][0][:, j]])
+        assert np.allclose(fd, an, rtol=1e-6, atol=1e-9), (name, idx, fd, an)
+
+
+def test_alpha_floor_skips_faint_gaussians():
+    """A Gaussian whose opacity at a pixel is below alpha_min = 1/255 is skipped there (not
+    composited, no transmittance change), while one just above it is composited."""
+    cam = axis_camera(f=50.0)
+    s, z_f, z_b = 0.02, 0.4, 0.6
+    amin = f64(1.0 / 255.0)
+    for ratio, kept in ((0.9, False), (1.1, True)):
+        sig_f = ratio * amin / math.exp(-0.5 * 0.5 / (f64(50.0) ** 2 * math.exp(2 * f64(math.log(s))) / f64(z_f) ** 2
+                                                      + f64(0.3)))
+        logit = math.log(sig_f / (1 - sig_f))
+        means = [[0, 0, z_f], [0, 0, z_b]]
+        sc = scenegen.tiny_scene(means, [[math.log(s)] * 3] * 2, [[1, 0, 0, 0]] * 2, [logit, 1.5],
+                                 [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]], [[0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+        img = oracle.render(sc, cam)
+        # exact alphas of the float32 scene at pixel (32, 24), r^2 = 0.5
+        def alpha_of(g, z):
+            sg = 1 / (1 + math.exp(-float(sc.opacity_logit[g])))
+            v = f64(50.0) ** 2 * math.exp(2 * float(sc.log_scale[0, g])) / f64(z) ** 2 + f64(0.3)
+            return min(f64(0.99), sg * math.exp(-0.5 * 0.5 / v))
+        af, ab = alpha_of(0, z_f), alpha_of(1, z_b)
+        assert (af >= amin) == kept
+        tf = (1 - ab) * ((1 - af) if kept else 1.0)
+        assert img["ncontrib"][24, 32] == (2 if kept else 1)
+        assert abs(img["t_final"][24, 32] - tf) < 1e-14
+        red = af if kept else 0.0
+        blue = ab * ((1 - af) if kept else 1.0)
+        assert np.allclose(img["rgb"][:, 24, 32], [red, 0.0, blue], atol=1e-14)
+        rows = oracle.pixel_rows(sc, cam, 32, 24)
+        assert list(rows["gids"]) == ([0, 1] if kept else [1])
+
+
 def test_eq1_eq2_sums(tiny):
     cfg, scene, cands, train = tiny
     img = oracle.render(scene, cands[2])
