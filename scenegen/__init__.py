@@ -105,14 +105,13 @@ def make_scene(n: int, clusters: int, k: int, seed: int, object_centric: bool = 
     assigns Gaussian g to cluster perm[g] mod C (equal sizes); means
     N(centre, spread^2) per axis; log-scales U[ln lo, ln hi] per axis;
     quaternions N(0, I4) normalised; opacity logits N(0, 1); colours U[0, 1)^3;
-    confidences q ~ U[0, 1).
+    confidences q ~ U[0, 1); the target id (object-centric workloads only).
 
     The object vector is one-hot by cluster and tempered by the confidence:
     logits o = log(q e_c + (1 - q)/K), so that softmax(o) equals that mixture
     exactly. Cluster c maps to channel c; channel 0 doubles as background.
-    A target id, if asked for, is the object cluster (id >= 1) with the highest centre: the
-    object on top of the pile, which the elevated initial views can see (a target is picked
-    from what the cameras observe).
+    A target id, if asked for, is drawn last, uniformly from the object ids 1 .. C - 1
+    (channel 0 is the background).
     """
     if k < clusters:
         raise ValueError("object-vector length must cover every cluster")
@@ -130,7 +129,7 @@ def make_scene(n: int, clusters: int, k: int, seed: int, object_centric: bool = 
     mix = np.broadcast_to(((1.0 - conf) / k)[:, None], (n, k)).copy()
     mix[np.arange(n), cluster] += conf
     obj_logit = np.log(mix)
-    target = int(1 + np.argmax(centres[1:, 2])) if object_centric else -1
+    target = int(rng.integers(1, clusters)) if object_centric else -1
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Scene(n=n, k=k, mean=f32(mean.T), log_scale=f32(log_scale.T), rot=f32(q.T),
                  opacity_logit=f32(opacity_logit), rgb=f32(rgb.T), obj_logit=f32(obj_logit.T),
