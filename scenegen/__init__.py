@@ -26,6 +26,7 @@ from typing import List, Optional
 import numpy as np
 
 CAMERA_STREAM_OFFSET = 1_000_003
+TARGET_POOL = 16  # object-centric targets are drawn among this many highest object clusters
 
 
 @dataclasses.dataclass(frozen=True)
@@ -110,8 +111,10 @@ def make_scene(n: int, clusters: int, k: int, seed: int, object_centric: bool = 
     The object vector is one-hot by cluster and tempered by the confidence:
     logits o = log(q e_c + (1 - q)/K), so that softmax(o) equals that mixture
     exactly. Cluster c maps to channel c; channel 0 doubles as background.
-    A target id, if asked for, is drawn last, uniformly from the object ids 1 .. C - 1
-    (channel 0 is the background).
+    A target id, if asked for, is drawn last, uniformly from the TARGET_POOL object clusters
+    (ids >= 1; channel 0 is the background) whose centres are highest: a target is specified
+    from what the initial views observe, and a uniform draw over every object would often
+    land on one buried at the bottom of the pile, which no elevated view sees.
     """
     if k < clusters:
         raise ValueError("object-vector length must cover every cluster")
@@ -129,7 +132,10 @@ def make_scene(n: int, clusters: int, k: int, seed: int, object_centric: bool = 
     mix = np.broadcast_to(((1.0 - conf) / k)[:, None], (n, k)).copy()
     mix[np.arange(n), cluster] += conf
     obj_logit = np.log(mix)
-    target = int(rng.integers(1, clusters)) if object_centric else -1
+    target = -1
+    if object_centric:
+        pool = 1 + np.argsort(-centres[1:, 2], kind="stable")[:min(TARGET_POOL, clusters - 1)]
+        target = int(pool[rng.integers(0, len(pool))])
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Scene(n=n, k=k, mean=f32(mean.T), log_scale=f32(log_scale.T), rot=f32(q.T),
                  opacity_logit=f32(opacity_logit), rgb=f32(rgb.T), obj_logit=f32(obj_logit.T),
