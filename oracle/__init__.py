@@ -138,6 +138,9 @@ def lib():
             L.or_pixel_rows.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_int, P, P, P, P]
             L.or_pixel_eval_frozen.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_int, P, P]
             L.or_score.argtypes = [P, C.c_int, P, C.c_int, P, P, P, C.c_int, P, P, P, P, P, P, P]
+            L.or_last_score_seconds.argtypes = [P, C.c_int]
+            L.or_last_score_seconds.restype = C.c_int
+            L.or_set_setup_threads.argtypes = [C.c_int]
             L.or_train_blocks.argtypes = [P, C.c_int, P, P, P, C.c_int, C.c_int, P, P, P, P, P]
             L.or_render_grad.argtypes = [P, P, P, P, C.c_int, P, P, P, P]
             _lib = L
@@ -330,11 +333,15 @@ class ScoreResult:
     best: int
     stats: np.ndarray      # [V][2] touched Gaussians U, contributing pairs P
     trace_total: np.ndarray = None  # [3] S_T of the trace criterion (0 for log det)
+    seconds: tuple = (0.0, 0.0)     # wall clock: training information + normalisers, candidates
+    cand_seconds: np.ndarray = None  # [V] wall clock of each candidate
 
 
 def score(scene, train_cams, cand_cams, rp: RasterParams = RasterParams(), ig: IGParams = IGParams(),
-          threads: Optional[int] = None) -> ScoreResult:
-    """Full next-best-view scoring of the candidates given the training views."""
+          threads: Optional[int] = None, setup_threads: int = 0) -> ScoreResult:
+    """Full next-best-view scoring of the candidates given the training views. setup_threads
+    > 0 runs the training views on that many threads (timing of the candidates alone)."""
+    lib().or_set_setup_threads(int(setup_threads))
     sb = _SceneBuf(scene)
     nt, nc = len(train_cams), len(cand_cams)
     tc, cc = _cams(train_cams), _cams(cand_cams)
@@ -344,7 +351,11 @@ def score(scene, train_cams, cand_cams, rp: RasterParams = RasterParams(), ig: I
     tt = np.zeros(3)
     st = lib().or_score(C.byref(sb.c), nt, tc, nc, cc, C.byref(rc), C.byref(igc), threads or default_threads(),
                         _ptr(igt), _ptr(igcand), _ptr(norm), _ptr(sc), C.byref(best), _ptr(stats), _ptr(tt))
-    return ScoreResult(int(st), igt[:nt], igcand[:nc], norm, sc[:nc], int(best.value), stats[:nc], tt)
+    secs = np.zeros(2 + nc)
+    lib().or_last_score_seconds(_ptr(secs), 2 + nc)
+    lib().or_set_setup_threads(0)
+    return ScoreResult(int(st), igt[:nt], igcand[:nc], norm, sc[:nc], int(best.value), stats[:nc], tt,
+                       (float(secs[0]), float(secs[1])), secs[2:])
 
 
 def train_blocks(scene, train_cams, query: Sequence[int], rp: RasterParams = RasterParams(),

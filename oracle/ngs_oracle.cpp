@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -1061,17 +1062,36 @@ int or_pixel_eval_frozen(const or_scene* s, const or_camera* cam, const or_raste
 // argmax (Eq. 5). ig_train [nt][3], ig_cand [nc][3], norm [3], scores [nc][4]
 // (normalised rgb, depth, object, combined). Returns 0, or -5 when an enabled
 // normaliser is not positive (scores then hold the raw gains only).
+// Wall-clock seconds of the last or_score call: [0] training information and normalisers,
+// [1] the candidates, then one entry per candidate (read by or_last_score_seconds; timing
+// only, no arithmetic). or_set_setup_threads(t > 0) runs the training views of later calls on
+// t threads instead of the call's own count (so that a single-threaded candidate timing does
+// not wait for a single-threaded training set).
+static std::vector<double> g_score_seconds(2, 0.0);
+static int g_setup_threads = 0;
+
+int or_last_score_seconds(double* out, int cap) {
+  const int n = (int)g_score_seconds.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = g_score_seconds[i];
+  return n;
+}
+
+void or_set_setup_threads(int t) { g_setup_threads = t; }
+
 int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or_camera* cand,
              const or_raster* rp, const or_ig* ig, int threads, double* ig_train, double* ig_cand,
              double* norm, double* scores, int32_t* best, int64_t* stats /*[nc][2]: U, pairs*/,
              double* trace_total /*[3] S_T of the trace criterion, may be NULL*/) {
+  using clock = std::chrono::steady_clock;
+  const auto t_start = clock::now();
+  g_score_seconds.assign(2 + (size_t)std::max(nc, 0), 0.0);
   GaussTerms gt = gaussian_terms(*s, *ig);
   const int k = s->k;
   std::vector<BlocksResult> tv;
   for (int t = 0; t < nt; ++t) {
     ViewCtx V{s, &train[t], rp, ig, &gt};
     view_setup(V);
-    tv.push_back(view_blocks(V, threads));
+    tv.push_back(view_blocks(V, g_setup_threads > 0 ? g_setup_threads : threads));
   }
   std::map<int, Blocks> HT = build_train(tv, gt, *ig, k);
   // trace criterion: f(V) = 1 / S_V with S_V = sum over all n Gaussians of trace(H_V,g^-1)
@@ -1101,7 +1121,9 @@ int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or
   const double beta[3] = {1.0, ig->beta_d, ig->beta_o};
   int b = -1;
   double bestv = -INFINITY;
+  const auto t_cand = clock::now();
   for (int c = 0; c < nc; ++c) {
+    const auto t_c = clock::now();
     ViewCtx V{s, &cand[c], rp, ig, &gt};
     view_setup(V);
     BlocksResult br = view_blocks(V, threads);
@@ -1117,8 +1139,11 @@ int or_score(const or_scene* s, int nt, const or_camera* train, int nc, const or
     }
     scores[4 * c + 3] = tot;
     if (status == 0 && tot > bestv) { bestv = tot; b = c; }
+    g_score_seconds[2 + c] = std::chrono::duration<double>(clock::now() - t_c).count();
   }
   *best = b;
+  g_score_seconds[0] = std::chrono::duration<double>(t_cand - t_start).count();
+  g_score_seconds[1] = std::chrono::duration<double>(clock::now() - t_cand).count();
   return status;
 }
 
