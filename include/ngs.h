@@ -184,11 +184,16 @@ typedef struct {
  *     rect of a weighted Gaussian reaches; the others add nothing to any statistic),
  * [5] views whose slot workspace overflowed,
  * [6] entries the back-to-front walk stages (per visited tile, from its last contributor
- *     to its nearest weighted entry that reaches a strip). */
-#define NGS_STATS_LEN 7
+ *     to its nearest weighted entry that reaches a strip),
+ * [7] contributing (pixel, Gaussian) pairs of the back-to-front walk (each updates the
+ *     pixel's colour, depth and object suffixes),
+ * [8] per-pixel records of weighted contributing pairs (each enters the 94 + 6k products of
+ *     the Gaussian's statistics). */
+#define NGS_STATS_LEN 9
 
-/* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch,
- * 3 = ngs_render_backward, 4 = ngs_sur_render_features (ngs_surrogate.h).
+/* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch (and
+ * ngs_training_setup, ngs_score_graph_create), 3 = ngs_render_backward,
+ * 4 = ngs_sur_render_features (ngs_surrogate.h), 5 = ngs_count_pairs.
  * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
  * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
  * at most 32; at most 32 for op 4, where it is the views per grouped render). All host. */
@@ -219,14 +224,25 @@ ngs_status ngs_prepare_scene(ngs_ctx* ctx, ngs_scene* scene, const ngs_ig_params
 ngs_status ngs_project(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cam,
                        const ngs_raster_params* rp, ngs_projected* out, void* stream);
 
-/* Tile binning and sorting: every (tile, Gaussian) pair of the rects sorted by
- * (tile, float32 depth bits, gid), and per-tile [start, end) ranges. Radix sort:
+/* Tile binning and sorting of the tile-based rasterizer of the 3DGS pipeline the paper
+ * builds on (Sec. IV-A.2; Sec. III-B.1 modifies that rasterizer): every (tile, Gaussian)
+ * pair of the rects sorted by (tile, float32 depth bits, gid), and per-tile [start, end)
+ * ranges. Radix sort:
  * depth digits over the visible Gaussians, then a stable pass on tile digits over the
  * emitted pairs. Syncs (reads M). If M > capacity returns NGS_CAPACITY with M in
  * *n_pairs. ws: ngs_workspace_size(0, ...) bytes. */
 ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
                         const ngs_camera* cam, const ngs_raster_params* rp, ngs_tile_lists* out,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* Capacity pre-pass of a scoring batch (run before ngs_score_batch or before capturing
+ * ngs_score_graph_create, whose buffers are sized once): projects every candidate of the
+ * host camera array (as ngs_project) and writes its number of (tile, Gaussian) pairs of the
+ * tile-based rasterizer (Sec. IV-A.2), pairs[v] (device int64 [n_views]), so that
+ * dims.max_pairs can be set to max_v pairs[v]. ws: ngs_workspace_size(5, dims) bytes (one
+ * view's projection). Stream-ordered, no host synchronisation. */
+ngs_status ngs_count_pairs(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,
+                           const ngs_raster_params* rp, int64_t* pairs, void* ws, size_t ws_bytes, void* stream);
 
 /* Front-to-back compositing per 16x16 tile (Eq. 1-2): colour, depth, object vector O,
  * final transmittance, argmax id, mean confidence, contributor count. */
@@ -242,7 +258,7 @@ ngs_status ngs_render(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected*
  * w_g A_g into h (w_g = c_g, or 1 when conf_on_train = 0); call ngs_hessian_finalize
  * after the last training view. stats (device int64 [NGS_STATS_LEN]) may be NULL.
  * ws: ngs_workspace_size(1, ...) bytes; its slot capacity (max_slots) must cover every
- * Gaussian with c_g > 0 whose rectangle reaches a tile of the view, else NGS_CAPACITY. */
+ * Gaussian with c_g > 0 that contributes to a pixel of the view, else NGS_CAPACITY. */
 ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
                          const ngs_tile_lists* lists, const ngs_camera* cam,
                          const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,
@@ -273,6 +289,29 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
                            const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores,
                            int32_t* best, double* ig_raw, int64_t* stats, const ngs_dims* dims,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* Training information and Eq. 10 normalisers of the initial views T (Sec. III-B, Eq. 9-10),
+ * in one call: resets the store h, adds c_g A_t,g of every training view t (ACCUMULATE, so
+ * H_T = lambda I + sum_t c_g A_t,g), computes the stored blocks' log-dets (and traces of
+ * their inverses when h->trinv is given), scores every training view against the finished
+ * H_T, and writes (all device FP64, caller-owned):
+ *   ig_train [n_train][3]  raw gains IG_f(T, t) (criterion 1: trace reductions R_f);
+ *   normalisers [3]        n_f = mean over t of IG_f(T, t) (Eq. 10); criterion 1: the mean
+ *                          of the set-function gains R / (S (S - R));
+ *   trace_total [3]        (may be NULL) S_f = sum over all n Gaussians of trace(H_T,g^-1),
+ *                          Gaussians without a stored block counting l_f / lambda (criterion 1;
+ *                          0 otherwise): the value ngs_ig_params.trace_total must carry when
+ *                          the candidates are scored.
+ * train: host array of n_train cameras. ig: mode is ignored. ws / dims: as for
+ * ngs_score_batch (ngs_workspace_size(2, dims) bytes; the training views run one after
+ * another on its first buffer set). Syncs. Returns NGS_CAPACITY if a training view exceeds
+ * dims->max_pairs or dims->max_slots or the store exceeds h->capacity (needed slots in
+ * *h->n_slots), NGS_DEGENERATE if an enabled normaliser is not positive (the outputs are
+ * written all the same). */
+ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const ngs_camera* train,
+                              int32_t n_train, const ngs_raster_params* rp, const ngs_ig_params* ig,
+                              double* normalisers, double* trace_total, double* ig_train, const ngs_dims* dims,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* Launch shapes of a context (all calls on it that follow use them; zero fields = defaults).
  * ig_lanes_per_pixel: lanes of the information-gain tile kernel per pixel, 1, 2 or 4: the

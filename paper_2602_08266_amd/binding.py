@@ -21,10 +21,10 @@ NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
 NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
 MODE_SCORE, MODE_ACCUMULATE = 0, 1
 OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
-STATS_LEN = 7
+STATS_LEN = 9
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
-           "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_bin_sort", "ngs_render",
-           "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_score_batch",
+           "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_count_pairs", "ngs_bin_sort", "ngs_render",
+           "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_training_setup", "ngs_score_batch",
            "ngs_score_graph_create", "ngs_score_graph_launch", "ngs_score_graph_destroy", "ngs_set_tuning",
            "ngs_get_tuning",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_enable_class", "ngs_profile_kernels", "ngs_profile_kernel_name",
@@ -126,11 +126,13 @@ def lib():
         L.ngs_prepare_scene.argtypes = [P, P, P, P]
         L.ngs_project.argtypes = [P, P, P, P, P, P]
         L.ngs_bin_sort.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_count_pairs.argtypes = [P, P, P, i32, P, P, P, C.c_size_t, P]
         L.ngs_render.argtypes = [P, P, P, P, P, P, P, P]
         L.ngs_info_gain.argtypes = [P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_hessian_reset.argtypes = [P, P, i32, P]
         L.ngs_hessian_finalize.argtypes = [P, P, P]
         L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_training_setup.argtypes = [P, P, P, P, i32, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_score_graph_create.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, C.c_size_t,
                                              C.POINTER(P)]
         L.ngs_score_graph_launch.argtypes = [P, P]
@@ -362,6 +364,20 @@ def ngs_bin_sort(ctx: Context, scene: DeviceScene, proj: Projected, cam: ngs_cam
             continue
         _check("ngs_bin_sort", st, ctx)
         return lists
+
+
+def ngs_count_pairs(ctx: Context, scene: DeviceScene, cams: Sequence[ngs_camera], rp: ngs_raster_params,
+                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Pair count M of every candidate (device int64 [V]): the capacity pre-pass of a batch."""
+    nv = len(cams)
+    pairs = torch.zeros(max(nv, 1), dtype=torch.int64, device=scene.device)
+    if ws is None:
+        ws = _bytes(workspace_size(5, scene.n, scene.k), scene.device)
+    arr = (ngs_camera * max(nv, 1))(*cams)
+    sc = scene.c()
+    _check("ngs_count_pairs", lib().ngs_count_pairs(ctx.handle, _ref(sc), arr, nv, _ref(rp), _p(pairs), _p(ws),
+                                                    ws.numel(), _stream()), ctx)
+    return pairs[:nv]
 
 
 def ngs_render(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLists, cam: ngs_camera,
@@ -635,6 +651,23 @@ def ngs_score_batch(ctx: Context, scene: DeviceScene, h: Optional[Hessian], norm
     return scores[:nv], best, ig_raw[:nv]
 
 
+def ngs_training_setup(ctx: Context, scene: DeviceScene, h: Hessian, train: Sequence[ngs_camera],
+                       rp: ngs_raster_params, ig: ngs_ig_params, ws: ScoreWorkspace):
+    """H_T and the Eq. 10 normalisers of the training views (one library call). Returns device
+    tensors (normalisers [3], trace_total [3], ig_train [T][3])."""
+    nt = len(train)
+    dev = scene.device
+    norm = torch.zeros(3, dtype=torch.float64, device=dev)
+    trace_total = torch.zeros(3, dtype=torch.float64, device=dev)
+    ig_train = torch.zeros((max(nt, 1), 3), dtype=torch.float64, device=dev)
+    arr = (ngs_camera * max(nt, 1))(*train)
+    sc, hc = scene.c(), h.c()
+    _check("ngs_training_setup", lib().ngs_training_setup(ctx.handle, _ref(sc), _ref(hc), arr, nt, _ref(rp), _ref(ig),
+                                                          _p(norm), _p(trace_total), _p(ig_train), _ref(ws.dims),
+                                                          _p(ws.buf), ws.buf.numel(), _stream()), ctx)
+    return norm, trace_total, ig_train[:nt]
+
+
 class ngs_tuning(C.Structure):
     _fields_ = [("ig_lanes_per_pixel", C.c_int32)]
 
@@ -738,7 +771,6 @@ class NbvScorer:
         self.max_pairs, self.max_slots, self.views_in_flight = max_pairs, max_slots, views_in_flight
         ngs_prepare_scene(ctx, scene, ig)
         self.h = Hessian(scene.n, scene.k, store_capacity, scene.device)
-        self.igws = IgWorkspace(scene, max_slots)
         self.norm = None
         self.ig_train = None
         self.ws = None
@@ -749,33 +781,18 @@ class NbvScorer:
         return proj, lists
 
     def setup(self, train_cams: Sequence[ngs_camera]):
-        ngs_hessian_reset(self.ctx, self.h, self.scene.n)
-        acc = ngs_ig_params(*[getattr(self.ig, f[0]) for f in ngs_ig_params._fields_])
-        acc.mode = MODE_ACCUMULATE
-        for cam in train_cams:
-            proj, lists = self._view(cam)
-            ngs_info_gain(self.ctx, self.scene, proj, lists, cam, self.rp, acc, self.h, self.igws)
-        ngs_hessian_finalize(self.ctx, self.h)
-        sc = ngs_ig_params(*[getattr(self.ig, f[0]) for f in ngs_ig_params._fields_])
-        sc.mode = MODE_SCORE
-        gains = []
-        for cam in train_cams:
-            proj, lists = self._view(cam)
-            gains.append(ngs_info_gain(self.ctx, self.scene, proj, lists, cam, self.rp, sc, self.h, self.igws))
-        self.ig_train = torch.stack(gains).cpu().numpy()
+        """H_T and the Eq. 10 normalisers of the training views (ngs_training_setup); the
+        values come back to the host for ngs_score_batch, which takes them by value."""
+        if self.ws is None:
+            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
+        norm, trace_total, ig_train = ngs_training_setup(self.ctx, self.scene, self.h, list(train_cams), self.rp,
+                                                         self.ig, self.ws)
+        self.ig_train = ig_train.cpu().numpy()
         if self.ig.criterion == 1:
-            # S_f = sum over all Gaussians of trace(H_T,g^-1): stored slots from the store, the
-            # rest carry the prior lambda I; the normalisers average f(T + t) - f(T) = R/(S(S - R))
-            used = min(int(self.h.n_slots.item()), self.h.capacity)
-            lam = float(np.float32(self.ig.lambda_prior))
-            dims = np.array([14.0, 11.0, 11.0 + self.scene.k])
-            st = self.h.trinv[:, :used].sum(dim=1).cpu().numpy() + (self.scene.n - used) * dims / lam
+            st = trace_total.cpu().numpy()
             self.ig.trace_total = (C.c_double * 3)(*[float(x) for x in st])
             self.trace_total = st
-            conv = self.ig_train / (st * (st - self.ig_train))
-            self.norm = conv.mean(axis=0)
-        else:
-            self.norm = self.ig_train.mean(axis=0)
+        self.norm = norm.cpu().numpy()
         return self.norm
 
     def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None, scaled: bool = True):

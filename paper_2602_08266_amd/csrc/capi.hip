@@ -84,7 +84,7 @@ constexpr size_t kIgHeader = 256;
 int64_t ig_slots_for(size_t ws_bytes, int64_t n, int64_t k) {
   if (ws_bytes < kIgHeader) return 0;
   const size_t per = (size_t)ig_stat_stride(k) * 4 + 4 + 7 * kNGeo * 8;
-  const size_t fixed = al((size_t)std::max<int64_t>(n, 1) * 4) + al((size_t)NGS_MAX_TILES * 4) + 4 * kAlign;
+  const size_t fixed = ig_ws_fixed_bytes(n) + 4 * kAlign;
   if (ws_bytes < kIgHeader + fixed) return 0;
   int64_t s = (int64_t)((ws_bytes - kIgHeader - fixed) / per);
   while (s > 0 && kIgHeader + ig_ws_bytes(n, k, s) > ws_bytes) --s;
@@ -98,6 +98,7 @@ ngs_status ig_prepare(ngs_ctx* ctx, void* ws, size_t ws_bytes, int64_t n, int64_
   *sticky = static_cast<int32_t*>(ws);
   *w = ig_ws_carve(static_cast<char*>(ws) + kIgHeader, n, k, slots);
   NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(*sticky), 0u, kIgHeader / 4, st));
+  NGS_TRY_HIP(ctx, launch_ig_clear_flags(*w, n, st));
   return NGS_OK;
 }
 
@@ -129,6 +130,26 @@ size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
   const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
   return al(nn * 8) + al(nn * 12) + al(nn * 4) + al(nn * 4) + al(nn * 8) + al(nn * 4) + al(mp * 4) +
          al(2 * NGS_MAX_TILES * 4) + al(8) + al(bin_ws_bytes(n, max_pairs));
+}
+
+// One view's projection arrays (ngs_count_pairs).
+size_t proj_set_bytes(int64_t n) {
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  return al(nn * 8) + al(nn * 12) + al(nn * 4) + al(nn * 4) + al(nn * 8) + al(nn * 4);
+}
+
+ngs_projected proj_carve(void* ws, int64_t n) {
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t b) { char* r = p; p += al(b); return r; };
+  ngs_projected pr;
+  pr.mean2d = (float*)take(nn * 8);
+  pr.conic = (float*)take(nn * 12);
+  pr.depth = (float*)take(nn * 4);
+  pr.zkey = (uint32_t*)take(nn * 4);
+  pr.rect = (int16_t*)take(nn * 8);
+  pr.count = (uint32_t*)take(nn * 4);
+  return pr;
 }
 
 constexpr int kDefaultInFlight = 8;
@@ -268,6 +289,7 @@ ngs_status ngs_workspace_size(int32_t op, const ngs_dims* d, size_t* bytes) {
       *bytes = kIgHeader + 2 * (size_t)views_in_flight(d, kMaxFeatureGroup) *
                                al(batch_fixed_bytes(d->n, d->max_pairs) + feat_img_bytes());
       return NGS_OK;
+    case 5: *bytes = proj_set_bytes(d->n); return NGS_OK;
     default: return NGS_INVALID_ARG;
   }
 }
@@ -318,6 +340,27 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
     return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
   }
   NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, w, *out, nullptr, nullptr, st));
+  return NGS_OK;
+}
+
+ngs_status ngs_count_pairs(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* cams, int32_t n_views,
+                           const ngs_raster_params* rp, int64_t* pairs, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !cams || n_views < 0 || !pairs) return NGS_INVALID_ARG;
+  ngs_status s = check_scene(scene, false);
+  if (s != NGS_OK) return s;
+  for (int v = 0; v < n_views; ++v) {
+    s = check_cam(&cams[v], rp);
+    if (s != NGS_OK) return s;
+  }
+  if (!ws || ws_bytes < proj_set_bytes(scene->n)) return NGS_WORKSPACE_TOO_SMALL;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  const ngs_projected pr = proj_carve(ws, scene->n);
+  NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(pairs), 0u, 2 * (size_t)n_views, st));
+  for (int v = 0; v < n_views; ++v) {
+    NGS_TRY_HIP(ctx, launch_project(*scene, make_devcam(cams[v], kTile), *rp, pr, st));
+    NGS_TRY_HIP(ctx, launch_sum_counts(pr, scene->n, pairs + v, st));
+  }
   return NGS_OK;
 }
 
@@ -485,6 +528,92 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
 }
 
 }  // namespace
+
+extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
+                                         const ngs_camera* train, int32_t n_train, const ngs_raster_params* rp,
+                                         const ngs_ig_params* ig, double* normalisers, double* trace_total,
+                                         double* ig_train, const ngs_dims* dims, void* ws, size_t ws_bytes,
+                                         void* stream) {
+  if (!ctx || !scene || !h || !train || n_train < 1 || !rp || !ig || !normalisers || !ig_train || !dims)
+    return NGS_INVALID_ARG;
+  if (!h->slot_of || !h->n_slots || !h->gid_of || !h->h_rgb || !h->h_d || !h->h_o || !h->logdet || h->capacity < 1)
+    return NGS_INVALID_ARG;
+  if (ig->criterion == 1 && !h->trinv) return NGS_INVALID_ARG;
+  ngs_ig_params acc = *ig, sc = *ig;
+  acc.mode = NGS_MODE_ACCUMULATE;
+  sc.mode = NGS_MODE_SCORE;
+  // check_batch validates the scene, the cameras and the workspace against dims
+  ngs_status s = check_batch(scene, h, train, n_train, rp, &sc, dims, ws, ws_bytes);
+  if (s == NGS_INVALID_ARG && ig->criterion == 1) {
+    // S_f is what this call computes: validate without it
+    for (int f = 0; f < 3; ++f) sc.trace_total[f] = 1.0;
+    s = check_batch(scene, h, train, n_train, rp, &sc, dims, ws, ws_bytes);
+    sc.trace_total[0] = sc.trace_total[1] = sc.trace_total[2] = 0.0;
+  }
+  if (s != NGS_OK) return s;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  size_t need = 0;
+  s = ngs_workspace_size(2, dims, &need);
+  if (s != NGS_OK) return s;
+  // the training views run one after another on buffer set 0
+  const size_t per = need / (size_t)views_in_flight(dims);
+  const BatchWs b = batch_carve(ws, per, scene->n, dims->max_pairs);
+  IgWs w;
+  int32_t* sticky = nullptr;
+  s = ig_prepare(ctx, b.ig, b.ig_bytes, scene->n, scene->k, st, &w, &sticky);
+  if (s != NGS_OK) return s;
+  const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
+  const RasterConst rc = make_raster(*rp);
+  const int lpp = ctx->tuning.ig_lanes_per_pixel;
+  // H_T = lambda I + sum_t c_g A_t,g (Eq. 9 with the prior)
+  NGS_TRY_HIP(ctx, launch_fill_i32(h->slot_of, -1, (size_t)scene->n, st));
+  NGS_TRY_HIP(ctx, launch_fill_i32(h->n_slots, 0, 1, st));
+  NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ig_train), 0u, (size_t)6 * n_train, st));
+  for (int pass = 0; pass < 2; ++pass) {
+    const ngs_ig_params& p = pass == 0 ? acc : sc;
+    for (int t = 0; t < n_train; ++t) {
+      const DevCam dc = make_devcam(train[t], kTile);
+      NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
+      NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
+      NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, p, w, st));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w)));
+      NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, rc, p, w, nullptr, lpp, st));
+      NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, p, w, h, pass == 0 ? nullptr : ig_train + 3 * (size_t)t,
+                                          nullptr, sticky, st));
+    }
+    if (pass == 0) {
+      // a view beyond the pair or slot capacity, or a store beyond its capacity, stops here
+      int64_t of = 0, used = 0;
+      s = read_i64(ctx, sticky, 4, st, &of);
+      if (s == NGS_OK) s = read_i64(ctx, h->n_slots, 4, st, &used);
+      if (s != NGS_OK) return s;
+      if (of || used > h->capacity) {
+        NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(sticky), 0u, 1, st));
+        return NGS_CAPACITY;
+      }
+      NGS_TRY_HIP(ctx, launch_hessian_logdet(h, (int32_t)used, ig->lambda_prior, st));
+    }
+  }
+  NGS_TRY_HIP(ctx, launch_train_normalisers(*h, scene->n, scene->k, *ig, ig_train, n_train, normalisers, trace_total,
+                                            st));
+  int64_t of = 0;
+  s = read_i64(ctx, sticky, 4, st, &of);
+  if (s != NGS_OK) return s;
+  if (of) {
+    NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(sticky), 0u, 1, st));
+    return NGS_CAPACITY;
+  }
+  // Eq. 10 needs positive normalisers for the enabled outputs
+  NGS_TRY_HIP(ctx, hipMemcpyAsync(ctx->pinned, normalisers, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
+  double nf[3];
+  std::memcpy(nf, ctx->pinned, sizeof nf);
+  for (int f = 0; f < 3; ++f)
+    if (((ig->outputs >> f) & 1u) && !(nf[f] > 0.0)) return NGS_DEGENERATE;
+  return NGS_OK;
+}
 
 struct ngs_score_graph {
   ngs_ctx* ctx = nullptr;

@@ -100,7 +100,7 @@ enum ProfId {
   kProfPrepare = 0, kProfProject, kProfDepthHist, kProfDepthScan, kProfDepthScatter, kProfCountScan,
   kProfEmit, kProfRanges, kProfKeys64, kProfRender, kProfIgTiles, kProfIgFinalize, kProfHessianLogdet,
   kProfCombine, kProfFill, kProfTileHist, kProfTileScan, kProfTileScatter, kProfIgAssign, kProfBwdTiles, kProfBwdParams, kProfSurGemm, kProfSurForward,
-  kProfSurBackward, kProfKernels
+  kProfSurBackward, kProfIgFront, kProfKernels
 };
 class ProfScope {
  public:
@@ -123,6 +123,8 @@ const char* prof_name(int id);
 hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st);
 hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
                           const ngs_projected& out, hipStream_t st);
+// Adds the view's pair count (sum of p.count over n Gaussians) to *total (device).
+hipError_t launch_sum_counts(const ngs_projected& p, int n, int64_t* total, hipStream_t st);
 
 // Radix-sort building blocks (sort.hip).
 struct SortWs {
@@ -186,10 +188,14 @@ struct IgWs {
   int32_t* n_slots;     // [1]
   int32_t* overflow;    // [1]
   double* pmat;         // [max_slots][7][11] chain-rule matrix P of each slot (finalize)
-  int32_t* tflag;       // [NGS_MAX_TILES] tiles reached by a slotted Gaussian's rect
+  int32_t* tflag;       // [NGS_MAX_TILES] tiles reached by a weighted Gaussian's rect
+  uint8_t* cflag;       // [n] Gaussians that contribute to a pixel (pass 1; zero between views)
+  float* pix_t;         // [NGS_MAX_TILES][256] final transmittance per pixel (pass 1)
+  int32_t* pix_last;    // [NGS_MAX_TILES][256] last contributor's list position, -1 for none
   int64_t max_slots;
 };
 int ig_stat_stride(int64_t k);
+size_t ig_ws_fixed_bytes(int64_t n);  // the part that does not grow with the slots
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
 // lpp: lanes per pixel of the tile kernel (1, 2 or 4; 0 = the default for k); it sets the
@@ -197,8 +203,11 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
                            const IgWs& w, int64_t* stats, int lpp, hipStream_t st);
-// The two halves of launch_ig_tiles: slot assignment (and, with a target object, the flags of
-// the tiles that a slotted Gaussian's rect reaches; see ig_tile_flags), then the tile walk.
+// The two halves of launch_ig_tiles: with a target object the flags of the tiles that a
+// weighted Gaussian's rect reaches (see ig_tile_flags; needed before the filtered binning),
+// then the walk (front pass, slots of the contributing weighted Gaussians, back pass).
+// launch_ig_clear_flags zeroes the contribution flags of a fresh workspace.
+hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st);
 hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const DevCam& cam, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st);
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
@@ -211,6 +220,9 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
                               double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);
 hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st);
+// Eq. 10 normalisers (and, for the trace criterion, S_f) from the training views' raw gains.
+hipError_t launch_train_normalisers(const ngs_hessian& h, int n, int k, const ngs_ig_params& ig, const double* ig_train,
+                                    int n_train, double* norm, double* trace_total, hipStream_t st);
 // Backward rasterizer (backward.hip).
 size_t bwd_ws_bytes(int64_t n, int64_t k);
 hipError_t launch_render_backward(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,

@@ -583,6 +583,50 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_r
   return hipGetLastError();
 }
 
+// Eq. 10 normalisers of the training set: n_f = mean over the training views t of IG_f(T, t).
+// For the trace-based f (Sec. III-B) the per-view quantity is the set-function gain
+// f(T + t) - f(T) = R / (S (S - R)) of the raw trace reduction R, where S_f = sum over every
+// Gaussian of trace(H_T,g^-1): the stored slots' traces plus l_f / lambda for each of the
+// other n - used Gaussians (H_T = lambda I). One block; the slot sum runs in a fixed order.
+__global__ __launch_bounds__(256) void k_train_norm(const double* __restrict__ trinv, const int32_t* __restrict__ n_slots,
+                                                     int capacity, int n, int k, double lambda, int criterion,
+                                                     const double* __restrict__ ig_train, int n_train,
+                                                     double* __restrict__ norm, double* __restrict__ trace_total) {
+  __shared__ double sm[3][256];
+  const int used = trinv ? min(*n_slots, capacity) : 0;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (criterion == 1 && trinv)
+    for (int s = threadIdx.x; s < used; s += 256)
+      for (int f = 0; f < 3; ++f) acc[f] += trinv[(size_t)f * capacity + s];
+  for (int f = 0; f < 3; ++f) sm[f][threadIdx.x] = acc[f];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int f = 0; f < 3; ++f) sm[f][threadIdx.x] += sm[f][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double dims[3] = {14.0, 11.0, 11.0 + (double)k};
+  for (int f = 0; f < 3; ++f) {
+    const double S = criterion == 1 ? sm[f][0] + (double)(n - used) * dims[f] / lambda : 0.0;
+    double mean = 0.0;
+    for (int t = 0; t < n_train; ++t) {
+      const double r = ig_train[3 * t + f];
+      mean += criterion == 1 ? r / (S * (S - r)) : r;
+    }
+    norm[f] = n_train > 0 ? mean / (double)n_train : 0.0;
+    if (trace_total) trace_total[f] = S;
+  }
+}
+
+hipError_t launch_train_normalisers(const ngs_hessian& h, int n, int k, const ngs_ig_params& ig, const double* ig_train,
+                                    int n_train, double* norm, double* trace_total, hipStream_t st) {
+  ProfScope ps(kProfCombine, st);
+  hipLaunchKernelGGL(k_train_norm, dim3(1), dim3(256), 0, st, ig.criterion == 1 ? h.trinv : nullptr, h.n_slots,
+                     h.capacity, n, k, (double)ig.lambda_prior, ig.criterion, ig_train, n_train, norm, trace_total);
+  return hipGetLastError();
+}
+
 hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st) {
   const int used = std::min(n_slots, h->capacity);
   if (used <= 0) return hipSuccess;

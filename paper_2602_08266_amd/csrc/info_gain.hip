@@ -11,21 +11,26 @@
 // the w's: the 94 + 6k statistics listed in common.hpp. This kernel produces them; the
 // FP64 chain rule through P, the blocks and the log-dets are in finalize.hip.
 //
-// Before the tile walk a pre-pass gives an accumulator slot to every Gaussian that has a
-// nonzero confidence weight and reaches at least one tile of the view, and zeroes the
-// slots; all other Gaussians get slot -1 and are never reduced.
-//
-// One 256-lane workgroup per tile. Pass 1 walks front to back to find each pixel's final
-// transmittance and last contributor. Pass 2 walks back to front from the tile's last
-// contributor, recovering T before each Gaussian as T_after / (1 - alpha) and keeping the
-// suffixes S in registers. For each slotted Gaussian, the wavefront's contributing lanes
-// write their per-pixel records (and object suffixes) to LDS rows, packed by rank, 16 rows
-// at a time; then every lane owns statistics (one or two scalar ones and the six Z_o
-// entries of one object channel) and sums them over the packed rows only, so the cost
-// follows the number of contributing pixels, not the 64 lanes. The sums go to the slot
-// with atomic adds on contiguous addresses. In both passes a wavefront only visits the
-// batch entries whose conservative 3-sigma bounding box reaches its 16 x 4 pixel strip (a
-// ballot mask); the skipped entries would fail the cut-off test at every one of its pixels.
+// The walk runs in three launches per view:
+//   1. k_ig_front, one 256-lane workgroup per tile, one lane per pixel: the front-to-back pass
+//      that gives each pixel its final transmittance and its last contributor (stored per
+//      pixel), and flags every Gaussian that contributes to some pixel;
+//   2. k_ig_slots: an accumulator slot for every flagged Gaussian with a nonzero confidence
+//      weight (U of them; every other Gaussian gets slot -1 and is never reduced), zeroed by
+//      k_ig_zero;
+//   3. k_ig_back, one workgroup per tile with one, two or four lanes per pixel: the
+//      back-to-front pass from the tile's last contributor, recovering T before each Gaussian
+//      as T_after / (1 - alpha) and keeping the suffixes S in registers. For each slotted
+//      Gaussian, the wavefront's contributing lanes write their per-pixel records (and object
+//      suffixes) to LDS rows, packed by rank, 16 rows at a time; then every lane owns
+//      statistics (one or two scalar ones and the six Z_o entries of one object channel) and
+//      sums them over the packed rows only, so the cost follows the number of contributing
+//      pixels, not the 64 lanes. The sums go to the slot with atomic adds on contiguous
+//      addresses.
+// In both passes a wavefront only visits the batch entries whose conservative 3-sigma
+// bounding box reaches its 16 x 4 pixel strip (a ballot mask); the skipped entries would fail
+// the cut-off test at every one of its pixels. With a target object (Eq. 12) a pre-pass marks
+// the tiles that the rect of a weighted Gaussian reaches, and both passes leave the others.
 #include "common.hpp"
 
 namespace ngs {
@@ -124,13 +129,114 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
          S.my[l] - S.hy[l] <= sy1;
 }
 
+// Pass 1 of one tile: 256 lanes, one per pixel, four wavefronts of 16 x 4 strips, each walking
+// the list on its own: lane l holds batch entry l in registers (the next batch is loaded
+// while the current one is walked), the walk reads an entry's values with readlane, and a
+// wavefront stops once all its pixels are done. Writes each pixel's final transmittance and
+// last contributor (list position, -1 for none), and flags (cflag[g] = 1) every Gaussian
+// that contributes to a pixel.
+__global__ __launch_bounds__(kTilePix) void k_ig_front(
+    int n, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
+    const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ opacity,
+    float* __restrict__ pix_t, int32_t* __restrict__ pix_last, uint8_t* __restrict__ cflag,
+    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag) {
+  __shared__ int tile_last_sh;
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  const int tile = blockIdx.x;
+  if (tflag && tflag[tile] == 0) return;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int pix = threadIdx.x;
+  const int px = tx * kTile + (pix & (kTile - 1));
+  const int py = ty * kTile + (pix / kTile);
+  const bool inside = px < cam.width && py < cam.height;
+  const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
+  const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
+  const float sy0 = (float)(ty * kTile + wave * 4) + 0.5f, sy1 = sy0 + 3.f;
+  float T = 1.f;
+  int last = -1, nc = 0;
+  bool done = !inside;
+  // batch entry of this lane: gid and geometry, the next batch's in flight
+  uint32_t g_n = 0u;
+  float nmx = 0.f, nmy = 0.f, nqa = 0.f, nqb = 0.f, nqc = 0.f, nop = 0.f;
+  auto load = [&](uint32_t b) {
+    if (b < end && lane < (int)(end - b)) {
+      g_n = gids[b + lane];
+      nmx = mean2d[g_n]; nmy = mean2d[n + g_n];
+      nqa = conic[g_n]; nqb = conic[n + g_n]; nqc = conic[2 * n + g_n];
+      nop = opacity[g_n];
+    }
+  };
+  load(start);
+  for (uint32_t b0 = start; b0 < end; b0 += kWave) {
+    if (__ballot(!done) == 0ull) break;
+    const int cnt = (int)min((uint32_t)kWave, end - b0);
+    const uint32_t eg = g_n;
+    const float emx = nmx, emy = nmy, eqa = nqa, eqb = nqb, eqc = nqc, eop = nop;
+    float ehx = -1.f, ehy = -1.f;
+    if (lane < cnt) conic_extent(eqa, eqb, eqc, rc.cutoff_q, &ehx, &ehy);
+    load(b0 + kWave);
+    uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
+                             emy - ehy <= sy1);
+    uint64_t mine = 0ull;  // batch entries that contribute to this lane's pixel
+    if (!done) {
+      while (live) {
+        const int j = __ffsll((unsigned long long)live) - 1;
+        live &= live - 1;
+        const float mxj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emx), j));
+        const float myj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emy), j));
+        const float qaj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqa), j));
+        const float qbj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqb), j));
+        const float qcj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqc), j));
+        const float opj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eop), j));
+        const float dx = fxp - mxj, dy = fyp - myj;
+        const float q = conic_q(qaj, qbj, qcj, dx, dy);
+        if (q > rc.cutoff_q) continue;
+        const float alpha = fminf(rc.alpha_max, gauss_alpha(opj, q));
+        if (alpha < rc.alpha_min) continue;
+        const float Tn = transmit(T, alpha);
+        if (Tn < rc.t_min) { done = true; break; }
+        T = Tn;
+        last = (int)(b0 + j);
+        ++nc;
+        mine |= 1ull << j;
+      }
+    }
+    // entries that contribute to some pixel of the wavefront: OR over the lanes' masks
+    uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      lo |= (uint32_t)__shfl_xor((int)lo, off);
+      hi |= (uint32_t)__shfl_xor((int)hi, off);
+    }
+    const uint64_t any = ((uint64_t)hi << 32) | lo;
+    if ((any >> lane) & 1ull) cflag[eg] = 1;
+  }
+  if (inside) {
+    pix_t[(size_t)tile * kTilePix + pix] = T;
+    pix_last[(size_t)tile * kTilePix + pix] = last;
+  }
+  if (!stats) return;
+  if (threadIdx.x == 0) tile_last_sh = -1;
+  __syncthreads();
+  if (last >= 0) atomicMax(&tile_last_sh, last);
+  int tot = nc;
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+  if (lane == 0 && tot) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)tot);
+  __syncthreads();
+  if (threadIdx.x == 0 && tile_last_sh >= 0)
+    atomicAdd((unsigned long long*)&stats[4], (unsigned long long)(tile_last_sh - (int)start + 1));
+}
+
 template <int KP, int LPP>
-__global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_ig_tile(
+__global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_ig_back(
     int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
     int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
-    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag) {
+    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag, const float* __restrict__ pix_t,
+    const int32_t* __restrict__ pix_last) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   IgShared<KP, LPP>& S = *reinterpret_cast<IgShared<KP, LPP>*>(smem_raw);
   constexpr int kThreads = kTilePix * LPP;
@@ -162,62 +268,18 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
   const float sy0 = (float)(ty * kTile + wave * kRowsW) + 0.5f, sy1 = sy0 + (float)(kRowsW - 1);
 
-  // ---- pass 1: front to back, final transmittance and last contributor -----------------
-  // Each wavefront walks on its own: lane l holds batch entry l in registers, the walk reads
-  // an entry's values with readlane, and a wavefront stops once all its pixels are done.
+  // final transmittance and last contributor of this lane's pixel (pass 1)
   float T = 1.f;
-  int last = -1, nc = 0;
-  bool done = !inside;
-  for (uint32_t b0 = start; b0 < end; b0 += kWave) {
-    if (__ballot(!done) == 0ull) break;
-    const int cnt = (int)min((uint32_t)kWave, end - b0);
-    float emx = 0.f, emy = 0.f, eqa = 0.f, eqb = 0.f, eqc = 0.f, eop = 0.f, ehx = -1.f, ehy = -1.f;
-    if (lane < cnt) {
-      const uint32_t g = gids[b0 + lane];
-      emx = mean2d[g]; emy = mean2d[n + g];
-      eqa = conic[g]; eqb = conic[n + g]; eqc = conic[2 * n + g];
-      eop = opacity[g];
-      conic_extent(eqa, eqb, eqc, rc.cutoff_q, &ehx, &ehy);
-    }
-    uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
-                             emy - ehy <= sy1);
-    if (!done) {
-      while (live) {
-        const int j = __ffsll((unsigned long long)live) - 1;
-        live &= live - 1;
-        const float mxj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emx), j));
-        const float myj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, emy), j));
-        const float qaj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqa), j));
-        const float qbj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqb), j));
-        const float qcj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eqc), j));
-        const float opj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eop), j));
-        const float dx = fxp - mxj, dy = fyp - myj;
-        const float q = conic_q(qaj, qbj, qcj, dx, dy);
-        if (q > rc.cutoff_q) continue;
-        const float alpha = fminf(rc.alpha_max, gauss_alpha(opj, q));
-        if (alpha < rc.alpha_min) continue;
-        const float Tn = transmit(T, alpha);
-        if (Tn < rc.t_min) { done = true; break; }
-        T = Tn;
-        last = (int)(b0 + j);
-        ++nc;
-      }
-    }
+  int last = -1;
+  if (inside) {
+    T = pix_t[(size_t)tile * kTilePix + pix];
+    last = pix_last[(size_t)tile * kTilePix + pix];
   }
-  // tile extent of pass 2 and whether any walked Gaussian carries weight
   if (threadIdx.x == 0) S.flag = -1;
   __syncthreads();
   if (last >= 0) atomicMax(&S.flag, last);
   __syncthreads();
   const int tile_last = S.flag;
-  if (stats) {
-    // contributing (pixel, Gaussian) pairs P
-    int tot = h == 0 ? nc : 0;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane == 0 && tot) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)tot);
-    if (threadIdx.x == 0 && tile_last >= 0)
-      atomicAdd((unsigned long long*)&stats[4], (unsigned long long)(tile_last - (int)start + 1));
-  }
   if (tile_last < 0) return;
   // the wavefront's last contributor: entries behind it contribute to none of its pixels
   int wave_last = last;
@@ -264,6 +326,8 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
 #pragma unroll
   for (int c = 0; c < KL; ++c) So[c] = 0.f;
   if (obj_eq2 && h == 0) So[0] = t_final;  // S~ = S_o + T_final e_0
+  // counts for the statistics: contributing (pixel, entry) pairs of this pass and records
+  uint32_t n_pass2 = 0u, n_rec = 0u;
   for (int hi = tile_last + 1; hi > first_w; hi -= kBatch) {
     const int lo = max(first_w, hi - kBatch);
     const int cnt = hi - lo;
@@ -353,6 +417,7 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
         // among the others
         const uint64_t pmask = cmask & kH0;
         const int cnt = __popcll(pmask);
+        n_rec += (uint32_t)cnt;
         const uint64_t below = (1ull << (lane - h)) - 1ull;
         const int rank = __popcll(pmask & below);
         const int nrank = __popcll(~pmask & kH0 & below);
@@ -404,12 +469,21 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
         }
       }
       if (contrib) {
+        n_pass2 += h == 0 ? 1u : 0u;
         Sr += S.r[j] * a; Sg += S.g[j] * a; Sb += S.b[j] * a;
         Sd += S.z[j] * a;
 #pragma unroll
         for (int c = 0; c < KL; ++c) So[c] += S.p[j][h * KL + c] * a;
         Tc = Tg;
       }
+    }
+  }
+  if (stats) {
+    uint32_t tot = n_pass2;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (lane == 0) {
+      if (tot) atomicAdd((unsigned long long*)&stats[7], (unsigned long long)tot);
+      if (n_rec) atomicAdd((unsigned long long*)&stats[8], (unsigned long long)n_rec);
     }
   }
 }
@@ -423,20 +497,41 @@ __global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots, int32_t* ove
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) tflag[i] = 0;
 }
 
-// Slot of every Gaussian for this view: a fresh slot for each one that has a nonzero
-// confidence weight and reaches a tile, -1 otherwise. Each 256-thread block covers
-// kAssignPer x 256 Gaussians (coalesced), ranks its selected ones with a block scan and
-// takes its slots with a single counter update. With tflag, every slotted Gaussian also marks
-// the tiles of its rect, so that the tile kernel can leave the other tiles at once; the cost
-// is the rect areas of the slotted Gaussians, small when only one object carries weight.
+// With a target object: flags the tiles that the rect of a weighted Gaussian (nonzero
+// confidence, reaching a tile) covers, so that both passes and the filtered binning can leave
+// the other tiles at once. A wavefront marks the rects of its weighted Gaussians together,
+// one Gaussian at a time; the cost is the rect areas of the weighted Gaussians, small when only
+// one object carries weight.
+__global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict__ conf,
+                                                 const uint32_t* __restrict__ count, const int16_t* __restrict__ rect,
+                                                 int32_t* __restrict__ tflag, int tiles_x, int tiles_y) {
+  const int lane = threadIdx.x % kWave;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  uint64_t m = __ballot(g < n && count[g] > 0u && conf[g] > 0.f);
+  const int gw = g - lane;
+  while (m) {
+    const int j = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const short4 r = *reinterpret_cast<const short4*>(rect + 4 * (size_t)(gw + j));
+    const int x0 = max((int)r.x, 0), y0 = max((int)r.y, 0);
+    const int x1 = min((int)r.z, tiles_x - 1), y1 = min((int)r.w, tiles_y - 1);
+    if (x1 < x0 || y1 < y0) continue;
+    const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
+    for (int t = lane; t < area; t += kWave) tflag[(y0 + t / w) * tiles_x + x0 + t % w] = 1;
+  }
+}
+
+// Slot of every Gaussian for this view: a fresh slot for each one that pass 1 flagged (it
+// contributes to a pixel) and that has a nonzero confidence weight, -1 otherwise; the flags
+// are cleared for the next view. Each 256-thread block covers kAssignPer x 256 Gaussians
+// (coalesced), ranks its selected ones with a block scan and takes its slots with a single
+// counter update.
 constexpr int kAssignPer = 4;
 
-__global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restrict__ conf,
-                                                   const uint32_t* __restrict__ count, int32_t* __restrict__ slot_of,
-                                                   int32_t* __restrict__ gid_of, int32_t* __restrict__ n_slots,
-                                                   int32_t* __restrict__ overflow, int max_slots,
-                                                   const int16_t* __restrict__ rect, int32_t* __restrict__ tflag,
-                                                   int tiles_x, int tiles_y) {
+__global__ __launch_bounds__(256) void k_ig_slots(int n, const float* __restrict__ conf, uint8_t* __restrict__ cflag,
+                                                  int32_t* __restrict__ slot_of, int32_t* __restrict__ gid_of,
+                                                  int32_t* __restrict__ n_slots, int32_t* __restrict__ overflow,
+                                                  int max_slots) {
   __shared__ int wsum[256 / kWave];
   __shared__ int base_sh;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -445,7 +540,10 @@ __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restric
 #pragma unroll
   for (int i = 0; i < kAssignPer; ++i) {
     const int g = g0 + i * 256;
-    if (g < n && count[g] > 0u && conf[g] > 0.f) bits |= 1u << i;
+    if (g < n && cflag[g]) {
+      cflag[g] = 0;
+      if (conf[g] > 0.f) bits |= 1u << i;
+    }
   }
   const int c = __popc(bits);
   int x = c;  // inclusive scan over the wavefront
@@ -464,7 +562,6 @@ __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restric
   __syncthreads();
   int slot = base_sh + x - c;
   for (int w = 0; w < wave; ++w) slot += wsum[w];
-  uint32_t slotted = 0u;
 #pragma unroll
   for (int i = 0; i < kAssignPer; ++i) {
     const int g = g0 + i * 256;
@@ -475,27 +572,10 @@ __global__ __launch_bounds__(256) void k_ig_assign(int n, const float* __restric
       slot_of[g] = slot;
       gid_of[slot] = g;
       ++slot;
-      slotted |= 1u << i;
     } else {
       slot_of[g] = -1;
       atomicOr(overflow, 1);
       ++slot;
-    }
-  }
-  if (!tflag) return;
-  // the wavefront marks the rects of its slotted Gaussians together, one Gaussian at a time
-  for (int i = 0; i < kAssignPer; ++i) {
-    uint64_t m = __ballot((slotted >> i) & 1u);
-    while (m) {
-      const int j = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      const int g = blockIdx.x * (256 * kAssignPer) + wave * kWave + j + i * 256;
-      const short4 r = *reinterpret_cast<const short4*>(rect + 4 * (size_t)g);
-      const int x0 = max((int)r.x, 0), y0 = max((int)r.y, 0);
-      const int x1 = min((int)r.z, tiles_x - 1), y1 = min((int)r.w, tiles_y - 1);
-      if (x1 < x0 || y1 < y0) continue;
-      const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
-      for (int t = lane; t < area; t += kWave) tflag[(y0 + t / w) * tiles_x + x0 + t % w] = 1;
     }
   }
 }
@@ -516,9 +596,9 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
   const size_t shm = sizeof(IgShared<KP, LPP>);
   static_assert(sizeof(IgShared<KP, LPP>) <= 65536, "IG kernel LDS");
   ProfScope ps(kProfIgTiles, st);
-  hipLaunchKernelGGL((k_ig_tile<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
+  hipLaunchKernelGGL((k_ig_back<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
-                     stats, tflag);
+                     stats, tflag, w.pix_t, w.pix_last);
   return hipGetLastError();
 }
 
@@ -526,23 +606,33 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
 
 int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
 
+size_t ig_ws_fixed_bytes(int64_t n) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  return al(nn * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al(nn) + 2 * al((size_t)NGS_MAX_TILES * kTilePix * 4);
+}
+
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  return al((size_t)ig_stat_stride(k) * (size_t)max_slots * 4) + al((size_t)std::max<int64_t>(n, 1) * 4) +
-         al((size_t)max_slots * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al((size_t)max_slots * 7 * kNGeo * 8);
+  return al((size_t)ig_stat_stride(k) * (size_t)max_slots * 4) + al((size_t)max_slots * 4) + ig_ws_fixed_bytes(n) +
+         al((size_t)max_slots * 7 * kNGeo * 8);
 }
 
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
   char* p = static_cast<char*>(ws);
   IgWs w;
   w.astride = ig_stat_stride(k);
   w.acc = (float*)p; p += al((size_t)w.astride * (size_t)max_slots * 4);
-  w.slot_of = (int32_t*)p; p += al((size_t)std::max<int64_t>(n, 1) * 4);
+  w.slot_of = (int32_t*)p; p += al(nn * 4);
   w.gid_of = (int32_t*)p; p += al((size_t)max_slots * 4);
   w.n_slots = (int32_t*)p; p += al(8);
   w.overflow = w.n_slots + 1;
   w.tflag = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * 4);
+  w.cflag = (uint8_t*)p; p += al(nn);
+  w.pix_t = (float*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
+  w.pix_last = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
   w.pmat = (double*)p;
   w.max_slots = max_slots;
   return w;
@@ -562,21 +652,36 @@ hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const De
     ProfScope ps(kProfFill, st);
     hipLaunchKernelGGL(k_ig_clear, dim3(1), dim3(256), 0, st, w.n_slots, w.overflow, tflag, ntiles);
   }
-  {
+  if (tflag && s.n > 0) {
     ProfScope ps(kProfIgAssign, st);
-    const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
-    hipLaunchKernelGGL(k_ig_assign, dim3(nb), dim3(256), 0, st, s.n, s.conf, p.count, w.slot_of, w.gid_of,
-                       w.n_slots, w.overflow, (int)w.max_slots, p.rect, tflag, cam.tiles_x, cam.tiles_y);
-    hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
-                       (int)w.max_slots, w.astride);
+    hipLaunchKernelGGL(k_ig_mark, dim3((s.n + 255) / 256), dim3(256), 0, st, s.n, s.conf, p.count, p.rect, tflag,
+                       cam.tiles_x, cam.tiles_y);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st) {
+  return launch_fill_u32(reinterpret_cast<uint32_t*>(w.cflag), 0u, ((size_t)std::max<int64_t>(n, 1) + 3) / 4, st);
 }
 
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                           hipStream_t st) {
   const int32_t* tflag = ig_tile_flags(ig, w);
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  {
+    ProfScope ps(kProfIgFront, st);
+    hipLaunchKernelGGL(k_ig_front, dim3(ntiles), dim3(kTilePix), 0, st, s.n, l.gids, l.ranges, cam, rc, p.mean2d,
+                       p.conic, s.opacity, w.pix_t, w.pix_last, w.cflag, stats, tflag);
+  }
+  {
+    ProfScope ps(kProfIgAssign, st);
+    const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
+    hipLaunchKernelGGL(k_ig_slots, dim3(nb), dim3(256), 0, st, s.n, s.conf, w.cflag, w.slot_of, w.gid_of, w.n_slots,
+                       w.overflow, (int)w.max_slots);
+    hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
+                       (int)w.max_slots, w.astride);
+  }
   // lanes per pixel (ig_lpp_valid): 0 picks the default of each object-vector width
   if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
                                 : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);

@@ -26,9 +26,9 @@ int64_t g_cnt[kProfKernels];
 
 const char* const kNames[kProfKernels] = {
     "prepare_scene", "project", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "count_scan",
-    "unused_emit", "unused_ranges", "tile_keys64", "render", "ig_tiles", "ig_finalize", "hessian_logdet",
+    "unused_emit", "unused_ranges", "tile_keys64", "render", "ig_back", "ig_finalize", "hessian_logdet",
     "score_combine", "fill", "tile_part_hist", "tile_part_scan", "tile_part_scatter", "ig_assign", "bwd_tiles", "bwd_params", "sur_gemm", "sur_forward",
-    "sur_backward"};
+    "sur_backward", "ig_front"};
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {

@@ -155,4 +155,30 @@ hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raste
   return hipGetLastError();
 }
 
+namespace {
+// Sum of the per-Gaussian tile counts (the view's pair count M) into *total.
+__global__ __launch_bounds__(256) void k_sum_counts(const uint32_t* __restrict__ count, int n,
+                                                    unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long sm[256 / 64];
+  unsigned long long v = 0ull;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) v += count[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = sm[0] + sm[1] + sm[2] + sm[3];
+    if (t) atomicAdd(total, t);
+  }
+}
+}  // namespace
+
+hipError_t launch_sum_counts(const ngs_projected& p, int n, int64_t* total, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 1024);
+  ProfScope ps(kProfCountScan, st);
+  hipLaunchKernelGGL(k_sum_counts, dim3(blocks), dim3(256), 0, st, p.count, n,
+                     reinterpret_cast<unsigned long long*>(total));
+  return hipGetLastError();
+}
+
 }  // namespace ngs
