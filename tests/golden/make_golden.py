@@ -4,7 +4,7 @@ Every value in the JSON files this script writes comes from ``oracle.score`` (FP
 oracle) on scenes and cameras regenerated from their seeds by ``scenegen``; nothing is taken
 from the GPU path. Run from the repository root:
 
-    python tests/golden/make_golden.py [mid|batched640 ...]
+    python tests/golden/make_golden.py [mid|batched640|batched ...]
 """
 import json
 import os
@@ -22,6 +22,9 @@ SPECS = {
     "mid": dict(seed=0, views=[0, 1, 40]),
     # object-centric scoring of the seeded target (Eq. 12), 1M Gaussians, k = 64, 640x480
     "batched640": dict(seed=0, views=[0, 17, 60]),
+    # the mixed-resolution batch: one view from each third (320x240, 640x480, 1280x720; view
+    # 200 is the batch's largest, 85M pairs)
+    "batched": dict(seed=0, views=[5, 120, 200]),
 }
 
 

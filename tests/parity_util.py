@@ -7,6 +7,16 @@ such a decision, so those "ambiguous" pixels only need |gpu - ref| <= 0.02 * max
 (one flipped Gaussian changes a pixel by at most sigma exp(-4.5) < 0.011 of a feature).
 Argmax ids: exact wherever the pixel is not ambiguous and the oracle's top-2 margin exceeds
 1e-5. Information gain: 1e-3 relative per output.
+
+The object vector O of a pixel (Eq. 2; its k entries sum to 1) is one rendered channel: its
+error is measured as a vector, ||O_gpu - O_ref||_1 <= 1e-4 ||O_ref||_1 = 1e-4. Entry by entry
+the relative bound does not hold in FP32: the 2D means are FP32 (half an ulp is 3e-5 px at
+640 px), so q = d^T Q d of a pixel 3 px from a mean is off by up to ~2e-5 relative and alpha
+by ~1e-4 at q near 9, and the transmittance behind a near-opaque Gaussian inherits its alpha
+error scaled by alpha / (1 - alpha); an entry of O fed mostly by Gaussians behind such a
+Gaussian can be off by a few 1e-4 of its own (small) value while the vector is within 1e-4.
+Every entry must still be within the per-entry bound of the other channels at 20x (2e-3 of
+max(|ref|, 1e-2)).
 """
 import numpy as np
 
@@ -37,7 +47,16 @@ def check_image(gpu, ref, k, depth_max):
     out["depth"] = check_channel("depth", gpu["depth"], ref["depth"], amb, depth_max)
     out["t_final"] = check_channel("t_final", gpu["t_final"], ref["t_final"], amb, 1.0)
     if gpu.get("obj") is not None:
-        out["obj"] = check_channel("obj", gpu["obj"], ref["obj"], amb[None], 1.0)
+        go = np.asarray(gpu["obj"], dtype=np.float64)
+        ro = np.asarray(ref["obj"], dtype=np.float64)
+        l1 = np.abs(go - ro).sum(axis=0)
+        bad = (l1 > REL * np.abs(ro).sum(axis=0)) & ~amb
+        assert not bad.any(), f"obj: {bad.sum()} pixels beyond 1e-4 in L1, worst {l1[bad].max():.3e}"
+        ent = np.abs(go - ro) > 20 * REL * np.maximum(np.abs(ro), TAU)
+        assert not (ent & ~amb[None]).any(), f"obj: {(ent & ~amb[None]).sum()} entries beyond 2e-3 rel"
+        if amb.any():
+            assert np.abs(go - ro)[:, amb].max() <= 0.02, "obj: ambiguous pixel off by more than 0.02"
+        out["obj"] = float(l1[~amb].max()) if (~amb).any() else 0.0
     if gpu.get("mean_conf") is not None:
         out["mean_conf"] = check_channel("mean_conf", gpu["mean_conf"], ref["kbar"], amb, 1.0)
     srt = np.sort(ref["obj"], axis=0)

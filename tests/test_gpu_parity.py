@@ -314,6 +314,42 @@ def test_score_batch_filtered_lists_mid(B, ctx, target):
     assert seen >= 2  # the target is in view of most candidates
 
 
+def test_count_pairs_prepass_matches_oracle(B, ctx):
+    """The capacity pre-pass (ngs_count_pairs) gives every view's pair count M exactly."""
+    log("test_count_pairs_prepass")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = device_scene(B, ctx, scene)
+    rp = B.raster_params()
+    away = scenegen.look_at(np.array([3.0, 0.0, 0.2]), 128, 96, 100.0, target=(6.0, 0.0, 0.2))
+    views = list(cands) + [away]
+    got = B.ngs_count_pairs(ctx, ds, [B.camera(c) for c in views], rp).cpu().numpy()
+    ref = [oracle.tile_lists(scene, c)["m"] for c in views]
+    log(f"  pairs {got.tolist()}")
+    assert got.tolist() == ref and ref[-1] == 0
+
+
+def test_training_setup_degenerate_and_capacity(B, ctx):
+    """ngs_training_setup reports a training set that sees nothing (all Eq. 10 normalisers
+    zero) as NGS_DEGENERATE, and a store smaller than the touched Gaussians as NGS_CAPACITY."""
+    log("test_training_setup errors")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = B.DeviceScene(scene, "cuda")
+    away = scenegen.look_at(np.array([3.0, 0.0, 0.2]), 128, 96, 100.0, target=(6.0, 0.0, 0.2))
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
+                         store_capacity=1 << 14)
+    with pytest.raises(B.NgsError) as e:
+        scorer.setup([B.camera(away)])
+    assert e.value.status == B.NGS_DEGENERATE
+    small = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
+                        store_capacity=8)
+    with pytest.raises(B.NgsError) as e:
+        small.setup([B.camera(c) for c in train])
+    assert e.value.status == B.NGS_CAPACITY
+    # the context and a correct store still work afterwards
+    norm = scorer.setup([B.camera(c) for c in train])
+    assert np.all(norm > 0)
+
+
 @pytest.mark.parametrize("target", [-1, 3])
 def test_greedy_nbv_sequence_tiny(B, ctx, target):
     """Three greedy steps: each chosen view joins the training set (H_T and normalisers are

@@ -48,25 +48,32 @@ def workload(name):
     return _cache[name]
 
 
-@pytest.mark.parametrize("name,view", [("mid", 0), ("batched640", 17)])
+@pytest.mark.parametrize("name,view", [("mid", 0), ("batched640", 17), ("batched", 5), ("batched", 200)])
 def test_lists_and_render_full_size(B, ctx, name, view):
-    log(f"full-size lists + render: {name} view {view}")
+    """Keys (64-bit), sorted lists, ranges and the capacity pre-pass bit for bit, and every
+    rendered plane (k = 64 object vectors included) against the oracle, at the workloads' full
+    sizes: 640x480, and the 320x240 and 1280x720 views of the mixed batch (view 200: 85M
+    pairs, 3,600 tiles)."""
+    log(f"full-size keys + lists + render: {name} view {view}")
     cfg, scene, cands, train = workload(name)
     cam = cands[view]
     ds = B.DeviceScene(scene, "cuda")
     B.ngs_prepare_scene(ctx, ds, B.ig_params(target_id=scene.target))
     rp = B.raster_params()
     c = B.camera(cam)
+    pairs = int(B.ngs_count_pairs(ctx, ds, [c], rp)[0].item())
     pr = B.ngs_project(ctx, ds, c, rp)
-    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=48 << 20)
+    lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=pairs, want_keys=True)
     m = int(lists.n_pairs.item())
     ref = oracle.tile_lists(scene, cam)
-    log(f"  pairs {m}")
-    assert m == ref["m"]
+    log(f"  pairs {m} ({cam.width}x{cam.height})")
+    assert m == ref["m"] == pairs
     assert np.array_equal(lists.gids[:m].cpu().numpy().view(np.uint32), ref["gids"])
     assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+    assert np.array_equal(lists.keys[:m].cpu().numpy().view(np.uint64), ref["keys"])
     del ref
-    img = B.ngs_render(ctx, ds, pr, lists, c, rp, want_obj=False)
+    img = B.ngs_render(ctx, ds, pr, lists, c, rp, want_obj=True)
+    del lists
     img = {k: (v.cpu().numpy() if v is not None else None) for k, v in img.items()}
     rimg = oracle.render(scene, cam)
     st = check_image(img, rimg, scene.k, depth_max=1.5)
@@ -87,7 +94,8 @@ def bench_shape(scene, width, height):
     return None
 
 
-@pytest.mark.parametrize("name,shape", [("mid", "default"), ("batched640", "default"), ("batched640", "bench")])
+@pytest.mark.parametrize("name,shape", [("mid", "default"), ("batched640", "default"), ("batched640", "bench"),
+                                        ("batched", "mixed")])
 def test_information_gain_full_size(B, ctx, name, shape):
     gold = json.load(open(os.path.join(HERE, "golden", f"ig_{name}_seed0.json")))
     log(f"full-size IG: {name} views {gold['views']} shape {shape}")
@@ -98,9 +106,16 @@ def test_information_gain_full_size(B, ctx, name, shape):
     # every Gaussian with a nonzero weight that reaches a tile takes a slot: up to n when the
     # whole scene is scored, a few per cent of n for one target (the bench's 32 buffer sets
     # take 2^17 slots each; more would overflow and fail loudly)
-    slots = 1 << 17 if shape == "bench" else max(scene.n, 1 << 16)
-    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=48 << 20, max_slots=slots,
-                         store_capacity=1 << 17)
+    slots = 1 << 17 if shape in ("bench", "mixed") else max(scene.n, 1 << 16)
+    max_pairs = 48 << 20
+    if shape == "mixed":
+        # capacity from the pre-pass over the sampled views and the training views
+        rp = B.raster_params()
+        cams = [B.camera(cands[v]) for v in gold["views"]] + [B.camera(t) for t in train]
+        max_pairs = int(B.ngs_count_pairs(ctx, ds, cams, rp).max().item())
+        log(f"  pre-pass: max pairs {max_pairs}")
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), ig, max_pairs=max_pairs, max_slots=slots,
+                         store_capacity=1 << 17, views_in_flight=4 if shape == "mixed" else 0)
     if shape == "bench":
         # the launch configuration the bench times: its tuned views in flight and lanes per pixel
         tuned = bench_shape(scene, cands[0].width, cands[0].height)
@@ -111,9 +126,23 @@ def test_information_gain_full_size(B, ctx, name, shape):
         log(f"  tuned shape: {tuned[0]} views in flight, {tuned[1]} lanes per pixel")
     # with the bench's shape the sample is repeated past the views in flight, so that every
     # buffer set is used and then reused in stream order
-    repeat = 1 if shape == "default" else scorer.views_in_flight // len(gold["views"]) + 2
+    # mixed: the three resolutions three times in one call on 4 buffer sets, so that every set
+    # serves views of different sizes in turn
+    repeat = {"default": 1, "mixed": 3}.get(shape, scorer.views_in_flight // len(gold["views"]) + 2)
     try:
         _check_gains(B, scorer, train, cands, gold, repeat)
+        if shape == "mixed":
+            # the same batch captured once into a HIP graph and replayed
+            views = list(gold["views"]) * repeat
+            g = B.ScoreGraph(ctx, ds, scorer.h, [B.camera(cands[v]) for v in views], B.raster_params(), ig,
+                             scorer.ws, normalisers=scorer.norm)
+            for rep in range(2):
+                scores, best, raw = g.replay()
+                raw = raw.cpu().numpy()
+                assert int(g.overflow.item()) == 0
+                for i, v in enumerate(views):
+                    check_gain(raw[i], gold["ig_cand"][i % len(gold["views"])], f"graph replay {rep} view {v}")
+            g.close()
     finally:
         B.ngs_set_tuning(ctx, 0)
 
