@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -50,14 +52,16 @@ def algorithmic_bytes(name, n, k, V, M, W, U, W2=0):
         return V * n * 12                        # rank order and the rect of every Gaussian
     if name == "tile_part_scatter":
         return 4 * M + V * n * 12                # final gid per pair + the same per-Gaussian reads
-    if name == "ig_tiles":
-        # front-to-back walk: list entry, 2D mean, conic and opacity of every walked entry;
+    if name == "ig_front":
+        # front-to-back walk: list entry, 2D mean, conic and opacity of every walked entry
+        return W * 28
+    if name == "ig_back":
         # back-to-front walk over the W2 entries from a tile's last contributor to its nearest
-        # weighted one: weight flag, depth, colour and the k-long probability row (the object
-        # suffixes of the weighted Gaussians in front sum the rows of every contributing
-        # Gaussian behind them); the statistics (94 + 6k floats) of every touched weighted
-        # Gaussian written
-        return W * 28 + W2 * (24 + 4 * k) + U * 4 * (94 + 6 * k)
+        # weighted one: list entry, geometry, weight flag, depth, colour and the k-long
+        # probability row (the object suffixes of the weighted Gaussians in front sum the rows
+        # of every contributing Gaussian behind them); the statistics (94 + 6k floats) of every
+        # touched weighted Gaussian written
+        return W2 * (48 + 4 * k) + U * 4 * (94 + 6 * k)
     return None
 
 
@@ -73,7 +77,8 @@ KERNEL_FILES = {
     "project": ["project.hip", "common.hpp"], "depth_sort_scatter": ["sort.hip", "common.hpp"],
     "depth_sort_hist": ["sort.hip", "common.hpp"], "count_scan": ["bin.hip", "common.hpp"],
     "tile_part_hist": ["bin.hip", "common.hpp"], "tile_part_scatter": ["bin.hip", "common.hpp"],
-    "ig_tiles": ["info_gain.hip", "common.hpp"], "ig_finalize": ["finalize.hip", "common.hpp"],
+    "ig_front": ["info_gain.hip", "common.hpp"], "ig_back": ["info_gain.hip", "common.hpp"],
+    "ig_finalize": ["finalize.hip", "common.hpp"],
 }
 
 
@@ -92,21 +97,70 @@ def read_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def ig_flops(name, k, P1, P2, R):
+    """FP32 operations of the information-gain walk kernels, from their own counts.
+    ig_front: P1 contributing (pixel, Gaussian) pairs of the front-to-back pass (offset,
+    quadratic form, opacity and transmittance: 15 each). ig_back: P2 contributing pairs of the
+    back-to-front pass (the same 15, T recovery 4, suffix updates of colour, depth and the k
+    object channels 2 (4 + k)) and R per-pixel records of weighted Gaussians (y and the channel
+    weights 24 + 5k, record products 36, and the 94 + 6k products summed into the statistics:
+    2 (94 + 6k))."""
+    if name == "ig_front":
+        return 15 * P1
+    if name == "ig_back":
+        return (19 + 2 * (4 + k)) * P2 + (60 + 5 * k + 2 * (94 + 6 * k)) * R
+    return None
+
+
 def cpu_baseline(workload_name, seed, views=3, threads=None):
     """The FP64 oracle timed on the host on a bounded sample: the first `views` candidate
-    views of the workload scored against H_T = lambda I (training blocks would triple the
-    time). Each view's work is split across the oracle's threads."""
+    views of the workload scored against the training set's H_T and Eq. 10 normalisers (built
+    by the oracle from the 4 training views first and timed apart); the oracle splits each
+    view's work across its threads."""
     import oracle
     import scenegen
     cfg, scene, cands, train = scenegen.make_workload(workload_name, seed)
     ig = oracle.IGParams(target_id=scene.target)
     th = threads or oracle.default_threads()
-    t0 = time.perf_counter()
-    oracle.score(scene, [], cands[:views], ig=ig, threads=th)
-    dt = time.perf_counter() - t0
-    return {"value": views / dt, "unit": "views/s", "cores": th, "kind": "oracle",
+    r = oracle.score(scene, train, cands[:views], ig=ig, threads=th)
+    setup_s, cand_s = r.seconds
+    mode = "object-centric" if scene.target >= 0 else "whole scene"
+    return {"value": views / cand_s, "unit": "views/s", "cores": th, "kind": "oracle",
             "sample": f"{views} candidate views ({cands[0].width}x{cands[0].height}, {scene.n} Gaussians, k={scene.k}, "
-                      f"object-centric), H_T = lambda I, FP64, {dt:.1f} s"}
+                      f"{mode}) scored against H_T of the {len(train)} training views, FP64: {cand_s:.1f} s "
+                      f"for the candidates (H_T and normalisers {setup_s:.1f} s, not counted)"}
+
+
+def cpu_plan(args):
+    """The oracle timed as planned for the reported CPU baseline: a seeded 16-candidate subset
+    scored against the training H_T, on all host cores (one call) and single-threaded (two
+    views, the training set built on all cores first), seconds per candidate view (median)."""
+    import statistics
+
+    import numpy as np
+
+    import oracle
+    import scenegen
+    cfg, scene, cands, train = scenegen.make_workload(args.workload, args.seed)
+    ig = oracle.IGParams(target_id=scene.target)
+    rng = np.random.default_rng(args.seed + 7)
+    subset = sorted(rng.choice(len(cands), size=min(16, len(cands)), replace=False).tolist())
+    allc = oracle.default_threads()
+    out = {"workload": args.workload, "subset": subset, "oracle_threads": allc, "host_cpu_count": os.cpu_count()}
+    log = lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush())
+    r = oracle.score(scene, train, [cands[v] for v in subset], ig=ig, threads=allc)
+    per = [float(x) for x in r.cand_seconds]
+    log(f"all cores ({allc} threads): setup {r.seconds[0]:.1f} s, candidates {per}")
+    out["all_cores"] = {"threads": allc, "views": len(subset), "median_s_per_view": statistics.median(per),
+                        "views_per_s": 1.0 / statistics.median(per), "setup_s": r.seconds[0], "per_view_s": per}
+    per1 = []
+    for v in subset[:2]:
+        r = oracle.score(scene, train, [cands[v]], ig=ig, threads=1, setup_threads=allc)
+        per1.append(float(r.cand_seconds[0]))
+        log(f"single thread: view {v} {per1[-1]:.1f} s (setup on {allc} threads {r.seconds[0]:.1f} s)")
+    out["single_thread"] = {"threads": 1, "views": len(per1), "median_s_per_view": statistics.median(per1),
+                            "views_per_s": 1.0 / statistics.median(per1), "per_view_s": per1}
+    print(json.dumps(out), flush=True)
 
 
 def run_backward(args):
@@ -291,6 +345,229 @@ def run_surrogate(args):
                      "avg_launch_us": round(gemm_ms / gemm_n * 1e3, 2) if gemm_n else None}}), flush=True)
 
 
+ALU_PEAK_TFLOPS = 157.3  # FP32 vector: 256 CUs x 128 lanes x 2 (FMA) x 2.4 GHz, the published MI355X figure
+
+
+def _round_up(x, m):
+    return (int(x) + m - 1) // m * m
+
+
+def make_scorer(B, ctx, ds, scene, rp, ig, cams, train, in_flight, log):
+    """Scorer whose pair capacity comes from the pre-pass (ngs_count_pairs) over the
+    candidates and the training views, rounded up to 1M pairs; whole-scene scoring takes a
+    statistics slot for every Gaussian that can contribute, one target a few per cent of n."""
+    pairs = B.ngs_count_pairs(ctx, ds, list(cams) + list(train), rp).cpu()
+    max_pairs = _round_up(int(pairs.max()), 1 << 20)
+    slots = 1 << 16 if scene.target >= 0 else _round_up(scene.n, 1 << 16)
+    log(f"capacity pre-pass: max pairs {int(pairs.max())} -> capacity {max_pairs}, slots {slots}")
+    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=max_pairs, max_slots=slots, store_capacity=1 << 17,
+                         views_in_flight=in_flight)
+    return scorer, pairs[:len(cams)]
+
+
+def serialized_roofline(B, ctx, scorer, cams, scene, K_views, log):
+    """One view in flight (launches never overlap): every kernel class bracketed by events for
+    the per-kernel breakdown, then only the dominant class, whose average launch duration and
+    kernel-counted work give the roofline. Also returns the per-view counts of the kernels."""
+    import torch
+    saved = scorer.views_in_flight
+    scorer.views_in_flight = 1
+    scorer.ws = None
+    scorer.score(cams)
+    torch.cuda.synchronize()
+    B.ngs_profile_enable(ctx, True)
+    scorer.score(cams)
+    torch.cuda.synchronize()
+    breakdown = {k: v for k, v in B.ngs_profile_read(ctx).items() if v[1] > 0}
+    dom = max(breakdown, key=lambda k: breakdown[k][0])
+    stats = torch.zeros(B.STATS_LEN, dtype=torch.int64, device="cuda:0")
+    B.ngs_profile_enable(ctx, True, only=dom)
+    torch.cuda.synchronize()
+    scorer.score(cams, stats)
+    torch.cuda.synchronize()
+    ms_tot, launches = B.ngs_profile_read(ctx)[dom]
+    B.ngs_profile_enable(ctx, False)
+    scorer.views_in_flight = saved
+    scorer.ws = None
+    st = stats.cpu().numpy().astype(np.float64)
+    V = len(cams)
+    counts = {"pairs_M": st[1] / V, "touched_weighted_U": st[2] / V, "contrib_pairs_P": st[3] / V,
+              "walked_entries_W": st[4] / V, "back_to_front_entries": st[6] / V,
+              "back_to_front_contrib_pairs": st[7] / V, "weighted_records": st[8] / V}
+    avg_s = ms_tot / launches / 1e3
+    per_launch = launches / V  # launches of the class per view
+    n, k = scene.n, scene.k
+    alg = algorithmic_bytes(dom, n, k, 1, st[1] / V, st[4] / V, st[2] / V, st[6] / V)
+    roof = {"kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches_timed": int(launches),
+            "views_in_flight": 1, "traffic": read_traffic(dom, scorer_workload_name(scene))}
+    hbm = None
+    if alg is not None:
+        b = alg / per_launch
+        hbm = {"achieved": round(b / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBS, 5), "algorithmic_bytes_per_launch": int(b)}
+    if dom in ("ig_front", "ig_back"):
+        fl = ig_flops(dom, k, st[3] / V, st[7] / V, st[8] / V) / per_launch
+        tf = fl / avg_s / 1e12
+        roof.update({"bound": "alu", "achieved": round(tf, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / ALU_PEAK_TFLOPS, 5), "flops_per_launch": int(fl), "hbm": hbm})
+    elif hbm is not None:
+        roof.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": hbm["frac"], "algorithmic_bytes_per_launch": hbm["algorithmic_bytes_per_launch"]})
+    else:
+        roof.update({"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None})
+    bd = {kk: round(v[0] / V * 1e3, 2) for kk, v in sorted(breakdown.items(), key=lambda x: -x[1][0])}
+    log(f"serialized pass: dominant {dom} {avg_s * 1e6:.1f} us per launch; per-view us {bd}")
+    return roof, counts, bd
+
+
+_WORKLOAD_OF_SCENE = {}
+
+
+def scorer_workload_name(scene):
+    return _WORKLOAD_OF_SCENE.get(id(scene), "")
+
+
+def run_exact(args, log):
+    import numpy as np  # noqa: F401
+    import torch
+
+    import scenegen
+    from paper_2602_08266_amd import binding as B
+
+    torch.cuda.set_device(0)
+    cfg, scene, cands, train = scenegen.make_workload(args.workload, args.seed, n_views=args.views)
+    _WORKLOAD_OF_SCENE[id(scene)] = args.workload
+    V = len(cands)
+    ctx = B.Context(0)
+    ds = B.DeviceScene(scene, "cuda:0")
+    rp = B.raster_params()
+    ig = B.ig_params(target_id=scene.target)
+    cam_c = [B.camera(c) for c in cands]
+    cam_t = [B.camera(c) for c in train]
+    scorer, pairs = make_scorer(B, ctx, ds, scene, rp, ig, cam_c, cam_t, args.in_flight, log)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    norm = scorer.setup(cam_t)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    tune = None
+    if not args.no_autotune:
+        # launch shapes from the package's tuning cache for this device and workload, else
+        # (or with --retune) timed now on 32 of the candidates
+        from paper_2602_08266_amd import autotune
+        if args.retune and os.path.exists(args.retune):
+            os.remove(args.retune)
+        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32, cache=args.retune or autotune.CACHE,
+                                   write_cache=bool(args.retune), log=log)
+    elif args.ig_lpp:
+        B.ngs_set_tuning(ctx, args.ig_lpp)
+    for _ in range(args.warmup):
+        scorer.score(cam_c)
+    torch.cuda.synchronize()
+    # headline: K scoring steps of every candidate, nothing but the scorer's own kernels
+    times = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        scores, best, raw = scorer.score(cam_c)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+    dt = sum(times)
+    K = args.steps
+    graph = None
+    if not args.no_graph:
+        # the same batch captured once into a HIP graph, replayed with one launch per step
+        g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.ws, normalisers=norm)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        graph = {"views_per_s": round(V * K / gdt, 2), "ms_per_step": round(gdt * 1e3 / K, 3),
+                 "overflow": int(g.overflow.item()), "best_view": int(g.best.item()),
+                 "max_rel_diff_vs_eager": float(((g.ig_raw - raw).abs() / raw.abs().clamp_min(1e-300)).max())}
+        g.close()
+    roofline, counts, breakdown = (None, {}, {})
+    if not args.no_profile:
+        roofline, counts, breakdown = serialized_roofline(B, ctx, scorer, cam_c, scene, V, log)
+    value = V * K / dt
+    ms_per_step = dt * 1e3 / K
+    path = None
+    if counts:
+        pb = path_bytes(scene.n, scene.k, 1, counts["pairs_M"], counts["touched_weighted_U"])
+        path = {"algorithmic_bytes_per_view": int(pb), "achieved_GBs": round(pb * value / 1e9, 1),
+                "frac_of_hbm_peak": round(pb * value / 1e9 / HBM_PEAK_GBS, 4)}
+    mode = f"object-centric target {scene.target}" if scene.target >= 0 else "whole-scene confidence (Eq. 7)"
+    res = sorted({(c.width, c.height) for c in cands})
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "views/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {scene.n} Gaussians, {cfg.clusters} clusters, k={scene.k}, "
+                               f"{V} candidate views at {', '.join(f'{w}x{h}' for w, h in res)}, {mode}, "
+                               f"radius U{list(cfg.radius)} m, {len(train)} training views",
+                   "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
+                   "views_in_flight": scorer.views_in_flight,
+                   "ig_lanes_per_pixel": B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"],
+                   "pair_capacity": scorer.max_pairs},
+        "roofline": roofline, "path": path, "setup_ms": round(setup_ms, 1),
+        "ms_per_step_median": round(float(np.median(times)) * 1e3, 3),
+        "counts_per_view": counts, "pairs_per_view_prepass": {"max": int(pairs.max()), "mean": float(pairs.double().mean())},
+        "best_view": int(best.item()), "normalisers": [float(x) for x in norm],
+        "kernels_us_per_view_serialized": breakdown, "graph": graph,
+        "autotune": None if tune is None else {"cached": tune.cached, "views_in_flight": tune.views_in_flight,
+                                               "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
+                                               "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
+    }
+    if args.workload == "batched640" and not args.no_mixed and args.views is None:
+        del scorer
+        torch.cuda.empty_cache()
+        out["mixed_batch"] = run_mixed(args, B, ctx, log)
+    ctx.close()
+    return out
+
+
+def run_mixed(args, B, ctx, log):
+    """The mixed-resolution batch on the same 1M-Gaussian scene: 256 candidates (86 at 320x240,
+    85 at 640x480, 85 at 1280x720) scored in one call per step, capacity from the pre-pass."""
+    import numpy as np  # noqa: F401
+    import torch
+
+    import scenegen
+    cfg, scene, cands, train = scenegen.make_workload("batched", args.seed)
+    ds = B.DeviceScene(scene, "cuda:0")
+    rp = B.raster_params()
+    ig = B.ig_params(target_id=scene.target)
+    cam_c = [B.camera(c) for c in cands]
+    scorer, pairs = make_scorer(B, ctx, ds, scene, rp, ig, cam_c, [B.camera(c) for c in train],
+                                args.in_flight, log)
+    scorer.setup([B.camera(c) for c in train])
+    tuned = B.ngs_get_tuning(ctx)
+    scorer.views_in_flight = args.mixed_in_flight
+    scorer.ws = None
+    scorer.score(cam_c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        scores, best, raw = scorer.score(cam_c)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    V = len(cands)
+    by_res = {}
+    for (w, h) in sorted({(c.width, c.height) for c in cands}):
+        idx = [i for i, c in enumerate(cands) if (c.width, c.height) == (w, h)]
+        by_res[f"{w}x{h}"] = {"views": len(idx), "mean_pairs": float(pairs[idx].double().mean()),
+                              "max_pairs": int(pairs[idx].max())}
+    res = {"workload": f"batched: {scene.n} Gaussians, k={scene.k}, {V} candidates (86 at 320x240, 85 at 640x480, "
+                       f"85 at 1280x720), object-centric target {scene.target}, radius U{list(cfg.radius)} m",
+           "views_per_s": round(V * args.steps / dt, 2), "ms_per_step": round(dt * 1e3 / args.steps, 3),
+           "views_in_flight": scorer.views_in_flight, "ig_lanes_per_pixel": tuned["ig_lanes_per_pixel"],
+           "pair_capacity": scorer.max_pairs, "by_resolution": by_res, "best_view": int(best.item())}
+    log(f"mixed batch: {res['views_per_s']} views/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +578,14 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--in-flight", type=int, default=8, help="candidate views scored concurrently")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with events")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the serialized pass (one view in flight, kernels bracketed by events) that gives "
+                         "the roofline and the per-kernel breakdown")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-resolution batch (256 views of 320x240, 640x480, 1280x720)")
+    ap.add_argument("--mixed-in-flight", type=int, default=32, help="views in flight of the mixed batch")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="only time the CPU oracle on a 16-view subset (all cores, and single-threaded)")
     ap.add_argument("--backward", action="store_true",
                     help="time the differentiable rasterizer (forward + loss + backward) on the 500k-Gaussian workload")
     ap.add_argument("--no-autotune", action="store_true",
@@ -344,130 +628,13 @@ def main():
         run_surrogate(args)
         return
 
-    import numpy as np
-    import torch
-
-    import scenegen
-    from paper_2602_08266_amd import binding as B
-
-    torch.cuda.set_device(0)
-    cfg, scene, cands, train = scenegen.make_workload(args.workload, args.seed, n_views=args.views)
-    V = len(cands)
-    ctx = B.Context(0)
-    ds = B.DeviceScene(scene, "cuda:0")
-    rp = B.raster_params()
-    ig = B.ig_params(target_id=scene.target)
-    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=48 << 20, max_slots=1 << 16, store_capacity=1 << 17,
-                         views_in_flight=args.in_flight)
-    cam_c = [B.camera(c) for c in cands]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    norm = scorer.setup([B.camera(c) for c in train])
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    tune = None
-    if not args.no_autotune:
-        # launch shapes from the package's tuning cache for this device and workload, else
-        # (or with --retune) timed now on 32 of the candidates
-        from paper_2602_08266_amd import autotune
-        if args.retune and os.path.exists(args.retune):
-            os.remove(args.retune)
-        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32, cache=args.retune or autotune.CACHE,
-                                   write_cache=bool(args.retune),
-                                   log=lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush()))
-    elif args.ig_lpp:
-        B.ngs_set_tuning(ctx, args.ig_lpp)
-    stats = torch.zeros(B.STATS_LEN, dtype=torch.int64, device="cuda:0")
-    for _ in range(args.warmup):
-        scorer.score(cam_c, stats)
-    torch.cuda.synchronize()
-    breakdown, dom = {}, None
-    if not args.no_profile:
-        # per-kernel breakdown from one more step with every kernel class bracketed by events,
-        # outside the timed region; inside it only the dominant class carries events
-        B.ngs_profile_enable(ctx, True)
-        scorer.score(cam_c)
-        torch.cuda.synchronize()
-        breakdown = {k: v for k, v in B.ngs_profile_read(ctx).items() if v[1] > 0}
-        dom = max(breakdown, key=lambda k: breakdown[k][0])
-        B.ngs_profile_enable(ctx, True, only=dom)
-    stats.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        scores, best, raw = scorer.score(cam_c, stats)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = B.ngs_profile_read(ctx) if not args.no_profile else {}
-    B.ngs_profile_enable(ctx, False)
-    st = stats.cpu().numpy()
-    graph = None
-    if not args.no_graph:
-        # the same batch captured once into a HIP graph, replayed with one launch per step
-        g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.ws, normalisers=norm)
-        g.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            g.replay()
-        torch.cuda.synchronize()
-        gdt = time.perf_counter() - t0
-        gbest = int(g.best.item())
-        graph = {"views_per_s": round(V * args.steps / gdt, 2), "ms_per_step": round(gdt * 1e3 / args.steps, 3),
-                 "overflow": int(g.overflow.item()), "best_view": gbest,
-                 "max_rel_diff_vs_eager": float(((g.ig_raw - raw).abs() / raw.abs().clamp_min(1e-300)).max())}
-        g.close()
-    K = args.steps
-    ms_per_step = dt * 1e3 / K
-    value = V * K / dt
-    # per step counts (stats accumulate over the timed calls)
-    M_step = int(st[1]) / K
-    W_step = int(st[4]) / K
-    U_step = int(st[2]) / K
-    W2_step = int(st[6]) / K
-    roofline = None
-    if prof and prof.get(dom, (0.0, 0))[1] > 0:
-        ms_tot, launches = prof[dom]
-        alg = algorithmic_bytes(dom, scene.n, scene.k, V, M_step, W_step, U_step, W2_step)
-        if alg is not None:
-            per_launch = alg / (launches / K)
-            avg_s = ms_tot / launches / 1e3
-            achieved = per_launch / avg_s / 1e9
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom, args.workload),
-                        "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
-                        "algorithmic_bytes_per_launch": int(per_launch)}
-        else:
-            roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
-                        "traffic": None, "kernel": dom, "avg_launch_us": round(ms_tot / launches * 1e3, 2)}
-    out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "views/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {scene.n} Gaussians, {cfg.clusters} clusters, k={scene.k}, "
-                               f"{V} candidate views at {cands[0].width}x{cands[0].height}, object-centric target "
-                               f"{scene.target}, radius U{list(cfg.radius)} m, 4 training views",
-                   "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
-                   "views_in_flight": scorer.views_in_flight, "ig_lanes_per_pixel": B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"]},
-        "roofline": roofline,
-        "path": {"algorithmic_bytes_per_view": int(path_bytes(scene.n, scene.k, V, M_step, U_step) / V),
-                 "achieved_GBs": round(path_bytes(scene.n, scene.k, V, M_step, U_step) / (ms_per_step / 1e3) / 1e9, 1),
-                 "frac_of_hbm_peak": round(path_bytes(scene.n, scene.k, V, M_step, U_step) / (ms_per_step / 1e3) / 1e9
-                                           / HBM_PEAK_GBS, 4)},
-        "setup_ms": round(setup_ms, 1),
-        "pairs_per_view": M_step / V, "walked_entries_per_view": W_step / V,
-        "back_to_front_entries_per_view": W2_step / V,
-        "contrib_pairs_per_view": int(st[3]) / K / V, "touched_weighted_per_view": int(st[2]) / K / V,
-        "best_view": int(best.item()), "normalisers": [float(x) for x in norm],
-        "kernels_ms_per_step": {k: round(v[0], 3) for k, v in sorted(breakdown.items(), key=lambda x: -x[1][0])},
-        "graph": graph,
-        "autotune": None if tune is None else {"cached": tune.cached, "views_in_flight": tune.views_in_flight,
-                                               "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
-                                               "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
-    }
+    if args.cpu_plan:
+        cpu_plan(args)
+        return
+    log = lambda m: (sys.stderr.write(m + "\n"), sys.stderr.flush())
+    out = run_exact(args, log)
     if not args.no_cpu_baseline:
-        sys.stderr.write("timing the CPU oracle on one view...\n")
-        sys.stderr.flush()
+        log("timing the CPU oracle on a sample of the candidates...")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
     print(json.dumps(out), flush=True)
 
