@@ -827,7 +827,7 @@ int64_t or_lists(const or_scene* s, const or_camera* cam, const or_raster* rp, i
   for (int g = 0; g < n; ++g) pr[g] = project_one(*s, g, *cam, *rp);
   Lists L = build_lists(pr, cam->width, cam->height, rp->tile);
   const int64_t M = (int64_t)L.gids.size();
-  if (cap >= M) {
+  if (cap >= M && keys && gids && ranges) {  // a call with no outputs only asks for M
     std::memcpy(keys, L.keys.data(), M * sizeof(uint64_t));
     std::memcpy(gids, L.gids.data(), M * sizeof(uint32_t));
     const int nt = L.tw * L.th;

@@ -245,6 +245,17 @@ def test_keys_rect_containment_and_lists(tiny):
 # Compositing
 # ------------------------------------------------------------------------------------------
 
+def test_lists_of_an_empty_view(tiny):
+    """A camera that sees no Gaussian has no pairs and empty ranges (the size query of the
+    oracle's list builder must not touch the outputs it was not given)."""
+    cfg, scene, cands, train = tiny
+    away = scenegen.look_at(np.array([3.0, 0.0, 0.2]), 128, 96, 100.0, target=(6.0, 0.0, 0.2))
+    tl = oracle.tile_lists(scene, away)
+    assert tl["m"] == 0 and not tl["ranges"].any()
+    img = oracle.render(scene, away)
+    assert np.all(img["t_final"] == 1.0) and img["ncontrib"].sum() == 0
+
+
 def test_brute_force_equals_tiled(tiny):
     cfg, scene, cands, train = tiny
     for cam in cands[:3]:
