@@ -44,7 +44,11 @@ ngs_status ngs_sur_workspace_size(int32_t batch, size_t* bytes);
 /* Writes the BF16 operand copies from the FP32 weights. */
 ngs_status ngs_sur_sync_bf16(ngs_ctx* ctx, const ngs_sur_params* params, void* stream);
 
-/* pred [batch] = network(x). Keeps the activations the backward pass needs in ws. */
+/* pred [batch] = network(x). Keeps the activations the backward pass needs in ws, laid out
+ * (for this batch) as: for each convolution l = 0..3 in turn, its im2col operand col_l (BF16
+ * [ci * 9][batch * ho * wo]) and its output act_l after the ReLU (FP32 [co][batch * ho * wo]);
+ * then the pooled activations (FP32 [128][batch]) and their BF16 copy, the hidden layer after
+ * its ReLU (FP32 [128][batch]) and its BF16 copy; every region starts on a 256-byte boundary. */
 ngs_status ngs_sur_forward(ngs_ctx* ctx, const ngs_sur_params* params, const float* x, int32_t batch,
                            float* pred, void* ws, size_t ws_bytes, void* stream);
 

@@ -39,6 +39,54 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = 8;
 constexpr int kMaxSplits = 64;
 
+// Eight consecutive BF16 words of a row (row-major source with leading dimension ld): one
+// 16-byte load when all eight lie in bounds and the address is 16-byte aligned, else word by
+// word (zero past the bounds).
+__device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ src, int row, int rows, int col, int cols,
+                                       int ld) {
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (row >= rows || col >= cols) return v;
+  const uint16_t* p = src + (size_t)row * ld + col;
+  if (col + 8 <= cols && (reinterpret_cast<uintptr_t>(p) & 15u) == 0u) return *reinterpret_cast<const uint4*>(p);
+  uint16_t w[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w[i] = col + i < cols ? p[i] : (uint16_t)0;
+  v.x = w[0] | ((uint32_t)w[1] << 16); v.y = w[2] | ((uint32_t)w[3] << 16);
+  v.z = w[4] | ((uint32_t)w[5] << 16); v.w = w[6] | ((uint32_t)w[7] << 16);
+  return v;
+}
+
+// Stages one operand tile (64 rows of the output dimension x 32 of K) from global memory: each
+// of the 256 threads loads eight consecutive words of the source's contiguous dimension. With
+// K contiguous (T = false for A, true for B) they are eight k of one row and go to LDS as one
+// 16-byte store; with the output dimension contiguous they are eight rows at one k and go to
+// LDS word by word (the tile is [row][k] either way, as the MFMA operands read it).
+template <bool KCONTIG>
+__device__ __forceinline__ uint4 stage_load(const uint16_t* __restrict__ src, int ld, int r0, int rows, int k0,
+                                            int kend, int tid) {
+  if (KCONTIG) {
+    const int rr = tid >> 2, kk = (tid & 3) * 8;
+    return load8(src, r0 + rr, rows, k0 + kk, kend, ld);
+  }
+  const int kk = tid >> 3, rr = (tid & 7) * 8;
+  return load8(src, k0 + kk, kend, r0 + rr, rows, ld);
+}
+
+template <bool KCONTIG>
+__device__ __forceinline__ void stage_store(uint16_t (*dst)[kGK + kGPad], uint4 v, int tid) {
+  if (KCONTIG) {
+    *reinterpret_cast<uint4*>(&dst[tid >> 2][(tid & 3) * 8]) = v;
+  } else {
+    const int kk = tid >> 3, rr = (tid & 7) * 8;
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dst[rr + 2 * i][kk] = (uint16_t)(w[i] & 0xFFFFu);
+      dst[rr + 2 * i + 1][kk] = (uint16_t)(w[i] >> 16);
+    }
+  }
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
                                                    const uint16_t* __restrict__ B, int ldb, float* __restrict__ C,
@@ -52,22 +100,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // A is [M][K] (K contiguous) unless transposed; B is [K][N] (N contiguous) unless transposed.
+  // The next K step's operands are loaded into registers while the current one is multiplied.
+  uint4 ra = stage_load<!TA>(A, lda, m0, M, kbeg, kend, tid);
+  uint4 rb = stage_load<TB>(B, ldb, n0, N, kbeg, kend, tid);
   for (int k0 = kbeg; k0 < kend; k0 += kGK) {
-    for (int e = tid; e < kGM * kGK; e += 256) {
-      const int mm = TA ? e % kGM : e / kGK, kk = TA ? e / kGM : e % kGK;
-      const int gm = m0 + mm, gk = k0 + kk;
-      uint16_t v = 0;
-      if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      As[mm][kk] = v;
-    }
-    for (int e = tid; e < kGN * kGK; e += 256) {
-      const int nn = TB ? e / kGK : e % kGN, kk = TB ? e % kGK : e / kGN;
-      const int gn = n0 + nn, gk = k0 + kk;
-      uint16_t v = 0;
-      if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-      Bs[nn][kk] = v;
-    }
+    stage_store<!TA>(As, ra, tid);
+    stage_store<TB>(Bs, rb, tid);
     __syncthreads();
+    if (k0 + kGK < kend) {
+      ra = stage_load<!TA>(A, lda, m0, M, k0 + kGK, kend, tid);
+      rb = stage_load<TB>(B, ldb, n0, N, k0 + kGK, kend, tid);
+    }
     const int kb = 8 * (lane >> 4);
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {

@@ -74,39 +74,75 @@ def test_forward_matches_reference(B, ctx, batch):
     assert np.allclose(pred, ref, atol=2e-3 * scale), float(np.abs(pred - ref).max() / scale)
 
 
-# Tolerances (norm-relative, per weight and bias tensor). The kernels take discrete
-# decisions in FP32 - the BF16 rounding of activations and the ReLU masks - where the reference
-# takes them in FP64; at small batches at most an operand or two round to the neighbouring BF16
-# value (below 1e-4); at 33 samples a ReLU input within ~1e-3 of zero can flip, which changes
-# one sample's whole backward pass (about 1/sqrt(33) of these sums, a few per cent).
-BWD_TOL = {2: (1e-4, 2e-1), 3: (1e-4, 2e-1), 33: (5e-2, 2e-1)}
+def forward_cache_from_gpu(net, batch):
+    """The GPU forward's own decisions, read from the workspace (layout documented at
+    ngs_sur_forward): the BF16 im2col operands and post-ReLU activations of every convolution,
+    the BF16 pooled and hidden operands and the post-ReLU hidden layer, as the reference's
+    backward cache."""
+    import torch
+    al = lambda x: (x + 255) // 256 * 256
+    ws = net.ws
+    off = 0
+    shapes = [(4, 32, 60, 80), (32, 64, 30, 40), (64, 128, 15, 20), (128, 128, 8, 10)]
+
+    def take(nbytes, dtype, shape):
+        nonlocal off
+        n = int(np.prod(shape))
+        t = ws[off:off + n * (2 if dtype == torch.bfloat16 else 4)].view(dtype).reshape(shape)
+        off += al(nbytes)
+        return t.to(torch.float64).cpu().numpy()
+
+    cache = {"col": [], "act": [], "shape": []}
+    for ci, co, H, W in shapes:
+        ho, wo = S.out_size(H), S.out_size(W)
+        n = batch * ho * wo
+        cache["col"].append(take(ci * 9 * n * 2, torch.bfloat16, (ci * 9, n)))
+        cache["act"].append(take(co * n * 4, torch.float32, (co, n)))
+        cache["shape"].append((ci, H, W))
+    take(128 * batch * 4, torch.float32, (128, batch))
+    cache["pool"] = take(128 * batch * 2, torch.bfloat16, (128, batch))
+    cache["hid"] = take(128 * batch * 4, torch.float32, (128, batch))
+    cache["hidr"] = take(128 * batch * 2, torch.bfloat16, (128, batch))
+    cache.update(S=4 * 5, B=batch)
+    return cache
 
 
 @pytest.mark.parametrize("batch", [2, 3, 33])
 def test_backward_matches_reference(B, ctx, batch):
+    """The backward kernels against the FP64 reference backward (BF16 rounding at the same
+    operand points) given the GPU forward's own ReLU masks and BF16 operands, element by element:
+    |gpu - ref| <= 2e-3 max |ref| per weight and bias tensor. What remains is FP32 accumulation
+    and the BF16 rounding of the pre-activation gradients, which FP32 and FP64 may round to
+    neighbouring BF16 values (one operand by 2^-8 relative). Given the reference's own FP64
+    forward instead, a ReLU input within FP32 error of zero can take the other side and change a
+    sample's whole backward pass; that comparison is logged, not asserted."""
     import torch
     log(f"test_backward batch={batch}")
     net, xd, w, b, x = net_and_input(B, ctx, batch, seed=10 + batch)
     net.forward(xd)
+    torch.cuda.synchronize()
+    cache = forward_cache_from_gpu(net, batch)
     rng = np.random.default_rng(7)
     dpred = rng.normal(size=batch).astype(np.float32)
     net.backward(xd, torch.tensor(dpred, device="cuda"))
-    _, cache = S.forward(w, b, x, bf=True)
     gw, gb = S.backward(w, cache, dpred.astype(np.float64), bf=True)
-    _, cache64 = S.forward(w, b, x, bf=False)
-    gw64, gb64 = S.backward(w, cache64, dpred.astype(np.float64), bf=False)
-    # Norm-relative errors against the BF16 reference and, for scale, against the plain FP64
-    # network (BF16 operand rounding alone moves these gradients by a few per cent).
+    # how many ReLU decisions of the GPU forward differ from the reference's own FP64 forward
+    _, own = S.forward(w, b, x, bf=True)
+    flips = sum(int(((own["act"][l] > 0) != (cache["act"][l] > 0)).sum()) for l in range(4))
+    flips += int(((own["hid"] > 0) != (cache["hid"] > 0)).sum())
+    gw_own, gb_own = S.backward(w, own, dpred.astype(np.float64), bf=True)
     bad = []
     for l in range(6):
-        for got, ref, ref64, name in ((net.gw[l], gw[l], gw64[l], "w"), (net.gb[l], gb[l], gb64[l], "b")):
+        for got, ref, ref_own, name in ((net.gw[l], gw[l], gw_own[l], "w"), (net.gb[l], gb[l], gb_own[l], "b")):
             got = got.cpu().numpy().astype(np.float64)
-            e_bf = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            e_64 = np.linalg.norm(got - ref64) / np.linalg.norm(ref64)
-            log(f"  layer {l} {name}: vs BF16 reference {e_bf:.2e}, vs FP64 network {e_64:.2e}")
-            tol_bf, tol_64 = BWD_TOL[batch]
-            if not (e_bf <= tol_bf and e_64 <= tol_64):
-                bad.append((l, name, e_bf, e_64))
+            scale = np.abs(ref).max()
+            err = np.abs(got - ref).max() / scale
+            e_own = np.linalg.norm(got - ref_own) / np.linalg.norm(ref_own)
+            log(f"  layer {l} {name}: max |gpu - ref| / max |ref| {err:.2e}; norm-relative vs the reference's own "
+                f"forward {e_own:.2e}")
+            if not err <= 2e-3:
+                bad.append((l, name, err))
+    log(f"  ReLU decisions of the GPU forward that differ from the FP64 reference forward: {flips}")
     assert not bad, bad
 
 
