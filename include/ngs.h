@@ -264,6 +264,23 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
                          const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,
                          double* ig_out, int64_t* stats, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ngs_info_gain with the same arguments and results,
+ * except that its workspace is a fixed array of NGS_STATIC_SCRATCH_BYTES in device memory that
+ * the library holds for the rest of the process, one copy per GPU (set up by ngs_create). No
+ * allocation or free happens in the call. The array must hold the per-Gaussian and per-pixel
+ * tables (about 5 n + 8.5M bytes) and at least one statistics slot, else NGS_WORKSPACE_TOO_SMALL;
+ * the slots it holds (about 47k at n = 1M and k = 64) must cover every weighted Gaussian that
+ * contributes to a pixel of the view, else NGS_CAPACITY. Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (other streams, other contexts, other host threads) race and give undefined results; calls
+ * in sequence are independent (each call clears what it reads before use). Syncs like
+ * ngs_info_gain. */
+#define NGS_STATIC_SCRATCH_BYTES (128u << 20)
+ngs_status ngs_info_gain_static(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                                const ngs_tile_lists* lists, const ngs_camera* cam,
+                                const ngs_raster_params* rp, const ngs_ig_params* ig, ngs_hessian* h,
+                                double* ig_out, int64_t* stats, void* stream);
+
 /* Clears a training store (slot_of = -1, n_slots = 0). */
 ngs_status ngs_hessian_reset(ngs_ctx* ctx, ngs_hessian* h, int32_t n, void* stream);
 /* Computes logdet (and trace of the inverse, when h->trinv is given) of every stored

@@ -24,7 +24,7 @@ OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
 STATS_LEN = 9
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_count_pairs", "ngs_bin_sort", "ngs_render",
-           "ngs_info_gain", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_training_setup", "ngs_score_batch",
+           "ngs_info_gain", "ngs_info_gain_static", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_training_setup", "ngs_score_batch",
            "ngs_score_graph_create", "ngs_score_graph_launch", "ngs_score_graph_destroy", "ngs_set_tuning",
            "ngs_get_tuning",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_enable_class", "ngs_profile_kernels", "ngs_profile_kernel_name",
@@ -129,6 +129,7 @@ def lib():
         L.ngs_count_pairs.argtypes = [P, P, P, i32, P, P, P, C.c_size_t, P]
         L.ngs_render.argtypes = [P, P, P, P, P, P, P, P]
         L.ngs_info_gain.argtypes = [P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.ngs_info_gain_static.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
         L.ngs_hessian_reset.argtypes = [P, P, i32, P]
         L.ngs_hessian_finalize.argtypes = [P, P, P]
         L.ngs_score_batch.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
@@ -610,6 +611,19 @@ def ngs_info_gain(ctx: Context, scene: DeviceScene, proj: Projected, lists: Tile
     _check("ngs_info_gain", lib().ngs_info_gain(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam), _ref(rp),
                                                 _ref(ig), _ref(hc) if hc is not None else None, _p(out),
                                                 _stats(stats), _p(ws.buf), ws.buf.numel(), _stream()), ctx)
+    return out
+
+
+def ngs_info_gain_static(ctx: Context, scene: DeviceScene, proj: Projected, lists: TileLists, cam: ngs_camera,
+                         rp: ngs_raster_params, ig: ngs_ig_params, h: Optional[Hessian], out: torch.Tensor,
+                         stats: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """ngs_info_gain on the library's fixed device scratch array (no allocation in the call);
+    `out` is a caller-owned FP64 [3] device tensor."""
+    sc, pc, lc = scene.c(), proj.c(), lists.c()
+    hc = h.c() if h is not None else None
+    _check("ngs_info_gain_static", lib().ngs_info_gain_static(ctx.handle, _ref(sc), _ref(pc), _ref(lc), _ref(cam),
+                                                              _ref(rp), _ref(ig), _ref(hc) if hc is not None else None,
+                                                              _p(out), _stats(stats), _stream()), ctx)
     return out
 
 

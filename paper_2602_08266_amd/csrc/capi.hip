@@ -3,6 +3,7 @@
 // no HIP error code crosses the boundary; every failure maps to an ngs_status.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -12,6 +13,7 @@ struct ngs_ctx {
   int device = 0;
   int32_t last_hip = 0;
   int64_t* pinned = nullptr;  // host-pinned scratch for reading device counters
+  void* scratch = nullptr;    // this device's copy of the static scratch array (device address)
   // Non-blocking streams (default priority) on which ngs_score_batch keeps several views in
   // flight, and the events that fork them from and join them to the caller's stream.
   std::vector<hipStream_t> lanes;
@@ -22,9 +24,34 @@ struct ngs_ctx {
   ngs_tuning tuning{};  // launch shapes (ngs_set_tuning); zero = defaults
 };
 
+// Workspace of ngs_info_gain_static: a fixed array in device memory, one copy per GPU the
+// library runs on, held until the process ends. In host code `scratch` is only a stand-in
+// for the symbol; its device address is taken once per device with hipGetSymbolAddress (at
+// ngs_create, with the device current) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[NGS_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace ngs;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which must be `device`), taken once.
+hipError_t static_scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 inline size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -238,6 +265,7 @@ ngs_status ngs_create(int device, ngs_ctx** out) {
   c->device = device;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = static_scratch_address(device, &c->scratch);
   if (e != hipSuccess) {
     delete c;
     return NGS_HIP_ERROR;
@@ -436,6 +464,20 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
     return NGS_CAPACITY;
   }
   return NGS_OK;
+}
+
+ngs_status ngs_info_gain_static(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projected* proj,
+                                const ngs_tile_lists* lists, const ngs_camera* cam, const ngs_raster_params* rp,
+                                const ngs_ig_params* ig, ngs_hessian* h, double* ig_out, int64_t* stats,
+                                void* stream) {
+  if (!ctx || !ctx->scratch) return NGS_INVALID_ARG;
+  if (!scene || scene->n < 0 || scene->k <= 0) return NGS_INVALID_ARG;
+  if (scene->k > NGS_MAX_K) return NGS_UNSUPPORTED;
+  // the slot statistics of ngs_info_gain must fit the fixed array: at least one slot
+  if (ig_slots_for(NGS_STATIC_SCRATCH_BYTES, scene->n, scene->k) < 1) return NGS_WORKSPACE_TOO_SMALL;
+  // every call on this device shares the array; ngs_info_gain clears what must start at zero
+  return ngs_info_gain(ctx, scene, proj, lists, cam, rp, ig, h, ig_out, stats, ctx->scratch,
+                       NGS_STATIC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"
