@@ -192,6 +192,7 @@ struct IgWs {
   uint8_t* cflag;       // [n] Gaussians that contribute to a pixel (pass 1; zero between views)
   float* pix_t;         // [NGS_MAX_TILES][256] final transmittance per pixel (pass 1)
   int32_t* pix_last;    // [NGS_MAX_TILES][256] last contributor's list position, -1 for none
+  int2* wave_range;     // [NGS_MAX_TILES][4] per 16 x 4 strip: first weighted and last contributor
   int64_t max_slots;
 };
 int ig_stat_stride(int64_t k);

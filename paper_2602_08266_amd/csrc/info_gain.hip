@@ -133,13 +133,17 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
 // the list on its own: lane l holds batch entry l in registers (the next batch is loaded
 // while the current one is walked), the walk reads an entry's values with readlane, and a
 // wavefront stops once all its pixels are done. Writes each pixel's final transmittance and
-// last contributor (list position, -1 for none), and flags (cflag[g] = 1) every Gaussian
-// that contributes to a pixel.
+// last contributor (list position, -1 for none), flags (cflag[g] = 1) every Gaussian that
+// contributes to a pixel, and per wavefront the list positions of its first contributor with a
+// nonzero weight and of its last contributor (wave_range; INT_MAX / -1 when none): the back
+// pass of a wavefront needs no entry outside that range, since only weighted contributors
+// write records and only the contributors behind them feed their suffixes.
 __global__ __launch_bounds__(kTilePix) void k_ig_front(
     int n, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
     const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ opacity,
-    float* __restrict__ pix_t, int32_t* __restrict__ pix_last, uint8_t* __restrict__ cflag,
-    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag) {
+    const float* __restrict__ conf, float* __restrict__ pix_t, int32_t* __restrict__ pix_last,
+    int2* __restrict__ wave_range, uint8_t* __restrict__ cflag, int64_t* __restrict__ stats,
+    const int32_t* __restrict__ tflag) {
   __shared__ int tile_last_sh;
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
@@ -156,6 +160,7 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
   const float sy0 = (float)(ty * kTile + wave * 4) + 0.5f, sy1 = sy0 + 3.f;
   float T = 1.f;
   int last = -1, nc = 0;
+  int wave_first = INT_MAX;
   bool done = !inside;
   // batch entry of this lane: gid and geometry, the next batch's in flight
   uint32_t g_n = 0u;
@@ -211,12 +216,22 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
       hi |= (uint32_t)__shfl_xor((int)hi, off);
     }
     const uint64_t any = ((uint64_t)hi << 32) | lo;
-    if ((any >> lane) & 1ull) cflag[eg] = 1;
+    bool weighted = false;
+    if ((any >> lane) & 1ull) {
+      cflag[eg] = 1;
+      weighted = conf[eg] > 0.f;
+    }
+    const uint64_t wm = __ballot(weighted);
+    if (wave_first == INT_MAX && wm) wave_first = (int)b0 + __ffsll((unsigned long long)wm) - 1;
   }
   if (inside) {
     pix_t[(size_t)tile * kTilePix + pix] = T;
     pix_last[(size_t)tile * kTilePix + pix] = last;
   }
+  int wave_last = last;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
+  if (lane == 0) wave_range[(size_t)tile * (kTilePix / kWave) + wave] = make_int2(wave_first, wave_last);
   if (!stats) return;
   if (threadIdx.x == 0) tile_last_sh = -1;
   __syncthreads();
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
     const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
     int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
     int64_t* __restrict__ stats, const int32_t* __restrict__ tflag, const float* __restrict__ pix_t,
-    const int32_t* __restrict__ pix_last) {
+    const int32_t* __restrict__ pix_last, const int2* __restrict__ wave_range) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   IgShared<KP, LPP>& S = *reinterpret_cast<IgShared<KP, LPP>*>(smem_raw);
   constexpr int kThreads = kTilePix * LPP;
@@ -268,53 +283,28 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
   const float sy0 = (float)(ty * kTile + wave * kRowsW) + 0.5f, sy1 = sy0 + (float)(kRowsW - 1);
 
-  // final transmittance and last contributor of this lane's pixel (pass 1)
+  // final transmittance and last contributor of this lane's pixel, and the list ranges of the
+  // front pass's 16 x 4 strips: the tile's back pass runs from the last contributor of any of
+  // its pixels to the first weighted contributor of any of them; a wavefront skips the entries
+  // outside the range of the front strip that holds its rows (4 / LPP of them)
   float T = 1.f;
   int last = -1;
   if (inside) {
     T = pix_t[(size_t)tile * kTilePix + pix];
     last = pix_last[(size_t)tile * kTilePix + pix];
   }
-  if (threadIdx.x == 0) S.flag = -1;
-  __syncthreads();
-  if (last >= 0) atomicMax(&S.flag, last);
-  __syncthreads();
-  const int tile_last = S.flag;
-  if (tile_last < 0) return;
-  // the wavefront's last contributor: entries behind it contribute to none of its pixels
-  int wave_last = last;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) wave_last = max(wave_last, __shfl_xor(wave_last, off));
-  // The wavefront's nearest weighted entry whose box reaches its strip: its part of pass 2
-  // ends there, because entries in front of it only feed the suffixes of entries further in
-  // front, none of which writes a record for its pixels. The tile's pass 2 ends at the
-  // nearest over its wavefronts.
-  __syncthreads();
-  if (threadIdx.x == 0) S.flag = INT_MAX;
-  __syncthreads();
-  int wave_first = INT_MAX;
-  for (int b0 = (int)start; b0 <= wave_last; b0 += kWave) {
-    const int i = b0 + lane;
-    bool hit = false;
-    if (i <= wave_last) {
-      const uint32_t g = gids[i];
-      if (slot_of[g] >= 0) {
-        float hx, hy;
-        conic_extent(conic[g], conic[n + g], conic[2 * n + g], rc.cutoff_q, &hx, &hy);
-        const float mx = mean2d[g], my = mean2d[n + g];
-        hit = mx + hx >= sx0 && mx - hx <= sx1 && my + hy >= sy0 && my - hy <= sy1;
-      }
-    }
-    const uint64_t hm = __ballot(hit);
-    if (hm) {
-      wave_first = b0 + __ffsll((unsigned long long)hm) - 1;
-      break;
+  int tile_last = -1, first_w = INT_MAX, wave_first = INT_MAX, wave_last = -1;
+  constexpr int kFrontWaves = kTilePix / kWave;  // 16 x 4 strips of the front pass
+  for (int fw = 0; fw < kFrontWaves; ++fw) {
+    const int2 r = wave_range[(size_t)tile * kFrontWaves + fw];
+    tile_last = max(tile_last, r.y);
+    first_w = min(first_w, r.x);
+    if (fw == wave * kRowsW / 4) {
+      wave_first = min(wave_first, r.x);
+      wave_last = max(wave_last, r.y);
     }
   }
-  if (lane == 0 && wave_first != INT_MAX) atomicMin(&S.flag, wave_first);
-  __syncthreads();
-  const int first_w = S.flag;
-  if (first_w > tile_last) return;
+  if (tile_last < 0 || first_w > tile_last) return;
   if (stats && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&stats[6], (unsigned long long)(tile_last - first_w + 1));
 
@@ -598,7 +588,7 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
   ProfScope ps(kProfIgTiles, st);
   hipLaunchKernelGGL((k_ig_back<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
                      p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
-                     stats, tflag, w.pix_t, w.pix_last);
+                     stats, tflag, w.pix_t, w.pix_last, w.wave_range);
   return hipGetLastError();
 }
 
@@ -609,7 +599,8 @@ int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
 size_t ig_ws_fixed_bytes(int64_t n) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
-  return al(nn * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al(nn) + 2 * al((size_t)NGS_MAX_TILES * kTilePix * 4);
+  return al(nn * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al(nn) + 2 * al((size_t)NGS_MAX_TILES * kTilePix * 4) +
+         al((size_t)NGS_MAX_TILES * (kTilePix / kWave) * 8);
 }
 
 size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots) {
@@ -633,6 +624,7 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   w.cflag = (uint8_t*)p; p += al(nn);
   w.pix_t = (float*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
   w.pix_last = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
+  w.wave_range = (int2*)p; p += al((size_t)NGS_MAX_TILES * (kTilePix / kWave) * 8);
   w.pmat = (double*)p;
   w.max_slots = max_slots;
   return w;
@@ -672,7 +664,7 @@ hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_
   {
     ProfScope ps(kProfIgFront, st);
     hipLaunchKernelGGL(k_ig_front, dim3(ntiles), dim3(kTilePix), 0, st, s.n, l.gids, l.ranges, cam, rc, p.mean2d,
-                       p.conic, s.opacity, w.pix_t, w.pix_last, w.cflag, stats, tflag);
+                       p.conic, s.opacity, s.conf, w.pix_t, w.pix_last, w.wave_range, w.cflag, stats, tflag);
   }
   {
     ProfScope ps(kProfIgAssign, st);
