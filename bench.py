@@ -415,7 +415,8 @@ def serialized_roofline(B, ctx, scorer, cams, scene, K_views, log):
     V = len(cams)
     counts = {"pairs_M": st[1] / V, "touched_weighted_U": st[2] / V, "contrib_pairs_P": st[3] / V,
               "walked_entries_W": st[4] / V, "back_to_front_entries": st[6] / V,
-              "back_to_front_contrib_pairs": st[7] / V, "weighted_records": st[8] / V}
+              "back_to_front_contrib_pairs": st[7] / V, "weighted_records": st[8] / V,
+              "contrib_tile_pairs_F": st[9] / V}
     avg_s = ms_tot / launches / 1e3
     per_launch = launches / V  # launches of the class per view
     n, k = scene.n, scene.k
@@ -504,7 +505,7 @@ def run_exact(args, log):
     graph = None
     if not args.no_graph:
         # the same batch captured once into a HIP graph, replayed with one launch per step
-        g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.ws, normalisers=norm)
+        g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.workspace(), normalisers=norm)
         g.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -538,6 +539,8 @@ def run_exact(args, log):
                    "views_per_step": V, "gaussians": scene.n, "k": scene.k, "scorer": "exact",
                    "views_in_flight": scorer.views_in_flight,
                    "ig_lanes_per_pixel": B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"],
+                   "ig_waves_per_simd": B.ngs_get_tuning(ctx)["ig_waves_per_simd"],
+                   "bin_chunk": B.ngs_get_tuning(ctx)["bin_chunk"],
                    "pair_capacity": scorer.max_pairs},
         "roofline": roofline, "path": path, "setup_ms": round(setup_ms, 1),
         "ms_per_step_median": round(float(np.median(times)) * 1e3, 3),
@@ -546,6 +549,8 @@ def run_exact(args, log):
         "kernels_us_per_view_serialized": breakdown, "graph": graph,
         "autotune": None if tune is None else {"cached": tune.cached, "views_in_flight": tune.views_in_flight,
                                                "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
+                                               "ig_waves_per_simd": tune.ig_waves_per_simd,
+                                               "bin_chunk": tune.bin_chunk,
                                                "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
     }
     if args.workload == "batched640" and not args.no_mixed and args.views is None:
@@ -582,6 +587,19 @@ def run_mixed(args, B, ctx, log):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     V = len(cands)
+    # the same 256-view batch captured once into a HIP graph: one launch per step
+    g = B.ScoreGraph(ctx, ds, scorer.h, cam_c, rp, ig, scorer.workspace(), normalisers=scorer.norm)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    gdt = time.perf_counter() - t0
+    graph = {"views_per_s": round(V * args.steps / gdt, 2), "ms_per_step": round(gdt * 1e3 / args.steps, 3),
+             "overflow": int(g.overflow.item()), "best_view": int(g.best.item()),
+             "max_rel_diff_vs_eager": float(((g.ig_raw - raw).abs() / raw.abs().clamp_min(1e-300)).max())}
+    g.close()
     by_res = {}
     for (w, h) in sorted({(c.width, c.height) for c in cands}):
         idx = [i for i, c in enumerate(cands) if (c.width, c.height) == (w, h)]
@@ -591,7 +609,7 @@ def run_mixed(args, B, ctx, log):
                        f"85 at 1280x720), object-centric target {scene.target}, radius U{list(cfg.radius)} m",
            "views_per_s": round(V * args.steps / dt, 2), "ms_per_step": round(dt * 1e3 / args.steps, 3),
            "views_in_flight": scorer.views_in_flight, "ig_lanes_per_pixel": tuned["ig_lanes_per_pixel"],
-           "pair_capacity": scorer.max_pairs, "by_resolution": by_res, "best_view": int(best.item())}
+           "pair_capacity": scorer.max_pairs, "by_resolution": by_res, "best_view": int(best.item()), "graph": graph}
     log(f"mixed batch: {res['views_per_s']} views/s")
     return res
 

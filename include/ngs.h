@@ -118,7 +118,11 @@ typedef struct {
 
 /* Per-view projection (one entry per Gaussian). rect holds each Gaussian's inclusive
  * tile bounds (x0, y0, x1, y1) together (8 bytes, 8-byte aligned; a culled Gaussian has
- * (0, 0, -1, -1)); count = number of tiles (0: culled). zkey = bits of float32(Z). */
+ * (0, 0, -1, -1)); count = number of tiles (0: culled). zkey = bits of float32(Z).
+ * splat (16-byte aligned) packs what the information walk reads of an entry into one
+ * record per Gaussian: [n][8] = 2D mean x, y, conic xx, xy, yy, opacity, half-extents x, y
+ * of the ellipse q <= cutoff_q (widened for rounding). ngs_project writes it when it is not
+ * NULL (the scene must then be prepared: it copies the opacity); ngs_info_gain reads it. */
 typedef struct {
   float* mean2d;    /* [2][n] */
   float* conic;     /* [3][n] Q = Sigma2^-1: xx, xy, yy */
@@ -126,6 +130,7 @@ typedef struct {
   uint32_t* zkey;   /* [n] */
   int16_t* rect;    /* [n][4] */
   uint32_t* count;  /* [n] */
+  float* splat;     /* [n][8] or NULL */
 } ngs_projected;
 
 /* Per-view tile lists: (tile, depth, gid)-sorted Gaussian ids and per-tile ranges.
@@ -184,12 +189,14 @@ typedef struct {
  *     rect of a weighted Gaussian reaches; the others add nothing to any statistic),
  * [5] views whose slot workspace overflowed,
  * [6] entries the back-to-front walk stages (per visited tile, from its last contributor
- *     to its nearest weighted entry that reaches a strip),
+ *     to its first weighted contributor),
  * [7] contributing (pixel, Gaussian) pairs of the back-to-front walk (each updates the
  *     pixel's colour, depth and object suffixes),
  * [8] per-pixel records of weighted contributing pairs (each enters the 94 + 6k products of
- *     the Gaussian's statistics). */
-#define NGS_STATS_LEN 9
+ *     the Gaussian's statistics),
+ * [9] contributing (tile, Gaussian) pairs F (a Gaussian composited at some pixel of the tile),
+ *     over the tiles the information walk visits. */
+#define NGS_STATS_LEN 10
 
 /* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch (and
  * ngs_training_setup, ngs_score_graph_create), 3 = ngs_render_backward,
@@ -337,9 +344,19 @@ ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian*
  * lanes). Allowed: k <= 8: 1, 2; k <= 32: 1, 2, 4; k <= 64: 1, 2. Default: 1 for k <= 8,
  * else 2. A value not allowed for the scene's k makes ngs_info_gain, ngs_score_batch and
  * ngs_score_graph_create return NGS_INVALID_ARG. Results agree across shapes to rounding.
+ * ig_waves_per_simd: 0 (default) or 4: with two lanes per pixel and k > 16, the back pass of
+ * the information walk is compiled for four waves per SIMD (two workgroups per CU, a few
+ * registers spilled) instead of one workgroup per CU; any other combination makes the calls
+ * above return NGS_INVALID_ARG.
+ * bin_chunk: least entries per chunk of the second binning level (ngs_bin_sort,
+ * ngs_score_batch, ngs_training_setup; 0 = 512, else a power of two in [256, 8192]): longer chunks leave fewer
+ * partly written lines in the tile lists, shorter ones spread the scatter over more
+ * workgroups. Results do not depend on it.
  * The autotuner of the Python package picks these and views_in_flight by timing. */
 typedef struct {
   int32_t ig_lanes_per_pixel;
+  int32_t ig_waves_per_simd;
+  int32_t bin_chunk;
 } ngs_tuning;
 ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* tuning);
 ngs_status ngs_get_tuning(const ngs_ctx* ctx, ngs_tuning* tuning);

@@ -99,6 +99,22 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
                                    const ngs_raster_params* rp, const float* weight, float depth_scale, float* x,
                                    const ngs_dims* dims, void* ws, size_t ws_bytes, void* stream);
 
+/* The surrogate-guided choice with the exact information gain as judge: ranks the n_views
+ * candidates (host camera array) by the network's predictions pred (device FP32 [n_views],
+ * e.g. ngs_sur_forward over the maps of ngs_sur_render_features), re-scores the best
+ * `rescore` of them exactly (as ngs_score_batch with h, normalisers, rp, ig, dims and ws;
+ * Eq. 5, 10, 11) and returns in *best (host) the index into cams of the exact argmax among
+ * them. chosen (host int32 [rescore]) receives the re-scored candidates' indices by descending
+ * prediction (lower index first on ties, a prediction that is not a number last); scores
+ * (device FP32 [rescore][4]) and ig_raw (device FP64 [rescore][3]) their exact scores and
+ * gains, in that order. rescore > n_views re-scores every candidate. Syncs. Status as
+ * ngs_score_batch. */
+ngs_status ngs_sur_pick(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                        const ngs_camera* cams, int32_t n_views, const float* pred, int32_t rescore,
+                        const ngs_raster_params* rp, const ngs_ig_params* ig, int32_t* chosen, float* scores,
+                        double* ig_raw, int32_t* best, int64_t* stats, const ngs_dims* dims, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* c [m][n] = op(a) op(b) + beta c with BF16 a, b (raw 16-bit words) and FP32 c on the matrix
  * cores. op(a) = a [m][k] (lda) or, with trans_a, a^T of a [k][m]; op(b) = b [k][n] (ldb) or,
  * with trans_b, b^T of b [n][k]. The kernel every surrogate layer uses. */

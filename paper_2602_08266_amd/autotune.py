@@ -1,9 +1,10 @@
 """Autotuner of the batched scorer's launch shapes.
 
-It times ngs_score_batch on a sample of the real candidate set for every pair of
-views_in_flight (buffer sets and context streams kept busy at once) and lanes per pixel of the
-information-gain tile kernel (which sets its workgroup size and the packed rows it stages in LDS
-per reduction round), keeps the fastest, and applies it to the context (ngs_set_tuning) and to
+It times ngs_score_batch on a sample of the real candidate set for every combination of
+views_in_flight (buffer sets and context streams kept busy at once), lanes per pixel of the
+information-gain back pass (which sets its workgroup size and the packed rows it stages in LDS
+per reduction round) and, where the library has both builds, its waves per SIMD (one or two
+workgroups per CU), keeps the fastest, and applies it to the context (ngs_set_tuning) and to
 the scorer's workspace. Results may be cached in a JSON file keyed by the device, the scene
 size and the resolution mix of the sample.
 """
@@ -20,6 +21,7 @@ import torch
 from . import binding as B
 
 VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16, 24, 32)
+BIN_CHUNKS = (1024, 2048, 4096)  # tried at the best shape after the default (512)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
@@ -32,6 +34,11 @@ def lpp_choices(k: int) -> Tuple[int, ...]:
     return (1, 2)
 
 
+def waves_choices(k: int, lpp: int) -> Tuple[int, ...]:
+    """Waves per SIMD of the back pass the library accepts (0 = the default build)."""
+    return (0, 4) if lpp == 2 and k > 16 else (0,)
+
+
 @dataclass
 class TuneResult:
     views_in_flight: int
@@ -39,6 +46,8 @@ class TuneResult:
     ms_per_view: float
     table: List[Dict] = field(default_factory=list)
     cached: bool = False
+    ig_waves_per_simd: int = 0
+    bin_chunk: int = 0
 
 
 def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max_slots: int) -> str:
@@ -67,33 +76,59 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
             hit = json.load(f).get(key)
         if hit:
             res = TuneResult(hit["views_in_flight"], hit["ig_lanes_per_pixel"], hit["ms_per_view"], hit["table"],
-                             cached=True)
+                             cached=True, ig_waves_per_simd=hit.get("ig_waves_per_simd", 0),
+                             bin_chunk=hit.get("bin_chunk", 0))
             apply(ctx, scorer, res)
             return res
     lpps = tuple(lpps) if lpps else lpp_choices(scorer.scene.k)
     table = []
     best = None
     for lpp in lpps:
-        B.ngs_set_tuning(ctx, lpp)
-        for v in vif:
-            scorer.views_in_flight = v
-            scorer.ws = None  # resized for v buffer sets on the next score()
-            scorer.score(sub)
-            torch.cuda.synchronize()
-            t = float("inf")
-            for _ in range(reps):
-                t0 = time.perf_counter()
+        for waves in waves_choices(scorer.scene.k, lpp):
+            B.ngs_set_tuning(ctx, lpp, waves)
+            for v in vif:
+                scorer.views_in_flight = v
+                scorer.ws = None  # resized for v buffer sets on the next score()
                 scorer.score(sub)
                 torch.cuda.synchronize()
-                t = min(t, time.perf_counter() - t0)
-            ms = t / len(sub) * 1e3
-            table.append({"views_in_flight": v, "ig_lanes_per_pixel": lpp, "ms_per_view": round(ms, 4)})
-            if log:
-                log(f"autotune: views_in_flight {v:2d}, lanes per pixel {lpp}: {ms:.3f} ms/view")
-            if best is None or ms < best[0]:
-                best = (ms, v, lpp)
+                t = float("inf")
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    scorer.score(sub)
+                    torch.cuda.synchronize()
+                    t = min(t, time.perf_counter() - t0)
+                ms = t / len(sub) * 1e3
+                table.append({"views_in_flight": v, "ig_lanes_per_pixel": lpp, "ig_waves_per_simd": waves,
+                              "ms_per_view": round(ms, 4)})
+                if log:
+                    log(f"autotune: views_in_flight {v:2d}, lanes per pixel {lpp}, waves per SIMD {waves}: "
+                        f"{ms:.3f} ms/view")
+                if best is None or ms < best[0]:
+                    best = (ms, v, lpp, waves)
+    # then the binning chunk size at the best shape
+    best_chunk = 0
+    scorer.views_in_flight = best[1]
     scorer.ws = None
-    res = TuneResult(best[1], best[2], best[0], table)
+    for chunk in BIN_CHUNKS:
+        B.ngs_set_tuning(ctx, best[2], best[3], chunk)
+        scorer.score(sub)
+        torch.cuda.synchronize()
+        t = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            scorer.score(sub)
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+        ms = t / len(sub) * 1e3
+        table.append({"views_in_flight": best[1], "ig_lanes_per_pixel": best[2], "ig_waves_per_simd": best[3],
+                      "bin_chunk": chunk, "ms_per_view": round(ms, 4)})
+        if log:
+            log(f"autotune: binning chunk {chunk}: {ms:.3f} ms/view")
+        if ms < best[0]:
+            best = (ms, best[1], best[2], best[3])
+            best_chunk = chunk
+    scorer.ws = None
+    res = TuneResult(best[1], best[2], best[0], table, ig_waves_per_simd=best[3], bin_chunk=best_chunk)
     apply(ctx, scorer, res)
     if cache and write_cache:
         data = {}
@@ -107,6 +142,6 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
 
 
 def apply(ctx: B.Context, scorer: B.NbvScorer, res: TuneResult):
-    B.ngs_set_tuning(ctx, res.ig_lanes_per_pixel)
+    B.ngs_set_tuning(ctx, res.ig_lanes_per_pixel, res.ig_waves_per_simd, res.bin_chunk)
     scorer.views_in_flight = res.views_in_flight
     scorer.ws = None

@@ -21,7 +21,7 @@ NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
 NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
 MODE_SCORE, MODE_ACCUMULATE = 0, 1
 OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
-STATS_LEN = 9
+STATS_LEN = 10
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_count_pairs", "ngs_bin_sort", "ngs_render",
            "ngs_info_gain", "ngs_info_gain_static", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_training_setup", "ngs_score_batch",
@@ -29,7 +29,7 @@ EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs
            "ngs_get_tuning",
            "ngs_render_backward", "ngs_profile_enable", "ngs_profile_enable_class", "ngs_profile_kernels", "ngs_profile_kernel_name",
            "ngs_profile_read", "ngs_sur_workspace_size", "ngs_sur_sync_bf16", "ngs_sur_forward", "ngs_sur_backward",
-           "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_novelty", "ngs_sur_render_features", "ngs_gemm_bf16"]
+           "ngs_sur_mse", "ngs_sur_adam", "ngs_sur_features", "ngs_sur_novelty", "ngs_sur_render_features", "ngs_sur_pick", "ngs_gemm_bf16"]
 
 
 class NgsError(RuntimeError):
@@ -65,7 +65,7 @@ class ngs_ig_params(C.Structure):
 
 
 class ngs_projected(C.Structure):
-    _fields_ = [("mean2d", P), ("conic", P), ("depth", P), ("zkey", P), ("rect", P), ("count", P)]
+    _fields_ = [("mean2d", P), ("conic", P), ("depth", P), ("zkey", P), ("rect", P), ("count", P), ("splat", P)]
 
 
 class ngs_tile_lists(C.Structure):
@@ -151,6 +151,7 @@ def lib():
         L.ngs_sur_novelty.argtypes = [P, P, P, C.c_float, P, P]
         L.ngs_sur_render_features.argtypes = [P, P, P, i32, P, P, C.c_float, P, P, P, C.c_size_t, P]
         L.ngs_gemm_bf16.argtypes = [P, i32, i32, i32, i32, i32, P, i32, P, i32, P, i32, C.c_float, P]
+        L.ngs_sur_pick.argtypes = [P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
         L.ngs_profile_enable.argtypes = [P, i32]
         L.ngs_profile_enable_class.argtypes = [P, i32]
         L.ngs_profile_kernels.restype = i32
@@ -272,10 +273,11 @@ class Projected:
     zkey: torch.Tensor
     rect: torch.Tensor
     count: torch.Tensor
+    splat: Optional[torch.Tensor] = None
 
     def c(self) -> ngs_projected:
         return ngs_projected(_p(self.mean2d), _p(self.conic), _p(self.depth), _p(self.zkey), _p(self.rect),
-                             _p(self.count))
+                             _p(self.count), _p(self.splat))
 
 
 @dataclass
@@ -339,7 +341,8 @@ def ngs_project(ctx: Context, scene: DeviceScene, cam: ngs_camera, rp: ngs_raste
                     torch.empty(n, dtype=torch.float32, device=dev),
                     torch.empty(n, dtype=torch.int32, device=dev),
                     torch.empty((n, 4), dtype=torch.int16, device=dev),
-                    torch.empty(n, dtype=torch.int32, device=dev))
+                    torch.empty(n, dtype=torch.int32, device=dev),
+                    torch.empty((n, 8), dtype=torch.float32, device=dev))
     sc, pc = scene.c(), out.c()
     _check("ngs_project", lib().ngs_project(ctx.handle, _ref(sc), _ref(cam), _ref(rp), _ref(pc), _stream()), ctx)
     return out
@@ -597,6 +600,31 @@ def ngs_sur_novelty(ctx: Context, scene: DeviceScene, h: Optional[Hessian], lamb
     return out
 
 
+def ngs_sur_pick(ctx: Context, scene: DeviceScene, h: Optional[Hessian], normalisers: Sequence[float],
+                 cams: Sequence[ngs_camera], pred: torch.Tensor, rescore: int, rp: ngs_raster_params,
+                 ig: ngs_ig_params, ws: "ScoreWorkspace", stats: Optional[torch.Tensor] = None):
+    """Exact re-score of the network's best `rescore` candidates and the exact argmax among
+    them (one library call). Returns (best index into cams, chosen indices, scores [R][4],
+    raw gains [R][3])."""
+    nv = len(cams)
+    r = max(1, min(int(rescore), nv))
+    dev = scene.device
+    chosen = (C.c_int32 * r)()
+    scores = torch.empty((r, 4), dtype=torch.float32, device=dev)
+    ig_raw = torch.empty((r, 3), dtype=torch.float64, device=dev)
+    best = C.c_int32(-1)
+    arr = (ngs_camera * nv)(*cams)
+    norm = (C.c_double * 3)(*[float(x) for x in normalisers])
+    sc = scene.c()
+    hc = h.c() if h is not None else None
+    pred = pred.contiguous()
+    _check("ngs_sur_pick", lib().ngs_sur_pick(ctx.handle, _ref(sc), _ref(hc) if hc is not None else None, norm, arr,
+                                              nv, _p(pred), r, _ref(rp), _ref(ig), chosen, _p(scores), _p(ig_raw),
+                                              C.byref(best), _stats(stats), _ref(ws.dims), _p(ws.buf), ws.buf.numel(),
+                                              _stream()), ctx)
+    return int(best.value), list(chosen), scores, ig_raw
+
+
 class IgWorkspace:
     def __init__(self, scene: DeviceScene, max_slots: int = 1 << 16):
         self.buf = _bytes(workspace_size(1, scene.n, scene.k, max_slots=max_slots), scene.device)
@@ -683,18 +711,19 @@ def ngs_training_setup(ctx: Context, scene: DeviceScene, h: Hessian, train: Sequ
 
 
 class ngs_tuning(C.Structure):
-    _fields_ = [("ig_lanes_per_pixel", C.c_int32)]
+    _fields_ = [("ig_lanes_per_pixel", C.c_int32), ("ig_waves_per_simd", C.c_int32), ("bin_chunk", C.c_int32)]
 
 
-def ngs_set_tuning(ctx: Context, ig_lanes_per_pixel: int = 0):
-    t = ngs_tuning(int(ig_lanes_per_pixel))
+def ngs_set_tuning(ctx: Context, ig_lanes_per_pixel: int = 0, ig_waves_per_simd: int = 0, bin_chunk: int = 0):
+    t = ngs_tuning(int(ig_lanes_per_pixel), int(ig_waves_per_simd), int(bin_chunk))
     _check("ngs_set_tuning", lib().ngs_set_tuning(ctx.handle, _ref(t)), ctx)
 
 
 def ngs_get_tuning(ctx: Context) -> Dict[str, int]:
     t = ngs_tuning()
     _check("ngs_get_tuning", lib().ngs_get_tuning(ctx.handle, _ref(t)), ctx)
-    return {"ig_lanes_per_pixel": int(t.ig_lanes_per_pixel)}
+    return {"ig_lanes_per_pixel": int(t.ig_lanes_per_pixel), "ig_waves_per_simd": int(t.ig_waves_per_simd),
+            "bin_chunk": int(t.bin_chunk)}
 
 
 class ScoreGraph:
@@ -789,6 +818,12 @@ class NbvScorer:
         self.ig_train = None
         self.ws = None
 
+    def workspace(self) -> "ScoreWorkspace":
+        """The batch workspace for the current views_in_flight (allocated on first use)."""
+        if self.ws is None:
+            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
+        return self.ws
+
     def _view(self, cam: ngs_camera):
         proj = ngs_project(self.ctx, self.scene, cam, self.rp)
         lists = ngs_bin_sort(self.ctx, self.scene, proj, cam, self.rp, capacity=self.max_pairs)
@@ -797,10 +832,8 @@ class NbvScorer:
     def setup(self, train_cams: Sequence[ngs_camera]):
         """H_T and the Eq. 10 normalisers of the training views (ngs_training_setup); the
         values come back to the host for ngs_score_batch, which takes them by value."""
-        if self.ws is None:
-            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
         norm, trace_total, ig_train = ngs_training_setup(self.ctx, self.scene, self.h, list(train_cams), self.rp,
-                                                         self.ig, self.ws)
+                                                         self.ig, self.workspace())
         self.ig_train = ig_train.cpu().numpy()
         if self.ig.criterion == 1:
             st = trace_total.cpu().numpy()
@@ -811,10 +844,8 @@ class NbvScorer:
 
     def score(self, cams: Sequence[ngs_camera], stats: Optional[torch.Tensor] = None, scaled: bool = True):
         """Scores the candidates. scaled=False drops the Eq. 10 normalisation (normalisers 1)."""
-        if self.ws is None:
-            self.ws = score_workspace(self.scene, self.max_pairs, self.max_slots, self.views_in_flight)
         norm = self.norm if scaled else [1.0, 1.0, 1.0]
-        return ngs_score_batch(self.ctx, self.scene, self.h, norm, cams, self.rp, self.ig, self.ws, stats)
+        return ngs_score_batch(self.ctx, self.scene, self.h, norm, cams, self.rp, self.ig, self.workspace(), stats)
 
     def greedy(self, train_cams: Sequence[ngs_camera], cand_cams: Sequence[ngs_camera], steps: int,
                follow: Optional[Sequence[int]] = None, scaled: bool = True):

@@ -27,9 +27,9 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Exclusive scan (u64) of count[gid_sorted[i]]: per-block local scan and block totals.
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const uint32_t* __restrict__ count,
-                                                             const uint32_t* __restrict__ order, int n,
+// Exclusive scan (u64) of the tile counts in depth order (from the sorted rects): per-block
+// local scan and block totals.
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const short4* __restrict__ rect_sorted, int n,
                                                              uint64_t* __restrict__ out, uint64_t* __restrict__ bsum) {
   __shared__ uint64_t sm[kScanThreads];
   const int t = threadIdx.x;
@@ -38,7 +38,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(const uint32_t* __r
   uint64_t run = 0;
   for (int j = 0; j < kScanItems; ++j) {
     const int i = base + j;
-    const uint64_t c = (i < n) ? (uint64_t)count[order[i]] : 0ull;
+    uint64_t c = 0ull;
+    if (i < n) {  // the tile count of the rect (0 for a culled Gaussian's empty rect)
+      const short4 r = rect_sorted[i];
+      c = r.z >= r.x && r.w >= r.y ? (uint64_t)((r.z - r.x + 1) * (r.w - r.y + 1)) : 0ull;
+    }
     v[j] = run;
     run += c;
   }
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict_
 }
 
 constexpr int kPartRanks = 512;  // depth ranks per level-1 partition block (one wavefront)
-constexpr int kChunk2 = 512;     // least row entries per level-2 chunk
+constexpr int kChunk2 = 512;     // least row entries per level-2 chunk (default; tunable)
 constexpr int kHist2 = 1 << 22;  // level-2 count table entries (tiles_x * chunks)
 constexpr int kGrid2 = 8192;     // persistent level-2 blocks
 
@@ -111,11 +115,11 @@ struct RectL {
 };
 
 __device__ __forceinline__ RectL part_lane_load(int n, int r, const uint32_t* __restrict__ order,
-                                                const int16_t* __restrict__ rect) {
+                                                const int16_t* __restrict__ rect_sorted) {
   RectL l{0u, 0u, 1, 0, 1.f};
   if (r < n) {
     const uint32_t g = order[r];
-    const short4 b = reinterpret_cast<const short4*>(rect)[g];
+    const short4 b = reinterpret_cast<const short4*>(rect_sorted)[r];
     l.gid = g;
     l.org = (uint32_t)(uint16_t)b.x | ((uint32_t)(uint16_t)b.y << 16);
     l.w = b.z - b.x + 1;
@@ -246,7 +250,8 @@ __global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* __res
 __global__ __launch_bounds__(256) void k_row_starts(const uint32_t* __restrict__ rtot, int rows, int tiles_x,
                                                     const uint64_t* __restrict__ m_total, int64_t capacity,
                                                     uint32_t* __restrict__ rstart, uint32_t* __restrict__ nch,
-                                                    uint32_t* __restrict__ cp, uint32_t* __restrict__ meta) {
+                                                    uint32_t* __restrict__ cp, uint32_t* __restrict__ meta,
+                                                    int64_t* __restrict__ n_pairs, uint32_t chunk_min) {
   __shared__ uint32_t sm[256];
   __shared__ uint32_t k2_sh;
   constexpr int kPer = NGS_MAX_TILES / 256;
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256) void k_row_starts(const uint32_t* __restrict__
   if (threadIdx.x == 0) {
     const uint64_t room = (uint64_t)kHist2 / (uint64_t)tiles_x - (uint64_t)rows;  // >= 1, see kHist2
     const uint64_t k2 = ((uint64_t)m1 + room - 1) / room;
-    k2_sh = (uint32_t)(k2 > (uint64_t)kChunk2 ? k2 : (uint64_t)kChunk2);
+    k2_sh = (uint32_t)(k2 > (uint64_t)chunk_min ? k2 : (uint64_t)chunk_min);
   }
   __syncthreads();
   const uint32_t K2 = k2_sh;
@@ -301,6 +306,7 @@ __global__ __launch_bounds__(256) void k_row_starts(const uint32_t* __restrict__
       nch[t0 + j] = (!over) ? (rtot[t0 + j] + K2 - 1) / K2 : 0u;
     }
   if (threadIdx.x == 0) {
+    *n_pairs = (int64_t)M;
     cp[rows] = sm[255];
     meta[0] = (uint32_t)min(M, (uint64_t)0xFFFFFFFFu);
     meta[1] = K2;
@@ -580,6 +586,7 @@ size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
   b += align_up(256 * nb * 4, 256);
   b += align_up(256 * 4, 256);
   b += align_up(mp * 8, 256);                          // row entries
+  b += align_up(nn * 8, 256);                          // rects in depth order
   b += align_up((size_t)kHist2 * 4, 256);              // level-2 counts
   b += 4 * align_up(((size_t)NGS_MAX_TILES + 1) * 4, 256);  // rtot, rstart, nch, cp
   b += align_up(16, 256);                              // meta
@@ -604,6 +611,7 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
   w.sort.rowtot = (uint32_t*)take(256 * 4);
   w.sort.max_blocks = nb;
   w.rl = (uint2*)take(mp * 8);
+  w.rect_sorted = (int16_t*)take(nn * 8);
   w.hist2 = (uint32_t*)take((size_t)kHist2 * 4);
   w.rtot = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
   w.rstart = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
@@ -616,18 +624,17 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
 // Depth sort of all n Gaussians (culled ones carry key 0xFFFFFFFF and sort last) and the
 // exclusive scan of their tile counts in that order; offsets[n] = M.
 hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st) {
-  hipError_t e = launch_iota(w.dvals[1], (size_t)n, st);
-  if (e != hipSuccess) return e;
   uint32_t *ko, *vo;
-  // inputs: zkey (read only) and iota in dvals[1]; ping-pong (dkeys[0], dvals[0]) / (dkeys[1], dvals[1])
-  e = radix_sort_pairs(p.zkey, w.dvals[1], w.dkeys[0], w.dvals[0], w.dkeys[1], w.dvals[1], (size_t)n, 0, 32,
-                       w.sort, st, &ko, &vo, kProfDepthHist);
+  // inputs: zkey (read only), values = gids (implicit); ping-pong (dkeys[0], dvals[0]) / (dkeys[1], dvals[1])
+  hipError_t e = radix_sort_pairs(p.zkey, nullptr, w.dkeys[0], w.dvals[0], w.dkeys[1], w.dvals[1], (size_t)n, 0, 32,
+                                  w.sort, st, &ko, &vo, kProfDepthHist, p.rect, w.rect_sorted);
   if (e != hipSuccess) return e;
   // 4 passes: result in (dkeys[1], dvals[1])
   const int nb = (n + kScanTile - 1) / kScanTile;
   if (n > 0) {
     ProfScope ps(kProfCountScan, st);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, st, p.count, vo, n, w.offsets, w.blocksum);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, st,
+                       reinterpret_cast<const short4*>(w.rect_sorted), n, w.offsets, w.blocksum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, w.blocksum, nb, w.offsets + n);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, w.offsets, n, w.blocksum);
   } else {
@@ -638,36 +645,36 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
 
 hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
-                             const int32_t* keep) {
+                             const int32_t* keep, int chunk2) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int rows = cam.tiles_y, tx = cam.tiles_x;
   const uint32_t* order = w.dvals[1];
   const uint64_t* m_total = w.offsets + n;
-  hipError_t e = launch_copy_u32(reinterpret_cast<uint32_t*>(out.n_pairs), reinterpret_cast<const uint32_t*>(m_total),
-                                 2, st);
-  if (e != hipSuccess) return e;
-  if (n == 0) return launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st);
+  if (n == 0) {
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.n_pairs), 0u, 2, st);
+    return e != hipSuccess ? e : launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st);
+  }
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), rows * 4, st, n, order, p.rect, rows, w.phist, nblk);
+    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, rows, w.phist, nblk);
   }
   {
     ProfScope ps(kProfTileScan, st);
     hipLaunchKernelGGL(k_part_scan_rows, dim3(rows), dim3(256), 0, st, w.phist, nblk, w.rtot);
     hipLaunchKernelGGL(k_row_starts, dim3(1), dim3(256), 0, st, w.rtot, rows, tx, m_total, out.capacity, w.rstart,
-                       w.nch, w.cp, w.meta);
+                       w.nch, w.cp, w.meta, out.n_pairs, (uint32_t)(chunk2 > 0 ? chunk2 : kChunk2));
   }
   {
     ProfScope ps(kProfTileScatter, st);
     if (rows <= kWave)
-      hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
+      hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk), dim3(kWave), 0, st, n, order, w.rect_sorted, rows, w.phist, nblk,
                          w.rstart, w.meta, w.rl);
     else if (rows <= 2 * kWave)
-      hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk), dim3(kWave), 0, st, n, order, p.rect, rows, w.phist, nblk,
+      hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk), dim3(kWave), 0, st, n, order, w.rect_sorted, rows, w.phist, nblk,
                          w.rstart, w.meta, w.rl);
     else
-      hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk), dim3(kWave), rows * 4, st, n, order, p.rect, rows, w.phist,
+      hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, rows, w.phist,
                          nblk, w.rstart, w.meta, w.rl);
   }
   {

@@ -14,6 +14,7 @@ struct ngs_ctx {
   int32_t last_hip = 0;
   int64_t* pinned = nullptr;  // host-pinned scratch for reading device counters
   void* scratch = nullptr;    // this device's copy of the static scratch array (device address)
+  int32_t* dev_small = nullptr;  // 256 bytes of device memory for internal results (ngs_sur_pick)
   // Non-blocking streams (default priority) on which ngs_score_batch keeps several views in
   // flight, and the events that fork them from and join them to the caller's stream.
   std::vector<hipStream_t> lanes;
@@ -155,7 +156,7 @@ struct BatchWs {
 
 size_t batch_fixed_bytes(int64_t n, int64_t max_pairs) {
   const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
-  return al(nn * 8) + al(nn * 12) + al(nn * 4) + al(nn * 4) + al(nn * 8) + al(nn * 4) + al(mp * 4) +
+  return al(nn * 8) + al(nn * 12) + al(nn * 4) + al(nn * 4) + al(nn * 8) + al(nn * 4) + al(nn * 32) + al(mp * 4) +
          al(2 * NGS_MAX_TILES * 4) + al(8) + al(bin_ws_bytes(n, max_pairs));
 }
 
@@ -176,6 +177,7 @@ ngs_projected proj_carve(void* ws, int64_t n) {
   pr.zkey = (uint32_t*)take(nn * 4);
   pr.rect = (int16_t*)take(nn * 8);
   pr.count = (uint32_t*)take(nn * 4);
+  pr.splat = nullptr;  // the pre-pass only counts pairs
   return pr;
 }
 
@@ -238,6 +240,7 @@ BatchWs batch_carve(void* ws, size_t ws_bytes, int64_t n, int64_t max_pairs) {
   b.proj.zkey = (uint32_t*)take(nn * 4);
   b.proj.rect = (int16_t*)take(nn * 8);
   b.proj.count = (uint32_t*)take(nn * 4);
+  b.proj.splat = (float*)take(nn * 32);
   b.lists.gids = (uint32_t*)take(mp * 4);
   b.lists.ranges = (uint32_t*)take(2 * NGS_MAX_TILES * 4);
   b.lists.n_pairs = (int64_t*)take(8);
@@ -266,7 +269,9 @@ ngs_status ngs_create(int device, ngs_ctx** out) {
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault);
   if (e == hipSuccess) e = static_scratch_address(device, &c->scratch);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dev_small, 256);
   if (e != hipSuccess) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return NGS_HIP_ERROR;
   }
@@ -283,6 +288,7 @@ ngs_status ngs_destroy(ngs_ctx* ctx) {
   for (hipEvent_t e : ctx->half_done)
     if (e) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->dev_small) (void)hipFree(ctx->dev_small);
   delete ctx;
   return NGS_OK;
 }
@@ -340,6 +346,7 @@ ngs_status ngs_project(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* c
   if (s == NGS_OK) s = check_cam(cam, rp);
   if (s == NGS_OK) s = check_proj(out);
   if (s != NGS_OK) return s;
+  if (out->splat && scene->n > 0 && !scene->opacity) return NGS_INVALID_ARG;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
   NGS_TRY_HIP(ctx, launch_project(*scene, make_devcam(*cam, kTile), *rp, *out, (hipStream_t)stream));
   return NGS_OK;
@@ -367,7 +374,7 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
     NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
     return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
   }
-  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, w, *out, nullptr, nullptr, st));
+  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, w, *out, nullptr, nullptr, st, nullptr, ctx->tuning.bin_chunk));
   return NGS_OK;
 }
 
@@ -441,9 +448,12 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
   if (ig->mode == NGS_MODE_ACCUMULATE && (!h || !h->slot_of || !h->n_slots || !h->gid_of || !h->h_rgb || !h->h_d || !h->h_o))
     return NGS_INVALID_ARG;
   if (ig->mode == NGS_MODE_SCORE && !ig_out) return NGS_INVALID_ARG;
+  if (!proj->splat && scene->n > 0) return NGS_INVALID_ARG;
   if (h && (h->k != scene->k || (h->capacity > 0 && !h->logdet))) return NGS_INVALID_ARG;
   if (ig->criterion == 1 && ig->mode == NGS_MODE_SCORE && h && h->capacity > 0 && !h->trinv) return NGS_INVALID_ARG;
-  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel) ||
+      !ig_waves_valid(scene->k, ctx->tuning.ig_lanes_per_pixel, ctx->tuning.ig_waves_per_simd))
+    return NGS_INVALID_ARG;
   if (!ws) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
@@ -454,7 +464,7 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
   if (ig_out) NGS_TRY_HIP(ctx, hipMemsetAsync(ig_out, 0, 3 * sizeof(double), st));
   const DevCam dc = make_devcam(*cam, kTile);
   NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, dc, make_raster(*rp), *ig, w, stats, ctx->tuning.ig_lanes_per_pixel,
-                                   st));
+                                   st, ctx->tuning.ig_waves_per_simd));
   NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_out ? ig_out : nullptr, stats, sticky, st));
   int64_t of = 0;
   s = read_i64(ctx, sticky, 4, st, &of);
@@ -555,9 +565,10 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     // slots first: with a target object only the lists of tiles that a weighted Gaussian
     // reaches are written, the only ones the information walk reads
     NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, *ig, igs[i], ls));
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i])));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i]),
+                                       ctx->tuning.bin_chunk));
     NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats,
-                                    ctx->tuning.ig_lanes_per_pixel, ls));
+                                    ctx->tuning.ig_lanes_per_pixel, ls, ctx->tuning.ig_waves_per_simd));
     NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v, stats, sticky, ls));
   }
   for (int i = 0; i < lanes; ++i) {
@@ -593,7 +604,9 @@ extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, n
     sc.trace_total[0] = sc.trace_total[1] = sc.trace_total[2] = 0.0;
   }
   if (s != NGS_OK) return s;
-  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel) ||
+      !ig_waves_valid(scene->k, ctx->tuning.ig_lanes_per_pixel, ctx->tuning.ig_waves_per_simd))
+    return NGS_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
   size_t need = 0;
@@ -620,8 +633,10 @@ extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, n
       NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
       NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
       NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, p, w, st));
-      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w)));
-      NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, rc, p, w, nullptr, lpp, st));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w),
+                                         ctx->tuning.bin_chunk));
+      NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, rc, p, w, nullptr, lpp, st,
+                                      ctx->tuning.ig_waves_per_simd));
       NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, p, w, h, pass == 0 ? nullptr : ig_train + 3 * (size_t)t,
                                           nullptr, sticky, st));
     }
@@ -673,7 +688,9 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     return NGS_INVALID_ARG;
   ngs_status s = check_batch(scene, h, cams, n_views, rp, ig, dims, ws, ws_bytes);
   if (s != NGS_OK) return s;
-  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel) ||
+      !ig_waves_valid(scene->k, ctx->tuning.ig_lanes_per_pixel, ctx->tuning.ig_waves_per_simd))
+    return NGS_INVALID_ARG;
   for (int f = 0; f < 3; ++f)
     if (((ig->outputs >> f) & 1u) && !(normalisers[f] > 0.0)) return NGS_DEGENERATE;
   hipStream_t st = (hipStream_t)stream;
@@ -699,6 +716,46 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
   return NGS_OK;
 }
 
+ngs_status ngs_sur_pick(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
+                        const ngs_camera* cams, int32_t n_views, const float* pred, int32_t rescore,
+                        const ngs_raster_params* rp, const ngs_ig_params* ig, int32_t* chosen, float* scores,
+                        double* ig_raw, int32_t* best, int64_t* stats, const ngs_dims* dims, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!ctx || !cams || n_views < 1 || !pred || rescore < 1 || !chosen || !scores || !ig_raw || !best)
+    return NGS_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
+  // the network's ranking: candidates by descending prediction, lower index first on ties,
+  // a prediction that is not a number last
+  std::vector<float> p((size_t)n_views);
+  NGS_TRY_HIP(ctx, hipMemcpyAsync(p.data(), pred, p.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+  NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
+  std::vector<int32_t> order((size_t)n_views);
+  for (int32_t v = 0; v < n_views; ++v) order[v] = v;
+  const int32_t r = std::min(rescore, n_views);
+  auto ahead = [&](int32_t a, int32_t b) {
+    const bool na = std::isnan(p[a]), nb = std::isnan(p[b]);
+    if (na != nb) return nb;
+    if (!na && p[a] != p[b]) return p[a] > p[b];
+    return a < b;
+  };
+  std::partial_sort(order.begin(), order.begin() + r, order.end(), ahead);
+  std::vector<ngs_camera> sel((size_t)r);
+  for (int32_t i = 0; i < r; ++i) {
+    chosen[i] = order[i];
+    sel[i] = cams[order[i]];
+  }
+  // the exact information gain judges the network's choice
+  ngs_status s = ngs_score_batch(ctx, scene, h, normalisers, sel.data(), r, rp, ig, scores, ctx->dev_small, ig_raw,
+                                 stats, dims, ws, ws_bytes, stream);
+  if (s != NGS_OK) return s;
+  int64_t local = -1;
+  s = read_i64(ctx, ctx->dev_small, 4, st, &local);
+  if (s != NGS_OK) return s;
+  *best = (local >= 0 && local < r) ? chosen[local] : -1;
+  return NGS_OK;
+}
+
 ngs_status ngs_score_graph_create(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h, const double* normalisers,
                                   const ngs_camera* cams, int32_t n_views, const ngs_raster_params* rp,
                                   const ngs_ig_params* ig, float* scores, int32_t* best, double* ig_raw,
@@ -711,7 +768,9 @@ ngs_status ngs_score_graph_create(ngs_ctx* ctx, const ngs_scene* scene, ngs_hess
     return NGS_INVALID_ARG;
   ngs_status s = check_batch(scene, h, cams, n_views, rp, ig, dims, ws, ws_bytes);
   if (s != NGS_OK) return s;
-  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel)) return NGS_INVALID_ARG;
+  if (!ig_lpp_valid(scene->k, ctx->tuning.ig_lanes_per_pixel) ||
+      !ig_waves_valid(scene->k, ctx->tuning.ig_lanes_per_pixel, ctx->tuning.ig_waves_per_simd))
+    return NGS_INVALID_ARG;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
   s = ensure_lanes(ctx, std::max(1, std::min(views_in_flight(dims), n_views)));
   if (s != NGS_OK) return s;
@@ -775,6 +834,9 @@ ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* t) {
   if (!ctx || !t) return NGS_INVALID_ARG;
   if (t->ig_lanes_per_pixel != 0 && t->ig_lanes_per_pixel != 1 && t->ig_lanes_per_pixel != 2 &&
       t->ig_lanes_per_pixel != 4)
+    return NGS_INVALID_ARG;
+  if (t->ig_waves_per_simd != 0 && t->ig_waves_per_simd != 4) return NGS_INVALID_ARG;
+  if (t->bin_chunk != 0 && (t->bin_chunk < 256 || t->bin_chunk > 8192 || (t->bin_chunk & (t->bin_chunk - 1))))
     return NGS_INVALID_ARG;
   ctx->tuning = *t;
   return NGS_OK;
@@ -951,7 +1013,8 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
     for (int i = 0; i < g; ++i) {
       hipStream_t ls = ctx->lanes[i];
       if (q >= 2) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ls, ctx->half_done[half], 0));
-      const BatchWs b = batch_carve(base + (size_t)(half * G + i) * per, fixed, scene->n, dims->max_pairs);
+      BatchWs b = batch_carve(base + (size_t)(half * G + i) * per, fixed, scene->n, dims->max_pairs);
+      b.proj.splat = nullptr;  // the render reads the planes, not the walk records
       const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
       const DevCam dc = make_devcam(cams[v0 + i], kTile);
       NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));

@@ -136,7 +136,8 @@ size_t sort_blocks_for(size_t n);
 hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_a,
                             uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
                             int begin_bit, int end_bit, const SortWs& ws, hipStream_t st,
-                            uint32_t** keys_out, uint32_t** vals_out, int prof_base);
+                            uint32_t** keys_out, uint32_t** vals_out, int prof_base,
+                            const void* rec_in = nullptr, void* rec_sorted = nullptr);
 hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st);
@@ -154,6 +155,7 @@ struct BinWs {
   uint32_t* ptot;       // pairs per tile [4096]
   SortWs sort;
   uint2* rl;            // level 1 output: {gid, x0 | w << 16} per (row, Gaussian) [max_pairs]
+  int16_t* rect_sorted; // [n][4] the tile rects in depth order (written by the last sort pass)
   uint32_t* hist2;      // level 2: pairs per (tile, chunk), row by row
   uint32_t *rtot, *rstart, *nch, *cp;  // per row: entries, start, chunks, chunk prefix [4097]
   uint32_t* meta;       // M, entries per chunk, chunks, overflow
@@ -165,9 +167,11 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
 // be NULL) is raised; stats[1] (may be NULL) accumulates the pair count. keep (may be NULL:
 // every tile) flags the tiles whose lists are wanted: the others get empty ranges and none of
 // their gids is written, while the wanted lists and M stay those of the full binning.
+// chunk2: least row entries per level-2 chunk (0 = 512): longer chunks write longer runs per
+// tile and leave fewer partly written lines, shorter ones spread the scatter over more blocks.
 hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
-                             const int32_t* keep = nullptr);
+                             const int32_t* keep = nullptr, int chunk2 = 0);
 
 // Rendering (render.hip).
 hipError_t launch_render(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
@@ -201,9 +205,11 @@ size_t ig_ws_bytes(int64_t n, int64_t k, int64_t max_slots);
 IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
 // lpp: lanes per pixel of the tile kernel (1, 2 or 4; 0 = the default for k); it sets the
 // workgroup size and the rows per LDS reduction round. ig_lpp_valid tells which k allow which.
+// waves: waves per SIMD of the back pass (0 = default, 4 = the two-workgroups-per-CU variant;
+// see ig_waves_valid).
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
                            const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
-                           const IgWs& w, int64_t* stats, int lpp, hipStream_t st);
+                           const IgWs& w, int64_t* stats, int lpp, hipStream_t st, int waves = 0);
 // The two halves of launch_ig_tiles: with a target object the flags of the tiles that a
 // weighted Gaussian's rect reaches (see ig_tile_flags; needed before the filtered binning),
 // then the walk (front pass, slots of the contributing weighted Gaussians, back pass).
@@ -213,10 +219,11 @@ hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const De
                             const IgWs& w, hipStream_t st);
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
-                          hipStream_t st);
+                          hipStream_t st, int waves = 0);
 // Tile flags of w when launch_ig_assign fills them (a target object), else nullptr.
 const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w);
 bool ig_lpp_valid(int64_t k, int lpp);
+bool ig_waves_valid(int64_t k, int lpp, int waves);
 hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
                               double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);

@@ -139,12 +139,16 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
 // pass of a wavefront needs no entry outside that range, since only weighted contributors
 // write records and only the contributors behind them feed their suffixes.
 __global__ __launch_bounds__(kTilePix) void k_ig_front(
-    int n, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
-    const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ opacity,
-    const float* __restrict__ conf, float* __restrict__ pix_t, int32_t* __restrict__ pix_last,
+    const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
+    const float4* __restrict__ splat, const float* __restrict__ conf, float* __restrict__ pix_t,
+    int32_t* __restrict__ pix_last,
     int2* __restrict__ wave_range, uint8_t* __restrict__ cflag, int64_t* __restrict__ stats,
     const int32_t* __restrict__ tflag) {
   __shared__ int tile_last_sh;
+  // with stats: the tile's list positions that contribute to some pixel (one bit per position,
+  // the first kFBits of the list; beyond them each strip counts its own)
+  constexpr int kFBits = 8192;
+  __shared__ uint32_t fbits[kFBits / 32];
   const int ntiles = cam.tiles_x * cam.tiles_y;
   const int tile = blockIdx.x;
   if (tflag && tflag[tile] == 0) return;
@@ -158,19 +162,23 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
   const uint32_t start = ranges[tile], end = ranges[ntiles + tile];
   const float sx0 = (float)(tx * kTile) + 0.5f, sx1 = sx0 + (float)(kTile - 1);
   const float sy0 = (float)(ty * kTile + wave * 4) + 0.5f, sy1 = sy0 + 3.f;
+  if (stats) {
+    for (int i = threadIdx.x; i < kFBits / 32; i += kTilePix) fbits[i] = 0u;
+    __syncthreads();
+  }
+  uint32_t f_far = 0u;  // contributing positions beyond the bitmap (this strip)
   float T = 1.f;
   int last = -1, nc = 0;
   int wave_first = INT_MAX;
   bool done = !inside;
-  // batch entry of this lane: gid and geometry, the next batch's in flight
+  // batch entry of this lane: gid and its walk record, the next batch's in flight
   uint32_t g_n = 0u;
-  float nmx = 0.f, nmy = 0.f, nqa = 0.f, nqb = 0.f, nqc = 0.f, nop = 0.f;
+  float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = make_float4(0.f, 0.f, 0.f, -1.f);
   auto load = [&](uint32_t b) {
     if (b < end && lane < (int)(end - b)) {
       g_n = gids[b + lane];
-      nmx = mean2d[g_n]; nmy = mean2d[n + g_n];
-      nqa = conic[g_n]; nqb = conic[n + g_n]; nqc = conic[2 * n + g_n];
-      nop = opacity[g_n];
+      na = splat[2 * (size_t)g_n];
+      nb = splat[2 * (size_t)g_n + 1];
     }
   };
   load(start);
@@ -178,9 +186,8 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
     if (__ballot(!done) == 0ull) break;
     const int cnt = (int)min((uint32_t)kWave, end - b0);
     const uint32_t eg = g_n;
-    const float emx = nmx, emy = nmy, eqa = nqa, eqb = nqb, eqc = nqc, eop = nop;
-    float ehx = -1.f, ehy = -1.f;
-    if (lane < cnt) conic_extent(eqa, eqb, eqc, rc.cutoff_q, &ehx, &ehy);
+    const float emx = na.x, emy = na.y, eqa = na.z, eqb = na.w, eqc = nb.x, eop = nb.y;
+    const float ehx = nb.z, ehy = nb.w;
     load(b0 + kWave);
     uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
                              emy - ehy <= sy1);
@@ -216,6 +223,17 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
       hi |= (uint32_t)__shfl_xor((int)hi, off);
     }
     const uint64_t any = ((uint64_t)hi << 32) | lo;
+    if (stats && any) {
+      const uint32_t rel = b0 - start;  // a multiple of 64
+      if (rel + kWave <= (uint32_t)kFBits) {
+        if (lane == 0) {
+          if ((uint32_t)any) atomicOr(&fbits[rel / 32], (uint32_t)any);
+          if ((uint32_t)(any >> 32)) atomicOr(&fbits[rel / 32 + 1], (uint32_t)(any >> 32));
+        }
+      } else {
+        f_far += (uint32_t)__popcll(any);
+      }
+    }
     bool weighted = false;
     if ((any >> lane) & 1ull) {
       cflag[eg] = 1;
@@ -239,16 +257,24 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
   int tot = nc;
   for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
   if (lane == 0 && tot) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)tot);
+  // contributing (tile, Gaussian) pairs F
+  uint32_t f = lane == 0 ? f_far : 0u;
+  for (int i = threadIdx.x; i < kFBits / 32; i += kTilePix) f += (uint32_t)__popc(fbits[i]);
+  for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off);
+  if (lane == 0 && f) atomicAdd((unsigned long long*)&stats[9], (unsigned long long)f);
   __syncthreads();
   if (threadIdx.x == 0 && tile_last_sh >= 0)
     atomicAdd((unsigned long long*)&stats[4], (unsigned long long)(tile_last_sh - (int)start + 1));
 }
 
-template <int KP, int LPP>
-__global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_ig_back(
+// WPS: waves per SIMD the register allocation must allow (the launch bound): 3 with one lane
+// per pixel, 1 with two or four (one 512- or 1024-lane workgroup per CU), or 4 for the
+// two-lane variant that keeps two workgroups per CU at the cost of a few spilled registers.
+template <int KP, int LPP, int WPS>
+__global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
     int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
-    const float* __restrict__ mean2d, const float* __restrict__ conic, const float* __restrict__ depth,
-    const float* __restrict__ opacity, const float* __restrict__ rgb, const float* __restrict__ prob,
+    const float4* __restrict__ splat, const float* __restrict__ depth, const float* __restrict__ rgb,
+    const float* __restrict__ prob,
     int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
     int64_t* __restrict__ stats, const int32_t* __restrict__ tflag, const float* __restrict__ pix_t,
     const int32_t* __restrict__ pix_last, const int2* __restrict__ wave_range) {
@@ -325,12 +351,12 @@ __global__ __launch_bounds__(kTilePix * LPP, 3 / LPP > 0 ? 3 / LPP : 1) void k_i
     if ((int)threadIdx.x < cnt) {
       const int j = threadIdx.x;
       const uint32_t g = gids[lo + j];
+      const float4 a = splat[2 * (size_t)g], b = splat[2 * (size_t)g + 1];
       S.slot[j] = slot_of[g];
-      S.mx[j] = mean2d[g]; S.my[j] = mean2d[n + g];
-      S.qa[j] = conic[g]; S.qb[j] = conic[n + g]; S.qc[j] = conic[2 * n + g];
-      S.op[j] = opacity[g]; S.z[j] = depth[g];
+      S.mx[j] = a.x; S.my[j] = a.y; S.qa[j] = a.z; S.qb[j] = a.w;
+      S.qc[j] = b.x; S.op[j] = b.y; S.hx[j] = b.z; S.hy[j] = b.w;
+      S.z[j] = depth[g];
       S.r[j] = rgb[g]; S.g[j] = rgb[n + g]; S.b[j] = rgb[2 * n + g];
-      conic_extent(S.qa[j], S.qb[j], S.qc[j], rc.cutoff_q, &S.hx[j], &S.hy[j]);
     }
     for (int idx = threadIdx.x; idx < cnt * KP; idx += kThreads) {
       const int j = idx / KP, c = idx % KP;
@@ -578,7 +604,7 @@ __global__ __launch_bounds__(256) void k_ig_zero(float4* __restrict__ acc, const
     acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int KP, int LPP>
+template <int KP, int LPP, int WPS = (3 / LPP > 0 ? 3 / LPP : 1)>
 hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                        const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, const int32_t* tflag, int64_t* stats,
                        hipStream_t st) {
@@ -586,9 +612,9 @@ hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_til
   const size_t shm = sizeof(IgShared<KP, LPP>);
   static_assert(sizeof(IgShared<KP, LPP>) <= 65536, "IG kernel LDS");
   ProfScope ps(kProfIgTiles, st);
-  hipLaunchKernelGGL((k_ig_back<KP, LPP>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
-                     p.mean2d, p.conic, p.depth, s.opacity, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride, w.slot_of,
-                     stats, tflag, w.pix_t, w.pix_last, w.wave_range);
+  hipLaunchKernelGGL((k_ig_back<KP, LPP, WPS>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
+                     reinterpret_cast<const float4*>(p.splat), p.depth, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride,
+                     w.slot_of, stats, tflag, w.pix_t, w.pix_last, w.wave_range);
   return hipGetLastError();
 }
 
@@ -658,13 +684,14 @@ hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st) {
 
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
-                          hipStream_t st) {
+                          hipStream_t st, int waves) {
   const int32_t* tflag = ig_tile_flags(ig, w);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   {
     ProfScope ps(kProfIgFront, st);
-    hipLaunchKernelGGL(k_ig_front, dim3(ntiles), dim3(kTilePix), 0, st, s.n, l.gids, l.ranges, cam, rc, p.mean2d,
-                       p.conic, s.opacity, s.conf, w.pix_t, w.pix_last, w.wave_range, w.cflag, stats, tflag);
+    hipLaunchKernelGGL(k_ig_front, dim3(ntiles), dim3(kTilePix), 0, st, l.gids, l.ranges, cam, rc,
+                       reinterpret_cast<const float4*>(p.splat), s.conf, w.pix_t, w.pix_last, w.wave_range, w.cflag,
+                       stats, tflag);
   }
   {
     ProfScope ps(kProfIgAssign, st);
@@ -684,17 +711,19 @@ hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_
                                    : launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
   if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
                         : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                                   : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+                        : waves == 4 ? launch_ig_k<32, 2, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                                     : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
   return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                  : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+         : waves == 4 ? launch_ig_k<64, 2, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
+                      : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
 }
 
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
-                           hipStream_t st) {
+                           hipStream_t st, int waves) {
   hipError_t e = launch_ig_assign(s, p, cam, ig, w, st);
   if (e != hipSuccess) return e;
-  return launch_ig_walk(s, p, l, cam, rc, ig, w, stats, lpp, st);
+  return launch_ig_walk(s, p, l, cam, rc, ig, w, stats, lpp, st, waves);
 }
 
 bool ig_lpp_valid(int64_t k, int lpp) {
@@ -702,6 +731,12 @@ bool ig_lpp_valid(int64_t k, int lpp) {
   if (k <= 8) return lpp == 1 || lpp == 2;
   if (k <= 32) return lpp == 1 || lpp == 2 || lpp == 4;
   return lpp == 1 || lpp == 2;
+}
+
+bool ig_waves_valid(int64_t k, int lpp, int waves) {
+  if (waves == 0) return true;
+  const int l = lpp == 0 ? (k <= 8 ? 1 : 2) : lpp;
+  return waves == 4 && l == 2 && k > 16;
 }
 
 }  // namespace ngs

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
                                                  double eps2d, int tile, float* __restrict__ mean2d,
                                                  float* __restrict__ conic, float* __restrict__ depth,
                                                  uint32_t* __restrict__ zkey, int16_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ count) {
+                                                 uint32_t* __restrict__ count, const float* __restrict__ opacity,
+                                                 float cutoff_q, float4* __restrict__ splat) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   double R[9];
@@ -131,6 +132,14 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   if (!valid) { x0 = 0; y0 = 0; x1 = -1; y1 = -1; }
   reinterpret_cast<short4*>(rect)[g] = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
   count[g] = valid ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+  if (splat) {
+    // what a tile walk reads of an entry, in one 32-byte record: 2D mean, conic, opacity and
+    // the half-extents of the ellipse q <= cutoff (no entry of a culled Gaussian is walked)
+    float hx = -1.f, hy = -1.f;
+    if (valid) conic_extent(qa, qb, qc, cutoff_q, &hx, &hy);
+    splat[2 * (size_t)g] = make_float4(mxf, myf, qa, qb);
+    splat[2 * (size_t)g + 1] = make_float4(qc, valid ? opacity[g] : 0.f, hx, hy);
+  }
 }
 
 }  // namespace
@@ -151,7 +160,7 @@ hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raste
   ProfScope ps(kProfProject, st);
   hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, cam,
                      (double)rp.z_near, (double)rp.eps2d, rp.tile, out.mean2d, out.conic, out.depth, out.zkey,
-                     out.rect, out.count);
+                     out.rect, out.count, s.opacity, rp.cutoff_q, reinterpret_cast<float4*>(out.splat));
   return hipGetLastError();
 }
 

@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
                                                           const uint32_t* __restrict__ vin, size_t n, int shift,
                                                           const uint32_t* __restrict__ hist, size_t nblocks,
                                                           const uint32_t* __restrict__ rowtot,
-                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          const uint2* __restrict__ rin, uint2* __restrict__ rout) {
   // The block's 2048 pairs are first ranked into digit order in LDS (stable), then streamed
   // out: consecutive lanes write consecutive positions of each digit's run.
   __shared__ uint32_t sm[kSortThreads];
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
   for (int j = 0; j < kSortItems; ++j) {
     const int li = j * kSortThreads + t;
     keys[j] = li < cnt ? kin[blk + li] : 0u;
-    vals[j] = li < cnt ? vin[blk + li] : 0u;
+    vals[j] = li < cnt ? (vin ? vin[blk + li] : (uint32_t)(blk + li)) : 0u;
     if (li < cnt) atomicAdd(&wcnt[0][(keys[j] >> shift) & (kRadix - 1)], 1u);
   }
   __syncthreads();
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
     const uint32_t pos = gbase[d] + ((uint32_t)i - lstart[d]);
     kout[pos] = key;
     vout[pos] = sv[i];
+    if (rout) rout[pos] = rin[sv[i]];  // an 8-byte record of the value's, carried into sorted order
   }
 }
 
@@ -196,11 +198,13 @@ hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st) {
 }
 
 // Sorts bits [begin_bit, end_bit) of the keys; the result is in (*keys_out, *vals_out),
-// which is one of the two ping-pong buffers (a, b). The inputs are only read.
+// which is one of the two ping-pong buffers (a, b). The inputs are only read; vals_in NULL
+// stands for the values 0, 1, ..., n - 1 (the keys' own positions). With rec_in (8-byte
+// records indexed by value) the last pass also writes rec_sorted[i] = rec_in[value of i].
 hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_a,
                             uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n, int begin_bit,
                             int end_bit, const SortWs& ws, hipStream_t st, uint32_t** keys_out,
-                            uint32_t** vals_out, int prof_base) {
+                            uint32_t** vals_out, int prof_base, const void* rec_in, void* rec_sorted) {
   const size_t nb = sort_blocks_for(n);
   if (nb > ws.max_blocks) return hipErrorInvalidValue;
   const uint32_t* kin = keys_in;
@@ -221,8 +225,10 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, ui
     }
     {
       ProfScope ps(prof_base + 2, st);
+      const bool last = shift + kRadixBits >= end_bit;
       hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, n, shift, ws.hist, nb,
-                         ws.rowtot, kdst, vdst);
+                         ws.rowtot, kdst, vdst, last ? static_cast<const uint2*>(rec_in) : nullptr,
+                         last ? static_cast<uint2*>(rec_sorted) : nullptr);
     }
     *keys_out = kdst;
     *vals_out = vdst;

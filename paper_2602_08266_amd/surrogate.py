@@ -98,6 +98,48 @@ def predict(net: B.Surrogate, x: torch.Tensor, batch: int = 256) -> torch.Tensor
     return torch.cat(out)
 
 
+class Pipeline:
+    """What the surrogate-guided choice needs for one scene: the device scene (whole-scene
+    confidence, Eq. 7), the exact scorer set up on the training views (H_T, Eq. 10
+    normalisers), the per-Gaussian novelty weights and the batched feature renderer."""
+
+    def __init__(self, ctx: B.Context, scene, train: Sequence, views_in_flight: int = 32,
+                 max_pairs: int = 1 << 23, feature_in_flight: int = 32):
+        self.ctx = ctx
+        self.rp = B.raster_params()
+        self.ds = B.DeviceScene(scene, "cuda")
+        ig = B.ig_params(target_id=-1)
+        self.scorer = B.NbvScorer(ctx, self.ds, self.rp, ig, max_pairs=max_pairs, max_slots=max(scene.n, 1 << 16),
+                                  store_capacity=max(scene.n, 1 << 16), views_in_flight=views_in_flight)
+        self.scorer.setup([B.camera(c) for c in train])
+        self.weight = B.ngs_sur_novelty(ctx, self.ds, self.scorer.h, ig.lambda_prior)
+        self.fr = B.FeatureRenderer(ctx, self.ds, max_pairs=max_pairs, views_in_flight=feature_in_flight)
+
+
+@dataclass
+class Pick:
+    best: int                 # index (into the candidates) of the exact argmax among the re-scored
+    pred: torch.Tensor        # [V] network predictions
+    chosen: List[int]         # the re-scored candidates, by descending prediction
+    scores: torch.Tensor      # [R][4] their exact scores (Eq. 10-11)
+    seconds: float            # wall clock of the whole choice (features, network, re-score)
+
+
+def pick(ctx: B.Context, scorer: B.NbvScorer, net: B.Surrogate, fr: B.FeatureRenderer, cams: Sequence,
+         rp, weight: Optional[torch.Tensor], rescore: int = 256, batch: int = 256) -> Pick:
+    """The surrogate-guided next-best-view choice: the candidates' feature maps and the
+    network's predictions, then the exact scorer on the network's best `rescore` candidates and
+    the exact argmax among them (ngs_sur_pick). The scorer must be set up (H_T, normalisers)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = fr(cams, rp, DEPTH_SCALE, weight=weight)
+    pred = predict(net, x, batch)
+    best, chosen, scores, _ = B.ngs_sur_pick(ctx, scorer.scene, scorer.h, scorer.norm, cams, pred, rescore, rp,
+                                             scorer.ig, scorer.workspace())
+    torch.cuda.synchronize()
+    return Pick(best, pred, chosen, scores, time.perf_counter() - t0)
+
+
 @dataclass
 class Agreement:
     """Ranking agreement of the surrogate with the exact scores on held-out scenes. The

@@ -100,6 +100,28 @@ def test_bin_sort_bitexact(B, ctx, wl, view):
     assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
 
 
+@pytest.mark.parametrize("chunk", [256, 2048, 8192])
+def test_bin_sort_bitexact_every_chunk_size(B, ctx, chunk):
+    """The second binning level's chunk size (a tuning knob) changes no list: 200k Gaussians
+    at 640x480 against the oracle, bit for bit."""
+    log(f"test_bin_sort chunk {chunk}")
+    cfg, scene, cands, train = scenegen.make_workload("mid", 0, n_views=2)
+    ds = device_scene(B, ctx, scene)
+    rp = B.raster_params()
+    c = B.camera(cands[1])
+    pr = B.ngs_project(ctx, ds, c, rp)
+    B.ngs_set_tuning(ctx, 0, 0, chunk)
+    try:
+        lists = B.ngs_bin_sort(ctx, ds, pr, c, rp, capacity=1 << 24)
+    finally:
+        B.ngs_set_tuning(ctx, 0)
+    ref = oracle.tile_lists(scene, cands[1])
+    m = int(lists.n_pairs.item())
+    assert m == ref["m"]
+    assert np.array_equal(lists.gids[:m].cpu().numpy().view(np.uint32), ref["gids"])
+    assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+
+
 @pytest.mark.parametrize("w,h", [(2304, 64), (64, 1100), (64, 2100), (1300, 40)])
 def test_bin_sort_bitexact_tile_grid_shapes(B, ctx, w, h):
     """Tile grids that take the other counter paths of the two-level partition: more than
@@ -222,6 +244,9 @@ def test_score_pipeline_tiny(B, ctx, target):
         assert int(best.item()) == ref.best
     st = stats.cpu().numpy()
     assert st[0] == len(cands) and st[5] == 0
+    # contributing (tile, Gaussian) pairs: at least one per touched Gaussian, at most one per
+    # contributing (pixel, Gaussian) pair and per emitted (tile, Gaussian) pair
+    assert st[2] <= st[9] <= min(st[3], st[1])
     log(f"  best gpu {int(best.item())} oracle {ref.best}; stats {st}")
 
 
@@ -328,6 +353,35 @@ def test_count_pairs_prepass_matches_oracle(B, ctx):
     assert got.tolist() == ref and ref[-1] == 0
 
 
+def test_surrogate_pick_rescores_the_network_choice(B, ctx):
+    """ngs_sur_pick: the candidates ranked by the given predictions (descending, lower index on
+    ties), the best `rescore` of them scored exactly as ngs_score_batch scores them, and the
+    exact argmax among those returned as an index into the full candidate list."""
+    import torch
+    log("test_surrogate_pick")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    ds = B.DeviceScene(scene, "cuda")
+    rp, ig = B.raster_params(), B.ig_params()
+    scorer = B.NbvScorer(ctx, ds, rp, ig, max_pairs=1 << 18, max_slots=1 << 14, store_capacity=1 << 14)
+    norm = scorer.setup([B.camera(c) for c in train])
+    cams = [B.camera(c) for c in cands]
+    full_scores, full_best, _ = scorer.score(cams)
+    full_scores = full_scores.cpu().numpy()
+    rng = np.random.default_rng(3)
+    pred_np = rng.normal(size=len(cams)).astype(np.float32)
+    pred_np[5] = pred_np[2]  # a tie: the lower index goes first
+    pred = torch.tensor(pred_np, device="cuda")
+    order = sorted(range(len(cams)), key=lambda i: (-pred_np[i], i))
+    for r in (1, 3, len(cams), len(cams) + 4):
+        best, chosen, scores, raw = B.ngs_sur_pick(ctx, ds, scorer.h, norm, cams, pred, r, rp, ig, scorer.workspace())
+        rr = min(r, len(cams))
+        assert chosen == order[:rr]
+        sc = scores.cpu().numpy()
+        assert np.allclose(sc, full_scores[chosen], rtol=1e-4, atol=0.0)
+        assert best == chosen[int(np.argmax(sc[:, 3]))]
+    assert best == int(full_best.item())
+
+
 def test_training_setup_degenerate_and_capacity(B, ctx):
     """ngs_training_setup reports a training set that sees nothing (all Eq. 10 normalisers
     zero) as NGS_DEGENERATE, and a store smaller than the touched Gaussians as NGS_CAPACITY."""
@@ -418,12 +472,13 @@ def test_abi_errors(B, ctx):
     assert L.ngs_render_backward(ctx.handle, None, None, None, None, None, 0, None, None, None, 0, None) == B.NGS_INVALID_ARG
 
 
-@pytest.mark.parametrize("k,lpp", [(4, 1), (4, 2), (8, 1), (8, 2), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2),
-                                   (32, 4), (64, 1), (64, 2)])
-def test_info_gain_every_launch_shape(B, ctx, k, lpp):
+@pytest.mark.parametrize("k,lpp,waves", [(4, 1, 0), (4, 2, 0), (8, 1, 0), (8, 2, 0), (16, 1, 0), (16, 2, 0),
+                                         (16, 4, 0), (32, 1, 0), (32, 2, 0), (32, 2, 4), (32, 4, 0), (64, 1, 0),
+                                         (64, 2, 0), (64, 2, 4)])
+def test_info_gain_every_launch_shape(B, ctx, k, lpp, waves):
     """Every lanes-per-pixel shape the autotuner may pick (ngs_set_tuning) scores a small
     scene with a training store to the oracle's gains (1e-3 relative)."""
-    log(f"test_info_gain_every_launch_shape k={k} lpp={lpp}")
+    log(f"test_info_gain_every_launch_shape k={k} lpp={lpp} waves={waves}")
     clusters = min(8, k)
     scene = scenegen.make_scene(3000, clusters, k, seed=21)
     cfg = scenegen.SceneConfig("shape", 3000, clusters, k, 4, ((128, 96, 4),), 500.0, (0.6, 0.6))
@@ -431,9 +486,9 @@ def test_info_gain_every_launch_shape(B, ctx, k, lpp):
     ds = B.DeviceScene(scene, "cuda")
     ref = oracle.score(scene, train, cands)
     assert ref.status == 0
-    B.ngs_set_tuning(ctx, lpp)
+    B.ngs_set_tuning(ctx, lpp, waves)
     try:
-        assert B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"] == lpp
+        assert B.ngs_get_tuning(ctx) == {"ig_lanes_per_pixel": lpp, "ig_waves_per_simd": waves, "bin_chunk": 0}
         scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
                              store_capacity=1 << 14, views_in_flight=2)
         norm = scorer.setup([B.camera(c) for c in train])
@@ -451,15 +506,18 @@ def test_tuning_rejects_shapes_the_width_does_not_allow(B, ctx):
     ds = B.DeviceScene(scene, "cuda")
     with pytest.raises(B.NgsError):
         B.ngs_set_tuning(ctx, 3)
-    B.ngs_set_tuning(ctx, 4)
-    try:
-        scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 16, max_slots=1 << 12,
-                             store_capacity=1 << 12)
-        cam = scenegen.look_at(np.array([0.6, 0.0, 0.3]), 64, 48, 60.0)
-        with pytest.raises(B.NgsError):
-            scorer.setup([B.camera(cam)])
-    finally:
-        B.ngs_set_tuning(ctx, 0)
+    with pytest.raises(B.NgsError):
+        B.ngs_set_tuning(ctx, 2, 3)
+    cam = scenegen.look_at(np.array([0.6, 0.0, 0.3]), 64, 48, 60.0)
+    for lpp, waves in ((4, 0), (1, 4)):  # four lanes at k = 64; the 4-wave build with one lane
+        B.ngs_set_tuning(ctx, lpp, waves)
+        try:
+            scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 16, max_slots=1 << 12,
+                                 store_capacity=1 << 12)
+            with pytest.raises(B.NgsError):
+                scorer.setup([B.camera(cam)])
+        finally:
+            B.ngs_set_tuning(ctx, 0)
 
 
 @pytest.mark.parametrize("wl,target", [("tiny", -1), ("tiny", 3), ("k64", -1)])

@@ -81,7 +81,7 @@ def test_lists_and_render_full_size(B, ctx, name, view):
 
 
 def bench_shape(scene, width, height):
-    """(views in flight, lanes per pixel) that the bench takes from the package's tuning cache
+    """(views in flight, lanes per pixel, waves per SIMD) that the bench takes from the tuning cache
     for this scene size and resolution on gfx950, or None."""
     from paper_2602_08266_amd import autotune
     if not os.path.exists(autotune.CACHE):
@@ -90,7 +90,7 @@ def bench_shape(scene, width, height):
         k = json.loads(key)
         if k["dev"] == "gfx950" and k["n"] == scene.n and k["k"] == scene.k and \
                 [r for r, _ in k["res"]] == [f"{width}x{height}"]:
-            return v["views_in_flight"], v["ig_lanes_per_pixel"]
+            return v["views_in_flight"], v["ig_lanes_per_pixel"], v.get("ig_waves_per_simd", 0), v.get("bin_chunk", 0)
     return None
 
 
@@ -122,8 +122,8 @@ def test_information_gain_full_size(B, ctx, name, shape):
         if tuned is None:
             pytest.skip("no tuned shape for this workload in the package cache")
         scorer.views_in_flight = tuned[0]
-        B.ngs_set_tuning(ctx, tuned[1])
-        log(f"  tuned shape: {tuned[0]} views in flight, {tuned[1]} lanes per pixel")
+        B.ngs_set_tuning(ctx, tuned[1], tuned[2], tuned[3])
+        log(f"  tuned shape: {tuned[0]} views in flight, {tuned[1]} lanes per pixel, {tuned[2]} waves per SIMD")
     # with the bench's shape the sample is repeated past the views in flight, so that every
     # buffer set is used and then reused in stream order
     # mixed: the three resolutions three times in one call on 4 buffer sets, so that every set
