@@ -29,8 +29,11 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Exclusive scan (u64) of the tile counts in depth order (from the sorted rects): per-block
 // local scan and block totals.
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const short4* __restrict__ rect_sorted, int n,
-                                                             uint64_t* __restrict__ out, uint64_t* __restrict__ bsum) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const short4* rect_sorted_, int n, uint64_t* out_,
+                                                             uint64_t* bsum_, size_t vs) {
+  const short4* __restrict__ rect_sorted = vp(rect_sorted_, vs);
+  uint64_t* __restrict__ out = vp(out_, vs);
+  uint64_t* __restrict__ bsum = vp(bsum_, vs);
   __shared__ uint64_t sm[kScanThreads];
   const int t = threadIdx.x;
   const int base = blockIdx.x * kScanTile + t * kScanItems;
@@ -61,8 +64,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(const short4* __res
 }
 
 // Single block: exclusive scan of the block totals in place; writes the grand total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(uint64_t* __restrict__ bsum, int nb,
-                                                              uint64_t* __restrict__ total) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(uint64_t* bsum_, int nb, uint64_t* total_,
+                                                              size_t vs) {
+  uint64_t* __restrict__ bsum = vp(bsum_, vs);
+  uint64_t* __restrict__ total = vp(total_, vs);
   __shared__ uint64_t sm[kScanThreads];
   const int t = threadIdx.x;
   uint64_t carry = 0;
@@ -84,8 +89,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(uint64_t* __restri
   if (t == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* __restrict__ out, int n,
-                                                           const uint64_t* __restrict__ bsum) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* out_, int n, const uint64_t* bsum_, size_t vs) {
+  uint64_t* __restrict__ out = vp(out_, vs);
+  const uint64_t* __restrict__ bsum = vp(bsum_, vs);
   const int i = blockIdx.x * kScanTile + threadIdx.x;
   const uint64_t add = bsum[blockIdx.x];
   for (int j = 0; j < kScanItems; ++j) {
@@ -160,8 +166,11 @@ __device__ __forceinline__ int part_tile(const RectU& u, int j, int tiles_x) {
 }
 
 // Per row of a (row, block) count table: exclusive scan across blocks (in place); totals.
-__global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ hist, int nblk,
-                                                        uint32_t* __restrict__ tot) {
+__global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* hist_, int nblk, uint32_t* tot_, GroupDims gd,
+                                                        size_t vs) {
+  if ((int)blockIdx.x >= gd.ty[blockIdx.y]) return;  // past this view's rows
+  uint32_t* __restrict__ hist = vp(hist_, vs);
+  uint32_t* __restrict__ tot = vp(tot_, vs);
   __shared__ uint32_t sm[256];
   uint32_t* row = hist + (size_t)blockIdx.x * nblk;
   uint32_t carry = 0;
@@ -187,11 +196,15 @@ __global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* __restrict__ h
 // start = end = the number of pairs in lower tiles. If the pairs (m_total, the count scan's
 // total) exceed the list capacity, every range is left empty and *overflow is raised (the
 // scatters then write nothing).
-__global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict__ tot, int ntiles,
-                                                     uint32_t* __restrict__ ranges, int64_t capacity,
-                                                     int32_t* __restrict__ overflow, int64_t* __restrict__ stats,
-                                                     const uint64_t* __restrict__ m_total,
-                                                     const int32_t* __restrict__ keep) {
+__global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* tot_, GroupDims gd, uint32_t* ranges_,
+                                                     int64_t capacity, int32_t* __restrict__ overflow,
+                                                     int64_t* __restrict__ stats, const uint64_t* m_total_,
+                                                     const int32_t* keep_, size_t vs) {
+  const uint32_t* __restrict__ tot = vp(tot_, vs);
+  uint32_t* __restrict__ ranges = vp(ranges_, vs);
+  const uint64_t* __restrict__ m_total = vp(m_total_, vs);
+  const int32_t* __restrict__ keep = vp(keep_, vs);
+  const int ntiles = gd.tx[blockIdx.y] * gd.ty[blockIdx.y];
   __shared__ uint32_t sm[256];
   constexpr int kPer = NGS_MAX_TILES / 256;
   const int t0 = threadIdx.x * kPer;
@@ -226,9 +239,12 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* __restrict_
 // ---- level 1: rows ------------------------------------------------------------------------
 // Pass 1a: row entries per (row, block), row-major: rhist[r * nblk + block]. Counting needs
 // no order, so each lane adds its own Gaussian's rows.
-__global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* __restrict__ order,
-                                                    const int16_t* __restrict__ rect, int rows,
-                                                    uint32_t* __restrict__ rhist, int nblk) {
+__global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* order_, const int16_t* rect_,
+                                                    GroupDims gd, uint32_t* rhist_, int nblk, size_t vs) {
+  const uint32_t* __restrict__ order = vp(order_, vs);
+  const int16_t* __restrict__ rect = vp(rect_, vs);
+  uint32_t* __restrict__ rhist = vp(rhist_, vs);
+  const int rows = gd.ty[blockIdx.y];
   extern __shared__ uint32_t cnt[];  // [rows]
   const int lane = threadIdx.x;
   const int chunk = part_chunk(blockIdx.x, nblk);
@@ -247,11 +263,17 @@ __global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* __res
 // Pass 1b (one block): row starts, the level-2 chunking and the overflow decision.
 // meta: [0] M (all pairs), [1] entries per level-2 chunk K2, [2] chunks NC, [3] over.
 // K2 keeps the level-2 count table within kHist2 entries: tiles_x * NC <= kHist2.
-__global__ __launch_bounds__(256) void k_row_starts(const uint32_t* __restrict__ rtot, int rows, int tiles_x,
-                                                    const uint64_t* __restrict__ m_total, int64_t capacity,
-                                                    uint32_t* __restrict__ rstart, uint32_t* __restrict__ nch,
-                                                    uint32_t* __restrict__ cp, uint32_t* __restrict__ meta,
-                                                    int64_t* __restrict__ n_pairs, uint32_t chunk_min) {
+__global__ __launch_bounds__(256) void k_row_starts(const uint32_t* rtot_, GroupDims gd, const uint64_t* m_total_,
+                                                    int64_t capacity, uint32_t* rstart_, uint32_t* nch_, uint32_t* cp_,
+                                                    uint32_t* meta_, int64_t* n_pairs_, uint32_t chunk_min, size_t vs) {
+  const uint32_t* __restrict__ rtot = vp(rtot_, vs);
+  const uint64_t* __restrict__ m_total = vp(m_total_, vs);
+  uint32_t* __restrict__ rstart = vp(rstart_, vs);
+  uint32_t* __restrict__ nch = vp(nch_, vs);
+  uint32_t* __restrict__ cp = vp(cp_, vs);
+  uint32_t* __restrict__ meta = vp(meta_, vs);
+  int64_t* __restrict__ n_pairs = vp(n_pairs_, vs);
+  const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
   __shared__ uint32_t sm[256];
   __shared__ uint32_t k2_sh;
   constexpr int kPer = NGS_MAX_TILES / 256;
@@ -373,11 +395,17 @@ __device__ __forceinline__ void place_batch_reg(uint32_t (&cr)[NR], int b0, int 
 // Pass 1c: every Gaussian's row entries {gid, x0 | w << 16} to their row segments, in depth
 // order within a row. NR > 0: counters in registers (rows <= 64 NR), else in LDS.
 template <int NR>
-__global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* __restrict__ order,
-                                                       const int16_t* __restrict__ rect, int rows,
-                                                       const uint32_t* __restrict__ rhist, int nblk,
-                                                       const uint32_t* __restrict__ rstart,
-                                                       const uint32_t* __restrict__ meta, uint2* __restrict__ rl) {
+__global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* order_, const int16_t* rect_,
+                                                       GroupDims gd, const uint32_t* rhist_, int nblk,
+                                                       const uint32_t* rstart_, const uint32_t* meta_, uint2* rl_,
+                                                       size_t vs) {
+  const uint32_t* __restrict__ order = vp(order_, vs);
+  const int16_t* __restrict__ rect = vp(rect_, vs);
+  const uint32_t* __restrict__ rhist = vp(rhist_, vs);
+  const uint32_t* __restrict__ rstart = vp(rstart_, vs);
+  const uint32_t* __restrict__ meta = vp(meta_, vs);
+  uint2* __restrict__ rl = vp(rl_, vs);
+  const int rows = gd.ty[blockIdx.y];
   extern __shared__ uint32_t cnt[];  // [rows] when NR == 0
   if (meta[3]) return;
   const int lane = threadIdx.x;
@@ -433,11 +461,17 @@ __device__ __forceinline__ Chunk2 chunk2_of(uint32_t ci, int rows, const uint32_
 
 // Pass 2a: pairs per (tile, chunk); the table of row r holds tiles_x rows of nch[r] chunk
 // counts at tiles_x * cp[r]. Persistent: blocks stride over the chunks.
-__global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* __restrict__ rl, int rows, int tiles_x,
-                                                      const uint32_t* __restrict__ rstart,
-                                                      const uint32_t* __restrict__ rtot, const uint32_t* __restrict__ cp,
-                                                      const uint32_t* __restrict__ nch, const uint32_t* __restrict__ meta,
-                                                      uint32_t* __restrict__ hist2) {
+__global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
+                                                      const uint32_t* rtot_, const uint32_t* cp_, const uint32_t* nch_,
+                                                      const uint32_t* meta_, uint32_t* hist2_, size_t vs) {
+  const uint2* __restrict__ rl = vp(rl_, vs);
+  const uint32_t* __restrict__ rstart = vp(rstart_, vs);
+  const uint32_t* __restrict__ rtot = vp(rtot_, vs);
+  const uint32_t* __restrict__ cp = vp(cp_, vs);
+  const uint32_t* __restrict__ nch = vp(nch_, vs);
+  const uint32_t* __restrict__ meta = vp(meta_, vs);
+  uint32_t* __restrict__ hist2 = vp(hist2_, vs);
+  const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
   extern __shared__ uint32_t lds2[];  // cnt [tiles_x], chunk prefix [rows]
   uint32_t* cnt = lds2;
   uint32_t* cpl = lds2 + tiles_x;
@@ -465,9 +499,16 @@ __global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* __restrict__ 
 }
 
 // Pass 2b: per tile, exclusive scan of its counts across its row's chunks (in place); totals.
-__global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* __restrict__ hist2, int tiles_x,
-                                                    const uint32_t* __restrict__ cp, const uint32_t* __restrict__ nch,
-                                                    const uint32_t* __restrict__ meta, uint32_t* __restrict__ tot) {
+__global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* hist2_, GroupDims gd, const uint32_t* cp_,
+                                                    const uint32_t* nch_, const uint32_t* meta_, uint32_t* tot_,
+                                                    size_t vs) {
+  const int tiles_x = gd.tx[blockIdx.y];
+  if ((int)blockIdx.x >= tiles_x * gd.ty[blockIdx.y]) return;  // past this view's tiles
+  uint32_t* __restrict__ hist2 = vp(hist2_, vs);
+  const uint32_t* __restrict__ cp = vp(cp_, vs);
+  const uint32_t* __restrict__ nch = vp(nch_, vs);
+  const uint32_t* __restrict__ meta = vp(meta_, vs);
+  uint32_t* __restrict__ tot = vp(tot_, vs);
   __shared__ uint32_t sm[256];
   const int tile = blockIdx.x;
   const int r = tile / tiles_x, x = tile % tiles_x;
@@ -498,16 +539,23 @@ __global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* __restrict__ hist2
 // tiles_x output runs open, so the L2 completes their lines. NR > 0: counters in registers
 // (tiles_x <= 64 NR), else in LDS.
 template <int NR>
-__global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* __restrict__ rl, int rows, int tiles_x,
-                                                         const uint32_t* __restrict__ rstart,
-                                                         const uint32_t* __restrict__ rtot,
-                                                         const uint32_t* __restrict__ cp,
-                                                         const uint32_t* __restrict__ nch,
-                                                         const uint32_t* __restrict__ meta,
-                                                         const uint32_t* __restrict__ hist2,
-                                                         const uint32_t* __restrict__ ranges, int64_t capacity,
-                                                         uint32_t* __restrict__ gids_out,
-                                                         const int32_t* __restrict__ keep) {
+__global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
+                                                         const uint32_t* rtot_, const uint32_t* cp_,
+                                                         const uint32_t* nch_, const uint32_t* meta_,
+                                                         const uint32_t* hist2_, const uint32_t* ranges_,
+                                                         int64_t capacity, uint32_t* gids_out_, const int32_t* keep_,
+                                                         size_t vs) {
+  const uint2* __restrict__ rl = vp(rl_, vs);
+  const uint32_t* __restrict__ rstart = vp(rstart_, vs);
+  const uint32_t* __restrict__ rtot = vp(rtot_, vs);
+  const uint32_t* __restrict__ cp = vp(cp_, vs);
+  const uint32_t* __restrict__ nch = vp(nch_, vs);
+  const uint32_t* __restrict__ meta = vp(meta_, vs);
+  const uint32_t* __restrict__ hist2 = vp(hist2_, vs);
+  const uint32_t* __restrict__ ranges = vp(ranges_, vs);
+  uint32_t* __restrict__ gids_out = vp(gids_out_, vs);
+  const int32_t* __restrict__ keep = vp(keep_, vs);
+  const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
   extern __shared__ uint32_t lds2[];  // cnt [tiles_x] (NR == 0), chunk prefix [rows]
   uint32_t* cnt = lds2;
   uint32_t* cpl = lds2 + (NR > 0 ? 0 : tiles_x);
@@ -623,84 +671,88 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
 
 // Depth sort of all n Gaussians (culled ones carry key 0xFFFFFFFF and sort last) and the
 // exclusive scan of their tile counts in that order; offsets[n] = M.
-hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st) {
+hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st, int g, size_t vs) {
   uint32_t *ko, *vo;
   // inputs: zkey (read only), values = gids (implicit); ping-pong (dkeys[0], dvals[0]) / (dkeys[1], dvals[1])
   hipError_t e = radix_sort_pairs(p.zkey, nullptr, w.dkeys[0], w.dvals[0], w.dkeys[1], w.dvals[1], (size_t)n, 0, 32,
-                                  w.sort, st, &ko, &vo, kProfDepthHist, p.rect, w.rect_sorted);
+                                  w.sort, st, &ko, &vo, kProfDepthHist, p.rect, w.rect_sorted, g, vs);
   if (e != hipSuccess) return e;
   // 4 passes: result in (dkeys[1], dvals[1])
   const int nb = (n + kScanTile - 1) / kScanTile;
   if (n > 0) {
     ProfScope ps(kProfCountScan, st);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, st,
-                       reinterpret_cast<const short4*>(w.rect_sorted), n, w.offsets, w.blocksum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, w.blocksum, nb, w.offsets + n);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, w.offsets, n, w.blocksum);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb, g), dim3(kScanThreads), 0, st,
+                       reinterpret_cast<const short4*>(w.rect_sorted), n, w.offsets, w.blocksum, vs);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1, g), dim3(kScanThreads), 0, st, w.blocksum, nb, w.offsets + n, vs);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb, g), dim3(kScanThreads), 0, st, w.offsets, n, w.blocksum, vs);
   } else {
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(w.offsets), 0u, 2, st);
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(w.offsets), 0u, 2, st, g, vs);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
 
-hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
+hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, const BinWs& w,
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
                              const int32_t* keep, int chunk2) {
-  const int ntiles = cam.tiles_x * cam.tiles_y;
-  const int rows = cam.tiles_y, tx = cam.tiles_x;
+  const int g = G.g;
+  const size_t vs = G.vs;
+  const int rows = G.max_tiles_y, tx = G.max_tiles_x, ntiles = G.max_ntiles;  // largest view of the group
   const uint32_t* order = w.dvals[1];
   const uint64_t* m_total = w.offsets + n;
   if (n == 0) {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.n_pairs), 0u, 2, st);
-    return e != hipSuccess ? e : launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.n_pairs), 0u, 2, st, g, vs);
+    return e != hipSuccess ? e : launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st, g, vs);
   }
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
+  const int grid2 = std::max(256, kGrid2 / g);  // persistent level-2 blocks per view
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_row_hist, dim3(nblk), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, rows, w.phist, nblk);
+    hipLaunchKernelGGL(k_row_hist, dim3(nblk, g), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, G.dims, w.phist,
+                       nblk, vs);
   }
   {
     ProfScope ps(kProfTileScan, st);
-    hipLaunchKernelGGL(k_part_scan_rows, dim3(rows), dim3(256), 0, st, w.phist, nblk, w.rtot);
-    hipLaunchKernelGGL(k_row_starts, dim3(1), dim3(256), 0, st, w.rtot, rows, tx, m_total, out.capacity, w.rstart,
-                       w.nch, w.cp, w.meta, out.n_pairs, (uint32_t)(chunk2 > 0 ? chunk2 : kChunk2));
+    hipLaunchKernelGGL(k_part_scan_rows, dim3(rows, g), dim3(256), 0, st, w.phist, nblk, w.rtot, G.dims, vs);
+    hipLaunchKernelGGL(k_row_starts, dim3(1, g), dim3(256), 0, st, w.rtot, G.dims, m_total, out.capacity, w.rstart,
+                       w.nch, w.cp, w.meta, out.n_pairs, (uint32_t)(chunk2 > 0 ? chunk2 : kChunk2), vs);
   }
   {
     ProfScope ps(kProfTileScatter, st);
     if (rows <= kWave)
-      hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk), dim3(kWave), 0, st, n, order, w.rect_sorted, rows, w.phist, nblk,
-                         w.rstart, w.meta, w.rl);
+      hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk, g), dim3(kWave), 0, st, n, order, w.rect_sorted, G.dims, w.phist,
+                         nblk, w.rstart, w.meta, w.rl, vs);
     else if (rows <= 2 * kWave)
-      hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk), dim3(kWave), 0, st, n, order, w.rect_sorted, rows, w.phist, nblk,
-                         w.rstart, w.meta, w.rl);
+      hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk, g), dim3(kWave), 0, st, n, order, w.rect_sorted, G.dims, w.phist,
+                         nblk, w.rstart, w.meta, w.rl, vs);
     else
-      hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, rows, w.phist,
-                         nblk, w.rstart, w.meta, w.rl);
+      hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk, g), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, G.dims,
+                         w.phist, nblk, w.rstart, w.meta, w.rl, vs);
   }
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_tile2_hist, dim3(kGrid2), dim3(kWave), (tx + rows) * 4, st, w.rl, rows, tx, w.rstart, w.rtot,
-                       w.cp, w.nch, w.meta, w.hist2);
+    hipLaunchKernelGGL(k_tile2_hist, dim3(grid2, g), dim3(kWave), (tx + rows) * 4, st, w.rl, G.dims, w.rstart, w.rtot,
+                       w.cp, w.nch, w.meta, w.hist2, vs);
   }
   {
     ProfScope ps(kProfTileScan, st);
-    hipLaunchKernelGGL(k_tile2_scan, dim3(ntiles), dim3(256), 0, st, w.hist2, tx, w.cp, w.nch, w.meta, w.ptot);
-    hipLaunchKernelGGL(k_part_ranges, dim3(1), dim3(256), 0, st, w.ptot, ntiles, out.ranges, out.capacity, overflow,
-                       stats, m_total, keep);
+    hipLaunchKernelGGL(k_tile2_scan, dim3(ntiles, g), dim3(256), 0, st, w.hist2, G.dims, w.cp, w.nch, w.meta, w.ptot,
+                       vs);
+    hipLaunchKernelGGL(k_part_ranges, dim3(1, g), dim3(256), 0, st, w.ptot, G.dims, out.ranges, out.capacity, overflow,
+                       stats, m_total, keep, vs);
   }
   {
     ProfScope ps(kProfTileScatter, st);
     if (tx <= kWave)
-      hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
-                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
+      hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(grid2, g), dim3(kWave), rows * 4, st, w.rl, G.dims, w.rstart,
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
     else if (tx <= 2 * kWave)
-      hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(kGrid2), dim3(kWave), rows * 4, st, w.rl, rows, tx, w.rstart,
-                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
+      hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(grid2, g), dim3(kWave), rows * 4, st, w.rl, G.dims, w.rstart,
+                         w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
     else
-      hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(kGrid2), dim3(kWave), (tx + rows) * 4, st, w.rl, rows, tx,
-                         w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep);
+      hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(grid2, g), dim3(kWave), (tx + rows) * 4, st, w.rl, G.dims,
+                         w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
   }
-  if (out.keys) {
+  if (out.keys && g == 1) {
     ProfScope ps(kProfKeys64, st);
     hipLaunchKernelGGL(k_keys64, dim3(ntiles), dim3(256), 0, st, out.ranges, ntiles, out.gids, p.zkey, out.keys);
   }

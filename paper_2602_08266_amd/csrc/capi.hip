@@ -348,7 +348,7 @@ ngs_status ngs_project(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camera* c
   if (s != NGS_OK) return s;
   if (out->splat && scene->n > 0 && !scene->opacity) return NGS_INVALID_ARG;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  NGS_TRY_HIP(ctx, launch_project(*scene, make_devcam(*cam, kTile), *rp, *out, (hipStream_t)stream));
+  NGS_TRY_HIP(ctx, launch_project(*scene, single_group(make_devcam(*cam, kTile)), *rp, *out, (hipStream_t)stream));
   return NGS_OK;
 }
 
@@ -363,7 +363,7 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
   if (!ws || ws_bytes < bin_ws_bytes(scene->n, out->capacity)) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  const DevCam dc = make_devcam(*cam, kTile);
+  const Group G1 = single_group(make_devcam(*cam, kTile));
   const BinWs w = bin_ws_carve(ws, scene->n, out->capacity);
   NGS_TRY_HIP(ctx, bin_count_pairs(*proj, scene->n, w, st));
   int64_t m = 0;
@@ -374,7 +374,7 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
     NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
     return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
   }
-  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, dc, w, *out, nullptr, nullptr, st, nullptr, ctx->tuning.bin_chunk));
+  NGS_TRY_HIP(ctx, bin_emit_and_sort(*proj, scene->n, G1, w, *out, nullptr, nullptr, st, nullptr, ctx->tuning.bin_chunk));
   return NGS_OK;
 }
 
@@ -393,7 +393,7 @@ ngs_status ngs_count_pairs(ngs_ctx* ctx, const ngs_scene* scene, const ngs_camer
   const ngs_projected pr = proj_carve(ws, scene->n);
   NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(pairs), 0u, 2 * (size_t)n_views, st));
   for (int v = 0; v < n_views; ++v) {
-    NGS_TRY_HIP(ctx, launch_project(*scene, make_devcam(cams[v], kTile), *rp, pr, st));
+    NGS_TRY_HIP(ctx, launch_project(*scene, single_group(make_devcam(cams[v], kTile)), *rp, pr, st));
     NGS_TRY_HIP(ctx, launch_sum_counts(pr, scene->n, pairs + v, st));
   }
   return NGS_OK;
@@ -462,10 +462,10 @@ ngs_status ngs_info_gain(ngs_ctx* ctx, const ngs_scene* scene, const ngs_project
   s = ig_prepare(ctx, ws, ws_bytes, scene->n, scene->k, st, &w, &sticky);
   if (s != NGS_OK) return s;
   if (ig_out) NGS_TRY_HIP(ctx, hipMemsetAsync(ig_out, 0, 3 * sizeof(double), st));
-  const DevCam dc = make_devcam(*cam, kTile);
-  NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, dc, make_raster(*rp), *ig, w, stats, ctx->tuning.ig_lanes_per_pixel,
+  const Group G1 = single_group(make_devcam(*cam, kTile));
+  NGS_TRY_HIP(ctx, launch_ig_tiles(*scene, *proj, *lists, G1, make_raster(*rp), *ig, w, stats, ctx->tuning.ig_lanes_per_pixel,
                                    st, ctx->tuning.ig_waves_per_simd));
-  NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, w, h, ig_out ? ig_out : nullptr, stats, sticky, st));
+  NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, G1, *rp, *ig, w, h, ig_out ? ig_out : nullptr, stats, sticky, st));
   int64_t of = 0;
   s = read_i64(ctx, sticky, 4, st, &of);
   if (s != NGS_OK) return s;
@@ -552,26 +552,33 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
   NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
   for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   // List overflow is caught on the device (empty ranges, sticky flag) and reported once the
-  // batch has run. View v runs on lane v mod lanes, which reuses that lane's buffers in
-  // stream order.
-  for (int v = 0; v < n_views; ++v) {
-    const int i = v % lanes;
-    hipStream_t ls = ctx->lanes[i];
+  // batch has run. Views go in groups of gsz consecutive views, one launch per kernel and
+  // group (grid.y = view of the group); the buffer sets of a group are consecutive, per bytes
+  // apart. Two groups are in flight: group q runs on lane q mod 2 with the sets from
+  // (q mod 2) * gsz on, which it reuses in stream order.
+  const int gsz = lanes == 1 ? 1 : std::min(kMaxGroup, lanes / 2);
+  const int nlanes = lanes == 1 ? 1 : 2;
+  std::vector<DevCam> dcs(n_views);
+  for (int v = 0; v < n_views; ++v) dcs[v] = make_devcam(cams[v], kTile);
+  for (int v0 = 0, q = 0; v0 < n_views; v0 += gsz, ++q) {
+    const int g = std::min(gsz, n_views - v0);
+    const int i = (q % nlanes) * gsz;
+    hipStream_t ls = ctx->lanes[q % nlanes];
     const BatchWs& b = sets[i];
     const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
-    const DevCam dc = make_devcam(cams[v], kTile);
-    NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
-    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
+    const Group G = make_group(&dcs[v0], g, per);
+    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, b.proj, ls));
+    NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls, g, per));
     // slots first: with a target object only the lists of tiles that a weighted Gaussian
     // reaches are written, the only ones the information walk reads
-    NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, *ig, igs[i], ls));
-    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i]),
+    NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, G, *ig, igs[i], ls));
+    NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i]),
                                        ctx->tuning.bin_chunk));
-    NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, make_raster(*rp), *ig, igs[i], stats,
+    NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, G, make_raster(*rp), *ig, igs[i], stats,
                                     ctx->tuning.ig_lanes_per_pixel, ls, ctx->tuning.ig_waves_per_simd));
-    NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v, stats, sticky, ls));
+    NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, G, *rp, *ig, igs[i], h, ig_raw + 3 * (size_t)v0, stats, sticky, ls));
   }
-  for (int i = 0; i < lanes; ++i) {
+  for (int i = 0; i < nlanes; ++i) {
     NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ctx->lanes[i]));
     NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
   }
@@ -629,15 +636,15 @@ extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, n
   for (int pass = 0; pass < 2; ++pass) {
     const ngs_ig_params& p = pass == 0 ? acc : sc;
     for (int t = 0; t < n_train; ++t) {
-      const DevCam dc = make_devcam(train[t], kTile);
-      NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, st));
+      const Group G1 = single_group(make_devcam(train[t], kTile));
+      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, b.proj, st));
       NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
-      NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, dc, p, w, st));
-      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w),
+      NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, G1, p, w, st));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G1, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w),
                                          ctx->tuning.bin_chunk));
-      NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, dc, rc, p, w, nullptr, lpp, st,
+      NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, G1, rc, p, w, nullptr, lpp, st,
                                       ctx->tuning.ig_waves_per_simd));
-      NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, dc, *rp, p, w, h, pass == 0 ? nullptr : ig_train + 3 * (size_t)t,
+      NGS_TRY_HIP(ctx, launch_ig_finalize(*scene, G1, *rp, p, w, h, pass == 0 ? nullptr : ig_train + 3 * (size_t)t,
                                           nullptr, sticky, st));
     }
     if (pass == 0) {
@@ -1016,10 +1023,10 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
       BatchWs b = batch_carve(base + (size_t)(half * G + i) * per, fixed, scene->n, dims->max_pairs);
       b.proj.splat = nullptr;  // the render reads the planes, not the walk records
       const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
-      const DevCam dc = make_devcam(cams[v0 + i], kTile);
-      NGS_TRY_HIP(ctx, launch_project(*scene, dc, *rp, b.proj, ls));
+      const Group G1 = single_group(make_devcam(cams[v0 + i], kTile));
+      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, b.proj, ls));
       NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
-      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, dc, bw, b.lists, sticky, nullptr, ls));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G1, bw, b.lists, sticky, nullptr, ls));
       NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ls));
       NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
     }

@@ -7,6 +7,7 @@
 #include <climits>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/ngs.h"
 #include "../../include/ngs_surrogate.h"
@@ -76,6 +77,52 @@ struct DevCam {
   int width, height, tiles_x, tiles_y;
 };
 
+// Several views in one launch: grid.y is the view of the group, view v's buffers lie v * vs
+// bytes past the pointers passed (buffer sets of equal layout, one after another), and its
+// camera is cams.c[v]. Grids are sized for the largest view of the group; blocks past a view's
+// own extent leave at once. A single view is the group {1, 0, {cam}}.
+constexpr int kMaxGroup = 16;
+struct GroupCams {
+  DevCam c[kMaxGroup];
+};
+struct GroupDims {  // tile grid of each view (what the binning kernels need of the cameras)
+  int tx[kMaxGroup], ty[kMaxGroup];
+};
+struct Group {
+  int g = 1;
+  size_t vs = 0;
+  GroupCams cams;
+  GroupDims dims;
+  int max_tiles_x = 0, max_tiles_y = 0, max_ntiles = 0, max_width = 0, max_height = 0;
+};
+
+// This block's view of a per-view pointer.
+template <class T>
+__device__ __forceinline__ T* vp(T* p, size_t vs) {
+  using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<Byte*>(p) + (size_t)blockIdx.y * vs) : p;
+}
+
+inline Group make_group(const DevCam* cams, int g, size_t vs) {
+  Group G;
+  G.g = g;
+  G.vs = vs;
+  for (int i = 0; i < kMaxGroup; ++i) G.dims.tx[i] = G.dims.ty[i] = 0;
+  for (int i = 0; i < g; ++i) {
+    G.cams.c[i] = cams[i];
+    G.dims.tx[i] = cams[i].tiles_x;
+    G.dims.ty[i] = cams[i].tiles_y;
+    G.max_tiles_x = std::max(G.max_tiles_x, cams[i].tiles_x);
+    G.max_tiles_y = std::max(G.max_tiles_y, cams[i].tiles_y);
+    G.max_ntiles = std::max(G.max_ntiles, cams[i].tiles_x * cams[i].tiles_y);
+    G.max_width = std::max(G.max_width, cams[i].width);
+    G.max_height = std::max(G.max_height, cams[i].height);
+  }
+  return G;
+}
+
+inline Group single_group(const DevCam& cam) { return make_group(&cam, 1, 0); }
+
 inline DevCam make_devcam(const ngs_camera& c, int tile) {
   DevCam d;
   for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
@@ -121,7 +168,7 @@ const char* prof_name(int id);
 
 // Launchers implemented in the .hip files (stream-ordered, no synchronisation).
 hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st);
-hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
                           const ngs_projected& out, hipStream_t st);
 // Adds the view's pair count (sum of p.count over n Gaussians) to *total (device).
 hipError_t launch_sum_counts(const ngs_projected& p, int n, int64_t* total, hipStream_t st);
@@ -137,9 +184,9 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, ui
                             uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n,
                             int begin_bit, int end_bit, const SortWs& ws, hipStream_t st,
                             uint32_t** keys_out, uint32_t** vals_out, int prof_base,
-                            const void* rec_in = nullptr, void* rec_sorted = nullptr);
+                            const void* rec_in = nullptr, void* rec_sorted = nullptr, int g = 1, size_t vs = 0);
 hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st);
-hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st, int g = 1, size_t vs = 0);
 hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st);
 // Device-to-device copy of n 32-bit words by a kernel (graph-capturable like the fills: the
 // scoring path records no memset or memcpy nodes).
@@ -162,14 +209,14 @@ struct BinWs {
 };
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);
-hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st);
+hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st, int g = 1, size_t vs = 0);
 // Pairs beyond out.capacity are not written: the ranges are left empty and *overflow (may
 // be NULL) is raised; stats[1] (may be NULL) accumulates the pair count. keep (may be NULL:
 // every tile) flags the tiles whose lists are wanted: the others get empty ranges and none of
 // their gids is written, while the wanted lists and M stay those of the full binning.
 // chunk2: least row entries per level-2 chunk (0 = 512): longer chunks write longer runs per
 // tile and leave fewer partly written lines, shorter ones spread the scatter over more blocks.
-hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const DevCam& cam, const BinWs& w,
+hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, const BinWs& w,
                              const ngs_tile_lists& out, int32_t* overflow, int64_t* stats, hipStream_t st,
                              const int32_t* keep = nullptr, int chunk2 = 0);
 
@@ -208,23 +255,25 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots);
 // waves: waves per SIMD of the back pass (0 = default, 4 = the two-workgroups-per-CU variant;
 // see ig_waves_valid).
 hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l,
-                           const DevCam& cam, const RasterConst& rc, const ngs_ig_params& ig,
+                           const Group& G, const RasterConst& rc, const ngs_ig_params& ig,
                            const IgWs& w, int64_t* stats, int lpp, hipStream_t st, int waves = 0);
 // The two halves of launch_ig_tiles: with a target object the flags of the tiles that a
 // weighted Gaussian's rect reaches (see ig_tile_flags; needed before the filtered binning),
 // then the walk (front pass, slots of the contributing weighted Gaussians, back pass).
 // launch_ig_clear_flags zeroes the contribution flags of a fresh workspace.
-hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st);
-hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const DevCam& cam, const ngs_ig_params& ig,
+hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st, int g = 1, size_t vs = 0);
+hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Group& G, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st);
-hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                           hipStream_t st, int waves = 0);
 // Tile flags of w when launch_ig_assign fills them (a target object), else nullptr.
 const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w);
 bool ig_lpp_valid(int64_t k, int lpp);
 bool ig_waves_valid(int64_t k, int lpp, int waves);
-hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+// ig_out: three gains per view of the group, view after view (scoring); accumulation takes
+// a group of one view.
+hipError_t launch_ig_finalize(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
                               const ngs_ig_params& ig, const IgWs& w, ngs_hessian* h,
                               double* ig_out, int64_t* stats, int32_t* sticky, hipStream_t st);
 hipError_t launch_hessian_logdet(ngs_hessian* h, int32_t n_slots, float lambda_prior, hipStream_t st);

@@ -312,10 +312,14 @@ __device__ __forceinline__ int store_len(int f, int k) { return f == 0 ? 105 : (
 // register budget of the whole finalize kernel.
 __global__ __launch_bounds__(64) void k_fin_chain(int n, const float* __restrict__ mean,
                                                   const float* __restrict__ log_scale, const float* __restrict__ rot,
-                                                  DevCam cam, double eps2d, const float* __restrict__ acc, int astride,
-                                                  int max_slots, const int32_t* __restrict__ gid_of,
-                                                  const int32_t* __restrict__ n_slots, double* __restrict__ pmat) {
-  const int used = min(*n_slots, max_slots);
+                                                  GroupCams gc, double eps2d, const float* acc_, int astride,
+                                                  int max_slots, const int32_t* gid_of_, const int32_t* n_slots_,
+                                                  double* pmat_, size_t vs) {
+  const DevCam cam = gc.c[blockIdx.y];
+  const float* __restrict__ acc = vp(acc_, vs);
+  const int32_t* __restrict__ gid_of = vp(gid_of_, vs);
+  double* __restrict__ pmat = vp(pmat_, vs);
+  const int used = min(*vp(n_slots_, vs), max_slots);
   for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < used; slot += gridDim.x * blockDim.x) {
     const float a2f = acc[(size_t)slot * astride + kStatYd + tri_idx(6, 6, 7)];
     if (!(a2f > 0.f)) continue;
@@ -331,14 +335,19 @@ __global__ __launch_bounds__(64) void k_fin_chain(int n, const float* __restrict
 template <bool TRACE>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, int k, const float* __restrict__ mean, const float* __restrict__ log_scale, const float* __restrict__ rot,
-    const float* __restrict__ conf, const float* __restrict__ prob, DevCam cam, double eps2d, double lambda,
-    uint32_t outputs, int mode, int conf_on_train, int criterion, const float* __restrict__ acc, int astride,
-    int max_slots,
-    const int32_t* __restrict__ gid_of, const int32_t* __restrict__ n_slots, const int32_t* __restrict__ overflow,
-    ngs_hessian h, int has_h, double* __restrict__ ig_out, int64_t* __restrict__ stats, int32_t* __restrict__ sticky,
-    const double* __restrict__ pmat) {
+    const float* __restrict__ conf, const float* __restrict__ prob, double eps2d, double lambda, uint32_t outputs,
+    int mode, int conf_on_train, int criterion, const float* acc_, int astride, int max_slots, const int32_t* gid_of_,
+    const int32_t* n_slots_, const int32_t* overflow_, ngs_hessian h, int has_h, double* ig_out_,
+    int64_t* __restrict__ stats, int32_t* __restrict__ sticky, const double* pmat_, size_t vs) {
   __shared__ FinShared S;
-  const int used = min(*n_slots, max_slots);
+  // view blockIdx.y of the group: its workspace vs bytes on, its three gains after the
+  // previous views' (scoring only: accumulation into the store runs one view per launch)
+  const float* __restrict__ acc = vp(acc_, vs);
+  const int32_t* __restrict__ gid_of = vp(gid_of_, vs);
+  const int32_t* __restrict__ overflow = vp(overflow_, vs);
+  const double* __restrict__ pmat = vp(pmat_, vs);
+  double* __restrict__ ig_out = ig_out_ + 3 * (size_t)blockIdx.y;
+  const int used = min(*vp(n_slots_, vs), max_slots);
   if (blockIdx.x == 0 && threadIdx.x == 0 && *overflow) {
     if (stats) atomicAdd((unsigned long long*)&stats[5], 1ull);
     if (sticky) atomicOr(sticky, 1);
@@ -565,21 +574,23 @@ __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ ig_r
 
 }  // namespace
 
-hipError_t launch_ig_finalize(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp, const ngs_ig_params& ig,
+hipError_t launch_ig_finalize(const ngs_scene& s, const Group& G, const ngs_raster_params& rp, const ngs_ig_params& ig,
                               const IgWs& w, ngs_hessian* h, double* ig_out, int64_t* stats, int32_t* sticky,
                               hipStream_t st) {
+  // accumulation writes the shared store: two views of one launch would race on a slot
+  if (ig.mode == NGS_MODE_ACCUMULATE && G.g != 1) return hipErrorInvalidValue;
   ngs_hessian hh{};
   if (h) hh = *h;
-  const int blocks = (int)std::min<int64_t>(w.max_slots, 4096);
+  const int blocks = (int)std::min<int64_t>(w.max_slots, std::max(512, 4096 / G.g));
+  const int cblocks = (int)std::min<int64_t>((w.max_slots + 63) / 64, std::max(256, 2048 / G.g));
   ProfScope ps(kProfIgFinalize, st);
-  hipLaunchKernelGGL(k_fin_chain, dim3((unsigned)std::min<int64_t>((w.max_slots + 63) / 64, 2048)), dim3(64), 0, st,
-                     s.n, s.mean, s.log_scale, s.rot, cam, (double)rp.eps2d, w.acc, w.astride, (int)w.max_slots,
-                     w.gid_of, w.n_slots, w.pmat);
+  hipLaunchKernelGGL(k_fin_chain, dim3(cblocks, G.g), dim3(64), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams,
+                     (double)rp.eps2d, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.pmat, G.vs);
   auto fin = ig.criterion == 1 ? k_finalize<true> : k_finalize<false>;
-  hipLaunchKernelGGL(fin, dim3(blocks), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf, s.prob,
-                     cam, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
+  hipLaunchKernelGGL(fin, dim3(blocks, G.g), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
+                     s.prob, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,
                      ig.criterion, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.overflow, hh, h ? 1 : 0,
-                     ig_out, stats, sticky, (const double*)w.pmat);
+                     ig_out, stats, sticky, (const double*)w.pmat, G.vs);
   return hipGetLastError();
 }
 

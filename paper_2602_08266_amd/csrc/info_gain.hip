@@ -139,11 +139,19 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
 // pass of a wavefront needs no entry outside that range, since only weighted contributors
 // write records and only the contributors behind them feed their suffixes.
 __global__ __launch_bounds__(kTilePix) void k_ig_front(
-    const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
-    const float4* __restrict__ splat, const float* __restrict__ conf, float* __restrict__ pix_t,
-    int32_t* __restrict__ pix_last,
-    int2* __restrict__ wave_range, uint8_t* __restrict__ cflag, int64_t* __restrict__ stats,
-    const int32_t* __restrict__ tflag) {
+    const uint32_t* gids_, const uint32_t* ranges_, GroupCams gc, RasterConst rc, const float4* splat_,
+    const float* __restrict__ conf, float* pix_t_, int32_t* pix_last_, int2* wave_range_, uint8_t* cflag_,
+    int64_t* __restrict__ stats, const int32_t* tflag_, size_t vs) {
+  const DevCam cam = gc.c[blockIdx.y];
+  if ((int)blockIdx.x >= cam.tiles_x * cam.tiles_y) return;  // past this view's tiles
+  const uint32_t* __restrict__ gids = vp(gids_, vs);
+  const uint32_t* __restrict__ ranges = vp(ranges_, vs);
+  const float4* __restrict__ splat = vp(splat_, vs);
+  float* __restrict__ pix_t = vp(pix_t_, vs);
+  int32_t* __restrict__ pix_last = vp(pix_last_, vs);
+  int2* __restrict__ wave_range = vp(wave_range_, vs);
+  uint8_t* __restrict__ cflag = vp(cflag_, vs);
+  const int32_t* __restrict__ tflag = vp(tflag_, vs);
   __shared__ int tile_last_sh;
   // with stats: the tile's list positions that contribute to some pixel (one bit per position,
   // the first kFBits of the list; beyond them each strip counts its own)
@@ -272,12 +280,22 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
 // two-lane variant that keeps two workgroups per CU at the cost of a few spilled registers.
 template <int KP, int LPP, int WPS>
 __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
-    int n, int k, const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges, DevCam cam, RasterConst rc,
-    const float4* __restrict__ splat, const float* __restrict__ depth, const float* __restrict__ rgb,
-    const float* __restrict__ prob,
-    int obj_eq2, float* __restrict__ acc, int astride, const int32_t* __restrict__ slot_of,
-    int64_t* __restrict__ stats, const int32_t* __restrict__ tflag, const float* __restrict__ pix_t,
-    const int32_t* __restrict__ pix_last, const int2* __restrict__ wave_range) {
+    int n, int k, const uint32_t* gids_, const uint32_t* ranges_, GroupCams gc, RasterConst rc, const float4* splat_,
+    const float* depth_, const float* __restrict__ rgb, const float* __restrict__ prob, int obj_eq2, float* acc_,
+    int astride, const int32_t* slot_of_, int64_t* __restrict__ stats, const int32_t* tflag_, const float* pix_t_,
+    const int32_t* pix_last_, const int2* wave_range_, size_t vs) {
+  const DevCam cam = gc.c[blockIdx.y];
+  if ((int)blockIdx.x >= cam.tiles_x * cam.tiles_y) return;  // past this view's tiles
+  const uint32_t* __restrict__ gids = vp(gids_, vs);
+  const uint32_t* __restrict__ ranges = vp(ranges_, vs);
+  const float4* __restrict__ splat = vp(splat_, vs);
+  const float* __restrict__ depth = vp(depth_, vs);
+  float* __restrict__ acc = vp(acc_, vs);
+  const int32_t* __restrict__ slot_of = vp(slot_of_, vs);
+  const int32_t* __restrict__ tflag = vp(tflag_, vs);
+  const float* __restrict__ pix_t = vp(pix_t_, vs);
+  const int32_t* __restrict__ pix_last = vp(pix_last_, vs);
+  const int2* __restrict__ wave_range = vp(wave_range_, vs);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   IgShared<KP, LPP>& S = *reinterpret_cast<IgShared<KP, LPP>*>(smem_raw);
   constexpr int kThreads = kTilePix * LPP;
@@ -504,7 +522,12 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
   }
 }
 
-__global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots, int32_t* overflow, int32_t* tflag, int ntiles) {
+__global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots_, int32_t* overflow_, int32_t* tflag_, GroupDims gd,
+                                                  size_t vs) {
+  int32_t* n_slots = vp(n_slots_, vs);
+  int32_t* overflow = vp(overflow_, vs);
+  int32_t* tflag = vp(tflag_, vs);
+  const int ntiles = gd.tx[blockIdx.y] * gd.ty[blockIdx.y];
   if (threadIdx.x == 0) {
     *n_slots = 0;
     *overflow = 0;
@@ -518,9 +541,12 @@ __global__ __launch_bounds__(256) void k_ig_clear(int32_t* n_slots, int32_t* ove
 // the other tiles at once. A wavefront marks the rects of its weighted Gaussians together,
 // one Gaussian at a time; the cost is the rect areas of the weighted Gaussians, small when only
 // one object carries weight.
-__global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict__ conf,
-                                                 const uint32_t* __restrict__ count, const int16_t* __restrict__ rect,
-                                                 int32_t* __restrict__ tflag, int tiles_x, int tiles_y) {
+__global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict__ conf, const uint32_t* count_,
+                                                 const int16_t* rect_, int32_t* tflag_, GroupDims gd, size_t vs) {
+  const uint32_t* __restrict__ count = vp(count_, vs);
+  const int16_t* __restrict__ rect = vp(rect_, vs);
+  int32_t* __restrict__ tflag = vp(tflag_, vs);
+  const int tiles_x = gd.tx[blockIdx.y], tiles_y = gd.ty[blockIdx.y];
   const int lane = threadIdx.x % kWave;
   const int g = blockIdx.x * 256 + threadIdx.x;
   uint64_t m = __ballot(g < n && count[g] > 0u && conf[g] > 0.f);
@@ -544,10 +570,14 @@ __global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict_
 // counter update.
 constexpr int kAssignPer = 4;
 
-__global__ __launch_bounds__(256) void k_ig_slots(int n, const float* __restrict__ conf, uint8_t* __restrict__ cflag,
-                                                  int32_t* __restrict__ slot_of, int32_t* __restrict__ gid_of,
-                                                  int32_t* __restrict__ n_slots, int32_t* __restrict__ overflow,
-                                                  int max_slots) {
+__global__ __launch_bounds__(256) void k_ig_slots(int n, const float* __restrict__ conf, uint8_t* cflag_,
+                                                  int32_t* slot_of_, int32_t* gid_of_, int32_t* n_slots_,
+                                                  int32_t* overflow_, int max_slots, size_t vs) {
+  uint8_t* __restrict__ cflag = vp(cflag_, vs);
+  int32_t* __restrict__ slot_of = vp(slot_of_, vs);
+  int32_t* __restrict__ gid_of = vp(gid_of_, vs);
+  int32_t* __restrict__ n_slots = vp(n_slots_, vs);
+  int32_t* __restrict__ overflow = vp(overflow_, vs);
   __shared__ int wsum[256 / kWave];
   __shared__ int base_sh;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -597,24 +627,26 @@ __global__ __launch_bounds__(256) void k_ig_slots(int n, const float* __restrict
 }
 
 // Zero the statistic rows of the assigned slots.
-__global__ __launch_bounds__(256) void k_ig_zero(float4* __restrict__ acc, const int32_t* __restrict__ n_slots,
-                                                 int max_slots, int astride) {
+__global__ __launch_bounds__(256) void k_ig_zero(float4* acc_, const int32_t* n_slots_, int max_slots, int astride,
+                                                 size_t vs) {
+  float4* __restrict__ acc = vp(acc_, vs);
+  const int32_t* __restrict__ n_slots = vp(n_slots_, vs);
   const size_t total = (size_t)min(*n_slots, max_slots) * (size_t)(astride / 4);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
     acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 template <int KP, int LPP, int WPS = (3 / LPP > 0 ? 3 / LPP : 1)>
-hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+hipError_t launch_ig_k(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
                        const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, const int32_t* tflag, int64_t* stats,
                        hipStream_t st) {
-  const int ntiles = cam.tiles_x * cam.tiles_y;
+  const int ntiles = G.max_ntiles;
   const size_t shm = sizeof(IgShared<KP, LPP>);
   static_assert(sizeof(IgShared<KP, LPP>) <= 65536, "IG kernel LDS");
   ProfScope ps(kProfIgTiles, st);
-  hipLaunchKernelGGL((k_ig_back<KP, LPP, WPS>), dim3(ntiles), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids, l.ranges, cam, rc,
-                     reinterpret_cast<const float4*>(p.splat), p.depth, s.rgb, s.prob, ig.obj_eq2, w.acc, w.astride,
-                     w.slot_of, stats, tflag, w.pix_t, w.pix_last, w.wave_range);
+  hipLaunchKernelGGL((k_ig_back<KP, LPP, WPS>), dim3(ntiles, G.g), dim3(kTilePix * LPP), shm, st, s.n, s.k, l.gids,
+                     l.ranges, G.cams, rc, reinterpret_cast<const float4*>(p.splat), p.depth, s.rgb, s.prob, ig.obj_eq2,
+                     w.acc, w.astride, w.slot_of, stats, tflag, w.pix_t, w.pix_last, w.wave_range, G.vs);
   return hipGetLastError();
 }
 
@@ -662,68 +694,67 @@ const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w) {
   return ig.target_id >= 0 ? w.tflag : nullptr;
 }
 
-hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const DevCam& cam, const ngs_ig_params& ig,
+hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Group& G, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st) {
   int32_t* tflag = const_cast<int32_t*>(ig_tile_flags(ig, w));
-  const int ntiles = cam.tiles_x * cam.tiles_y;
   {
     ProfScope ps(kProfFill, st);
-    hipLaunchKernelGGL(k_ig_clear, dim3(1), dim3(256), 0, st, w.n_slots, w.overflow, tflag, ntiles);
+    hipLaunchKernelGGL(k_ig_clear, dim3(1, G.g), dim3(256), 0, st, w.n_slots, w.overflow, tflag, G.dims, G.vs);
   }
   if (tflag && s.n > 0) {
     ProfScope ps(kProfIgAssign, st);
-    hipLaunchKernelGGL(k_ig_mark, dim3((s.n + 255) / 256), dim3(256), 0, st, s.n, s.conf, p.count, p.rect, tflag,
-                       cam.tiles_x, cam.tiles_y);
+    hipLaunchKernelGGL(k_ig_mark, dim3((s.n + 255) / 256, G.g), dim3(256), 0, st, s.n, s.conf, p.count, p.rect, tflag,
+                       G.dims, G.vs);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st) {
-  return launch_fill_u32(reinterpret_cast<uint32_t*>(w.cflag), 0u, ((size_t)std::max<int64_t>(n, 1) + 3) / 4, st);
+hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st, int g, size_t vs) {
+  return launch_fill_u32(reinterpret_cast<uint32_t*>(w.cflag), 0u, ((size_t)std::max<int64_t>(n, 1) + 3) / 4, st, g,
+                         vs);
 }
 
-hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                           hipStream_t st, int waves) {
   const int32_t* tflag = ig_tile_flags(ig, w);
-  const int ntiles = cam.tiles_x * cam.tiles_y;
   {
     ProfScope ps(kProfIgFront, st);
-    hipLaunchKernelGGL(k_ig_front, dim3(ntiles), dim3(kTilePix), 0, st, l.gids, l.ranges, cam, rc,
+    hipLaunchKernelGGL(k_ig_front, dim3(G.max_ntiles, G.g), dim3(kTilePix), 0, st, l.gids, l.ranges, G.cams, rc,
                        reinterpret_cast<const float4*>(p.splat), s.conf, w.pix_t, w.pix_last, w.wave_range, w.cflag,
-                       stats, tflag);
+                       stats, tflag, G.vs);
   }
   {
     ProfScope ps(kProfIgAssign, st);
     const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
-    hipLaunchKernelGGL(k_ig_slots, dim3(nb), dim3(256), 0, st, s.n, s.conf, w.cflag, w.slot_of, w.gid_of, w.n_slots,
-                       w.overflow, (int)w.max_slots);
-    hipLaunchKernelGGL(k_ig_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(w.acc), w.n_slots,
-                       (int)w.max_slots, w.astride);
+    hipLaunchKernelGGL(k_ig_slots, dim3(nb, G.g), dim3(256), 0, st, s.n, s.conf, w.cflag, w.slot_of, w.gid_of,
+                       w.n_slots, w.overflow, (int)w.max_slots, G.vs);
+    hipLaunchKernelGGL(k_ig_zero, dim3(std::max(64, 1024 / G.g), G.g), dim3(256), 0, st,
+                       reinterpret_cast<float4*>(w.acc), w.n_slots, (int)w.max_slots, w.astride, G.vs);
   }
   // lanes per pixel (ig_lpp_valid): 0 picks the default of each object-vector width
-  if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                                : launch_ig_k<4, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);
-  if (s.k <= 8) return lpp == 2 ? launch_ig_k<8, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                                : launch_ig_k<8, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st);
-  if (s.k <= 16) return lpp == 1 ? launch_ig_k<16, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                        : lpp == 4 ? launch_ig_k<16, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                                   : launch_ig_k<16, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
-  if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                        : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                        : waves == 4 ? launch_ig_k<32, 2, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                                     : launch_ig_k<32, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
-  return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-         : waves == 4 ? launch_ig_k<64, 2, 4>(s, p, l, cam, rc, ig, w, tflag, stats, st)
-                      : launch_ig_k<64, 2>(s, p, l, cam, rc, ig, w, tflag, stats, st);
+  if (s.k <= 4) return lpp == 2 ? launch_ig_k<4, 2>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                                : launch_ig_k<4, 1>(s, p, l, G, rc, ig, w, tflag, stats, st);
+  if (s.k <= 8) return lpp == 2 ? launch_ig_k<8, 2>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                                : launch_ig_k<8, 1>(s, p, l, G, rc, ig, w, tflag, stats, st);
+  if (s.k <= 16) return lpp == 1 ? launch_ig_k<16, 1>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                        : lpp == 4 ? launch_ig_k<16, 4>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                                   : launch_ig_k<16, 2>(s, p, l, G, rc, ig, w, tflag, stats, st);
+  if (s.k <= 32) return lpp == 1 ? launch_ig_k<32, 1>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                        : lpp == 4 ? launch_ig_k<32, 4>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                        : waves == 4 ? launch_ig_k<32, 2, 4>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                                     : launch_ig_k<32, 2>(s, p, l, G, rc, ig, w, tflag, stats, st);
+  return lpp == 1 ? launch_ig_k<64, 1>(s, p, l, G, rc, ig, w, tflag, stats, st)
+         : waves == 4 ? launch_ig_k<64, 2, 4>(s, p, l, G, rc, ig, w, tflag, stats, st)
+                      : launch_ig_k<64, 2>(s, p, l, G, rc, ig, w, tflag, stats, st);
 }
 
-hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const DevCam& cam,
+hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
                            const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                            hipStream_t st, int waves) {
-  hipError_t e = launch_ig_assign(s, p, cam, ig, w, st);
+  hipError_t e = launch_ig_assign(s, p, G, ig, w, st);
   if (e != hipSuccess) return e;
-  return launch_ig_walk(s, p, l, cam, rc, ig, w, stats, lpp, st, waves);
+  return launch_ig_walk(s, p, l, G, rc, ig, w, stats, lpp, st, waves);
 }
 
 bool ig_lpp_valid(int64_t k, int lpp) {

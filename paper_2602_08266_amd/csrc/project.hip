@@ -56,14 +56,20 @@ __device__ inline int tile_floor(double v, int tile, int lim) {
 // Sigma2 = M T^T; +eps on the diagonal; conic; lambda_max; radius; rect.
 __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ mean,
                                                  const float* __restrict__ log_scale,
-                                                 const float* __restrict__ rot, DevCam cam, double z_near,
-                                                 double eps2d, int tile, float* __restrict__ mean2d,
-                                                 float* __restrict__ conic, float* __restrict__ depth,
-                                                 uint32_t* __restrict__ zkey, int16_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ count, const float* __restrict__ opacity,
-                                                 float cutoff_q, float4* __restrict__ splat) {
+                                                 const float* __restrict__ rot, GroupCams gc, size_t vs, double z_near,
+                                                 double eps2d, int tile, float* mean2d_, float* conic_, float* depth_,
+                                                 uint32_t* zkey_, int16_t* rect_, uint32_t* count_,
+                                                 const float* __restrict__ opacity, float cutoff_q, float4* splat_) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
+  const DevCam cam = gc.c[blockIdx.y];
+  float* __restrict__ mean2d = vp(mean2d_, vs);
+  float* __restrict__ conic = vp(conic_, vs);
+  float* __restrict__ depth = vp(depth_, vs);
+  uint32_t* __restrict__ zkey = vp(zkey_, vs);
+  int16_t* __restrict__ rect = vp(rect_, vs);
+  uint32_t* __restrict__ count = vp(count_, vs);
+  float4* __restrict__ splat = vp(splat_, vs);
   double R[9];
   for (int i = 0; i < 9; ++i) R[i] = (double)cam.R[i];
   const double mu0 = mean[g], mu1 = mean[n + g], mu2 = mean[2 * n + g];
@@ -153,12 +159,12 @@ hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hip
   return hipGetLastError();
 }
 
-hipError_t launch_project(const ngs_scene& s, const DevCam& cam, const ngs_raster_params& rp,
+hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
                           const ngs_projected& out, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfProject, st);
-  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, cam,
+  hipLaunchKernelGGL(k_project, dim3(blocks, G.g), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams, G.vs,
                      (double)rp.z_near, (double)rp.eps2d, rp.tile, out.mean2d, out.conic, out.depth, out.zkey,
                      out.rect, out.count, s.opacity, rp.cutoff_q, reinterpret_cast<float4*>(out.splat));
   return hipGetLastError();

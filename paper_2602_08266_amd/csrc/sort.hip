@@ -17,8 +17,12 @@ constexpr int kSortItems = 8;
 constexpr int kSortTileElems = kSortThreads * kSortItems;  // 2048 keys per block
 constexpr int kWavesPerBlock = kSortThreads / kWave;
 
-__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys, size_t n, int shift,
-                                                       uint32_t* __restrict__ hist, size_t nblocks) {
+// Every kernel below sorts grid.y arrays at once: view v's arrays lie v * vs bytes past those
+// passed.
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* keys_, size_t n, int shift, uint32_t* hist_,
+                                                       size_t nblocks, size_t vs) {
+  const uint32_t* __restrict__ keys = vp(keys_, vs);
+  uint32_t* __restrict__ hist = vp(hist_, vs);
   __shared__ uint32_t h[kRadix];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -51,8 +55,10 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sm, uint32
 
 // One block per digit: exclusive scan of that digit's counts across blocks, in place;
 // rowtot[d] = total count of digit d.
-__global__ __launch_bounds__(kSortThreads) void k_scan_rows(uint32_t* __restrict__ hist, size_t nblocks,
-                                                            uint32_t* __restrict__ rowtot) {
+__global__ __launch_bounds__(kSortThreads) void k_scan_rows(uint32_t* hist_, size_t nblocks, uint32_t* rowtot_,
+                                                            size_t vs) {
+  uint32_t* __restrict__ hist = vp(hist_, vs);
+  uint32_t* __restrict__ rowtot = vp(rowtot_, vs);
   __shared__ uint32_t sm[kSortThreads];
   uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
   uint32_t carry = 0;
@@ -67,12 +73,18 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_rows(uint32_t* __restrict
   if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin, size_t n, int shift,
-                                                          const uint32_t* __restrict__ hist, size_t nblocks,
-                                                          const uint32_t* __restrict__ rowtot,
-                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          const uint2* __restrict__ rin, uint2* __restrict__ rout) {
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* kin_, const uint32_t* vin_, size_t n,
+                                                          int shift, const uint32_t* hist_, size_t nblocks,
+                                                          const uint32_t* rowtot_, uint32_t* kout_, uint32_t* vout_,
+                                                          const uint2* rin_, uint2* rout_, size_t vs) {
+  const uint32_t* __restrict__ kin = vp(kin_, vs);
+  const uint32_t* __restrict__ vin = vp(vin_, vs);
+  const uint32_t* __restrict__ hist = vp(hist_, vs);
+  const uint32_t* __restrict__ rowtot = vp(rowtot_, vs);
+  uint32_t* __restrict__ kout = vp(kout_, vs);
+  uint32_t* __restrict__ vout = vp(vout_, vs);
+  const uint2* __restrict__ rin = vp(rin_, vs);
+  uint2* __restrict__ rout = vp(rout_, vs);
   // The block's 2048 pairs are first ranked into digit order in LDS (stable), then streamed
   // out: consecutive lanes write consecutive positions of each digit's run.
   __shared__ uint32_t sm[kSortThreads];
@@ -155,7 +167,8 @@ __global__ void k_iota(uint32_t* v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = (uint32_t)i;
 }
-__global__ void k_fill_u32(uint32_t* v, uint32_t x, size_t n) {
+__global__ void k_fill_u32(uint32_t* v_, uint32_t x, size_t n, size_t vs) {
+  uint32_t* v = vp(v_, vs);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = x;
 }
@@ -178,10 +191,10 @@ hipError_t launch_iota(uint32_t* v, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, n);
   return hipGetLastError();
 }
-hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st) {
+hipError_t launch_fill_u32(uint32_t* v, uint32_t x, size_t n, hipStream_t st, int g, size_t vs) {
   if (!n) return hipSuccess;
   ProfScope ps(kProfFill, st);
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, x, n);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256), g), dim3(256), 0, st, v, x, n, vs);
   return hipGetLastError();
 }
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st) {
@@ -198,13 +211,15 @@ hipError_t launch_fill_i32(int32_t* v, int32_t x, size_t n, hipStream_t st) {
 }
 
 // Sorts bits [begin_bit, end_bit) of the keys; the result is in (*keys_out, *vals_out),
-// which is one of the two ping-pong buffers (a, b). The inputs are only read; vals_in NULL
+// which is one of the two ping-pong buffers (a, b), for g arrays at once (view v's at v * vs
+// bytes past those passed). The inputs are only read; vals_in NULL
 // stands for the values 0, 1, ..., n - 1 (the keys' own positions). With rec_in (8-byte
 // records indexed by value) the last pass also writes rec_sorted[i] = rec_in[value of i].
 hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_a,
                             uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, size_t n, int begin_bit,
                             int end_bit, const SortWs& ws, hipStream_t st, uint32_t** keys_out,
-                            uint32_t** vals_out, int prof_base, const void* rec_in, void* rec_sorted) {
+                            uint32_t** vals_out, int prof_base, const void* rec_in, void* rec_sorted, int g,
+                            size_t vs) {
   const size_t nb = sort_blocks_for(n);
   if (nb > ws.max_blocks) return hipErrorInvalidValue;
   const uint32_t* kin = keys_in;
@@ -217,18 +232,18 @@ hipError_t radix_sort_pairs(const uint32_t* keys_in, const uint32_t* vals_in, ui
   for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
     {
       ProfScope ps(prof_base, st);
-      hipLaunchKernelGGL(k_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, n, shift, ws.hist, nb);
+      hipLaunchKernelGGL(k_hist, dim3((unsigned)nb, g), dim3(kSortThreads), 0, st, kin, n, shift, ws.hist, nb, vs);
     }
     {
       ProfScope ps(prof_base + 1, st);
-      hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kSortThreads), 0, st, ws.hist, nb, ws.rowtot);
+      hipLaunchKernelGGL(k_scan_rows, dim3(kRadix, g), dim3(kSortThreads), 0, st, ws.hist, nb, ws.rowtot, vs);
     }
     {
       ProfScope ps(prof_base + 2, st);
       const bool last = shift + kRadixBits >= end_bit;
-      hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, n, shift, ws.hist, nb,
+      hipLaunchKernelGGL(k_scatter, dim3((unsigned)nb, g), dim3(kSortThreads), 0, st, kin, vin, n, shift, ws.hist, nb,
                          ws.rowtot, kdst, vdst, last ? static_cast<const uint2*>(rec_in) : nullptr,
-                         last ? static_cast<uint2*>(rec_sorted) : nullptr);
+                         last ? static_cast<uint2*>(rec_sorted) : nullptr, vs);
     }
     *keys_out = kdst;
     *vals_out = vdst;
