@@ -392,6 +392,41 @@ __device__ __forceinline__ void place_batch_reg(uint32_t (&cr)[NR], int b0, int 
   }
 }
 
+// place_batch_reg restricted to the bins that some lane covers and keep_mask keeps: the
+// union of the 64 spans is OR-reduced over the wavefront (one 64-bit word per 64 bins), so the
+// loop visits only bins that receive entries (the spans of 64 depth-ordered entries of a row
+// leave gaps, and the bins of unwanted tiles are not visited at all).
+template <int NR, class Emit>
+__device__ __forceinline__ void place_batch_masked(uint32_t (&cr)[NR], int b0, int len, int lane, Emit emit,
+                                                   const uint64_t (&keep_mask)[NR]) {
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i2 = 0; i2 < NR; ++i2) {
+    // this lane's span within bins [64 i2, 64 i2 + 64)
+    const int a = max(b0 - i2 * kWave, 0), b = min(b0 + len - i2 * kWave, kWave);
+    uint64_t u = 0ull;
+    if (len > 0 && a < b) u = (b - a == kWave ? ~0ull : ((1ull << (b - a)) - 1ull)) << a;
+    uint32_t ulo = (uint32_t)u, uhi = (uint32_t)(u >> 32);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      ulo |= (uint32_t)__shfl_xor((int)ulo, off);
+      uhi |= (uint32_t)__shfl_xor((int)uhi, off);
+    }
+    uint64_t todo = (((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)uhi) << 32) |
+                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)ulo)) & keep_mask[i2];
+    while (todo) {
+      const int bit = __builtin_ctzll(todo);
+      todo &= todo - 1ull;
+      const int c = i2 * kWave + bit;
+      const bool cover = len > 0 && b0 <= c && c < b0 + len;
+      const uint64_t m = __ballot(cover);
+      const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)cr[i2], bit);
+      if (cover) emit(c, base + (uint32_t)__popcll(m & below));
+      if (lane == bit) cr[i2] = base + (uint32_t)__popcll(m);
+    }
+  }
+}
+
 // Pass 1c: every Gaussian's row entries {gid, x0 | w << 16} to their row segments, in depth
 // order within a row. NR > 0: counters in registers (rows <= 64 NR), else in LDS.
 template <int NR>
@@ -537,7 +572,7 @@ __global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* hist2_, GroupDims 
 // chunks of the row for the tile) + (earlier pairs of this chunk). Entries of a row are in
 // depth order and the placement keeps lane order within a tile: stable. A block keeps at most
 // tiles_x output runs open, so the L2 completes their lines. NR > 0: counters in registers
-// (tiles_x <= 64 NR), else in LDS.
+// (tiles_x <= 64 NR) and only the covered, wanted tiles visited; else counters in LDS.
 template <int NR>
 __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
                                                          const uint32_t* rtot_, const uint32_t* cp_,
@@ -588,14 +623,13 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
       uint2 e = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
       if (i < c.end) e = rl[i];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
-      const int lo = wave_min(w > 0 ? x0 : INT_MAX), hi = wave_max(w > 0 ? x0 + w - 1 : -1);
       auto emit = [&](int, uint32_t pos) {
         if ((int64_t)pos < capacity) gids_out[pos] = e.x;
       };
       if constexpr (NR > 0) {
-        const auto kept = [&](int t) { return ((NR > 1 && t >= kWave ? km[NR - 1] : km[0]) >> (t & (kWave - 1))) & 1ull; };
-        place_batch_reg<NR>(cr, x0, w, lo, hi, lane, emit, kept);
+        place_batch_masked<NR>(cr, x0, w, lane, emit, km);
       } else {
+        const int lo = wave_min(w > 0 ? x0 : INT_MAX), hi = wave_max(w > 0 ? x0 + w - 1 : -1);
         const auto kept = [&](int t) { return !keep || keep[tbase + t] != 0; };
         place_batch(cnt, x0, w, lo, hi, lane, emit, kept);
       }

@@ -229,6 +229,14 @@ ngs_image feat_img_carve(char* p) {
   return im;
 }
 
+// The projection outputs that the information walks read: the 2D means and conics are in the
+// splat records, so their separate arrays are not written.
+ngs_projected walk_only(ngs_projected p) {
+  p.mean2d = nullptr;
+  p.conic = nullptr;
+  return p;
+}
+
 BatchWs batch_carve(void* ws, size_t ws_bytes, int64_t n, int64_t max_pairs) {
   const size_t nn = (size_t)std::max<int64_t>(n, 1), mp = (size_t)std::max<int64_t>(max_pairs, 1);
   char* p = static_cast<char*>(ws);
@@ -567,7 +575,7 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     const BatchWs& b = sets[i];
     const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
     const Group G = make_group(&dcs[v0], g, per);
-    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, b.proj, ls));
+    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, walk_only(b.proj), ls));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls, g, per));
     // slots first: with a target object only the lists of tiles that a weighted Gaussian
     // reaches are written, the only ones the information walk reads
@@ -637,7 +645,7 @@ extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, n
     const ngs_ig_params& p = pass == 0 ? acc : sc;
     for (int t = 0; t < n_train; ++t) {
       const Group G1 = single_group(make_devcam(train[t], kTile));
-      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, b.proj, st));
+      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, walk_only(b.proj), st));
       NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
       NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, G1, p, w, st));
       NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G1, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w),

@@ -127,11 +127,13 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     qb = (float)(-b / det);
     qc = (float)(a / det);
   }
-  mean2d[g] = mxf;
-  mean2d[n + g] = myf;
-  conic[g] = qa;
-  conic[n + g] = qb;
-  conic[2 * n + g] = qc;
+  if (mean2d) {  // the walks of the scoring path read the splat records instead
+    mean2d[g] = mxf;
+    mean2d[n + g] = myf;
+    conic[g] = qa;
+    conic[n + g] = qb;
+    conic[2 * n + g] = qc;
+  }
   const float zf = (float)Z;
   depth[g] = zf;
   zkey[g] = valid ? __float_as_uint(zf) : 0xFFFFFFFFu;
