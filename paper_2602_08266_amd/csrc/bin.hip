@@ -22,81 +22,49 @@ namespace ngs {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // counts summed per block
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Exclusive scan (u64) of the tile counts in depth order (from the sorted rects): per-block
-// local scan and block totals.
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const short4* rect_sorted_, int n, uint64_t* out_,
-                                                             uint64_t* bsum_, size_t vs) {
-  const short4* __restrict__ rect_sorted = vp(rect_sorted_, vs);
-  uint64_t* __restrict__ out = vp(out_, vs);
+// The view's pair count M = sum of the per-Gaussian tile counts, in two launches with no
+// atomics: block partials, then one block per view adds them up in order.
+__global__ __launch_bounds__(kScanThreads) void k_count_partials(const uint32_t* count_, int n, uint64_t* bsum_,
+                                                                 size_t vs) {
+  const uint32_t* __restrict__ count = vp(count_, vs);
   uint64_t* __restrict__ bsum = vp(bsum_, vs);
-  __shared__ uint64_t sm[kScanThreads];
+  __shared__ uint64_t sm[kScanThreads / kWave];
   const int t = threadIdx.x;
-  const int base = blockIdx.x * kScanTile + t * kScanItems;
-  uint64_t v[kScanItems];
-  uint64_t run = 0;
+  uint64_t v = 0ull;
   for (int j = 0; j < kScanItems; ++j) {
-    const int i = base + j;
-    uint64_t c = 0ull;
-    if (i < n) {  // the tile count of the rect (0 for a culled Gaussian's empty rect)
-      const short4 r = rect_sorted[i];
-      c = r.z >= r.x && r.w >= r.y ? (uint64_t)((r.z - r.x + 1) * (r.w - r.y + 1)) : 0ull;
-    }
-    v[j] = run;
-    run += c;
+    const int i = blockIdx.x * kScanTile + j * kScanThreads + t;
+    if (i < n) v += count[i];
   }
-  sm[t] = run;
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (t % kWave == 0) sm[t / kWave] = v;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint64_t add = (t >= off) ? sm[t - off] : 0ull;
-    __syncthreads();
-    sm[t] += add;
-    __syncthreads();
+  if (t == 0) {
+    uint64_t s = 0ull;
+    for (int w = 0; w < kScanThreads / kWave; ++w) s += sm[w];
+    bsum[blockIdx.x] = s;
   }
-  const uint64_t excl = sm[t] - run;
-  for (int j = 0; j < kScanItems; ++j)
-    if (base + j < n) out[base + j] = excl + v[j];
-  if (t == kScanThreads - 1) bsum[blockIdx.x] = sm[t];
 }
 
-// Single block: exclusive scan of the block totals in place; writes the grand total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(uint64_t* bsum_, int nb, uint64_t* total_,
+__global__ __launch_bounds__(kScanThreads) void k_count_total(const uint64_t* bsum_, int nb, uint64_t* total_,
                                                               size_t vs) {
-  uint64_t* __restrict__ bsum = vp(bsum_, vs);
-  uint64_t* __restrict__ total = vp(total_, vs);
-  __shared__ uint64_t sm[kScanThreads];
-  const int t = threadIdx.x;
-  uint64_t carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
-    const int i = b0 + t;
-    const uint64_t v = (i < nb) ? bsum[i] : 0ull;
-    sm[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const uint64_t add = (t >= off) ? sm[t - off] : 0ull;
-      __syncthreads();
-      sm[t] += add;
-      __syncthreads();
-    }
-    if (i < nb) bsum[i] = carry + sm[t] - v;
-    carry += sm[kScanThreads - 1];
-    __syncthreads();
-  }
-  if (t == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint64_t* out_, int n, const uint64_t* bsum_, size_t vs) {
-  uint64_t* __restrict__ out = vp(out_, vs);
   const uint64_t* __restrict__ bsum = vp(bsum_, vs);
-  const int i = blockIdx.x * kScanTile + threadIdx.x;
-  const uint64_t add = bsum[blockIdx.x];
-  for (int j = 0; j < kScanItems; ++j) {
-    const int ii = i + j * kScanThreads;
-    if (ii < n) out[ii] += add;
+  uint64_t* __restrict__ total = vp(total_, vs);
+  __shared__ uint64_t sm[kScanThreads / kWave];
+  const int t = threadIdx.x;
+  uint64_t v = 0ull;
+  for (int i = t; i < nb; i += kScanThreads) v += bsum[i];
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (t % kWave == 0) sm[t / kWave] = v;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t s = 0ull;
+    for (int w = 0; w < kScanThreads / kWave; ++w) s += sm[w];
+    *total = s;
   }
 }
 
@@ -193,8 +161,8 @@ __global__ __launch_bounds__(256) void k_part_scan_rows(uint32_t* hist_, int nbl
 }
 
 // Tile starts (exclusive scan of the per-tile totals) -> ranges; an empty tile gets
-// start = end = the number of pairs in lower tiles. If the pairs (m_total, the count scan's
-// total) exceed the list capacity, every range is left empty and *overflow is raised (the
+// start = end = the number of pairs in lower tiles. If the pairs (m_total, the sum of the
+// tile counts) exceed the list capacity, every range is left empty and *overflow is raised (the
 // scatters then write nothing).
 __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* tot_, GroupDims gd, uint32_t* ranges_,
                                                      int64_t capacity, int32_t* __restrict__ overflow,
@@ -236,25 +204,73 @@ __global__ __launch_bounds__(256) void k_part_ranges(const uint32_t* tot_, Group
   }
 }
 
+// Bins [64 i2, 64 i2 + 64) covered by the span [b0, b0 + len), as bits.
+__device__ __forceinline__ uint64_t span_bits(int b0, int len, int i2) {
+  const int a = max(b0 - i2 * kWave, 0), b = min(b0 + len - i2 * kWave, kWave);
+  if (len <= 0 || a >= b) return 0ull;
+  return (b - a == kWave ? ~0ull : ((1ull << (b - a)) - 1ull)) << a;
+}
+
+// ---- wanted entries --------------------------------------------------------------------------
+// With keep flags (tiles_x <= 128), a row entry whose span reaches no wanted tile of its row is
+// not binned at all: both row passes apply the same test, so the wanted tiles' lists are those of
+// the full binning. Row y's wanted tiles: bit x % 64 of rkm[2 y + x / 64].
+__global__ __launch_bounds__(256) void k_keep_rows(const int32_t* keep_, GroupDims gd, unsigned long long* rkm_,
+                                                   size_t vs) {
+  const int32_t* __restrict__ keep = vp(keep_, vs);
+  unsigned long long* __restrict__ rkm = vp(rkm_, vs);
+  const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
+  for (int y = threadIdx.x; y < rows; y += blockDim.x) {
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    for (int x = 0; x < tiles_x; ++x)
+      if (keep[y * tiles_x + x] != 0) {
+        if (x < 64) m0 |= 1ull << x;
+        else m1 |= 1ull << (x - 64);
+      }
+    rkm[2 * y] = m0;
+    rkm[2 * y + 1] = m1;
+  }
+}
+
+// Row masks of the view in LDS (rows <= 128), and whether row r of a span whose tiles are
+// (m0, m1) (span_bits of its x range) holds a wanted tile.
+__device__ __forceinline__ void load_row_masks(unsigned long long* rk_sh, const unsigned long long* rkm, int rows) {
+  for (int i = threadIdx.x; i < 2 * rows; i += blockDim.x) rk_sh[i] = rkm[i];
+  __syncthreads();
+}
+__device__ __forceinline__ bool row_wanted(const unsigned long long* rk_sh, int r, uint64_t m0, uint64_t m1) {
+  return ((m0 & rk_sh[2 * r]) | (m1 & rk_sh[2 * r + 1])) != 0ull;
+}
+
 // ---- level 1: rows ------------------------------------------------------------------------
 // Pass 1a: row entries per (row, block), row-major: rhist[r * nblk + block]. Counting needs
 // no order, so each lane adds its own Gaussian's rows.
 __global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* order_, const int16_t* rect_,
-                                                    GroupDims gd, uint32_t* rhist_, int nblk, size_t vs) {
+                                                    GroupDims gd, uint32_t* rhist_, int nblk,
+                                                    const unsigned long long* rkm_, size_t vs) {
   const uint32_t* __restrict__ order = vp(order_, vs);
   const int16_t* __restrict__ rect = vp(rect_, vs);
   uint32_t* __restrict__ rhist = vp(rhist_, vs);
+  const unsigned long long* __restrict__ rkm = vp(rkm_, vs);
   const int rows = gd.ty[blockIdx.y];
   extern __shared__ uint32_t cnt[];  // [rows]
+  __shared__ unsigned long long rk_sh[2 * 2 * kWave];
   const int lane = threadIdx.x;
   const int chunk = part_chunk(blockIdx.x, nblk);
   for (int t = lane; t < rows; t += kWave) cnt[t] = 0u;
+  if (rkm) load_row_masks(rk_sh, rkm, rows);
   __syncthreads();
   const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
     const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
-    const int y0 = (int)(l.org >> 16), h = l.area / l.w;
-    for (int j = 0; j < h; ++j) atomicAdd(&cnt[y0 + j], 1u);
+    const int y0 = (int)(l.org >> 16), h = l.area / l.w, x0 = (int)(l.org & 0xFFFFu);
+    if (rkm) {
+      const uint64_t m0 = span_bits(x0, l.w, 0), m1 = span_bits(x0, l.w, 1);
+      for (int j = 0; j < h; ++j)
+        if (row_wanted(rk_sh, y0 + j, m0, m1)) atomicAdd(&cnt[y0 + j], 1u);
+    } else {
+      for (int j = 0; j < h; ++j) atomicAdd(&cnt[y0 + j], 1u);
+    }
   }
   __syncthreads();
   for (int t = lane; t < rows; t += kWave) rhist[(size_t)t * nblk + chunk] = cnt[t];
@@ -350,18 +366,18 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Places the current 64 entries (lane order = depth order) of one segment family: for every
-// bin c in [lo, hi], the lanes whose span [b0, b0 + len) covers c take consecutive positions
+// bin c in [lo, hi], the lanes that cover c (covers(c): c in the lane's span, and wanted) take consecutive positions
 // cnt[c] + (covering lanes below them), and cnt[c] advances by their number. No atomics:
 // ballots give the ranks, and each bin's writes are one coalesced run.
 // Bins for which keep(c) is false are passed over: nothing is written for them and their
 // counters stay as they were.
-template <class Emit, class Keep>
-__device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int lo, int hi, int lane, Emit emit,
-                                            Keep keep) {
+template <class Emit, class Keep, class Covers>
+__device__ __forceinline__ void place_batch(uint32_t* cnt, int lo, int hi, int lane, Emit emit, Keep keep,
+                                            Covers covers) {
   const uint64_t below = (1ull << lane) - 1ull;
   for (int c = lo; c <= hi; ++c) {
     if (!keep(c)) continue;
-    const bool cover = len > 0 && b0 <= c && c < b0 + len;
+    const bool cover = covers(c);
     const uint64_t m = __ballot(cover);
     if (!m) continue;
     const uint32_t base = cnt[c];
@@ -370,59 +386,32 @@ __device__ __forceinline__ void place_batch(uint32_t* cnt, int b0, int len, int 
   }
 }
 
-// The same with the counters in registers: lane l holds bin l in cr[0] and bin 64 + l in
-// cr[1] (NR = 2), read with readlane at the (uniform) bin; for at most 64 NR bins.
-template <int NR, class Emit, class Keep>
-__device__ __forceinline__ void place_batch_reg(uint32_t (&cr)[NR], int b0, int len, int lo, int hi, int lane,
-                                                Emit emit, Keep keep) {
-  const uint64_t below = (1ull << lane) - 1ull;
-  for (int c = lo; c <= hi; ++c) {
-    if (!keep(c)) continue;
-    const bool cover = len > 0 && b0 <= c && c < b0 + len;
-    const uint64_t m = __ballot(cover);
-    if (!m) continue;
-    const int src = c & (kWave - 1);
-    const bool hi_half = NR > 1 && c >= kWave;
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(hi_half ? cr[NR - 1] : cr[0]), src);
-    if (cover) emit(c, base + (uint32_t)__popcll(m & below));
-    if (lane == src) {
-      if (hi_half) cr[NR - 1] = base + (uint32_t)__popcll(m);
-      else cr[0] = base + (uint32_t)__popcll(m);
-    }
-  }
-}
-
-// place_batch_reg restricted to the bins that some lane covers and keep_mask keeps: the
-// union of the 64 spans is OR-reduced over the wavefront (one 64-bit word per 64 bins), so the
-// loop visits only bins that receive entries (the spans of 64 depth-ordered entries of a row
-// leave gaps, and the bins of unwanted tiles are not visited at all).
+// place_batch with the counters in registers (lane l holds bin 64 i2 + l in cr[i2], read with
+// readlane at the uniform bin), over the bins that some lane covers: u[i2] holds this lane's
+// bins of word i2 (bit c % 64 of word c / 64). The union of the 64 lanes' bins (OR over the wavefront) is
+// walked bit by bit, so only bins that receive entries are visited (the bins of 64 depth-ordered
+// entries leave gaps, and unwanted bins are masked out of u by the caller).
 template <int NR, class Emit>
-__device__ __forceinline__ void place_batch_masked(uint32_t (&cr)[NR], int b0, int len, int lane, Emit emit,
-                                                   const uint64_t (&keep_mask)[NR]) {
-  const uint64_t below = (1ull << lane) - 1ull;
+__device__ __forceinline__ void place_batch_masked(uint32_t (&cr)[NR], const uint64_t (&u)[NR], Emit emit) {
 #pragma unroll
   for (int i2 = 0; i2 < NR; ++i2) {
-    // this lane's span within bins [64 i2, 64 i2 + 64)
-    const int a = max(b0 - i2 * kWave, 0), b = min(b0 + len - i2 * kWave, kWave);
-    uint64_t u = 0ull;
-    if (len > 0 && a < b) u = (b - a == kWave ? ~0ull : ((1ull << (b - a)) - 1ull)) << a;
-    uint32_t ulo = (uint32_t)u, uhi = (uint32_t)(u >> 32);
+    uint32_t ulo = (uint32_t)u[i2], uhi = (uint32_t)(u[i2] >> 32);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       ulo |= (uint32_t)__shfl_xor((int)ulo, off);
       uhi |= (uint32_t)__shfl_xor((int)uhi, off);
     }
-    uint64_t todo = (((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)uhi) << 32) |
-                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)ulo)) & keep_mask[i2];
+    uint64_t todo = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)uhi) << 32) |
+                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)ulo);
     while (todo) {
       const int bit = __builtin_ctzll(todo);
       todo &= todo - 1ull;
-      const int c = i2 * kWave + bit;
-      const bool cover = len > 0 && b0 <= c && c < b0 + len;
+      const bool cover = (u[i2] >> bit) & 1ull;
       const uint64_t m = __ballot(cover);
       const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)cr[i2], bit);
-      if (cover) emit(c, base + (uint32_t)__popcll(m & below));
-      if (lane == bit) cr[i2] = base + (uint32_t)__popcll(m);
+      // base + the covering lanes below this one
+      if (cover) emit(i2 * kWave + bit, __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base)));
+      if ((int)__lane_id() == bit) cr[i2] = base + (uint32_t)__popcll(m);
     }
   }
 }
@@ -433,13 +422,14 @@ template <int NR>
 __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* order_, const int16_t* rect_,
                                                        GroupDims gd, const uint32_t* rhist_, int nblk,
                                                        const uint32_t* rstart_, const uint32_t* meta_, uint2* rl_,
-                                                       size_t vs) {
+                                                       const unsigned long long* rkm_, size_t vs) {
   const uint32_t* __restrict__ order = vp(order_, vs);
   const int16_t* __restrict__ rect = vp(rect_, vs);
   const uint32_t* __restrict__ rhist = vp(rhist_, vs);
   const uint32_t* __restrict__ rstart = vp(rstart_, vs);
   const uint32_t* __restrict__ meta = vp(meta_, vs);
   uint2* __restrict__ rl = vp(rl_, vs);
+  const unsigned long long* __restrict__ rkm = vp(rkm_, vs);
   const int rows = gd.ty[blockIdx.y];
   extern __shared__ uint32_t cnt[];  // [rows] when NR == 0
   if (meta[3]) return;
@@ -456,16 +446,37 @@ __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* or
     for (int t = lane; t < rows; t += kWave) cnt[t] = rstart[t] + rhist[(size_t)t * nblk + chunk];
     __syncthreads();
   }
+  __shared__ unsigned long long rk_sh[2 * 2 * kWave];
+  if (NR > 0 && rkm) load_row_masks(rk_sh, rkm, rows);
   const int r0 = chunk * kPartRanks;
   for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
     const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
-    const int y0 = (int)(l.org >> 16), h = l.area / l.w;
-    const int lo = wave_min(h > 0 ? y0 : INT_MAX), hi = wave_max(h > 0 ? y0 + h - 1 : -1);
-    const uint2 e = make_uint2(l.gid, (l.org & 0xFFFFu) | ((uint32_t)l.w << 16));
+    const int y0 = (int)(l.org >> 16), h = l.area / l.w, x0 = (int)(l.org & 0xFFFFu);
+    const uint2 e = make_uint2(l.gid, (uint32_t)x0 | ((uint32_t)l.w << 16));
     auto emit = [&](int, uint32_t pos) { rl[pos] = e; };
-    const auto all = [](int) { return true; };
-    if constexpr (NR > 0) place_batch_reg<NR>(cr, y0, h, lo, hi, lane, emit, all);
-    else place_batch(cnt, y0, h, lo, hi, lane, emit, all);
+    if constexpr (NR > 0) {
+      // this lane's rows: those of its span, less (with row masks) the rows where the span
+      // reaches no wanted tile
+      uint64_t u[NR];
+#pragma unroll
+      for (int i2 = 0; i2 < NR; ++i2) u[i2] = span_bits(y0, h, i2);
+      if (rkm) {
+        const uint64_t m0 = span_bits(x0, l.w, 0), m1 = span_bits(x0, l.w, 1);
+        for (int j = 0; j < h; ++j) {
+          const int r = y0 + j;
+          if (!row_wanted(rk_sh, r, m0, m1)) {
+            if (NR == 1 || r < kWave) u[0] &= ~(1ull << (r & (kWave - 1)));
+            else u[NR - 1] &= ~(1ull << (r & (kWave - 1)));
+          }
+        }
+      }
+      place_batch_masked<NR>(cr, u, emit);
+    } else {
+      const int lo = wave_min(h > 0 ? y0 : INT_MAX), hi = wave_max(h > 0 ? y0 + h - 1 : -1);
+      const auto all = [](int) { return true; };
+      const auto covers = [&](int r) { return h > 0 && y0 <= r && r < y0 + h; };
+      place_batch(cnt, lo, hi, lane, emit, all, covers);
+    }
   }
 }
 
@@ -596,6 +607,7 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
   uint32_t* cpl = lds2 + (NR > 0 ? 0 : tiles_x);
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
+  const uint32_t cap32 = (uint32_t)min(capacity, (int64_t)0xFFFFFFFF);
   const int lane = threadIdx.x;
   if (blockIdx.x >= NC) return;
   for (int r = lane; r < rows; r += kWave) cpl[r] = cp[r];
@@ -624,14 +636,18 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
       if (i < c.end) e = rl[i];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
       auto emit = [&](int, uint32_t pos) {
-        if ((int64_t)pos < capacity) gids_out[pos] = e.x;
+        if (pos < cap32) gids_out[pos] = e.x;
       };
       if constexpr (NR > 0) {
-        place_batch_masked<NR>(cr, x0, w, lane, emit, km);
+        uint64_t u[NR];
+#pragma unroll
+        for (int i2 = 0; i2 < NR; ++i2) u[i2] = span_bits(x0, w, i2) & km[i2];
+        place_batch_masked<NR>(cr, u, emit);
       } else {
         const int lo = wave_min(w > 0 ? x0 : INT_MAX), hi = wave_max(w > 0 ? x0 + w - 1 : -1);
         const auto kept = [&](int t) { return !keep || keep[tbase + t] != 0; };
-        place_batch(cnt, x0, w, lo, hi, lane, emit, kept);
+        const auto covers = [&](int t) { return w > 0 && x0 <= t && t < x0 + w; };
+        place_batch(cnt, lo, hi, lane, emit, kept, covers);
       }
     }
   }
@@ -650,7 +666,7 @@ __global__ __launch_bounds__(256) void k_keys64(const uint32_t* __restrict__ ran
 
 // Workspace layout (all 256-byte aligned):
 //   dkeys[2], dvals[2]: u32 [n]          depth-sort ping-pong
-//   offsets: u64 [n + 1], blocksum: u64 [ceil(n / 1024) + 1]
+//   m_total: u64 [1], blocksum: u64 [ceil(n / 4096) + 1]
 //   phist: u32 [4096][ceil(n / 256)]     pairs per (tile, partition block)
 //   ptot: u32 [4096]
 //   hist: u32 [256][blocks(n)], rowtot: u32 [256]   radix-sort scratch
@@ -661,7 +677,7 @@ size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
   const size_t mp = (size_t)std::max<int64_t>(max_pairs, 1);
   size_t b = 0;
   b += 4 * align_up(nn * 4, 256);
-  b += align_up((nn + 1) * 8, 256);
+  b += align_up(8, 256);
   b += align_up(((nn + kScanTile - 1) / kScanTile + 1) * 8, 256);
   b += align_up((size_t)NGS_MAX_TILES * nblk * 4, 256);
   b += align_up((size_t)NGS_MAX_TILES * 4, 256);
@@ -672,6 +688,7 @@ size_t bin_ws_bytes(int64_t n, int64_t max_pairs) {
   b += align_up((size_t)kHist2 * 4, 256);              // level-2 counts
   b += 4 * align_up(((size_t)NGS_MAX_TILES + 1) * 4, 256);  // rtot, rstart, nch, cp
   b += align_up(16, 256);                              // meta
+  b += align_up((size_t)NGS_MAX_TILES * 16, 256);      // wanted-tile masks per row
   return b;
 }
 
@@ -685,7 +702,7 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
   BinWs w;
   for (int i = 0; i < 2; ++i) w.dkeys[i] = (uint32_t*)take(nn * 4);
   for (int i = 0; i < 2; ++i) w.dvals[i] = (uint32_t*)take(nn * 4);
-  w.offsets = (uint64_t*)take((nn + 1) * 8);
+  w.m_total = (uint64_t*)take(8);
   w.blocksum = (uint64_t*)take(((nn + kScanTile - 1) / kScanTile + 1) * 8);
   w.phist = (uint32_t*)take((size_t)NGS_MAX_TILES * nblk * 4);
   w.ptot = (uint32_t*)take((size_t)NGS_MAX_TILES * 4);
@@ -700,11 +717,12 @@ BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs) {
   w.nch = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
   w.cp = (uint32_t*)take(((size_t)NGS_MAX_TILES + 1) * 4);
   w.meta = (uint32_t*)take(16);
+  w.rkm = (unsigned long long*)take((size_t)NGS_MAX_TILES * 16);
   return w;
 }
 
 // Depth sort of all n Gaussians (culled ones carry key 0xFFFFFFFF and sort last) and the
-// exclusive scan of their tile counts in that order; offsets[n] = M.
+// view's pair count M (*m_total).
 hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStream_t st, int g, size_t vs) {
   uint32_t *ko, *vo;
   // inputs: zkey (read only), values = gids (implicit); ping-pong (dkeys[0], dvals[0]) / (dkeys[1], dvals[1])
@@ -715,12 +733,10 @@ hipError_t bin_count_pairs(const ngs_projected& p, int n, const BinWs& w, hipStr
   const int nb = (n + kScanTile - 1) / kScanTile;
   if (n > 0) {
     ProfScope ps(kProfCountScan, st);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb, g), dim3(kScanThreads), 0, st,
-                       reinterpret_cast<const short4*>(w.rect_sorted), n, w.offsets, w.blocksum, vs);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1, g), dim3(kScanThreads), 0, st, w.blocksum, nb, w.offsets + n, vs);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb, g), dim3(kScanThreads), 0, st, w.offsets, n, w.blocksum, vs);
+    hipLaunchKernelGGL(k_count_partials, dim3(nb, g), dim3(kScanThreads), 0, st, p.count, n, w.blocksum, vs);
+    hipLaunchKernelGGL(k_count_total, dim3(1, g), dim3(kScanThreads), 0, st, w.blocksum, nb, w.m_total, vs);
   } else {
-    e = launch_fill_u32(reinterpret_cast<uint32_t*>(w.offsets), 0u, 2, st, g, vs);
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(w.m_total), 0u, 2, st, g, vs);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
@@ -732,17 +748,23 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, cons
   const size_t vs = G.vs;
   const int rows = G.max_tiles_y, tx = G.max_tiles_x, ntiles = G.max_ntiles;  // largest view of the group
   const uint32_t* order = w.dvals[1];
-  const uint64_t* m_total = w.offsets + n;
+  const uint64_t* m_total = w.m_total;
   if (n == 0) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out.n_pairs), 0u, 2, st, g, vs);
     return e != hipSuccess ? e : launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st, g, vs);
   }
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
   const int grid2 = std::max(256, kGrid2 / g);  // persistent level-2 blocks per view
+  const unsigned long long* rkm = nullptr;
+  if (keep && tx <= 2 * kWave && rows <= 2 * kWave) {
+    ProfScope ps(kProfTileHist, st);
+    hipLaunchKernelGGL(k_keep_rows, dim3(1, g), dim3(256), 0, st, keep, G.dims, w.rkm, vs);
+    rkm = w.rkm;
+  }
   {
     ProfScope ps(kProfTileHist, st);
     hipLaunchKernelGGL(k_row_hist, dim3(nblk, g), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, G.dims, w.phist,
-                       nblk, vs);
+                       nblk, rkm, vs);
   }
   {
     ProfScope ps(kProfTileScan, st);
@@ -754,13 +776,13 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, cons
     ProfScope ps(kProfTileScatter, st);
     if (rows <= kWave)
       hipLaunchKernelGGL(k_row_scatter<1>, dim3(nblk, g), dim3(kWave), 0, st, n, order, w.rect_sorted, G.dims, w.phist,
-                         nblk, w.rstart, w.meta, w.rl, vs);
+                         nblk, w.rstart, w.meta, w.rl, rkm, vs);
     else if (rows <= 2 * kWave)
       hipLaunchKernelGGL(k_row_scatter<2>, dim3(nblk, g), dim3(kWave), 0, st, n, order, w.rect_sorted, G.dims, w.phist,
-                         nblk, w.rstart, w.meta, w.rl, vs);
+                         nblk, w.rstart, w.meta, w.rl, rkm, vs);
     else
       hipLaunchKernelGGL(k_row_scatter<0>, dim3(nblk, g), dim3(kWave), rows * 4, st, n, order, w.rect_sorted, G.dims,
-                         w.phist, nblk, w.rstart, w.meta, w.rl, vs);
+                         w.phist, nblk, w.rstart, w.meta, w.rl, rkm, vs);
   }
   {
     ProfScope ps(kProfTileHist, st);

@@ -375,10 +375,10 @@ ngs_status ngs_bin_sort(ngs_ctx* ctx, const ngs_scene* scene, const ngs_projecte
   const BinWs w = bin_ws_carve(ws, scene->n, out->capacity);
   NGS_TRY_HIP(ctx, bin_count_pairs(*proj, scene->n, w, st));
   int64_t m = 0;
-  s = read_i64(ctx, w.offsets + scene->n, 8, st, &m);
+  s = read_i64(ctx, w.m_total, 8, st, &m);
   if (s != NGS_OK) return s;
   if (m > out->capacity || m >= (int64_t)UINT32_MAX) {
-    NGS_TRY_HIP(ctx, hipMemcpyAsync(out->n_pairs, w.offsets + scene->n, 8, hipMemcpyDeviceToDevice, st));
+    NGS_TRY_HIP(ctx, hipMemcpyAsync(out->n_pairs, w.m_total, 8, hipMemcpyDeviceToDevice, st));
     NGS_TRY_HIP(ctx, hipStreamSynchronize(st));
     return m >= (int64_t)UINT32_MAX ? NGS_UNSUPPORTED : NGS_CAPACITY;
   }

@@ -196,8 +196,8 @@ hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStre
 struct BinWs {
   uint32_t* dkeys[2];   // depth keys ping-pong [n]
   uint32_t* dvals[2];   // gids ping-pong [n]
-  uint64_t* offsets;    // [n + 1] exclusive scan of tile counts in depth order
-  uint64_t* blocksum;   // scan partials
+  uint64_t* m_total;    // [1] the view's pair count M
+  uint64_t* blocksum;   // partial sums of the tile counts
   uint32_t* phist;      // level 1: row entries per (row, block) [4096][ceil(n / 512)]
   uint32_t* ptot;       // pairs per tile [4096]
   SortWs sort;
@@ -206,6 +206,7 @@ struct BinWs {
   uint32_t* hist2;      // level 2: pairs per (tile, chunk), row by row
   uint32_t *rtot, *rstart, *nch, *cp;  // per row: entries, start, chunks, chunk prefix [4097]
   uint32_t* meta;       // M, entries per chunk, chunks, overflow
+  unsigned long long* rkm;  // [NGS_MAX_TILES][2] per row: its wanted tiles (with keep flags)
 };
 size_t bin_ws_bytes(int64_t n, int64_t max_pairs);
 BinWs bin_ws_carve(void* ws, int64_t n, int64_t max_pairs);

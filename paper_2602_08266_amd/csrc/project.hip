@@ -44,8 +44,10 @@ __global__ __launch_bounds__(256) void k_prepare(int n, int k, const float* __re
   conf[g] = c;
 }
 
-__device__ inline int tile_floor(double v, int tile, int lim) {
-  double f = floor(v / (double)tile);
+// floor(v / tile) clamped to [-1, lim]. The tile size is a power of two (16), so v * (1 / tile)
+// is exactly v / tile and the multiply gives the same bits as the division.
+__device__ inline int tile_floor(double v, double inv_tile, int lim) {
+  double f = floor(v * inv_tile);
   if (f < -1.0) f = -1.0;
   if (f > (double)lim) f = (double)lim;
   return (int)f;
@@ -54,22 +56,28 @@ __device__ inline int tile_floor(double v, int tile, int lim) {
 // One thread per Gaussian. FP64 key path in the order: X = R mu + t (row by row,
 // left to right), Z; m = (f X / Z) + c; Sigma3 = Rg diag(s^2) Rg^T; T = Jp R; M = T Sigma3;
 // Sigma2 = M T^T; +eps on the diagonal; conic; lambda_max; radius; rect.
+// Views of a group are the fastest-moving part of the block index (block b: view b % nv,
+// Gaussians from 256 (b / nv)), so the views of one range of Gaussians run together and read
+// its scene entries from the L2 once.
 __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ mean,
                                                  const float* __restrict__ log_scale,
-                                                 const float* __restrict__ rot, GroupCams gc, size_t vs, double z_near,
-                                                 double eps2d, int tile, float* mean2d_, float* conic_, float* depth_,
-                                                 uint32_t* zkey_, int16_t* rect_, uint32_t* count_,
-                                                 const float* __restrict__ opacity, float cutoff_q, float4* splat_) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 const float* __restrict__ rot, GroupCams gc, int nv, size_t vs,
+                                                 double z_near, double eps2d, double inv_tile, float* mean2d_,
+                                                 float* conic_, float* depth_, uint32_t* zkey_, int16_t* rect_,
+                                                 uint32_t* count_, const float* __restrict__ opacity, float cutoff_q,
+                                                 float4* splat_) {
+  const int v = blockIdx.x % nv;
+  const int g = (blockIdx.x / nv) * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  const DevCam cam = gc.c[blockIdx.y];
-  float* __restrict__ mean2d = vp(mean2d_, vs);
-  float* __restrict__ conic = vp(conic_, vs);
-  float* __restrict__ depth = vp(depth_, vs);
-  uint32_t* __restrict__ zkey = vp(zkey_, vs);
-  int16_t* __restrict__ rect = vp(rect_, vs);
-  uint32_t* __restrict__ count = vp(count_, vs);
-  float4* __restrict__ splat = vp(splat_, vs);
+  const DevCam cam = gc.c[v];
+  const size_t off = (size_t)v * vs;
+  float* __restrict__ mean2d = mean2d_ ? (float*)((char*)mean2d_ + off) : nullptr;
+  float* __restrict__ conic = conic_ ? (float*)((char*)conic_ + off) : nullptr;
+  float* __restrict__ depth = (float*)((char*)depth_ + off);
+  uint32_t* __restrict__ zkey = (uint32_t*)((char*)zkey_ + off);
+  int16_t* __restrict__ rect = (int16_t*)((char*)rect_ + off);
+  uint32_t* __restrict__ count = (uint32_t*)((char*)count_ + off);
+  float4* __restrict__ splat = splat_ ? (float4*)((char*)splat_ + off) : nullptr;
   double R[9];
   for (int i = 0; i < 9; ++i) R[i] = (double)cam.R[i];
   const double mu0 = mean[g], mu1 = mean[n + g], mu2 = mean[2 * n + g];
@@ -116,10 +124,10 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     const double half = (a - c) * 0.5;
     const double lmax = (a + c) * 0.5 + sqrt(half * half + b * b);
     const double r = ceil(3.0 * sqrt(lmax));
-    x0 = max(0, tile_floor(mx - r, tile, cam.tiles_x));
-    x1 = min(cam.tiles_x - 1, tile_floor(mx + r, tile, cam.tiles_x));
-    y0 = max(0, tile_floor(my - r, tile, cam.tiles_y));
-    y1 = min(cam.tiles_y - 1, tile_floor(my + r, tile, cam.tiles_y));
+    x0 = max(0, tile_floor(mx - r, inv_tile, cam.tiles_x));
+    x1 = min(cam.tiles_x - 1, tile_floor(mx + r, inv_tile, cam.tiles_x));
+    y0 = max(0, tile_floor(my - r, inv_tile, cam.tiles_y));
+    y1 = min(cam.tiles_y - 1, tile_floor(my + r, inv_tile, cam.tiles_y));
     valid = (x0 <= x1) && (y0 <= y1);
     mxf = (float)mx;
     myf = (float)my;
@@ -166,9 +174,10 @@ hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_p
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfProject, st);
-  hipLaunchKernelGGL(k_project, dim3(blocks, G.g), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams, G.vs,
-                     (double)rp.z_near, (double)rp.eps2d, rp.tile, out.mean2d, out.conic, out.depth, out.zkey,
-                     out.rect, out.count, s.opacity, rp.cutoff_q, reinterpret_cast<float4*>(out.splat));
+  hipLaunchKernelGGL(k_project, dim3(blocks * G.g), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams, G.g,
+                     G.vs, (double)rp.z_near, (double)rp.eps2d, 1.0 / (double)rp.tile, out.mean2d, out.conic,
+                     out.depth, out.zkey, out.rect, out.count, s.opacity, rp.cutoff_q,
+                     reinterpret_cast<float4*>(out.splat));
   return hipGetLastError();
 }
 
