@@ -71,6 +71,10 @@ typedef struct {
   float* kappa;                /* [n] derived */
   float* conf;                 /* [n] derived */
   int32_t* label;              /* [n] derived */
+  double* cov3;                /* [9][n] derived, may be NULL: the 3D covariance
+                                  Sigma3 = Rg diag(s^2) Rg^T (row-major 3x3, FP64, the
+                                  projection's own operation order), so that ngs_project
+                                  reads it instead of recomputing it for every view */
 } ngs_scene;
 
 /* Pinhole camera: world -> camera rotation R (row-major) and translation t; OpenCV axes
@@ -220,7 +224,8 @@ int32_t ngs_last_hip_error(const ngs_ctx* ctx);
 ngs_status ngs_workspace_size(int32_t op, const ngs_dims* dims, size_t* bytes);
 
 /* Per-scene precompute: p = softmax(o) (Sec. III-A.1), sigma, kappa, the confidence
- * c_g of Eq. 7 (target_id < 0) or Eq. 12 (target_id >= 0), and labels. */
+ * c_g of Eq. 7 (target_id < 0) or Eq. 12 (target_id >= 0), labels, and (when cov3 is not
+ * NULL) each Gaussian's 3D covariance in FP64. */
 ngs_status ngs_prepare_scene(ngs_ctx* ctx, ngs_scene* scene, const ngs_ig_params* ig, void* stream);
 
 /* Projection of every Gaussian for one camera (host struct), following the 3DGS pipeline

@@ -44,7 +44,7 @@ P = C.c_void_p
 class ngs_scene(C.Structure):
     _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("mean", P), ("log_scale", P), ("rot", P),
                 ("opacity_logit", P), ("rgb", P), ("obj_logit", P), ("prob", P), ("opacity", P),
-                ("kappa", P), ("conf", P), ("label", P)]
+                ("kappa", P), ("conf", P), ("label", P), ("cov3", P)]
 
 
 class ngs_camera(C.Structure):
@@ -257,12 +257,13 @@ class DeviceScene:
         self.kappa = torch.empty_like(self.opacity)
         self.conf = torch.empty_like(self.opacity)
         self.label = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.cov3 = None  # allocated by ngs_prepare_scene, which fills it
         self.device = device
 
     def c(self) -> ngs_scene:
         return ngs_scene(self.n, self.k, _p(self.mean), _p(self.log_scale), _p(self.rot), _p(self.opacity_logit),
                          _p(self.rgb), _p(self.obj_logit), _p(self.prob), _p(self.opacity), _p(self.kappa),
-                         _p(self.conf), _p(self.label))
+                         _p(self.conf), _p(self.label), _p(getattr(self, "cov3", None)))
 
 
 @dataclass
@@ -330,6 +331,8 @@ def _bytes(nbytes: int, device: str = "cuda") -> torch.Tensor:
 # ------------------------------------------------------------------------------------------
 
 def ngs_prepare_scene(ctx: Context, scene: DeviceScene, ig: ngs_ig_params):
+    if getattr(scene, "cov3", None) is None:
+        scene.cov3 = torch.empty((9, max(scene.n, 1)), dtype=torch.float64, device=scene.device)
     sc = scene.c()
     _check("ngs_prepare_scene", lib().ngs_prepare_scene(ctx.handle, _ref(sc), _ref(ig), _stream()), ctx)
 

@@ -386,6 +386,19 @@ __device__ __forceinline__ void place_batch(uint32_t* cnt, int lo, int hi, int l
   }
 }
 
+// OR of a 32-bit value over the wavefront, by DPP moves (no LDS round trips): an inclusive OR
+// scan within each row of 16 lanes (shifts 1, 2, 4, 8), then the row totals broadcast into
+// the later rows (row_bcast 15 and 31); lane 63 ends with the OR of all 64 lanes.
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // place_batch with the counters in registers (lane l holds bin 64 i2 + l in cr[i2], read with
 // readlane at the uniform bin), over the bins that some lane covers: u[i2] holds this lane's
 // bins of word i2 (bit c % 64 of word c / 64). The union of the 64 lanes' bins (OR over the wavefront) is
@@ -395,14 +408,7 @@ template <int NR, class Emit>
 __device__ __forceinline__ void place_batch_masked(uint32_t (&cr)[NR], const uint64_t (&u)[NR], Emit emit) {
 #pragma unroll
   for (int i2 = 0; i2 < NR; ++i2) {
-    uint32_t ulo = (uint32_t)u[i2], uhi = (uint32_t)(u[i2] >> 32);
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      ulo |= (uint32_t)__shfl_xor((int)ulo, off);
-      uhi |= (uint32_t)__shfl_xor((int)uhi, off);
-    }
-    uint64_t todo = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)uhi) << 32) |
-                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)ulo);
+    uint64_t todo = ((uint64_t)wave_or32((uint32_t)(u[i2] >> 32)) << 32) | (uint64_t)wave_or32((uint32_t)u[i2]);
     while (todo) {
       const int bit = __builtin_ctzll(todo);
       todo &= todo - 1ull;
@@ -630,10 +636,13 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
       for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
       __syncthreads();
     }
+    // the next 64 entries are loaded while the current ones are placed
+    uint2 e_next = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
+    if (c.begin + lane < c.end) e_next = rl[c.begin + lane];
     for (uint32_t i0 = c.begin; i0 < c.end; i0 += kWave) {
-      const uint32_t i = i0 + lane;
-      uint2 e = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
-      if (i < c.end) e = rl[i];
+      const uint2 e = e_next;
+      e_next = make_uint2(0u, 0u);
+      if (i0 + kWave + lane < c.end) e_next = rl[i0 + kWave + lane];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
       auto emit = [&](int, uint32_t pos) {
         if (pos < cap32) gids_out[pos] = e.x;

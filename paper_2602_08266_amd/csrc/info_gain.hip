@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
       }
       float a = 0.f, Tg = 0.f, om = 0.f;
       if (contrib) {
-        om = 1.f / (1.f - alpha);
+        om = __builtin_amdgcn_rcpf(1.f - alpha);  // 1 ulp; 1 - alpha >= 0.01
         Tg = Tc * om;
         a = alpha * Tg;
       }

@@ -9,6 +9,28 @@
 namespace ngs {
 namespace {
 
+// Sigma3 = Rg diag(s^2) Rg^T of Gaussian g in FP64, in a fixed order: s = exp(log-scale),
+// the quaternion normalised by its norm, Rg from it, then each entry summed over k in order.
+__device__ inline void cov3_of(int n, int g, const float* __restrict__ log_scale, const float* __restrict__ rot,
+                               double S3[9]) {
+  const double s0 = exp((double)log_scale[g]), s1 = exp((double)log_scale[n + g]),
+               s2 = exp((double)log_scale[2 * n + g]);
+  const double sc2[3] = {s0 * s0, s1 * s1, s2 * s2};
+  const double qw = rot[g], qx = rot[n + g], qy = rot[2 * n + g], qz = rot[3 * n + g];
+  const double qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+  const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+  double Rg[9];
+  Rg[0] = 1.0 - 2.0 * (y * y + z * z); Rg[1] = 2.0 * (x * y - w * z);       Rg[2] = 2.0 * (x * z + w * y);
+  Rg[3] = 2.0 * (x * y + w * z);       Rg[4] = 1.0 - 2.0 * (x * x + z * z); Rg[5] = 2.0 * (y * z - w * x);
+  Rg[6] = 2.0 * (x * z - w * y);       Rg[7] = 2.0 * (y * z + w * x);       Rg[8] = 1.0 - 2.0 * (x * x + y * y);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc = acc + (Rg[3 * i + k] * sc2[k]) * Rg[3 * j + k];
+      S3[3 * i + j] = acc;
+    }
+}
+
 // p = softmax(o) (Sec. III-A.1), sigma = sigmoid(opacity logit), kappa = max_k p,
 // label = argmax_k o (identical to argmax_k p, lowest k on ties), and the confidence
 // c_g of Eq. 7 -- or Eq. 12 when a target object is given.
@@ -16,7 +38,9 @@ __global__ __launch_bounds__(256) void k_prepare(int n, int k, const float* __re
                                                  const float* __restrict__ op_logit, float alpha_obj,
                                                  float alpha_opa, int target, float* __restrict__ prob,
                                                  float* __restrict__ opacity, float* __restrict__ kappa,
-                                                 float* __restrict__ conf, int32_t* __restrict__ label) {
+                                                 float* __restrict__ conf, int32_t* __restrict__ label,
+                                                 const float* __restrict__ log_scale, const float* __restrict__ rot,
+                                                 double* __restrict__ cov3) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   float mx = logit[g];
@@ -42,6 +66,11 @@ __global__ __launch_bounds__(256) void k_prepare(int n, int k, const float* __re
                        : 0.f;
   }
   conf[g] = c;
+  if (cov3) {
+    double S3[9];
+    cov3_of(n, g, log_scale, rot, S3);
+    for (int i = 0; i < 9; ++i) cov3[(size_t)i * n + g] = S3[i];
+  }
 }
 
 // floor(v / tile) clamped to [-1, lim]. The tile size is a power of two (16), so v * (1 / tile)
@@ -54,14 +83,15 @@ __device__ inline int tile_floor(double v, double inv_tile, int lim) {
 }
 
 // One thread per Gaussian. FP64 key path in the order: X = R mu + t (row by row,
-// left to right), Z; m = (f X / Z) + c; Sigma3 = Rg diag(s^2) Rg^T; T = Jp R; M = T Sigma3;
+// left to right), Z; m = (f X / Z) + c; Sigma3 (cov3_of, or the scene's copy); T = Jp R; M = T Sigma3;
 // Sigma2 = M T^T; +eps on the diagonal; conic; lambda_max; radius; rect.
 // Views of a group are the fastest-moving part of the block index (block b: view b % nv,
 // Gaussians from 256 (b / nv)), so the views of one range of Gaussians run together and read
 // its scene entries from the L2 once.
 __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ mean,
                                                  const float* __restrict__ log_scale,
-                                                 const float* __restrict__ rot, GroupCams gc, int nv, size_t vs,
+                                                 const float* __restrict__ rot, const double* __restrict__ cov3,
+                                                 GroupCams gc, int nv, size_t vs,
                                                  double z_near, double eps2d, double inv_tile, float* mean2d_,
                                                  float* conic_, float* depth_, uint32_t* zkey_, int16_t* rect_,
                                                  uint32_t* count_, const float* __restrict__ opacity, float cutoff_q,
@@ -91,23 +121,12 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     const double fx = cam.fx, fy = cam.fy;
     const double mx = (fx * X[0]) / Z + (double)cam.cx;
     const double my = (fy * X[1]) / Z + (double)cam.cy;
-    const double s0 = exp((double)log_scale[g]), s1 = exp((double)log_scale[n + g]),
-                 s2 = exp((double)log_scale[2 * n + g]);
-    const double sc2[3] = {s0 * s0, s1 * s1, s2 * s2};
-    const double qw = rot[g], qx = rot[n + g], qy = rot[2 * n + g], qz = rot[3 * n + g];
-    const double qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
-    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
-    double Rg[9];
-    Rg[0] = 1.0 - 2.0 * (y * y + z * z); Rg[1] = 2.0 * (x * y - w * z);       Rg[2] = 2.0 * (x * z + w * y);
-    Rg[3] = 2.0 * (x * y + w * z);       Rg[4] = 1.0 - 2.0 * (x * x + z * z); Rg[5] = 2.0 * (y * z - w * x);
-    Rg[6] = 2.0 * (x * z - w * y);       Rg[7] = 2.0 * (y * z + w * x);       Rg[8] = 1.0 - 2.0 * (x * x + y * y);
     double S3[9];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        double acc = 0.0;
-        for (int k = 0; k < 3; ++k) acc = acc + (Rg[3 * i + k] * sc2[k]) * Rg[3 * j + k];
-        S3[3 * i + j] = acc;
-      }
+    if (cov3) {  // the scene's precomputed Sigma3: the same bits as cov3_of
+      for (int i = 0; i < 9; ++i) S3[i] = cov3[(size_t)i * n + g];
+    } else {
+      cov3_of(n, g, log_scale, rot, S3);
+    }
     const double Jp[6] = {fx / Z, 0.0, -(fx * X[0]) / (Z * Z), 0.0, fy / Z, -(fy * X[1]) / (Z * Z)};
     double T[6], M[6];
     for (int i = 0; i < 2; ++i)
@@ -165,7 +184,8 @@ hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hip
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfPrepare, st);
   hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, s.n, s.k, s.obj_logit, s.opacity_logit,
-                     ig.alpha_obj, ig.alpha_opa, ig.target_id, s.prob, s.opacity, s.kappa, s.conf, s.label);
+                     ig.alpha_obj, ig.alpha_opa, ig.target_id, s.prob, s.opacity, s.kappa, s.conf, s.label,
+                     s.log_scale, s.rot, s.cov3);
   return hipGetLastError();
 }
 
@@ -174,7 +194,8 @@ hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_p
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfProject, st);
-  hipLaunchKernelGGL(k_project, dim3(blocks * G.g), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams, G.g,
+  hipLaunchKernelGGL(k_project, dim3(blocks * G.g), dim3(256), 0, st, s.n, s.mean, s.log_scale, s.rot, s.cov3, G.cams,
+                     G.g,
                      G.vs, (double)rp.z_near, (double)rp.eps2d, 1.0 / (double)rp.tile, out.mean2d, out.conic,
                      out.depth, out.zkey, out.rect, out.count, s.opacity, rp.cutoff_q,
                      reinterpret_cast<float4*>(out.splat));

@@ -27,10 +27,30 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* keys_, si
   h[threadIdx.x] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * kSortTileElems;
+  if (shift < 16) {
 #pragma unroll 4
-  for (int j = 0; j < kSortItems; ++j) {
-    const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    for (int j = 0; j < kSortItems; ++j) {
+      const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
+      if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+  } else {
+    // the high digits of depth keys take few values: lanes with equal digits are grouped by
+    // ballots and one of them adds the group's count (no same-address LDS atomics)
+    const uint64_t lt_mask = (threadIdx.x % kWave == 0) ? 0ull : (~0ull >> (kWave - threadIdx.x % kWave));
+#pragma unroll 2
+    for (int j = 0; j < kSortItems; ++j) {
+      const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
+      const bool valid = i < n;
+      const uint32_t d = valid ? (keys[i] >> shift) & (kRadix - 1) : 0u;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      if (valid && (peers & lt_mask) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
   hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -86,43 +106,39 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* kin_, 
   const uint2* __restrict__ rin = vp(rin_, vs);
   uint2* __restrict__ rout = vp(rout_, vs);
   // The block's 2048 pairs are first ranked into digit order in LDS (stable), then streamed
-  // out: consecutive lanes write consecutive positions of each digit's run.
+  // out: consecutive lanes write consecutive positions of each digit's run. Wavefront w owns
+  // the block's pairs [512 w, 512 w + 512), item j of lane l being pair 512 w + 64 j + l, so
+  // (wavefront, item, lane) is the input order: each wavefront ranks its items in turn against
+  // its own running digit counts (no workgroup barrier per item), and one scan over
+  // (digit, wavefront) then places the wavefronts' runs one after another.
+  constexpr int kWaveElems = kSortTileElems / kWavesPerBlock;
   __shared__ uint32_t sm[kSortThreads];
   __shared__ uint32_t gbase[kRadix];           // global position of this block's first key of digit d
   __shared__ uint32_t lstart[kRadix];          // local position of the first key of digit d
-  __shared__ uint32_t lrun[kRadix];            // local running position of digit d
-  __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+  __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];  // per wavefront: digit counts, then its run start
   __shared__ uint32_t sk[kSortTileElems], sv[kSortTileElems];
   const int t = threadIdx.x;
   const int wave = t / kWave;
   const int lane = t % kWave;
   const size_t blk = (size_t)blockIdx.x * kSortTileElems;
   const int cnt = (int)min((size_t)kSortTileElems, n - blk);
-  uint32_t keys[kSortItems], vals[kSortItems];
-  wcnt[0][t] = 0u;
-  __syncthreads();
+  uint32_t keys[kSortItems], vals[kSortItems], idx[kSortItems];
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][t] = 0u;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const int li = j * kSortThreads + t;
+    const int li = wave * kWaveElems + j * kWave + lane;
     keys[j] = li < cnt ? kin[blk + li] : 0u;
     vals[j] = li < cnt ? (vin ? vin[blk + li] : (uint32_t)(blk + li)) : 0u;
-    if (li < cnt) atomicAdd(&wcnt[0][(keys[j] >> shift) & (kRadix - 1)], 1u);
-  }
-  __syncthreads();
-  {
-    uint32_t tot;
-    const uint32_t local = block_exclusive_scan(wcnt[0][t], sm, &tot);
-    lstart[t] = local;
-    lrun[t] = local;
-    const uint32_t digit_start = block_exclusive_scan(rowtot[t], sm, &tot);
-    gbase[t] = digit_start + hist[(size_t)t * nblocks + blockIdx.x];
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t* wc = wcnt[wave];
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const bool valid = j * kSortThreads + t < cnt;
+    const bool valid = wave * kWaveElems + j * kWave + lane < cnt;
     const uint32_t d = (keys[j] >> shift) & (kRadix - 1);
+    // lanes holding the same digit (8 ballots), this lane's rank among them, the lowest leads
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -130,29 +146,44 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* kin_, 
       const uint64_t bal = __ballot(bit);
       peers &= bit ? bal : ~bal;
     }
-    const uint32_t rank = __popcll(peers & lt_mask);
-    const bool leader = valid && (peers & lt_mask) == 0ull;
-    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][t] = 0u;
-    __syncthreads();
-    if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    {
-      uint32_t run = lrun[t];
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        const uint32_t c = wcnt[w][t];
-        wcnt[w][t] = run;
-        run += c;
-      }
-      lrun[t] = run;
+    const uint32_t before = wc[d];  // read by every lane before the leader advances it
+    idx[j] = before + (uint32_t)__popcll(peers & lt_mask);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (valid && (peers & lt_mask) == 0ull) wc[d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  __syncthreads();
+  {
+    // thread t = digit: the block's count of it, its local start, and each wavefront's run start
+    uint32_t tot_d = 0u;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) tot_d += wcnt[w][t];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(tot_d, sm, &tot);
+    lstart[t] = run;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      const uint32_t c = wcnt[w][t];
+      wcnt[w][t] = run;
+      run += c;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t lp = wcnt[wave][d] + rank;
+    const uint32_t digit_start = block_exclusive_scan(rowtot[t], sm, &tot);
+    gbase[t] = digit_start + hist[(size_t)t * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    if (wave * kWaveElems + j * kWave + lane < cnt) {
+      const uint32_t lp = wc[(keys[j] >> shift) & (kRadix - 1)] + idx[j];
       sk[lp] = keys[j];
       sv[lp] = vals[j];
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = t; i < cnt; i += kSortThreads) {
     const uint32_t key = sk[i];
     const uint32_t d = (key >> shift) & (kRadix - 1);
