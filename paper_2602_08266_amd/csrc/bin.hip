@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kScanThreads) void k_count_total(const uint64_t* bs
 constexpr int kPartRanks = 512;  // depth ranks per level-1 partition block (one wavefront)
 constexpr int kChunk2 = 512;     // least row entries per level-2 chunk (default; tunable)
 constexpr int kHist2 = 1 << 22;  // level-2 count table entries (tiles_x * chunks)
-constexpr int kGrid2 = 8192;     // persistent level-2 blocks
+constexpr int kGrid2 = 8192;     // persistent level-2 wavefronts
+constexpr int kWaves2 = 4;       // independent wavefronts per level-2 workgroup
 
 // One Gaussian's rect as seen by the whole wavefront: lane q's values broadcast.
 struct RectU {
@@ -487,6 +488,15 @@ __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* or
 }
 
 // ---- level 2: tiles within a row ----------------------------------------------------------
+// The level-2 kernels run kWaves2 independent wavefronts per workgroup (more wavefronts per CU
+// than one-wave workgroups get); each has its own LDS slice, so a wavefront-level barrier
+// orders its LDS accesses.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Chunk ci of the level-2 work: row (binary search over the chunk prefix) and its entries.
 struct Chunk2 {
   int row;
@@ -513,7 +523,7 @@ __device__ __forceinline__ Chunk2 chunk2_of(uint32_t ci, int rows, const uint32_
 
 // Pass 2a: pairs per (tile, chunk); the table of row r holds tiles_x rows of nch[r] chunk
 // counts at tiles_x * cp[r]. Persistent: blocks stride over the chunks.
-__global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
+__global__ __launch_bounds__(kWave * kWaves2) void k_tile2_hist(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
                                                       const uint32_t* rtot_, const uint32_t* cp_, const uint32_t* nch_,
                                                       const uint32_t* meta_, uint32_t* hist2_, size_t vs) {
   const uint2* __restrict__ rl = vp(rl_, vs);
@@ -524,29 +534,29 @@ __global__ __launch_bounds__(kWave) void k_tile2_hist(const uint2* rl_, GroupDim
   const uint32_t* __restrict__ meta = vp(meta_, vs);
   uint32_t* __restrict__ hist2 = vp(hist2_, vs);
   const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
-  extern __shared__ uint32_t lds2[];  // cnt [tiles_x], chunk prefix [rows]
-  uint32_t* cnt = lds2;
-  uint32_t* cpl = lds2 + tiles_x;
+  extern __shared__ uint32_t lds2[];  // chunk prefix [rows], then cnt [kWaves2][tiles_x]
+  uint32_t* cpl = lds2;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  uint32_t* cnt = lds2 + rows + wave * tiles_x;
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
-  const int lane = threadIdx.x;
-  if (blockIdx.x >= NC) return;
-  for (int r = lane; r < rows; r += kWave) cpl[r] = cp[r];
-  for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
-    __syncthreads();
+  if (blockIdx.x * kWaves2 >= NC) return;
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) cpl[r] = cp[r];
+  __syncthreads();
+  for (uint32_t ci = blockIdx.x * kWaves2 + wave; ci < NC; ci += gridDim.x * kWaves2) {
+    wave_sync();
     const Chunk2 c = chunk2_of(ci, rows, cpl, rstart, rtot, K2);
     for (int t = lane; t < tiles_x; t += kWave) cnt[t] = 0u;
-    __syncthreads();
+    wave_sync();
     for (uint32_t i = c.begin + lane; i < c.end; i += kWave) {
       const uint32_t xw = rl[i].y;
       const int x0 = (int)(xw & 0xFFFFu), w = (int)(xw >> 16);
       for (int j = 0; j < w; ++j) atomicAdd(&cnt[x0 + j], 1u);
     }
-    __syncthreads();
+    wave_sync();
     uint32_t* dst = hist2 + (size_t)tiles_x * cp[c.row];
     const uint32_t nc = nch[c.row];
     for (int t = lane; t < tiles_x; t += kWave) dst[(size_t)t * nc + c.idx] = cnt[t];
-    __syncthreads();
   }
 }
 
@@ -591,7 +601,7 @@ __global__ __launch_bounds__(256) void k_tile2_scan(uint32_t* hist2_, GroupDims 
 // tiles_x output runs open, so the L2 completes their lines. NR > 0: counters in registers
 // (tiles_x <= 64 NR) and only the covered, wanted tiles visited; else counters in LDS.
 template <int NR>
-__global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
+__global__ __launch_bounds__(kWave * kWaves2) void k_tile2_scatter(const uint2* rl_, GroupDims gd, const uint32_t* rstart_,
                                                          const uint32_t* rtot_, const uint32_t* cp_,
                                                          const uint32_t* nch_, const uint32_t* meta_,
                                                          const uint32_t* hist2_, const uint32_t* ranges_,
@@ -608,17 +618,18 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
   uint32_t* __restrict__ gids_out = vp(gids_out_, vs);
   const int32_t* __restrict__ keep = vp(keep_, vs);
   const int rows = gd.ty[blockIdx.y], tiles_x = gd.tx[blockIdx.y];
-  extern __shared__ uint32_t lds2[];  // cnt [tiles_x] (NR == 0), chunk prefix [rows]
-  uint32_t* cnt = lds2;
-  uint32_t* cpl = lds2 + (NR > 0 ? 0 : tiles_x);
+  extern __shared__ uint32_t lds2[];  // chunk prefix [rows], then (NR == 0) cnt [kWaves2][tiles_x]
+  uint32_t* cpl = lds2;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  uint32_t* cnt = lds2 + rows + wave * tiles_x;
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
   const uint32_t cap32 = (uint32_t)min(capacity, (int64_t)0xFFFFFFFF);
-  const int lane = threadIdx.x;
-  if (blockIdx.x >= NC) return;
-  for (int r = lane; r < rows; r += kWave) cpl[r] = cp[r];
-  for (uint32_t ci = blockIdx.x; ci < NC; ci += gridDim.x) {
-    __syncthreads();
+  if (blockIdx.x * kWaves2 >= NC) return;
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) cpl[r] = cp[r];
+  __syncthreads();
+  for (uint32_t ci = blockIdx.x * kWaves2 + wave; ci < NC; ci += gridDim.x * kWaves2) {
+    wave_sync();
     const Chunk2 c = chunk2_of(ci, rows, cpl, rstart, rtot, K2);
     const uint32_t* h = hist2 + (size_t)tiles_x * cp[c.row];
     const uint32_t nc = nch[c.row];
@@ -634,7 +645,7 @@ __global__ __launch_bounds__(kWave) void k_tile2_scatter(const uint2* rl_, Group
       }
     } else {
       for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
-      __syncthreads();
+      wave_sync();
     }
     // the next 64 entries are loaded while the current ones are placed
     uint2 e_next = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
@@ -763,7 +774,7 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, cons
     return e != hipSuccess ? e : launch_fill_u32(out.ranges, 0u, 2 * (size_t)ntiles, st, g, vs);
   }
   const int nblk = (n + kPartRanks - 1) / kPartRanks;
-  const int grid2 = std::max(256, kGrid2 / g);  // persistent level-2 blocks per view
+  const int grid2 = std::max(256, kGrid2 / g) / kWaves2;  // persistent level-2 workgroups per view
   const unsigned long long* rkm = nullptr;
   if (keep && tx <= 2 * kWave && rows <= 2 * kWave) {
     ProfScope ps(kProfTileHist, st);
@@ -795,7 +806,8 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, cons
   }
   {
     ProfScope ps(kProfTileHist, st);
-    hipLaunchKernelGGL(k_tile2_hist, dim3(grid2, g), dim3(kWave), (tx + rows) * 4, st, w.rl, G.dims, w.rstart, w.rtot,
+    hipLaunchKernelGGL(k_tile2_hist, dim3(grid2, g), dim3(kWave * kWaves2), (kWaves2 * tx + rows) * 4, st, w.rl, G.dims,
+                       w.rstart, w.rtot,
                        w.cp, w.nch, w.meta, w.hist2, vs);
   }
   {
@@ -808,13 +820,14 @@ hipError_t bin_emit_and_sort(const ngs_projected& p, int n, const Group& G, cons
   {
     ProfScope ps(kProfTileScatter, st);
     if (tx <= kWave)
-      hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(grid2, g), dim3(kWave), rows * 4, st, w.rl, G.dims, w.rstart,
+      hipLaunchKernelGGL(k_tile2_scatter<1>, dim3(grid2, g), dim3(kWave * kWaves2), rows * 4, st, w.rl, G.dims, w.rstart,
                          w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
     else if (tx <= 2 * kWave)
-      hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(grid2, g), dim3(kWave), rows * 4, st, w.rl, G.dims, w.rstart,
+      hipLaunchKernelGGL(k_tile2_scatter<2>, dim3(grid2, g), dim3(kWave * kWaves2), rows * 4, st, w.rl, G.dims, w.rstart,
                          w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
     else
-      hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(grid2, g), dim3(kWave), (tx + rows) * 4, st, w.rl, G.dims,
+      hipLaunchKernelGGL(k_tile2_scatter<0>, dim3(grid2, g), dim3(kWave * kWaves2), (kWaves2 * tx + rows) * 4, st, w.rl,
+                         G.dims,
                          w.rstart, w.rtot, w.cp, w.nch, w.meta, w.hist2, out.ranges, out.capacity, out.gids, keep, vs);
   }
   if (out.keys && g == 1) {
