@@ -541,6 +541,7 @@ def run_exact(args, log):
                    "ig_lanes_per_pixel": B.ngs_get_tuning(ctx)["ig_lanes_per_pixel"],
                    "ig_waves_per_simd": B.ngs_get_tuning(ctx)["ig_waves_per_simd"],
                    "bin_chunk": B.ngs_get_tuning(ctx)["bin_chunk"],
+                   "groups_in_flight": B.ngs_get_tuning(ctx)["groups_in_flight"],
                    "pair_capacity": scorer.max_pairs},
         "roofline": roofline, "path": path, "setup_ms": round(setup_ms, 1),
         "ms_per_step_median": round(float(np.median(times)) * 1e3, 3),
@@ -551,6 +552,7 @@ def run_exact(args, log):
                                                "ig_lanes_per_pixel": tune.ig_lanes_per_pixel,
                                                "ig_waves_per_simd": tune.ig_waves_per_simd,
                                                "bin_chunk": tune.bin_chunk,
+                                               "groups_in_flight": tune.groups_in_flight,
                                                "sample_ms_per_view": round(tune.ms_per_view, 4), "table": tune.table},
     }
     if args.workload == "batched640" and not args.no_mixed and args.views is None:

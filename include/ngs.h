@@ -357,11 +357,16 @@ ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian*
  * ngs_score_batch, ngs_training_setup; 0 = 512, else a power of two in [256, 8192]): longer chunks leave fewer
  * partly written lines in the tile lists, shorter ones spread the scatter over more
  * workgroups. Results do not depend on it.
+ * groups_in_flight: ngs_score_batch and ngs_score_graph_create run the views in groups, one
+ * launch per kernel and group, with this many groups in flight on context streams (0 = 2,
+ * else 1 to 4); a group has views_in_flight / groups_in_flight views (at most 16). Results do
+ * not depend on it.
  * The autotuner of the Python package picks these and views_in_flight by timing. */
 typedef struct {
   int32_t ig_lanes_per_pixel;
   int32_t ig_waves_per_simd;
   int32_t bin_chunk;
+  int32_t groups_in_flight;
 } ngs_tuning;
 ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* tuning);
 ngs_status ngs_get_tuning(const ngs_ctx* ctx, ngs_tuning* tuning);

@@ -4,8 +4,9 @@ It times ngs_score_batch on a sample of the real candidate set for every combina
 views_in_flight (buffer sets and context streams kept busy at once), lanes per pixel of the
 information-gain back pass (which sets its workgroup size and the packed rows it stages in LDS
 per reduction round) and, where the library has both builds, its waves per SIMD (one or two
-workgroups per CU), keeps the fastest, and applies it to the context (ngs_set_tuning) and to
-the scorer's workspace. Results may be cached in a JSON file keyed by the device, the scene
+workgroups per CU), then at the fastest of those the chunk size of the second binning level and
+the number of view groups in flight; keeps the fastest, and applies it to the context
+(ngs_set_tuning) and to the scorer's workspace. Results may be cached in a JSON file keyed by the device, the scene
 size and the resolution mix of the sample.
 """
 from __future__ import annotations
@@ -22,6 +23,7 @@ from . import binding as B
 
 VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16, 24, 32)
 BIN_CHUNKS = (1024, 2048, 4096)  # tried at the best shape after the default (512)
+GROUPS = (1, 3, 4)  # groups in flight tried at the best shape after the default (2)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
@@ -48,6 +50,7 @@ class TuneResult:
     cached: bool = False
     ig_waves_per_simd: int = 0
     bin_chunk: int = 0
+    groups_in_flight: int = 0
 
 
 def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max_slots: int) -> str:
@@ -77,7 +80,7 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
         if hit:
             res = TuneResult(hit["views_in_flight"], hit["ig_lanes_per_pixel"], hit["ms_per_view"], hit["table"],
                              cached=True, ig_waves_per_simd=hit.get("ig_waves_per_simd", 0),
-                             bin_chunk=hit.get("bin_chunk", 0))
+                             bin_chunk=hit.get("bin_chunk", 0), groups_in_flight=hit.get("groups_in_flight", 0))
             apply(ctx, scorer, res)
             return res
     lpps = tuple(lpps) if lpps else lpp_choices(scorer.scene.k)
@@ -127,8 +130,31 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
         if ms < best[0]:
             best = (ms, best[1], best[2], best[3])
             best_chunk = chunk
+    # then the number of view groups in flight
+    best_groups = 0
+    for groups in GROUPS:
+        if groups > best[1]:
+            continue
+        B.ngs_set_tuning(ctx, best[2], best[3], best_chunk, groups)
+        scorer.score(sub)
+        torch.cuda.synchronize()
+        t = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            scorer.score(sub)
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+        ms = t / len(sub) * 1e3
+        table.append({"views_in_flight": best[1], "ig_lanes_per_pixel": best[2], "ig_waves_per_simd": best[3],
+                      "bin_chunk": best_chunk, "groups_in_flight": groups, "ms_per_view": round(ms, 4)})
+        if log:
+            log(f"autotune: groups in flight {groups}: {ms:.3f} ms/view")
+        if ms < best[0]:
+            best = (ms, best[1], best[2], best[3])
+            best_groups = groups
     scorer.ws = None
-    res = TuneResult(best[1], best[2], best[0], table, ig_waves_per_simd=best[3], bin_chunk=best_chunk)
+    res = TuneResult(best[1], best[2], best[0], table, ig_waves_per_simd=best[3], bin_chunk=best_chunk,
+                     groups_in_flight=best_groups)
     apply(ctx, scorer, res)
     if cache and write_cache:
         data = {}
@@ -142,6 +168,6 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
 
 
 def apply(ctx: B.Context, scorer: B.NbvScorer, res: TuneResult):
-    B.ngs_set_tuning(ctx, res.ig_lanes_per_pixel, res.ig_waves_per_simd, res.bin_chunk)
+    B.ngs_set_tuning(ctx, res.ig_lanes_per_pixel, res.ig_waves_per_simd, res.bin_chunk, res.groups_in_flight)
     scorer.views_in_flight = res.views_in_flight
     scorer.ws = None

@@ -714,11 +714,13 @@ def ngs_training_setup(ctx: Context, scene: DeviceScene, h: Hessian, train: Sequ
 
 
 class ngs_tuning(C.Structure):
-    _fields_ = [("ig_lanes_per_pixel", C.c_int32), ("ig_waves_per_simd", C.c_int32), ("bin_chunk", C.c_int32)]
+    _fields_ = [("ig_lanes_per_pixel", C.c_int32), ("ig_waves_per_simd", C.c_int32), ("bin_chunk", C.c_int32),
+                ("groups_in_flight", C.c_int32)]
 
 
-def ngs_set_tuning(ctx: Context, ig_lanes_per_pixel: int = 0, ig_waves_per_simd: int = 0, bin_chunk: int = 0):
-    t = ngs_tuning(int(ig_lanes_per_pixel), int(ig_waves_per_simd), int(bin_chunk))
+def ngs_set_tuning(ctx: Context, ig_lanes_per_pixel: int = 0, ig_waves_per_simd: int = 0, bin_chunk: int = 0,
+                   groups_in_flight: int = 0):
+    t = ngs_tuning(int(ig_lanes_per_pixel), int(ig_waves_per_simd), int(bin_chunk), int(groups_in_flight))
     _check("ngs_set_tuning", lib().ngs_set_tuning(ctx.handle, _ref(t)), ctx)
 
 
@@ -726,7 +728,7 @@ def ngs_get_tuning(ctx: Context) -> Dict[str, int]:
     t = ngs_tuning()
     _check("ngs_get_tuning", lib().ngs_get_tuning(ctx.handle, _ref(t)), ctx)
     return {"ig_lanes_per_pixel": int(t.ig_lanes_per_pixel), "ig_waves_per_simd": int(t.ig_waves_per_simd),
-            "bin_chunk": int(t.bin_chunk)}
+            "bin_chunk": int(t.bin_chunk), "groups_in_flight": int(t.groups_in_flight)}
 
 
 class ScoreGraph:

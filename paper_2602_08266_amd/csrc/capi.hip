@@ -562,10 +562,10 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
   // List overflow is caught on the device (empty ranges, sticky flag) and reported once the
   // batch has run. Views go in groups of gsz consecutive views, one launch per kernel and
   // group (grid.y = view of the group); the buffer sets of a group are consecutive, per bytes
-  // apart. Two groups are in flight: group q runs on lane q mod 2 with the sets from
-  // (q mod 2) * gsz on, which it reuses in stream order.
-  const int gsz = lanes == 1 ? 1 : std::min(kMaxGroup, lanes / 2);
-  const int nlanes = lanes == 1 ? 1 : 2;
+  // apart. nlanes groups are in flight: group q runs on lane q mod nlanes with the sets from
+  // (q mod nlanes) * gsz on, which it reuses in stream order.
+  const int nlanes = std::max(1, std::min(ctx->tuning.groups_in_flight > 0 ? ctx->tuning.groups_in_flight : 2, lanes));
+  const int gsz = std::max(1, std::min(kMaxGroup, lanes / nlanes));
   std::vector<DevCam> dcs(n_views);
   for (int v = 0; v < n_views; ++v) dcs[v] = make_devcam(cams[v], kTile);
   for (int v0 = 0, q = 0; v0 < n_views; v0 += gsz, ++q) {
@@ -853,6 +853,7 @@ ngs_status ngs_set_tuning(ngs_ctx* ctx, const ngs_tuning* t) {
   if (t->ig_waves_per_simd != 0 && t->ig_waves_per_simd != 4) return NGS_INVALID_ARG;
   if (t->bin_chunk != 0 && (t->bin_chunk < 256 || t->bin_chunk > 8192 || (t->bin_chunk & (t->bin_chunk - 1))))
     return NGS_INVALID_ARG;
+  if (t->groups_in_flight < 0 || t->groups_in_flight > 4) return NGS_INVALID_ARG;
   ctx->tuning = *t;
   return NGS_OK;
 }

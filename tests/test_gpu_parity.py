@@ -122,6 +122,41 @@ def test_bin_sort_bitexact_every_chunk_size(B, ctx, chunk):
     assert np.array_equal(lists.ranges.cpu().numpy().view(np.uint32), ref["ranges"])
 
 
+@pytest.mark.parametrize("groups", [1, 3, 4])
+def test_score_batch_every_group_count(B, ctx, groups):
+    """The number of view groups in flight (a tuning knob) changes no gain: a batch of 11
+    views on 8 buffer sets (groups of 8 / groups views, a ragged last group) against the
+    oracle (1e-3 relative), object-centric target."""
+    log(f"test_score_batch groups {groups}")
+    scene = scenegen.make_scene(3000, 8, 16, seed=23, object_centric=True)
+    cfg = scenegen.SceneConfig("groups", 3000, 8, 16, 11, ((128, 96, 11),), 500.0, (0.6, 0.6))
+    cands, train = scenegen.make_cameras(cfg, 23)
+    target = scene.target
+    assert target >= 1
+    ds = B.DeviceScene(scene, "cuda")
+    ig = oracle.IGParams(target_id=target)
+    ref = oracle.score(scene, train, cands, ig=ig)
+    assert ref.status == 0
+    B.ngs_set_tuning(ctx, 0, 0, 0, groups)
+    try:
+        assert B.ngs_get_tuning(ctx)["groups_in_flight"] == groups
+        scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(target_id=target), max_pairs=1 << 18,
+                             max_slots=1 << 14, store_capacity=1 << 14, views_in_flight=8)
+        scorer.setup([B.camera(c) for c in train])
+        scores, best, raw = scorer.score([B.camera(c) for c in cands])
+        for v in range(len(cands)):
+            check_gain(raw[v].cpu().numpy(), ref.ig_cand[v], f"view {v}")
+    finally:
+        B.ngs_set_tuning(ctx, 0)
+
+
+def test_tuning_rejects_bad_group_count(B, ctx):
+    L = B.lib()
+    for bad in (-1, 5):
+        t = B.ngs_tuning(0, 0, 0, bad)
+        assert L.ngs_set_tuning(ctx.handle, B._ref(t)) == B.NGS_INVALID_ARG
+
+
 @pytest.mark.parametrize("w,h", [(2304, 64), (64, 1100), (64, 2100), (1300, 40)])
 def test_bin_sort_bitexact_tile_grid_shapes(B, ctx, w, h):
     """Tile grids that take the other counter paths of the two-level partition: more than
@@ -488,7 +523,8 @@ def test_info_gain_every_launch_shape(B, ctx, k, lpp, waves):
     assert ref.status == 0
     B.ngs_set_tuning(ctx, lpp, waves)
     try:
-        assert B.ngs_get_tuning(ctx) == {"ig_lanes_per_pixel": lpp, "ig_waves_per_simd": waves, "bin_chunk": 0}
+        assert B.ngs_get_tuning(ctx) == {"ig_lanes_per_pixel": lpp, "ig_waves_per_simd": waves, "bin_chunk": 0,
+                                         "groups_in_flight": 0}
         scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
                              store_capacity=1 << 14, views_in_flight=2)
         norm = scorer.setup([B.camera(c) for c in train])

@@ -90,7 +90,8 @@ def bench_shape(scene, width, height):
         k = json.loads(key)
         if k["dev"] == "gfx950" and k["n"] == scene.n and k["k"] == scene.k and \
                 [r for r, _ in k["res"]] == [f"{width}x{height}"]:
-            return v["views_in_flight"], v["ig_lanes_per_pixel"], v.get("ig_waves_per_simd", 0), v.get("bin_chunk", 0)
+            return (v["views_in_flight"], v["ig_lanes_per_pixel"], v.get("ig_waves_per_simd", 0), v.get("bin_chunk", 0),
+                    v.get("groups_in_flight", 0))
     return None
 
 
@@ -122,7 +123,7 @@ def test_information_gain_full_size(B, ctx, name, shape):
         if tuned is None:
             pytest.skip("no tuned shape for this workload in the package cache")
         scorer.views_in_flight = tuned[0]
-        B.ngs_set_tuning(ctx, tuned[1], tuned[2], tuned[3])
+        B.ngs_set_tuning(ctx, tuned[1], tuned[2], tuned[3], tuned[4])
         log(f"  tuned shape: {tuned[0]} views in flight, {tuned[1]} lanes per pixel, {tuned[2]} waves per SIMD")
     # with the bench's shape the sample is repeated past the views in flight, so that every
     # buffer set is used and then reused in stream order
