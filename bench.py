@@ -480,7 +480,7 @@ def run_exact(args, log):
         from paper_2602_08266_amd import autotune
         if args.retune and os.path.exists(args.retune):
             os.remove(args.retune)
-        tune = autotune.tune_score(ctx, scorer, cam_c, sample=32, cache=args.retune or autotune.CACHE,
+        tune = autotune.tune_score(ctx, scorer, cam_c, sample=64, cache=args.retune or autotune.CACHE,
                                    write_cache=bool(args.retune), log=log)
     elif args.ig_lpp:
         B.ngs_set_tuning(ctx, args.ig_lpp)
@@ -524,7 +524,9 @@ def run_exact(args, log):
     ms_per_step = dt * 1e3 / K
     path = None
     if counts:
-        pb = path_bytes(scene.n, scene.k, 1, counts["pairs_M"], counts["touched_weighted_U"])
+        # M of the 3DGS binning (the capacity pre-pass counts it; the scoring path's own lists
+        # keep only the pairs a walk can take, counts["pairs_M"])
+        pb = path_bytes(scene.n, scene.k, 1, float(pairs[:V].double().mean()), counts["touched_weighted_U"])
         path = {"algorithmic_bytes_per_view": int(pb), "achieved_GBs": round(pb * value / 1e9, 1),
                 "frac_of_hbm_peak": round(pb * value / 1e9 / HBM_PEAK_GBS, 4)}
     mode = f"object-centric target {scene.target}" if scene.target >= 0 else "whole-scene confidence (Eq. 7)"
@@ -642,7 +644,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --in-flight and --ig-lpp instead of the autotuned launch shapes")
     ap.add_argument("--retune", default="", metavar="CACHE",
-                    help="time every launch shape on 32 candidates (ignoring the package's tuning cache) and "
+                    help="time every launch shape on 64 candidates (ignoring the package's tuning cache) and "
                          "write the result to CACHE")
     ap.add_argument("--ig-lpp", type=int, default=0, help="with --no-autotune: lanes per pixel of the IG kernel")
     ap.add_argument("--no-graph", action="store_true",

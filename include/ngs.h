@@ -207,7 +207,7 @@ typedef struct {
  * 4 = ngs_sur_render_features (ngs_surrogate.h), 5 = ngs_count_pairs.
  * dims: n, k, width, height, pair capacity, slot capacity, and (ngs_score_batch only)
  * the number of views kept in flight at once, each with its own buffer set (<= 0: 8;
- * at most 32; at most 32 for op 4, where it is the views per grouped render). All host. */
+ * at most 64; at most 32 for op 4, where it is the views per grouped render). All host. */
 typedef struct {
   int64_t n, k, width, height, max_pairs, max_slots, views_in_flight;
 } ngs_dims;
@@ -309,10 +309,12 @@ ngs_status ngs_hessian_finalize(ngs_ctx* ctx, ngs_hessian* h, void* stream);
  * views); on return stats[0] = n_views. Returns NGS_DEGENERATE if an enabled normaliser is
  * not positive, NGS_CAPACITY if a view overflows dims->max_pairs or dims->max_slots. ws:
  * ngs_workspace_size(2, dims) bytes, carved by the same dims (host); syncs once per batch.
- * Up to dims->views_in_flight views run concurrently on streams of the context (created
- * on first use, non-blocking, default priority) that wait for the work already queued on
- * `stream` and that `stream` waits for before the combination; view v uses buffer set
- * v mod views_in_flight. Calls on one context must not overlap. */
+ * The views run in groups of up to 16 consecutive views, one launch per kernel and group,
+ * with ngs_tuning.groups_in_flight groups (default 2) in flight on streams of the context
+ * (created on first use, non-blocking, default priority) that wait for the work already
+ * queued on `stream` and that `stream` waits for before the combination; each group in
+ * flight owns dims->views_in_flight / groups_in_flight consecutive buffer sets and reuses
+ * them in stream order. Calls on one context must not overlap. */
 ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
                            const double* normalisers, const ngs_camera* cams, int32_t n_views,
                            const ngs_raster_params* rp, const ngs_ig_params* ig, float* scores,

@@ -23,7 +23,8 @@ from . import binding as B
 
 VIEWS_IN_FLIGHT = (2, 4, 8, 12, 16, 24, 32)
 BIN_CHUNKS = (1024, 2048, 4096)  # tried at the best shape after the default (512)
-GROUPS = (1, 3, 4)  # groups in flight tried at the best shape after the default (2)
+GROUPS = (1, 3, 4)  # groups in flight tried at the best shape after the default (2) ...
+GROUP_SHAPES = ((48, 3), (64, 4))  # ... and (views in flight, groups) with full groups of 16
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
@@ -64,7 +65,7 @@ def _key(scene: B.DeviceScene, cams: Sequence[B.ngs_camera], max_pairs: int, max
                        "slots": max_slots}, sort_keys=True)
 
 
-def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera], sample: int = 32,
+def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera], sample: int = 64,
                reps: int = 2, vif: Sequence[int] = VIEWS_IN_FLIGHT, lpps: Optional[Sequence[int]] = None,
                cache: Optional[str] = None, write_cache: bool = True, log=None) -> TuneResult:
     """Times every (views_in_flight, lanes per pixel) pair on `sample` evenly spaced candidates
@@ -130,11 +131,13 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
         if ms < best[0]:
             best = (ms, best[1], best[2], best[3])
             best_chunk = chunk
-    # then the number of view groups in flight
+    # then the number of view groups in flight (with more buffer sets for more groups)
     best_groups = 0
-    for groups in GROUPS:
-        if groups > best[1]:
+    for v, groups in [(best[1], gr) for gr in GROUPS] + list(GROUP_SHAPES):
+        if groups > v:
             continue
+        scorer.views_in_flight = v
+        scorer.ws = None
         B.ngs_set_tuning(ctx, best[2], best[3], best_chunk, groups)
         scorer.score(sub)
         torch.cuda.synchronize()
@@ -145,12 +148,12 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
             torch.cuda.synchronize()
             t = min(t, time.perf_counter() - t0)
         ms = t / len(sub) * 1e3
-        table.append({"views_in_flight": best[1], "ig_lanes_per_pixel": best[2], "ig_waves_per_simd": best[3],
+        table.append({"views_in_flight": v, "ig_lanes_per_pixel": best[2], "ig_waves_per_simd": best[3],
                       "bin_chunk": best_chunk, "groups_in_flight": groups, "ms_per_view": round(ms, 4)})
         if log:
-            log(f"autotune: groups in flight {groups}: {ms:.3f} ms/view")
+            log(f"autotune: {v} views in flight, groups in flight {groups}: {ms:.3f} ms/view")
         if ms < best[0]:
-            best = (ms, best[1], best[2], best[3])
+            best = (ms, v, best[2], best[3])
             best_groups = groups
     scorer.ws = None
     res = TuneResult(best[1], best[2], best[0], table, ig_waves_per_simd=best[3], bin_chunk=best_chunk,

@@ -387,19 +387,6 @@ __device__ __forceinline__ void place_batch(uint32_t* cnt, int lo, int hi, int l
   }
 }
 
-// OR of a 32-bit value over the wavefront, by DPP moves (no LDS round trips): an inclusive OR
-// scan within each row of 16 lanes (shifts 1, 2, 4, 8), then the row totals broadcast into
-// the later rows (row_bcast 15 and 31); lane 63 ends with the OR of all 64 lanes.
-__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
 // place_batch with the counters in registers (lane l holds bin 64 i2 + l in cr[i2], read with
 // readlane at the uniform bin), over the bins that some lane covers: u[i2] holds this lane's
 // bins of word i2 (bit c % 64 of word c / 64). The union of the 64 lanes' bins (OR over the wavefront) is

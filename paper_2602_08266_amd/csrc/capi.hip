@@ -182,7 +182,8 @@ ngs_projected proj_carve(void* ws, int64_t n) {
 }
 
 constexpr int kDefaultInFlight = 8;
-constexpr int kMaxInFlight = 32;
+constexpr int kMaxInFlight = 64;
+constexpr int kMaxGroupsInFlight = 4;  // context streams a scoring batch uses
 constexpr int kMaxFeatureGroup = 32;  // views per grouped render launch of the feature maps
 
 int views_in_flight(const ngs_dims* d, int cap = kMaxInFlight) {
@@ -557,8 +558,6 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
   }
   *sticky_out = sticky;
   NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(ig_raw), 0u, (size_t)6 * std::max(n_views, 1), st));
-  NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
-  for (int i = 0; i < lanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   // List overflow is caught on the device (empty ranges, sticky flag) and reported once the
   // batch has run. Views go in groups of gsz consecutive views, one launch per kernel and
   // group (grid.y = view of the group); the buffer sets of a group are consecutive, per bytes
@@ -566,6 +565,8 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
   // (q mod nlanes) * gsz on, which it reuses in stream order.
   const int nlanes = std::max(1, std::min(ctx->tuning.groups_in_flight > 0 ? ctx->tuning.groups_in_flight : 2, lanes));
   const int gsz = std::max(1, std::min(kMaxGroup, lanes / nlanes));
+  NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
+  for (int i = 0; i < nlanes; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   std::vector<DevCam> dcs(n_views);
   for (int v = 0; v < n_views; ++v) dcs[v] = make_devcam(cams[v], kTile);
   for (int v0 = 0, q = 0; v0 < n_views; v0 += gsz, ++q) {
@@ -575,7 +576,7 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     const BatchWs& b = sets[i];
     const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
     const Group G = make_group(&dcs[v0], g, per);
-    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, walk_only(b.proj), ls));
+    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, walk_only(b.proj), ls, 1));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls, g, per));
     // slots first: with a target object only the lists of tiles that a weighted Gaussian
     // reaches are written, the only ones the information walk reads
@@ -645,7 +646,7 @@ extern "C" ngs_status ngs_training_setup(ngs_ctx* ctx, const ngs_scene* scene, n
     const ngs_ig_params& p = pass == 0 ? acc : sc;
     for (int t = 0; t < n_train; ++t) {
       const Group G1 = single_group(make_devcam(train[t], kTile));
-      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, walk_only(b.proj), st));
+      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, walk_only(b.proj), st, 1));
       NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, st));
       NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, G1, p, w, st));
       NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G1, bw, b.lists, sticky, nullptr, st, ig_tile_flags(p, w),
@@ -710,7 +711,7 @@ ngs_status ngs_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian* h,
     if (((ig->outputs >> f) & 1u) && !(normalisers[f] > 0.0)) return NGS_DEGENERATE;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  s = ensure_lanes(ctx, std::max(1, std::min(views_in_flight(dims), n_views)));
+  s = ensure_lanes(ctx, std::max(1, std::min(kMaxGroupsInFlight, std::min(views_in_flight(dims), n_views))));
   if (s != NGS_OK) return s;
   int32_t* sticky = nullptr;
   s = enqueue_score_batch(ctx, scene, h, normalisers, nullptr, cams, n_views, rp, ig, scores, best, ig_raw, stats,
@@ -787,7 +788,7 @@ ngs_status ngs_score_graph_create(ngs_ctx* ctx, const ngs_scene* scene, ngs_hess
       !ig_waves_valid(scene->k, ctx->tuning.ig_lanes_per_pixel, ctx->tuning.ig_waves_per_simd))
     return NGS_INVALID_ARG;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  s = ensure_lanes(ctx, std::max(1, std::min(views_in_flight(dims), n_views)));
+  s = ensure_lanes(ctx, std::max(1, std::min(kMaxGroupsInFlight, std::min(views_in_flight(dims), n_views))));
   if (s != NGS_OK) return s;
   hipStream_t cs = nullptr;
   NGS_TRY_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1006,12 +1007,13 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
   if (!ws || ws_bytes < need) return NGS_WORKSPACE_TOO_SMALL;
   hipStream_t st = (hipStream_t)stream;
   NGS_TRY_HIP(ctx, hipSetDevice(ctx->device));
-  // Views go in groups of G: each view of a group is projected and binned on its own context
-  // stream, then one render launch composites the whole group (grid.y = view) and one launch
-  // writes its feature channels, both on `stream`. Groups alternate between two halves of
-  // the buffer sets, so binning of the next group overlaps the render of this one.
+  // Views go in groups of G: a group is projected and binned on a context stream with one
+  // launch per kernel and sub-group of at most 16 views (grid.y = view), then one render launch
+  // composites the whole group (grid.y = view) and one launch writes its feature channels,
+  // both on `stream`. Groups alternate between two halves of the buffer sets and two streams,
+  // so binning of the next group overlaps the render of this one.
   const int G = std::max(1, std::min(views_in_flight(dims, kMaxFeatureGroup), n_views));
-  s = ensure_lanes(ctx, G);
+  s = ensure_lanes(ctx, 2);
   if (s != NGS_OK) return s;
   int32_t* sticky = static_cast<int32_t*>(ws);
   NGS_TRY_HIP(ctx, hipMemsetAsync(sticky, 0, kIgHeader, st));
@@ -1019,30 +1021,33 @@ ngs_status ngs_sur_render_features(ngs_ctx* ctx, const ngs_scene* scene, const n
   char* base = static_cast<char*>(ws) + kIgHeader;
   const size_t fixed = al(batch_fixed_bytes(scene->n, dims->max_pairs));
   NGS_TRY_HIP(ctx, hipEventRecord(ctx->fork, st));
-  for (int i = 0; i < G; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
+  for (int i = 0; i < 2; ++i) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ctx->lanes[i], ctx->fork, 0));
   const RasterConst rc = make_raster(*rp);
   ngs_scene ws_scene = *scene;  // the render averages `weight` where it would average kappa
   if (weight) ws_scene.kappa = const_cast<float*>(weight);
+  std::vector<DevCam> dcs(n_views);
+  for (int v = 0; v < n_views; ++v) dcs[v] = make_devcam(cams[v], kTile);
   for (int q = 0, v0 = 0; v0 < n_views; ++q, v0 += G) {
     const int g = std::min(G, n_views - v0);
     const int half = q & 1;
-    for (int i = 0; i < g; ++i) {
-      hipStream_t ls = ctx->lanes[i];
-      if (q >= 2) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ls, ctx->half_done[half], 0));
-      BatchWs b = batch_carve(base + (size_t)(half * G + i) * per, fixed, scene->n, dims->max_pairs);
+    hipStream_t ls = ctx->lanes[half];
+    if (q >= 2) NGS_TRY_HIP(ctx, hipStreamWaitEvent(ls, ctx->half_done[half], 0));
+    char* first = base + (size_t)(half * G) * per;
+    for (int s0 = 0; s0 < g; s0 += kMaxGroup) {
+      const int sg = std::min(kMaxGroup, g - s0);
+      BatchWs b = batch_carve(first + (size_t)s0 * per, fixed, scene->n, dims->max_pairs);
       b.proj.splat = nullptr;  // the render reads the planes, not the walk records
       const BinWs bw = bin_ws_carve(b.bin, scene->n, dims->max_pairs);
-      const Group G1 = single_group(make_devcam(cams[v0 + i], kTile));
-      NGS_TRY_HIP(ctx, launch_project(*scene, G1, *rp, b.proj, ls));
-      NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls));
-      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G1, bw, b.lists, sticky, nullptr, ls));
-      NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[i], ls));
-      NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[i], 0));
+      const Group Gs = make_group(&dcs[v0 + s0], sg, per);
+      NGS_TRY_HIP(ctx, launch_project(*scene, Gs, *rp, b.proj, ls));
+      NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls, sg, per));
+      NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, Gs, bw, b.lists, sticky, nullptr, ls));
     }
-    char* first = base + (size_t)(half * G) * per;
+    NGS_TRY_HIP(ctx, hipEventRecord(ctx->lane_done[half], ls));
+    NGS_TRY_HIP(ctx, hipStreamWaitEvent(st, ctx->lane_done[half], 0));
     const BatchWs b0 = batch_carve(first, fixed, scene->n, dims->max_pairs);
     const ngs_image img0 = feat_img_carve(first + fixed);
-    const DevCam dc0 = make_devcam(cams[v0], kTile);  // every view is 80 x 60: one tile grid
+    const DevCam dc0 = dcs[v0];  // every view is 80 x 60: one tile grid
     NGS_TRY_HIP(ctx, launch_render_views(ws_scene, b0.proj, b0.lists, dc0, rc, img0, g, per, st));
     NGS_TRY_HIP(ctx, sur_features(img0, NGS_SUR_IN_W, NGS_SUR_IN_H, scene->k, depth_scale, x, n_views, v0, g, per,
                                   st));

@@ -96,6 +96,19 @@ struct Group {
   int max_tiles_x = 0, max_tiles_y = 0, max_ntiles = 0, max_width = 0, max_height = 0;
 };
 
+// OR of a 32-bit value over the wavefront, by DPP moves (no LDS round trips): an inclusive OR
+// scan within each row of 16 lanes (shifts 1, 2, 4, 8), then the row totals broadcast into
+// the later rows (row_bcast 15 and 31); lane 63 ends with the OR of all 64 lanes.
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // This block's view of a per-view pointer.
 template <class T>
 __device__ __forceinline__ T* vp(T* p, size_t vs) {
@@ -168,8 +181,11 @@ const char* prof_name(int id);
 
 // Launchers implemented in the .hip files (stream-ordered, no synchronisation).
 hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st);
+// tight: the tile rects of the information walks (only tiles with a pixel centre in the
+// ellipse's box; the lists then hold exactly the entries a walk can take); else the rects of
+// the 3DGS pipeline (box of the 3-sigma circle of the largest eigenvalue).
 hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
-                          const ngs_projected& out, hipStream_t st);
+                          const ngs_projected& out, hipStream_t st, int tight = 0);
 // Adds the view's pair count (sum of p.count over n Gaussians) to *total (device).
 hipError_t launch_sum_counts(const ngs_projected& p, int n, int64_t* total, hipStream_t st);
 

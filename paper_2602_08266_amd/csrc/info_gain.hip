@@ -179,24 +179,30 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
   int last = -1, nc = 0;
   int wave_first = INT_MAX;
   bool done = !inside;
-  // batch entry of this lane: gid and its walk record, the next batch's in flight
-  uint32_t g_n = 0u;
-  float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = make_float4(0.f, 0.f, 0.f, -1.f);
-  auto load = [&](uint32_t b) {
+  // batch entry of this lane: gid and its walk record; the next two batches' are in flight
+  // (a batch's walk is often short, and a record is a dependent gather behind its gid)
+  uint32_t g1 = 0u, g2 = 0u;
+  float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = make_float4(0.f, 0.f, 0.f, -1.f);
+  float4 a2 = a1, b2 = b1;
+  auto load = [&](uint32_t b, uint32_t& g, float4& ra, float4& rb) {
     if (b < end && lane < (int)(end - b)) {
-      g_n = gids[b + lane];
-      na = splat[2 * (size_t)g_n];
-      nb = splat[2 * (size_t)g_n + 1];
+      g = gids[b + lane];
+      ra = splat[2 * (size_t)g];
+      rb = splat[2 * (size_t)g + 1];
     }
   };
-  load(start);
+  load(start, g1, a1, b1);
+  load(start + kWave, g2, a2, b2);
   for (uint32_t b0 = start; b0 < end; b0 += kWave) {
     if (__ballot(!done) == 0ull) break;
     const int cnt = (int)min((uint32_t)kWave, end - b0);
-    const uint32_t eg = g_n;
-    const float emx = na.x, emy = na.y, eqa = na.z, eqb = na.w, eqc = nb.x, eop = nb.y;
-    const float ehx = nb.z, ehy = nb.w;
-    load(b0 + kWave);
+    const uint32_t eg = g1;
+    const float emx = a1.x, emy = a1.y, eqa = a1.z, eqb = a1.w, eqc = b1.x, eop = b1.y;
+    const float ehx = b1.z, ehy = b1.w;
+    g1 = g2;
+    a1 = a2;
+    b1 = b2;
+    load(b0 + 2 * kWave, g2, a2, b2);
     uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
                              emy - ehy <= sy1);
     uint64_t mine = 0ull;  // batch entries that contribute to this lane's pixel
@@ -224,13 +230,7 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
       }
     }
     // entries that contribute to some pixel of the wavefront: OR over the lanes' masks
-    uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      lo |= (uint32_t)__shfl_xor((int)lo, off);
-      hi |= (uint32_t)__shfl_xor((int)hi, off);
-    }
-    const uint64_t any = ((uint64_t)hi << 32) | lo;
+    const uint64_t any = ((uint64_t)wave_or32((uint32_t)(mine >> 32)) << 32) | (uint64_t)wave_or32((uint32_t)mine);
     if (stats && any) {
       const uint32_t rel = b0 - start;  // a multiple of 64
       if (rel + kWave <= (uint32_t)kFBits) {

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
                                                  double z_near, double eps2d, double inv_tile, float* mean2d_,
                                                  float* conic_, float* depth_, uint32_t* zkey_, int16_t* rect_,
                                                  uint32_t* count_, const float* __restrict__ opacity, float cutoff_q,
-                                                 float4* splat_) {
+                                                 float4* splat_, int tight) {
   const int v = blockIdx.x % nv;
   const int g = (blockIdx.x / nv) * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -150,9 +150,33 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     valid = (x0 <= x1) && (y0 <= y1);
     mxf = (float)mx;
     myf = (float)my;
-    qa = (float)(c / det);
-    qb = (float)(-b / det);
-    qc = (float)(a / det);
+    // the conic only feeds FP32 outputs (not the key path): one reciprocal for its three entries
+    const double inv_det = 1.0 / det;
+    qa = (float)(c * inv_det);
+    qb = (float)(-b * inv_det);
+    qc = (float)(a * inv_det);
+  }
+  // walk record: half-extents of the ellipse q <= cutoff (no entry of a culled Gaussian is walked)
+  float hx = -1.f, hy = -1.f;
+  if (valid) conic_extent(qa, qb, qc, cutoff_q, &hx, &hy);
+  if (tight && valid) {
+    // Tile rect of the information walks: only the tiles with a pixel centre inside the
+    // ellipse's box (kTile, the only tile size the library accepts). A walk takes an entry for a strip of pixel centres [s0, s1] when
+    // mx + hx >= s0 and mx - hx <= s1 in FP32; a tile's centres span [16 t + 0.5, 16 t + 15.5],
+    // and those bounds and the FP32 box edges are exact in FP64, so the tiles below are exactly
+    // those where the walk can take the entry: the others would be passed over at every pixel.
+    // (a degenerate conic has infinite extents: its circle rect is kept)
+    if (hx < 1e30f) {
+      const double ex0 = (double)(mxf - hx), ex1 = (double)(mxf + hx);
+      x0 = max(x0, (int)ceil((ex0 - ((double)kTile - 0.5)) * inv_tile));
+      x1 = min(x1, (int)floor((ex1 - 0.5) * inv_tile));
+    }
+    if (hy < 1e30f) {
+      const double ey0 = (double)(myf - hy), ey1 = (double)(myf + hy);
+      y0 = max(y0, (int)ceil((ey0 - ((double)kTile - 0.5)) * inv_tile));
+      y1 = min(y1, (int)floor((ey1 - 0.5) * inv_tile));
+    }
+    valid = (x0 <= x1) && (y0 <= y1);
   }
   if (mean2d) {  // the walks of the scoring path read the splat records instead
     mean2d[g] = mxf;
@@ -169,9 +193,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   count[g] = valid ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
   if (splat) {
     // what a tile walk reads of an entry, in one 32-byte record: 2D mean, conic, opacity and
-    // the half-extents of the ellipse q <= cutoff (no entry of a culled Gaussian is walked)
-    float hx = -1.f, hy = -1.f;
-    if (valid) conic_extent(qa, qb, qc, cutoff_q, &hx, &hy);
+    // the ellipse's half-extents
     splat[2 * (size_t)g] = make_float4(mxf, myf, qa, qb);
     splat[2 * (size_t)g + 1] = make_float4(qc, valid ? opacity[g] : 0.f, hx, hy);
   }
@@ -190,7 +212,7 @@ hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hip
 }
 
 hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
-                          const ngs_projected& out, hipStream_t st) {
+                          const ngs_projected& out, hipStream_t st, int tight) {
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfProject, st);
@@ -198,7 +220,7 @@ hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_p
                      G.g,
                      G.vs, (double)rp.z_near, (double)rp.eps2d, 1.0 / (double)rp.tile, out.mean2d, out.conic,
                      out.depth, out.zkey, out.rect, out.count, s.opacity, rp.cutoff_q,
-                     reinterpret_cast<float4*>(out.splat));
+                     reinterpret_cast<float4*>(out.splat), tight);
   return hipGetLastError();
 }
 

@@ -27,10 +27,30 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* keys_, si
   h[threadIdx.x] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * kSortTileElems;
+  if (shift < 24) {
 #pragma unroll 4
-  for (int j = 0; j < kSortItems; ++j) {
-    const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    for (int j = 0; j < kSortItems; ++j) {
+      const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
+      if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+  } else {
+    // the top digit of depth keys takes a handful of values: lanes with equal digits are
+    // grouped by ballots and one of them adds the group's count (no same-address LDS atomics)
+    const int lane = threadIdx.x % kWave;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    for (int j = 0; j < kSortItems; ++j) {
+      const size_t i = base + (size_t)j * kSortThreads + threadIdx.x;
+      const bool valid = i < n;
+      const uint32_t d = valid ? (keys[i] >> shift) & (kRadix - 1) : 0u;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      if (valid && (peers & lt_mask) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
   hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
