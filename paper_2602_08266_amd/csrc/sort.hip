@@ -56,21 +56,36 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* keys_, si
   hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Block-wide exclusive scan of one value per thread (256 threads); returns the total.
+// Inclusive sum over the wavefront's lanes 0..l, by DPP moves: a scan within each row of 16
+// lanes (shifts 1, 2, 4, 8), then the row totals carried into the later rows (row_bcast 15
+// and 31).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns the total. Each
+// wavefront scans its 64 values, then the earlier wavefronts' totals are added.
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sm, uint32_t* total) {
-  const int t = threadIdx.x;
-  sm[t] = v;
+  const int t = threadIdx.x, wave = t / kWave;
+  const uint32_t incl = wave_inclusive_scan(v);
+  if (t % kWave == kWave - 1) sm[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < kSortThreads; off <<= 1) {
-    const uint32_t add = (t >= off) ? sm[t - off] : 0u;
-    __syncthreads();
-    sm[t] += add;
-    __syncthreads();
+  uint32_t before = 0u, all = 0u;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) {
+    const uint32_t s = sm[w];
+    before += w < wave ? s : 0u;
+    all += s;
   }
-  const uint32_t incl = sm[t];
-  *total = sm[kSortThreads - 1];
-  __syncthreads();
-  return incl - v;
+  *total = all;
+  __syncthreads();  // sm is reused by the next scan
+  return before + incl - v;
 }
 
 // One block per digit: exclusive scan of that digit's counts across blocks, in place;
