@@ -72,6 +72,30 @@ __device__ __forceinline__ void conic_extent(float qa, float qb, float qc, float
   *hy = sqrtf(cut * qa / det) * 1.01f + 0.05f;
 }
 
+// Whether the ellipse q <= cut of a conic centred at (mx, my) can reach a pixel centre of the
+// strip [sx0, sx1] x [sy0, sy1] (pixel-centre bounds): the least q over the rectangle (0 when it
+// holds the centre; else on an edge, where q is a 1D quadratic minimised at a clamped point)
+// against the cut-off. The slack (1e-5 of the largest magnitude the three terms of q take on
+// the rectangle, plus 0.1 % of the cut-off) exceeds the FP32 rounding of q here and at any
+// pixel centre, so a pixel whose own q <= cut is never dropped. A degenerate conic always
+// reaches. The walks use it on top of the box test: an entry it rejects would be passed over at
+// every pixel of the strip.
+__device__ __forceinline__ bool ellipse_meets(float mx, float my, float qa, float qb, float qc, float sx0, float sx1,
+                                              float sy0, float sy1, float cut) {
+  const float dx0 = sx0 - mx, dx1 = sx1 - mx, dy0 = sy0 - my, dy1 = sy1 - my;
+  if (dx0 <= 0.f && dx1 >= 0.f && dy0 <= 0.f && dy1 >= 0.f) return true;
+  if (!(qa > 0.f) || !(qc > 0.f)) return true;
+  const float ia = __builtin_amdgcn_rcpf(qa), ic = __builtin_amdgcn_rcpf(qc);
+  const auto q = [&](float x, float y) { return qa * x * x + 2.f * qb * x * y + qc * y * y; };
+  float m = q(dx0, fminf(fmaxf(-qb * dx0 * ic, dy0), dy1));
+  m = fminf(m, q(dx1, fminf(fmaxf(-qb * dx1 * ic, dy0), dy1)));
+  m = fminf(m, q(fminf(fmaxf(-qb * dy0 * ia, dx0), dx1), dy0));
+  m = fminf(m, q(fminf(fmaxf(-qb * dy1 * ia, dx0), dx1), dy1));
+  const float ax = fmaxf(fabsf(dx0), fabsf(dx1)), ay = fmaxf(fabsf(dy0), fabsf(dy1));
+  const float mag = qa * ax * ax + 2.f * fabsf(qb) * ax * ay + qc * ay * ay;
+  return m <= cut * 1.001f + 1e-5f * mag;
+}
+
 struct DevCam {
   float R[9], t[3], fx, fy, cx, cy;
   int width, height, tiles_x, tiles_y;

@@ -124,9 +124,10 @@ struct IgShared {
 
 // Whether batch entry l's ellipse can reach the wavefront's strip (entries past cnt: no).
 template <class Sh>
-__device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, float sx1, float sy0, float sy1) {
+__device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, float sx1, float sy0, float sy1,
+                                        float cut) {
   return l < cnt && S.mx[l] + S.hx[l] >= sx0 && S.mx[l] - S.hx[l] <= sx1 && S.my[l] + S.hy[l] >= sy0 &&
-         S.my[l] - S.hy[l] <= sy1;
+         S.my[l] - S.hy[l] <= sy1 && ellipse_meets(S.mx[l], S.my[l], S.qa[l], S.qb[l], S.qc[l], sx0, sx1, sy0, sy1, cut);
 }
 
 // Pass 1 of one tile: 256 lanes, one per pixel, four wavefronts of 16 x 4 strips, each walking
@@ -204,7 +205,8 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
     b1 = b2;
     load(b0 + 2 * kWave, g2, a2, b2);
     uint64_t live = __ballot(lane < cnt && emx + ehx >= sx0 && emx - ehx <= sx1 && emy + ehy >= sy0 &&
-                             emy - ehy <= sy1);
+                             emy - ehy <= sy1 &&
+                             ellipse_meets(emx, emy, eqa, eqb, eqc, sx0, sx1, sy0, sy1, rc.cutoff_q));
     uint64_t mine = 0ull;  // batch entries that contribute to this lane's pixel
     if (!done) {
       while (live) {
@@ -382,7 +384,8 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
     }
     __syncthreads();
     uint64_t live =
-        __ballot(lo + lane <= wave_last && lo + lane >= wave_first && reaches(S, lane, cnt, sx0, sx1, sy0, sy1));
+        __ballot(lo + lane <= wave_last && lo + lane >= wave_first &&
+                 reaches(S, lane, cnt, sx0, sx1, sy0, sy1, rc.cutoff_q));
     while (live) {
       const int j = 63 - __clzll((long long)live);
       live &= ~(1ull << j);
