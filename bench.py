@@ -476,7 +476,7 @@ def run_exact(args, log):
     tune = None
     if not args.no_autotune:
         # launch shapes from the package's tuning cache for this device and workload, else
-        # (or with --retune) timed now on 32 of the candidates
+        # (or with --retune) timed now on 64 of the candidates
         from paper_2602_08266_amd import autotune
         if args.retune and os.path.exists(args.retune):
             os.remove(args.retune)
