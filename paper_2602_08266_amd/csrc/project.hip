@@ -41,36 +41,44 @@ __global__ __launch_bounds__(256) void k_prepare(int n, int k, const float* __re
                                                  float* __restrict__ conf, int32_t* __restrict__ label,
                                                  const float* __restrict__ log_scale, const float* __restrict__ rot,
                                                  double* __restrict__ cov3) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  float mx = logit[g];
-  int am = 0;
-  for (int c = 1; c < k; ++c) {
-    const float v = logit[(size_t)c * n + g];
-    if (v > mx) { mx = v; am = c; }
+  // the block's probability rows are staged in LDS (row stride k + 1 against bank conflicts)
+  // and written out as one contiguous, coalesced run
+  extern __shared__ float pst[];
+  const int g0 = blockIdx.x * blockDim.x;
+  const int g = g0 + threadIdx.x;
+  const int nb = min((int)blockDim.x, n - g0);
+  if (g < n) {
+    float mx = logit[g];
+    int am = 0;
+    for (int c = 1; c < k; ++c) {
+      const float v = logit[(size_t)c * n + g];
+      if (v > mx) { mx = v; am = c; }
+    }
+    float z = 0.f;
+    for (int c = 0; c < k; ++c) z += expf(logit[(size_t)c * n + g] - mx);
+    const float inv = 1.f / z;
+    for (int c = 0; c < k; ++c) pst[threadIdx.x * (k + 1) + c] = expf(logit[(size_t)c * n + g] - mx) * inv;
+    const float sig = 1.f / (1.f + expf(-op_logit[g]));
+    const float kap = inv;  // exp(0) / z at the argmax
+    opacity[g] = sig;
+    kappa[g] = kap;
+    label[g] = am;
+    float c;
+    if (target < 0) {
+      c = powf(kap, -alpha_obj) * powf(sig, -alpha_opa);
+    } else {
+      c = (am == target) ? powf(expf(logit[(size_t)target * n + g] - mx) * inv, -alpha_obj) * powf(sig, -alpha_opa)
+                         : 0.f;
+    }
+    conf[g] = c;
+    if (cov3) {
+      double S3[9];
+      cov3_of(n, g, log_scale, rot, S3);
+      for (int i = 0; i < 9; ++i) cov3[(size_t)i * n + g] = S3[i];
+    }
   }
-  float z = 0.f;
-  for (int c = 0; c < k; ++c) z += expf(logit[(size_t)c * n + g] - mx);
-  const float inv = 1.f / z;
-  for (int c = 0; c < k; ++c) prob[(size_t)g * k + c] = expf(logit[(size_t)c * n + g] - mx) * inv;
-  const float sig = 1.f / (1.f + expf(-op_logit[g]));
-  const float kap = inv;  // exp(0) / z at the argmax
-  opacity[g] = sig;
-  kappa[g] = kap;
-  label[g] = am;
-  float c;
-  if (target < 0) {
-    c = powf(kap, -alpha_obj) * powf(sig, -alpha_opa);
-  } else {
-    c = (am == target) ? powf(expf(logit[(size_t)target * n + g] - mx) * inv, -alpha_obj) * powf(sig, -alpha_opa)
-                       : 0.f;
-  }
-  conf[g] = c;
-  if (cov3) {
-    double S3[9];
-    cov3_of(n, g, log_scale, rot, S3);
-    for (int i = 0; i < 9; ++i) cov3[(size_t)i * n + g] = S3[i];
-  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb * k; i += blockDim.x) prob[(size_t)g0 * k + i] = pst[(i / k) * (k + 1) + i % k];
 }
 
 // floor(v / tile) clamped to [-1, lim]. The tile size is a power of two (16), so v * (1 / tile)
@@ -205,7 +213,8 @@ hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hip
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfPrepare, st);
-  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, st, s.n, s.k, s.obj_logit, s.opacity_logit,
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), (size_t)256 * (s.k + 1) * sizeof(float), st, s.n, s.k,
+                     s.obj_logit, s.opacity_logit,
                      ig.alpha_obj, ig.alpha_opa, ig.target_id, s.prob, s.opacity, s.kappa, s.conf, s.label,
                      s.log_scale, s.rot, s.cov3);
   return hipGetLastError();
