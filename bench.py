@@ -438,6 +438,14 @@ def serialized_roofline(B, ctx, scorer, cams, scene, K_views, log):
                      "frac": hbm["frac"], "algorithmic_bytes_per_launch": hbm["algorithmic_bytes_per_launch"]})
     else:
         roof.update({"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None})
+    # where the back-to-front walk's wavefronts spend their time (shader-clock cycles summed
+    # over them): the workgroup barrier before each batch, staging the batch, walking it, and
+    # the records of weighted contributors (a part of the walking)
+    cyc = st[10] + st[11] + st[12]
+    if cyc > 0:
+        roof["back_walk_wave_cycles"] = {
+            "per_view": round(cyc / V), "barrier": round(st[10] / cyc, 4), "staging": round(st[11] / cyc, 4),
+            "walking": round(st[12] / cyc, 4), "records_within_walking": round(st[13] / cyc, 4)}
     bd = {kk: round(v[0] / V * 1e3, 2) for kk, v in sorted(breakdown.items(), key=lambda x: -x[1][0])}
     log(f"serialized pass: dominant {dom} {avg_s * 1e6:.1f} us per launch; per-view us {bd}")
     return roof, counts, bd

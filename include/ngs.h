@@ -199,8 +199,12 @@ typedef struct {
  * [8] per-pixel records of weighted contributing pairs (each enters the 94 + 6k products of
  *     the Gaussian's statistics),
  * [9] contributing (tile, Gaussian) pairs F (a Gaussian composited at some pixel of the tile),
- *     over the tiles the information walk visits. */
-#define NGS_STATS_LEN 10
+ *     over the tiles the information walk visits,
+ * [10]-[13] shader-clock cycles (s_memtime) of the back-to-front walk's wavefronts, summed
+ *     over them: waiting at the per-batch workgroup barrier, staging a batch of entries into
+ *     LDS, walking it, and (a part of the walking) forming and reducing the records of
+ *     weighted contributors. A profile of where the walk spends its time, not a count. */
+#define NGS_STATS_LEN 14
 
 /* Workspace sizing. op: 0 = ngs_bin_sort, 1 = ngs_info_gain, 2 = ngs_score_batch (and
  * ngs_training_setup, ngs_score_graph_create), 3 = ngs_render_backward,

@@ -21,7 +21,7 @@ NGS_OK, NGS_INVALID_ARG, NGS_CAPACITY, NGS_WORKSPACE_TOO_SMALL = 0, -1, -2, -3
 NGS_HIP_ERROR, NGS_DEGENERATE, NGS_UNSUPPORTED = -4, -5, -6
 MODE_SCORE, MODE_ACCUMULATE = 0, 1
 OUT_RGB, OUT_DEPTH, OUT_OBJ = 1, 2, 4
-STATS_LEN = 10
+STATS_LEN = 14
 EXPORTS = ["ngs_create", "ngs_destroy", "ngs_status_string", "ngs_version", "ngs_last_hip_error",
            "ngs_workspace_size", "ngs_prepare_scene", "ngs_project", "ngs_count_pairs", "ngs_bin_sort", "ngs_render",
            "ngs_info_gain", "ngs_info_gain_static", "ngs_hessian_reset", "ngs_hessian_finalize", "ngs_training_setup", "ngs_score_batch",

@@ -364,10 +364,16 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
   if (obj_eq2 && h == 0) So[0] = t_final;  // S~ = S_o + T_final e_0
   // counts for the statistics: contributing (pixel, entry) pairs of this pass and records
   uint32_t n_pass2 = 0u, n_rec = 0u;
+  // with statistics: shader-clock cycles of this wavefront waiting at the batch barrier, staging
+  // batches, walking them, and (part of the walk) reducing records
+  const bool timed = stats != nullptr;
+  uint64_t c_bar = 0u, c_load = 0u, c_walk = 0u, c_rec = 0u;
   for (int hi = tile_last + 1; hi > first_w; hi -= kBatch) {
     const int lo = max(first_w, hi - kBatch);
     const int cnt = hi - lo;
+    const uint64_t t_a = timed ? __builtin_amdgcn_s_memtime() : 0u;
     __syncthreads();
+    const uint64_t t_b = timed ? __builtin_amdgcn_s_memtime() : 0u;
     if ((int)threadIdx.x < cnt) {
       const int j = threadIdx.x;
       const uint32_t g = gids[lo + j];
@@ -383,6 +389,9 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
       S.p[j][c] = (c < k) ? prob[(size_t)gids[lo + j] * k + c] : 0.f;
     }
     __syncthreads();
+    const uint64_t t_c = timed ? __builtin_amdgcn_s_memtime() : 0u;
+    c_bar += t_b - t_a;
+    c_load += t_c - t_b;
     uint64_t live =
         __ballot(lo + lane <= wave_last && lo + lane >= wave_first &&
                  reaches(S, lane, cnt, sx0, sx1, sy0, sy1, rc.cutoff_q));
@@ -411,6 +420,7 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
       const int slot = S.slot[j];
       const uint64_t cmask = __ballot(contrib);
       if (slot >= 0 && cmask) {
+        const uint64_t t_r = timed ? __builtin_amdgcn_s_memtime() : 0u;
         // record of this lane's pixel (all zero when it does not contribute)
         float rv[kRec];
         {
@@ -504,6 +514,7 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
           for (int i = 0; i < 6; ++i)
             if (z[i] != 0.f) atomicAdd(dst + kStatScalar + i * k + zc, z[i]);
         }
+        if (timed) c_rec += __builtin_amdgcn_s_memtime() - t_r;
       }
       if (contrib) {
         n_pass2 += h == 0 ? 1u : 0u;
@@ -514,6 +525,7 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
         Tc = Tg;
       }
     }
+    if (timed) c_walk += __builtin_amdgcn_s_memtime() - t_c;
   }
   if (stats) {
     uint32_t tot = n_pass2;
@@ -521,6 +533,10 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
     if (lane == 0) {
       if (tot) atomicAdd((unsigned long long*)&stats[7], (unsigned long long)tot);
       if (n_rec) atomicAdd((unsigned long long*)&stats[8], (unsigned long long)n_rec);
+      atomicAdd((unsigned long long*)&stats[10], (unsigned long long)c_bar);
+      atomicAdd((unsigned long long*)&stats[11], (unsigned long long)c_load);
+      atomicAdd((unsigned long long*)&stats[12], (unsigned long long)c_walk);
+      atomicAdd((unsigned long long*)&stats[13], (unsigned long long)c_rec);
     }
   }
 }
