@@ -89,19 +89,28 @@ struct RectL {
   float inv_w;
 };
 
-__device__ __forceinline__ RectL part_lane_load(int n, int r, const uint32_t* __restrict__ order,
-                                                const int16_t* __restrict__ rect_sorted) {
-  RectL l{0u, 0u, 1, 0, 1.f};
+// What a lane loads for depth rank r (past n: an empty rect), and the rect it describes.
+struct RectRaw {
+  uint32_t gid;
+  short4 b;
+};
+__device__ __forceinline__ RectRaw part_lane_raw(int n, int r, const uint32_t* __restrict__ order,
+                                                 const int16_t* __restrict__ rect_sorted) {
+  RectRaw q{0u, make_short4(0, 0, -1, -1)};
   if (r < n) {
-    const uint32_t g = order[r];
-    const short4 b = reinterpret_cast<const short4*>(rect_sorted)[r];
-    l.gid = g;
-    l.org = (uint32_t)(uint16_t)b.x | ((uint32_t)(uint16_t)b.y << 16);
-    l.w = b.z - b.x + 1;
-    l.area = b.z >= b.x ? l.w * (b.w - b.y + 1) : 0;
-    l.w = l.area > 0 ? l.w : 1;
-    l.inv_w = 1.f / (float)l.w;
+    q.gid = order[r];
+    q.b = reinterpret_cast<const short4*>(rect_sorted)[r];
   }
+  return q;
+}
+__device__ __forceinline__ RectL part_lane_rect(const RectRaw& q) {
+  RectL l;
+  l.gid = q.gid;
+  l.org = (uint32_t)(uint16_t)q.b.x | ((uint32_t)(uint16_t)q.b.y << 16);
+  l.w = q.b.z - q.b.x + 1;
+  l.area = q.b.z >= q.b.x ? l.w * (q.b.w - q.b.y + 1) : 0;
+  l.w = l.area > 0 ? l.w : 1;
+  l.inv_w = 1.f / (float)l.w;
   return l;
 }
 
@@ -262,8 +271,19 @@ __global__ __launch_bounds__(kWave) void k_row_hist(int n, const uint32_t* order
   if (rkm) load_row_masks(rk_sh, rkm, rows);
   __syncthreads();
   const int r0 = chunk * kPartRanks;
-  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
-    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
+  // all of the block's entries are loaded before the first is used (one wait for them all;
+  // in the scatter a wait for loads issued after stores would also wait for the stores)
+  constexpr int kSub = kPartRanks / kWave;
+  RectRaw raw[kSub];
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) raw[q] = part_lane_raw(n, r0 + q * kWave + lane, order, rect);
+  // one sub-batch at a time from raw[0], the rest moving down (static register indices)
+#pragma unroll 1
+  for (int q = 0; q < kSub; ++q) {
+    if (r0 + q * kWave >= n) break;
+    const RectL l = part_lane_rect(raw[0]);
+#pragma unroll
+    for (int t = 0; t + 1 < kSub; ++t) raw[t] = raw[t + 1];
     const int y0 = (int)(l.org >> 16), h = l.area / l.w, x0 = (int)(l.org & 0xFFFFu);
     if (rkm) {
       const uint64_t m0 = span_bits(x0, l.w, 0), m1 = span_bits(x0, l.w, 1);
@@ -443,8 +463,19 @@ __global__ __launch_bounds__(kWave) void k_row_scatter(int n, const uint32_t* or
   __shared__ unsigned long long rk_sh[2 * 2 * kWave];
   if (NR > 0 && rkm) load_row_masks(rk_sh, rkm, rows);
   const int r0 = chunk * kPartRanks;
-  for (int sub = 0; sub < kPartRanks && r0 + sub < n; sub += kWave) {
-    const RectL l = part_lane_load(n, r0 + sub + lane, order, rect);
+  // all of the block's entries are loaded before the first is used (one wait for them all;
+  // in the scatter a wait for loads issued after stores would also wait for the stores)
+  constexpr int kSub = kPartRanks / kWave;
+  RectRaw raw[kSub];
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) raw[q] = part_lane_raw(n, r0 + q * kWave + lane, order, rect);
+  // one sub-batch at a time from raw[0], the rest moving down (static register indices)
+#pragma unroll 1
+  for (int q = 0; q < kSub; ++q) {
+    if (r0 + q * kWave >= n) break;
+    const RectL l = part_lane_rect(raw[0]);
+#pragma unroll
+    for (int t = 0; t + 1 < kSub; ++t) raw[t] = raw[t + 1];
     const int y0 = (int)(l.org >> 16), h = l.area / l.w, x0 = (int)(l.org & 0xFFFFu);
     const uint2 e = make_uint2(l.gid, (uint32_t)x0 | ((uint32_t)l.w << 16));
     auto emit = [&](int, uint32_t pos) { rl[pos] = e; };
@@ -634,13 +665,35 @@ __global__ __launch_bounds__(kWave * kWaves2) void k_tile2_scatter(const uint2* 
       for (int t = lane; t < tiles_x; t += kWave) cnt[t] = ranges[tbase + t] + h[(size_t)t * nc + c.idx];
       wave_sync();
     }
-    // the next 64 entries are loaded while the current ones are placed
-    uint2 e_next = make_uint2(0u, 0u);  // w = 0 past the chunk: covers nothing
-    if (c.begin + lane < c.end) e_next = rl[c.begin + lane];
-    for (uint32_t i0 = c.begin; i0 < c.end; i0 += kWave) {
-      const uint2 e = e_next;
-      e_next = make_uint2(0u, 0u);
-      if (i0 + kWave + lane < c.end) e_next = rl[i0 + kWave + lane];
+    // Entries go in groups of kGrp batches of 64, the next group's loaded while the current one
+    // is placed: a wait for loads (which also waits for the stores before it) comes once per
+    // group, not once per batch. Entries past the chunk have w = 0 and cover nothing.
+    constexpr int kGrp = 8;
+    uint2 cur[kGrp], nxt[kGrp];
+#pragma unroll
+    for (int q = 0; q < kGrp; ++q) {
+      const uint32_t i = c.begin + (uint32_t)(q * kWave + lane);
+      cur[q] = i < c.end ? rl[i] : make_uint2(0u, 0u);
+    }
+    for (uint32_t g0 = c.begin; g0 < c.end; g0 += kWave * kGrp) {
+      // every entry of the group in registers before the next group's loads are issued (the
+      // empty asm consumes them, and its memory clobber keeps those loads behind it)
+      uint32_t any = 0u;
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) any |= cur[q].x | cur[q].y;
+      asm volatile("" ::"v"(any) : "memory");
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const uint32_t i = g0 + (uint32_t)((kGrp + q) * kWave + lane);
+        nxt[q] = i < c.end ? rl[i] : make_uint2(0u, 0u);
+      }
+      // one batch at a time from cur[0], the rest moving down (static register indices)
+#pragma unroll 1
+      for (int q = 0; q < kGrp; ++q) {
+      if (g0 + (uint32_t)(q * kWave) >= c.end) break;
+      const uint2 e = cur[0];
+#pragma unroll
+      for (int t = 0; t + 1 < kGrp; ++t) cur[t] = cur[t + 1];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
       auto emit = [&](int, uint32_t pos) {
         if (pos < cap32) gids_out[pos] = e.x;
@@ -656,6 +709,9 @@ __global__ __launch_bounds__(kWave * kWaves2) void k_tile2_scatter(const uint2* 
         const auto covers = [&](int t) { return w > 0 && x0 <= t && t < x0 + w; };
         place_batch(cnt, lo, hi, lane, emit, kept, covers);
       }
+      }
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) cur[q] = nxt[q];
     }
   }
 }
