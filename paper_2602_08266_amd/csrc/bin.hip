@@ -566,10 +566,20 @@ __global__ __launch_bounds__(kWave * kWaves2) void k_tile2_hist(const uint2* rl_
     const Chunk2 c = chunk2_of(ci, rows, cpl, rstart, rtot, K2);
     for (int t = lane; t < tiles_x; t += kWave) cnt[t] = 0u;
     wave_sync();
-    for (uint32_t i = c.begin + lane; i < c.end; i += kWave) {
-      const uint32_t xw = rl[i].y;
-      const int x0 = (int)(xw & 0xFFFFu), w = (int)(xw >> 16);
-      for (int j = 0; j < w; ++j) atomicAdd(&cnt[x0 + j], 1u);
+    // spans in groups of kGrp batches of 64, all loaded before any is counted (one wait per group)
+    constexpr int kGrp = 8;
+    for (uint32_t g0 = c.begin; g0 < c.end; g0 += kWave * kGrp) {
+      uint32_t xw[kGrp];
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const uint32_t i = g0 + (uint32_t)(q * kWave + lane);
+        xw[q] = i < c.end ? rl[i].y : 0u;  // w = 0 past the chunk
+      }
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const int x0 = (int)(xw[q] & 0xFFFFu), w = (int)(xw[q] >> 16);
+        for (int j = 0; j < w; ++j) atomicAdd(&cnt[x0 + j], 1u);
+      }
     }
     wave_sync();
     uint32_t* dst = hist2 + (size_t)tiles_x * cp[c.row];

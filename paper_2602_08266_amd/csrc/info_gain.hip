@@ -568,14 +568,17 @@ __global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict_
   const int tiles_x = gd.tx[blockIdx.y], tiles_y = gd.ty[blockIdx.y];
   const int lane = threadIdx.x % kWave;
   const int g = blockIdx.x * 256 + threadIdx.x;
-  uint64_t m = __ballot(g < n && count[g] > 0u && conf[g] > 0.f);
-  const int gw = g - lane;
+  const bool weighted = g < n && count[g] > 0u && conf[g] > 0.f;
+  // each lane's rect is loaded up front (the loop below only stores: no load waits behind them)
+  int2 rr = make_int2(0, -1);
+  if (weighted) rr = reinterpret_cast<const int2*>(rect)[g];
+  uint64_t m = __ballot(weighted);
   while (m) {
     const int j = __ffsll((unsigned long long)m) - 1;
     m &= m - 1;
-    const short4 r = *reinterpret_cast<const short4*>(rect + 4 * (size_t)(gw + j));
-    const int x0 = max((int)r.x, 0), y0 = max((int)r.y, 0);
-    const int x1 = min((int)r.z, tiles_x - 1), y1 = min((int)r.w, tiles_y - 1);
+    const int r01 = __builtin_amdgcn_readlane(rr.x, j), r23 = __builtin_amdgcn_readlane(rr.y, j);
+    const int x0 = max((int)(int16_t)(r01 & 0xFFFF), 0), y0 = max(r01 >> 16, 0);
+    const int x1 = min((int)(int16_t)(r23 & 0xFFFF), tiles_x - 1), y1 = min(r23 >> 16, tiles_y - 1);
     if (x1 < x0 || y1 < y0) continue;
     const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
     for (int t = lane; t < area; t += kWave) tflag[(y0 + t / w) * tiles_x + x0 + t % w] = 1;
