@@ -199,13 +199,27 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* kin_, 
     }
   }
   __syncthreads();
-  for (int i = t; i < cnt; i += kSortThreads) {
-    const uint32_t key = sk[i];
-    const uint32_t d = (key >> shift) & (kRadix - 1);
-    const uint32_t pos = gbase[d] + ((uint32_t)i - lstart[d]);
-    kout[pos] = key;
-    vout[pos] = sv[i];
-    if (rout) rout[pos] = rin[sv[i]];  // an 8-byte record of the value's, carried into sorted order
+  // every gathered record is loaded before anything is stored (a wait for loads issued after
+  // stores would also wait for the stores)
+  uint32_t ok[kSortItems], ov[kSortItems];
+  uint2 orr[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int i = t + j * kSortThreads;
+    ok[j] = i < cnt ? sk[i] : 0u;
+    ov[j] = i < cnt ? sv[i] : 0u;
+    if (rout && i < cnt) orr[j] = rin[ov[j]];  // an 8-byte record of the value's, carried into sorted order
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int i = t + j * kSortThreads;
+    if (i < cnt) {
+      const uint32_t d = (ok[j] >> shift) & (kRadix - 1);
+      const uint32_t pos = gbase[d] + ((uint32_t)i - lstart[d]);
+      kout[pos] = ok[j];
+      vout[pos] = ov[j];
+      if (rout) rout[pos] = orr[j];
+    }
   }
 }
 
