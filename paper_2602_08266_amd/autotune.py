@@ -133,8 +133,14 @@ def tune_score(ctx: B.Context, scorer: B.NbvScorer, cams: Sequence[B.ngs_camera]
             best_chunk = chunk
     # then the number of view groups in flight (with more buffer sets for more groups)
     best_groups = 0
+    # shapes whose buffer sets would take more than 40 % of the device are not tried (a
+    # whole-scene workload keeps a statistic row per Gaussian in every set)
+    budget = 0.4 * torch.cuda.get_device_properties(torch.cuda.current_device()).total_memory
     for v, groups in [(best[1], gr) for gr in GROUPS] + list(GROUP_SHAPES):
         if groups > v:
+            continue
+        if B.workspace_size(2, scorer.scene.n, scorer.scene.k, max_pairs=scorer.max_pairs,
+                            max_slots=scorer.max_slots, views_in_flight=v) > budget:
             continue
         scorer.views_in_flight = v
         scorer.ws = None

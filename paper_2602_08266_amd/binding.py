@@ -323,7 +323,13 @@ def workspace_size(op: int, n: int, k: int, width: int = 0, height: int = 0, max
 
 
 def _bytes(nbytes: int, device: str = "cuda") -> torch.Tensor:
-    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    try:
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    except torch.OutOfMemoryError:
+        # blocks cached by torch's allocator from earlier (freed) workspaces of other sizes
+        # can leave no contiguous range free: hand them back to the device and try once more
+        torch.cuda.empty_cache()
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
 # ------------------------------------------------------------------------------------------

@@ -576,11 +576,12 @@ ngs_status enqueue_score_batch(ngs_ctx* ctx, const ngs_scene* scene, ngs_hessian
     const BatchWs& b = sets[i];
     const BinWs bw = bin_ws_carve(b.bin, scene->n, max_pairs);
     const Group G = make_group(&dcs[v0], g, per);
-    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, walk_only(b.proj), ls, 1));
+    // with a target object the projection also flags the tiles that a weighted Gaussian
+    // reaches: only their lists are written, the only ones the information walk reads
+    NGS_TRY_HIP(ctx, launch_ig_clear(*ig, igs[i], G, ls));
+    NGS_TRY_HIP(ctx, launch_project(*scene, G, *rp, walk_only(b.proj), ls, 1,
+                                    const_cast<int32_t*>(ig_tile_flags(*ig, igs[i]))));
     NGS_TRY_HIP(ctx, bin_count_pairs(b.proj, scene->n, bw, ls, g, per));
-    // slots first: with a target object only the lists of tiles that a weighted Gaussian
-    // reaches are written, the only ones the information walk reads
-    NGS_TRY_HIP(ctx, launch_ig_assign(*scene, b.proj, G, *ig, igs[i], ls));
     NGS_TRY_HIP(ctx, bin_emit_and_sort(b.proj, scene->n, G, bw, b.lists, sticky, stats, ls, ig_tile_flags(*ig, igs[i]),
                                        ctx->tuning.bin_chunk));
     NGS_TRY_HIP(ctx, launch_ig_walk(*scene, b.proj, b.lists, G, make_raster(*rp), *ig, igs[i], stats,

@@ -207,9 +207,11 @@ const char* prof_name(int id);
 hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hipStream_t st);
 // tight: the tile rects of the information walks (only tiles with a pixel centre in the
 // ellipse's box; the lists then hold exactly the entries a walk can take); else the rects of
-// the 3DGS pipeline (box of the 3-sigma circle of the largest eigenvalue).
+// the 3DGS pipeline (box of the 3-sigma circle of the largest eigenvalue). tflag (per view at
+// the group's stride, cleared beforehand): also flag the tiles that the rects of weighted
+// Gaussians reach (what launch_ig_assign does after a projection without it).
 hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
-                          const ngs_projected& out, hipStream_t st, int tight = 0);
+                          const ngs_projected& out, hipStream_t st, int tight = 0, int32_t* tflag = nullptr);
 // Adds the view's pair count (sum of p.count over n Gaussians) to *total (device).
 hipError_t launch_sum_counts(const ngs_projected& p, int n, int64_t* total, hipStream_t st);
 
@@ -305,6 +307,9 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
 hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st, int g = 1, size_t vs = 0);
 hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Group& G, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st);
+// The first half of launch_ig_assign alone (slot counter, overflow flag and tile flags
+// cleared), for a projection that flags the tiles itself.
+hipError_t launch_ig_clear(const ngs_ig_params& ig, const IgWs& w, const Group& G, hipStream_t st);
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
                           const RasterConst& rc, const ngs_ig_params& ig, const IgWs& w, int64_t* stats, int lpp,
                           hipStream_t st, int waves = 0);

@@ -716,13 +716,18 @@ const int32_t* ig_tile_flags(const ngs_ig_params& ig, const IgWs& w) {
   return ig.target_id >= 0 ? w.tflag : nullptr;
 }
 
+hipError_t launch_ig_clear(const ngs_ig_params& ig, const IgWs& w, const Group& G, hipStream_t st) {
+  int32_t* tflag = const_cast<int32_t*>(ig_tile_flags(ig, w));
+  ProfScope ps(kProfFill, st);
+  hipLaunchKernelGGL(k_ig_clear, dim3(1, G.g), dim3(256), 0, st, w.n_slots, w.overflow, tflag, G.dims, G.vs);
+  return hipGetLastError();
+}
+
 hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Group& G, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st) {
   int32_t* tflag = const_cast<int32_t*>(ig_tile_flags(ig, w));
-  {
-    ProfScope ps(kProfFill, st);
-    hipLaunchKernelGGL(k_ig_clear, dim3(1, G.g), dim3(256), 0, st, w.n_slots, w.overflow, tflag, G.dims, G.vs);
-  }
+  hipError_t e = launch_ig_clear(ig, w, G, st);
+  if (e != hipSuccess) return e;
   if (tflag && s.n > 0) {
     ProfScope ps(kProfIgAssign, st);
     hipLaunchKernelGGL(k_ig_mark, dim3((s.n + 255) / 256, G.g), dim3(256), 0, st, s.n, s.conf, p.count, p.rect, tflag,

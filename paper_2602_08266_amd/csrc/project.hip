@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
                                                  double z_near, double eps2d, double inv_tile, float* mean2d_,
                                                  float* conic_, float* depth_, uint32_t* zkey_, int16_t* rect_,
                                                  uint32_t* count_, const float* __restrict__ opacity, float cutoff_q,
-                                                 float4* splat_, int tight) {
+                                                 float4* splat_, int tight, const float* __restrict__ conf,
+                                                 int32_t* tflag_) {
   const int v = blockIdx.x % nv;
   const int g = (blockIdx.x / nv) * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -205,6 +206,28 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     splat[2 * (size_t)g] = make_float4(mxf, myf, qa, qb);
     splat[2 * (size_t)g + 1] = make_float4(qc, valid ? opacity[g] : 0.f, hx, hy);
   }
+  if (tflag_) {
+    // With a target object: flag the tiles that the rect of a weighted Gaussian (nonzero
+    // confidence, reaching a tile) covers, so that the binning and both walks can leave the
+    // other tiles at once. The wavefront's live lanes mark one weighted Gaussian's rect at a
+    // time (lanes past n have left).
+    const uint64_t m0 = __ballot(valid && conf && conf[g] > 0.f);
+    if (m0) {
+      int32_t* __restrict__ tflag = (int32_t*)((char*)tflag_ + off);
+      const int lane = (int)__lane_id();
+      const uint64_t act = __ballot(true);
+      const int rank = (int)__popcll(act & ((1ull << lane) - 1ull)), na = (int)__popcll(act);
+      uint64_t m = m0;
+      while (m) {
+        const int j = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int X0 = __builtin_amdgcn_readlane(x0, j), Y0 = __builtin_amdgcn_readlane(y0, j);
+        const int X1 = __builtin_amdgcn_readlane(x1, j), Y1 = __builtin_amdgcn_readlane(y1, j);
+        const int w = X1 - X0 + 1, area = w * (Y1 - Y0 + 1);
+        for (int t = rank; t < area; t += na) tflag[(Y0 + t / w) * cam.tiles_x + X0 + t % w] = 1;
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -221,7 +244,7 @@ hipError_t launch_prepare_scene(const ngs_scene& s, const ngs_ig_params& ig, hip
 }
 
 hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_params& rp,
-                          const ngs_projected& out, hipStream_t st, int tight) {
+                          const ngs_projected& out, hipStream_t st, int tight, int32_t* tflag) {
   if (s.n == 0) return hipSuccess;
   const int blocks = (s.n + 255) / 256;
   ProfScope ps(kProfProject, st);
@@ -229,7 +252,7 @@ hipError_t launch_project(const ngs_scene& s, const Group& G, const ngs_raster_p
                      G.g,
                      G.vs, (double)rp.z_near, (double)rp.eps2d, 1.0 / (double)rp.tile, out.mean2d, out.conic,
                      out.depth, out.zkey, out.rect, out.count, s.opacity, rp.cutoff_q,
-                     reinterpret_cast<float4*>(out.splat), tight);
+                     reinterpret_cast<float4*>(out.splat), tight, s.conf, tflag);
   return hipGetLastError();
 }
 
