@@ -126,7 +126,7 @@ ngs_status ig_prepare(ngs_ctx* ctx, void* ws, size_t ws_bytes, int64_t n, int64_
   *sticky = static_cast<int32_t*>(ws);
   *w = ig_ws_carve(static_cast<char*>(ws) + kIgHeader, n, k, slots);
   NGS_TRY_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(*sticky), 0u, kIgHeader / 4, st));
-  NGS_TRY_HIP(ctx, launch_ig_clear_flags(*w, n, st));
+  NGS_TRY_HIP(ctx, launch_ig_reset_slots(*w, n, st));
   return NGS_OK;
 }
 

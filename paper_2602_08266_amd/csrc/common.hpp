@@ -277,13 +277,12 @@ hipError_t launch_render_views(const ngs_scene& s, const ngs_projected& p, const
 struct IgWs {
   float* acc;           // [max_slots][astride] per-view screen statistics, slot-major
   int astride;          // stat_len(k) rounded up to 16 floats
-  int32_t* slot_of;     // [n] per-view slot, -1 for Gaussians that are not reduced
+  int32_t* slot_of;     // [n] per-view slot, -1 for Gaussians that are not reduced (-1 between views)
   int32_t* gid_of;      // [max_slots]
   int32_t* n_slots;     // [1]
   int32_t* overflow;    // [1]
   double* pmat;         // [max_slots][7][11] chain-rule matrix P of each slot (finalize)
   int32_t* tflag;       // [NGS_MAX_TILES] tiles reached by a weighted Gaussian's rect
-  uint8_t* cflag;       // [n] Gaussians that contribute to a pixel (pass 1; zero between views)
   float* pix_t;         // [NGS_MAX_TILES][256] final transmittance per pixel (pass 1)
   int32_t* pix_last;    // [NGS_MAX_TILES][256] last contributor's list position, -1 for none
   int2* wave_range;     // [NGS_MAX_TILES][4] per 16 x 4 strip: first weighted and last contributor
@@ -303,8 +302,9 @@ hipError_t launch_ig_tiles(const ngs_scene& s, const ngs_projected& p, const ngs
 // The two halves of launch_ig_tiles: with a target object the flags of the tiles that a
 // weighted Gaussian's rect reaches (see ig_tile_flags; needed before the filtered binning),
 // then the walk (front pass, slots of the contributing weighted Gaussians, back pass).
-// launch_ig_clear_flags zeroes the contribution flags of a fresh workspace.
-hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st, int g = 1, size_t vs = 0);
+// launch_ig_reset_slots sets every Gaussian's slot of a fresh workspace to -1 (the front pass
+// claims slots from -1; the finalisation sets the claimed ones back).
+hipError_t launch_ig_reset_slots(const IgWs& w, int64_t n, hipStream_t st);
 hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Group& G, const ngs_ig_params& ig,
                             const IgWs& w, hipStream_t st);
 // The first half of launch_ig_assign alone (slot counter, overflow flag and tile flags

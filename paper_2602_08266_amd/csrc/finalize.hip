@@ -314,13 +314,15 @@ __global__ __launch_bounds__(64) void k_fin_chain(int n, const float* __restrict
                                                   const float* __restrict__ log_scale, const float* __restrict__ rot,
                                                   GroupCams gc, double eps2d, const float* acc_, int astride,
                                                   int max_slots, const int32_t* gid_of_, const int32_t* n_slots_,
-                                                  double* pmat_, size_t vs) {
+                                                  double* pmat_, int32_t* slot_of_, size_t vs) {
   const DevCam cam = gc.c[blockIdx.y];
   const float* __restrict__ acc = vp(acc_, vs);
   const int32_t* __restrict__ gid_of = vp(gid_of_, vs);
   double* __restrict__ pmat = vp(pmat_, vs);
   const int used = min(*vp(n_slots_, vs), max_slots);
+  int32_t* __restrict__ slot_of = vp(slot_of_, vs);
   for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < used; slot += gridDim.x * blockDim.x) {
+    slot_of[gid_of[slot]] = -1;  // unslotted again for the next view (the back pass has run)
     const float a2f = acc[(size_t)slot * astride + kStatYd + tri_idx(6, 6, 7)];
     if (!(a2f > 0.f)) continue;
     double P[7][kNGeo];
@@ -585,7 +587,8 @@ hipError_t launch_ig_finalize(const ngs_scene& s, const Group& G, const ngs_rast
   const int cblocks = (int)std::min<int64_t>((w.max_slots + 63) / 64, std::max(256, 2048 / G.g));
   ProfScope ps(kProfIgFinalize, st);
   hipLaunchKernelGGL(k_fin_chain, dim3(cblocks, G.g), dim3(64), 0, st, s.n, s.mean, s.log_scale, s.rot, G.cams,
-                     (double)rp.eps2d, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.pmat, G.vs);
+                     (double)rp.eps2d, w.acc, w.astride, (int)w.max_slots, w.gid_of, w.n_slots, w.pmat, w.slot_of,
+                     G.vs);
   auto fin = ig.criterion == 1 ? k_finalize<true> : k_finalize<false>;
   hipLaunchKernelGGL(fin, dim3(blocks, G.g), dim3(kFinThreads), 0, st, s.n, s.k, s.mean, s.log_scale, s.rot, s.conf,
                      s.prob, (double)rp.eps2d, (double)ig.lambda_prior, ig.outputs, ig.mode, ig.conf_on_train,

@@ -14,10 +14,10 @@
 // The walk runs in three launches per view:
 //   1. k_ig_front, one 256-lane workgroup per tile, one lane per pixel: the front-to-back pass
 //      that gives each pixel its final transmittance and its last contributor (stored per
-//      pixel), and flags every Gaussian that contributes to some pixel;
-//   2. k_ig_slots: an accumulator slot for every flagged Gaussian with a nonzero confidence
-//      weight (U of them; every other Gaussian gets slot -1 and is never reduced), zeroed by
-//      k_ig_zero;
+//      pixel); the first contribution of a Gaussian with a nonzero confidence weight claims
+//      its accumulator slot (U of them; every other Gaussian keeps slot -1 and is never
+//      reduced; the finalisation sets the claimed ones back to -1 for the next view);
+//   2. k_ig_zero: the claimed slots' statistics zeroed;
 //   3. k_ig_back, one workgroup per tile with one, two or four lanes per pixel: the
 //      back-to-front pass from the tile's last contributor, recovering T before each Gaussian
 //      as T_after / (1 - alpha) and keeping the suffixes S in registers. For each slotted
@@ -134,15 +134,17 @@ __device__ __forceinline__ bool reaches(const Sh& S, int l, int cnt, float sx0, 
 // the list on its own: lane l holds batch entry l in registers (the next batch is loaded
 // while the current one is walked), the walk reads an entry's values with readlane, and a
 // wavefront stops once all its pixels are done. Writes each pixel's final transmittance and
-// last contributor (list position, -1 for none), flags (cflag[g] = 1) every Gaussian that
-// contributes to a pixel, and per wavefront the list positions of its first contributor with a
+// last contributor (list position, -1 for none), claims a slot for every weighted Gaussian
+// that contributes to a pixel (slot_of[g]: -1 until claimed; the claim takes it to -2 with a
+// compare-and-swap, then to the slot from the counter), and per wavefront the list positions of its first contributor with a
 // nonzero weight and of its last contributor (wave_range; INT_MAX / -1 when none): the back
 // pass of a wavefront needs no entry outside that range, since only weighted contributors
 // write records and only the contributors behind them feed their suffixes.
 __global__ __launch_bounds__(kTilePix) void k_ig_front(
     const uint32_t* gids_, const uint32_t* ranges_, GroupCams gc, RasterConst rc, const float4* splat_,
-    const float* __restrict__ conf, float* pix_t_, int32_t* pix_last_, int2* wave_range_, uint8_t* cflag_,
-    int64_t* __restrict__ stats, const int32_t* tflag_, size_t vs) {
+    const float* __restrict__ conf, float* pix_t_, int32_t* pix_last_, int2* wave_range_, int32_t* slot_of_,
+    int32_t* gid_of_, int32_t* n_slots_, int32_t* overflow_, int max_slots, int64_t* __restrict__ stats,
+    const int32_t* tflag_, size_t vs) {
   const DevCam cam = gc.c[blockIdx.y];
   if ((int)blockIdx.x >= cam.tiles_x * cam.tiles_y) return;  // past this view's tiles
   const uint32_t* __restrict__ gids = vp(gids_, vs);
@@ -151,7 +153,10 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
   float* __restrict__ pix_t = vp(pix_t_, vs);
   int32_t* __restrict__ pix_last = vp(pix_last_, vs);
   int2* __restrict__ wave_range = vp(wave_range_, vs);
-  uint8_t* __restrict__ cflag = vp(cflag_, vs);
+  int32_t* __restrict__ slot_of = vp(slot_of_, vs);
+  int32_t* __restrict__ gid_of = vp(gid_of_, vs);
+  int32_t* __restrict__ n_slots = vp(n_slots_, vs);
+  int32_t* __restrict__ overflow = vp(overflow_, vs);
   const int32_t* __restrict__ tflag = vp(tflag_, vs);
   __shared__ int tile_last_sh;
   // with stats: the tile's list positions that contribute to some pixel (one bit per position,
@@ -246,8 +251,19 @@ __global__ __launch_bounds__(kTilePix) void k_ig_front(
     }
     bool weighted = false;
     if ((any >> lane) & 1ull) {
-      cflag[eg] = 1;
       weighted = conf[eg] > 0.f;
+      // the first contribution of a weighted Gaussian claims its slot (past the capacity the
+      // view overflows and the Gaussian stays unslotted)
+      if (weighted && slot_of[eg] == -1 && atomicCAS(&slot_of[eg], -1, -2) == -1) {
+        const int s = atomicAdd(n_slots, 1);
+        if (s < max_slots) {
+          gid_of[s] = (int32_t)eg;
+          slot_of[eg] = s;
+        } else {
+          slot_of[eg] = -1;
+          atomicOr(overflow, 1);
+        }
+      }
     }
     const uint64_t wm = __ballot(weighted);
     if (wave_first == INT_MAX && wm) wave_first = (int)b0 + __ffsll((unsigned long long)wm) - 1;
@@ -585,69 +601,6 @@ __global__ __launch_bounds__(256) void k_ig_mark(int n, const float* __restrict_
   }
 }
 
-// Slot of every Gaussian for this view: a fresh slot for each one that pass 1 flagged (it
-// contributes to a pixel) and that has a nonzero confidence weight, -1 otherwise; the flags
-// are cleared for the next view. Each 256-thread block covers kAssignPer x 256 Gaussians
-// (coalesced), ranks its selected ones with a block scan and takes its slots with a single
-// counter update.
-constexpr int kAssignPer = 4;
-
-__global__ __launch_bounds__(256) void k_ig_slots(int n, const float* __restrict__ conf, uint8_t* cflag_,
-                                                  int32_t* slot_of_, int32_t* gid_of_, int32_t* n_slots_,
-                                                  int32_t* overflow_, int max_slots, size_t vs) {
-  uint8_t* __restrict__ cflag = vp(cflag_, vs);
-  int32_t* __restrict__ slot_of = vp(slot_of_, vs);
-  int32_t* __restrict__ gid_of = vp(gid_of_, vs);
-  int32_t* __restrict__ n_slots = vp(n_slots_, vs);
-  int32_t* __restrict__ overflow = vp(overflow_, vs);
-  __shared__ int wsum[256 / kWave];
-  __shared__ int base_sh;
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int g0 = blockIdx.x * (256 * kAssignPer) + threadIdx.x;
-  uint32_t bits = 0u;
-#pragma unroll
-  for (int i = 0; i < kAssignPer; ++i) {
-    const int g = g0 + i * 256;
-    if (g < n && cflag[g]) {
-      cflag[g] = 0;
-      if (conf[g] > 0.f) bits |= 1u << i;
-    }
-  }
-  const int c = __popc(bits);
-  int x = c;  // inclusive scan over the wavefront
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (lane >= off) x += y;
-  }
-  if (lane == kWave - 1) wsum[wave] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < 256 / kWave; ++w) tot += wsum[w];
-    base_sh = tot ? atomicAdd(n_slots, tot) : 0;
-  }
-  __syncthreads();
-  int slot = base_sh + x - c;
-  for (int w = 0; w < wave; ++w) slot += wsum[w];
-#pragma unroll
-  for (int i = 0; i < kAssignPer; ++i) {
-    const int g = g0 + i * 256;
-    if (g >= n) break;
-    if (!((bits >> i) & 1u)) {
-      slot_of[g] = -1;
-    } else if (slot < max_slots) {
-      slot_of[g] = slot;
-      gid_of[slot] = g;
-      ++slot;
-    } else {
-      slot_of[g] = -1;
-      atomicOr(overflow, 1);
-      ++slot;
-    }
-  }
-}
-
 // Zero the statistic rows of the assigned slots.
 __global__ __launch_bounds__(256) void k_ig_zero(float4* acc_, const int32_t* n_slots_, int max_slots, int astride,
                                                  size_t vs) {
@@ -679,7 +632,7 @@ int ig_stat_stride(int64_t k) { return (stat_len((int)k) + 15) / 16 * 16; }
 size_t ig_ws_fixed_bytes(int64_t n) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
-  return al(nn * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + al(nn) + 2 * al((size_t)NGS_MAX_TILES * kTilePix * 4) +
+  return al(nn * 4) + al(8) + al((size_t)NGS_MAX_TILES * 4) + 2 * al((size_t)NGS_MAX_TILES * kTilePix * 4) +
          al((size_t)NGS_MAX_TILES * (kTilePix / kWave) * 8);
 }
 
@@ -701,7 +654,6 @@ IgWs ig_ws_carve(void* ws, int64_t n, int64_t k, int64_t max_slots) {
   w.n_slots = (int32_t*)p; p += al(8);
   w.overflow = w.n_slots + 1;
   w.tflag = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * 4);
-  w.cflag = (uint8_t*)p; p += al(nn);
   w.pix_t = (float*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
   w.pix_last = (int32_t*)p; p += al((size_t)NGS_MAX_TILES * kTilePix * 4);
   w.wave_range = (int2*)p; p += al((size_t)NGS_MAX_TILES * (kTilePix / kWave) * 8);
@@ -736,9 +688,9 @@ hipError_t launch_ig_assign(const ngs_scene& s, const ngs_projected& p, const Gr
   return hipGetLastError();
 }
 
-hipError_t launch_ig_clear_flags(const IgWs& w, int64_t n, hipStream_t st, int g, size_t vs) {
-  return launch_fill_u32(reinterpret_cast<uint32_t*>(w.cflag), 0u, ((size_t)std::max<int64_t>(n, 1) + 3) / 4, st, g,
-                         vs);
+hipError_t launch_ig_reset_slots(const IgWs& w, int64_t n, hipStream_t st) {
+  return launch_fill_u32(reinterpret_cast<uint32_t*>(w.slot_of), 0xFFFFFFFFu, (size_t)std::max<int64_t>(n, 1), st, 1,
+                         0);
 }
 
 hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_tile_lists& l, const Group& G,
@@ -748,14 +700,11 @@ hipError_t launch_ig_walk(const ngs_scene& s, const ngs_projected& p, const ngs_
   {
     ProfScope ps(kProfIgFront, st);
     hipLaunchKernelGGL(k_ig_front, dim3(G.max_ntiles, G.g), dim3(kTilePix), 0, st, l.gids, l.ranges, G.cams, rc,
-                       reinterpret_cast<const float4*>(p.splat), s.conf, w.pix_t, w.pix_last, w.wave_range, w.cflag,
-                       stats, tflag, G.vs);
+                       reinterpret_cast<const float4*>(p.splat), s.conf, w.pix_t, w.pix_last, w.wave_range, w.slot_of,
+                       w.gid_of, w.n_slots, w.overflow, (int)w.max_slots, stats, tflag, G.vs);
   }
   {
     ProfScope ps(kProfIgAssign, st);
-    const int nb = (std::max(s.n, 1) + 256 * kAssignPer - 1) / (256 * kAssignPer);
-    hipLaunchKernelGGL(k_ig_slots, dim3(nb, G.g), dim3(256), 0, st, s.n, s.conf, w.cflag, w.slot_of, w.gid_of,
-                       w.n_slots, w.overflow, (int)w.max_slots, G.vs);
     hipLaunchKernelGGL(k_ig_zero, dim3(std::max(64, 1024 / G.g), G.g), dim3(256), 0, st,
                        reinterpret_cast<float4*>(w.acc), w.n_slots, (int)w.max_slots, w.astride, G.vs);
   }
