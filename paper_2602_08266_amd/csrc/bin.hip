@@ -652,7 +652,10 @@ __global__ __launch_bounds__(kWave * kWaves2) void k_tile2_scatter(const uint2* 
   uint32_t* cnt = lds2 + rows + wave * tiles_x;
   if (meta[3]) return;
   const uint32_t K2 = meta[1], NC = meta[2];
-  const uint32_t cap32 = (uint32_t)min(capacity, (int64_t)0xFFFFFFFF);
+  // positions stay below M <= capacity here (a view whose M exceeds the capacity returned
+  // above); the clamp below only keeps a stray position inside the list buffer, without a
+  // branch per store
+  const uint32_t cap_last = (uint32_t)min(max(capacity, (int64_t)1) - 1, (int64_t)0xFFFFFFFF);
   if (blockIdx.x * kWaves2 >= NC) return;
   for (int r = threadIdx.x; r < rows; r += blockDim.x) cpl[r] = cp[r];
   __syncthreads();
@@ -706,7 +709,7 @@ __global__ __launch_bounds__(kWave * kWaves2) void k_tile2_scatter(const uint2* 
       for (int t = 0; t + 1 < kGrp; ++t) cur[t] = cur[t + 1];
       const int x0 = (int)(e.y & 0xFFFFu), w = (int)(e.y >> 16);
       auto emit = [&](int, uint32_t pos) {
-        if (pos < cap32) gids_out[pos] = e.x;
+        gids_out[min(pos, cap_last)] = e.x;
       };
       if constexpr (NR > 0) {
         uint64_t u[NR];
