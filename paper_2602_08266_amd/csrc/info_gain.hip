@@ -36,7 +36,9 @@
 namespace ngs {
 namespace {
 
-constexpr int kBatch = 32;
+// Entries staged per back-pass batch: 64 with one lane per pixel (fewer batch barriers), 32 in
+// the wider workgroups, whose LDS holds more record rows.
+template <int LPP> constexpr int batch_entries() { return LPP == 1 ? 64 : 32; }
 
 // Per-pixel record of a contributing (pixel, Gaussian) pair, laid out so that every scalar
 // statistic of common.hpp is the product of two of its entries:
@@ -113,10 +115,11 @@ __device__ __forceinline__ void reduce_rows(int R, const float (*rec)[kRec], con
 
 template <int KP, int LPP>
 struct IgShared {
-  float mx[kBatch], my[kBatch], qa[kBatch], qb[kBatch], qc[kBatch], op[kBatch];
-  float z[kBatch], r[kBatch], g[kBatch], b[kBatch], hx[kBatch], hy[kBatch];
-  int32_t slot[kBatch];
-  float p[kBatch][KP];
+  static constexpr int kB = batch_entries<LPP>();
+  float mx[kB], my[kB], qa[kB], qb[kB], qc[kB], op[kB];
+  float z[kB], r[kB], g[kB], b[kB], hx[kB], hy[kB];
+  int32_t slot[kB];
+  float p[kB][KP];
   float rec[kTilePix * LPP / kWave][chunk_rows<LPP>()][kRec];
   float so[kTilePix * LPP / kWave][chunk_rows<LPP>()][KP + 4];  // padded like the record rows
   int flag;
@@ -384,6 +387,7 @@ __global__ __launch_bounds__(kTilePix * LPP, WPS) void k_ig_back(
   // batches, walking them, and (part of the walk) reducing records
   const bool timed = stats != nullptr;
   uint64_t c_bar = 0u, c_load = 0u, c_walk = 0u, c_rec = 0u;
+  constexpr int kBatch = batch_entries<LPP>();
   for (int hi = tile_last + 1; hi > first_w; hi -= kBatch) {
     const int lo = max(first_w, hi - kBatch);
     const int cnt = hi - lo;
