@@ -7,7 +7,7 @@ every candidate view: projection, binning and sorting, the fused compositing +
 information-gain walk, the FP64 finalize, Eq. 10-11 and the argmax. The training set
 (4 views: H_T and the Eq. 10 normalisers) is built once before timing and reported apart.
 
-Prints one JSON line. With --gpus N > 1 it exits: this build targets one GPU.
+Prints one JSON line. With --gpus N > 1 it exits: the scorer runs on one GPU.
 """
 from __future__ import annotations
 
@@ -679,7 +679,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the scorer is not sharded across GPUs in this build "
+        print("bench.py measures one GPU only: the scorer is not sharded across GPUs "
               "(views would be split across GPUs with one all-gather of the scores).", file=sys.stderr)
         sys.exit(2)
     if args.backward:
