@@ -439,6 +439,31 @@ def test_training_setup_degenerate_and_capacity(B, ctx):
     assert np.all(norm > 0)
 
 
+def test_view_slot_overflow_then_recovers(B, ctx):
+    """More weighted Gaussians reach a view than its workspace has statistic slots: the front
+    pass's slot claims stop at the capacity and the call reports NGS_CAPACITY; a scorer with
+    enough slots on the same context and scene then matches the oracle (the claimed slots and
+    the refused ones leave no stale entries behind)."""
+    log("test_view_slot_overflow_then_recovers")
+    cfg, scene, cands, train = scenegen.make_workload("tiny", 0)
+    cands = cands[:4]
+    ds = B.DeviceScene(scene, "cuda")
+    small = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=8,
+                        store_capacity=1 << 14)
+    with pytest.raises(B.NgsError) as e:
+        small.setup([B.camera(c) for c in train])
+    assert e.value.status == B.NGS_CAPACITY
+    ref = oracle.score(scene, train, cands)
+    assert ref.status == 0
+    scorer = B.NbvScorer(ctx, ds, B.raster_params(), B.ig_params(), max_pairs=1 << 18, max_slots=1 << 14,
+                         store_capacity=1 << 14)
+    scorer.setup([B.camera(c) for c in train])
+    for rep in range(2):  # the second call reuses the workspace after the first call's claims
+        scores, best, raw = scorer.score([B.camera(c) for c in cands])
+        for v in range(len(cands)):
+            check_gain(raw[v].cpu().numpy(), ref.ig_cand[v], f"call {rep} view {v}")
+
+
 @pytest.mark.parametrize("target", [-1, 3])
 def test_greedy_nbv_sequence_tiny(B, ctx, target):
     """Three greedy steps: each chosen view joins the training set (H_T and normalisers are
